@@ -1,0 +1,122 @@
+"""Exact reference of the Ozaki-II p-bit matrix product, in plain Python ints.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, ``__graft_entry__.smoke()`` and
+the ``cpu_baseline`` leg of ``bench.py`` may import this module.  It shares
+no code with the GPU path and uses no moduli: the method reaches, exactly,
+the integer product of the shared-exponent integer matrices (Algorithm
+section, "Integerization with shared exponents", Eqs. 1-2), so this oracle
+is that definition written out, followed by the single final rounding.
+
+Steps, in the paper's notation:
+  t     = p + g + ceil(log2 K)                        (Eq. 3, g = 16 by default)
+  e_i   = max exp(a_ik) over the nonzero a_ik          (Eq. 1; 0 for an all-zero row)
+  a^_ik = round(a_ik * 2^(t - e_i)),  |a^_ik| <= 2^t   (Eq. 1, round = nearest-even)
+  f_j, b^_kj likewise per column of B
+  c^_ij = sum_k a^_ik b^_kj                            (Eq. 2, exact)
+  c_ij  = round_p(c^_ij * 2^(e_i + f_j - 2t))          (Eq. 2 + one rounding, nearest-even)
+
+Number format (MPFR convention, |x| < 2^exp): value = sign * mant * 2^(exp - p)
+with sign in {-1, 0, +1} (0 is the number zero) and 0 <= mant < 2^p; bits of
+the stored significand at or above p are ignored.  Outputs are normalised:
+2^(p-1) <= mant < 2^p, or (0, 0, 0) for zero.
+
+Readings of the paper that this file takes (listed with the others in the
+design notes): round() is round-to-nearest-even on the exact dyadic value;
+the final rounding is nearest-even; an all-zero row/column gets exponent 0;
+ceil(log2 K) is used for non-power-of-two K.
+"""
+from __future__ import annotations
+
+from typing import List, Sequence, Tuple
+
+
+def ceil_log2(K: int) -> int:
+    """ceil(log2 K) for K >= 1."""
+    if K < 1:
+        raise ValueError("K must be >= 1")
+    return (K - 1).bit_length()
+
+
+def internal_width(p: int, K: int, guard_bits: int = 16, t_bits: int = 0) -> int:
+    """t of Eq. 3; an explicit t_bits overrides it (the paper's t_bits option)."""
+    if t_bits:
+        return t_bits
+    return p + guard_bits + ceil_log2(K)
+
+
+def shared_exponent(entries: Sequence[Tuple[int, int, int]]) -> int:
+    """max exp over the nonzero entries (Eq. 1); 0 when every entry is zero."""
+    exps = [e for (s, _m, e) in entries if s != 0]
+    return max(exps) if exps else 0
+
+
+def round_half_even_shift(x: int, shift: int) -> int:
+    """RNE(x / 2^shift) for x >= 0, shift >= 0."""
+    if shift <= 0:
+        return x << (-shift)
+    q = x >> shift
+    r = x - (q << shift)
+    half = 1 << (shift - 1)
+    if r > half or (r == half and (q & 1)):
+        q += 1
+    return q
+
+
+def integerize(sign: int, mant: int, exp: int, e: int, t: int, p: int) -> int:
+    """a^ = round(a * 2^(t - e)) for a = sign * mant * 2^(exp - p) (Eq. 1)."""
+    if sign == 0:
+        return 0
+    mant &= (1 << p) - 1
+    s = t - p + exp - e            # a * 2^(t-e) = sign * mant * 2^s
+    mag = mant << s if s >= 0 else round_half_even_shift(mant, -s)
+    return -mag if sign < 0 else mag
+
+
+def round_to_precision(c: int, scale: int, p: int) -> Tuple[int, int, int]:
+    """(sign, mant, exp) of RNE_p(c * 2^scale) in the MPFR convention."""
+    if c == 0:
+        return (0, 0, 0)
+    sign = -1 if c < 0 else 1
+    mag = -c if c < 0 else c
+    nb = mag.bit_length()
+    if nb <= p:
+        mant = mag << (p - nb)
+    else:
+        mant = round_half_even_shift(mag, nb - p)
+        if mant == (1 << p):        # rounding carried into a new bit
+            mant >>= 1
+            nb += 1
+    return (sign, mant, nb + scale)
+
+
+def scaled_matrices(A, B, t: int):
+    """(A^, B^, e, f) of Eq. 1 for operand matrices A (M x K) and B (K x N)."""
+    p = A.p
+    M, K = A.sign.shape
+    K2, N = B.sign.shape
+    assert K == K2 and B.p == p
+    a_rows = [[A.value_parts(i, k) for k in range(K)] for i in range(M)]
+    b_cols = [[B.value_parts(k, j) for k in range(K)] for j in range(N)]
+    e = [shared_exponent(r) for r in a_rows]
+    f = [shared_exponent(c) for c in b_cols]
+    Ah = [[integerize(s, m, x, e[i], t, p) for (s, m, x) in a_rows[i]] for i in range(M)]
+    Bh = [[integerize(s, m, x, f[j], t, p) for (s, m, x) in b_cols[j]] for j in range(N)]
+    return Ah, Bh, e, f   # Bh is stored per column: Bh[j][k] = b^_kj
+
+
+def exact_product(Ah: List[List[int]], Bh_cols: List[List[int]]) -> List[List[int]]:
+    """c^_ij = sum_k a^_ik b^_kj (Eq. 2), exact."""
+    return [[sum(a * b for a, b in zip(Ah[i], Bh_cols[j])) for j in range(len(Bh_cols))]
+            for i in range(len(Ah))]
+
+
+def oz2_gemm_ref(A, B, guard_bits: int = 16, t_bits: int = 0):
+    """Full reference: returns t, e, f, c^ (ints) and C as (sign, mant, exp) triples."""
+    p = A.p
+    K = A.sign.shape[1]
+    t = internal_width(p, K, guard_bits, t_bits)
+    Ah, Bh, e, f = scaled_matrices(A, B, t)
+    chat = exact_product(Ah, Bh)
+    C = [[round_to_precision(chat[i][j], e[i] + f[j] - 2 * t, p)
+          for j in range(len(f))] for i in range(len(e))]
+    return {"t": t, "e": e, "f": f, "Ah": Ah, "Bh": Bh, "chat": chat, "C": C}
