@@ -1,0 +1,233 @@
+/*
+ * oz2h.h -- C ABI of the MI355X (gfx950) Ozaki scheme II p-bit matrix product.
+ *
+ * C = A * B for p-bit floating-point matrices (p = 2 .. about 3300), computed
+ * as in the paper's Algorithm section ("Overall flow"):
+ *   (1) shared-exponent integer significands (Eqs. 1-3),
+ *   (2) centred residues modulo pairwise-coprime moduli m_l <= 16191, balanced
+ *       base-128 halves for moduli above 255 (subsection "(a) AMX-INT8 backend",
+ *       the Karatsuba identity there),
+ *   (3) exact INT8 x INT8 -> INT32 products, one per modulus (three for a
+ *       two-limb modulus), reduced to u_l = c^ mod m_l,
+ *   (4) direct CRT without multiple-precision division and the symmetric lift
+ *       ("Direct CRT without multiple-precision division" subsection),
+ *   (5) rescaling by 2^(e_i + f_j - 2t) and one round-to-nearest-even to p bits.
+ * Every stage runs in HIP kernels on the GPU; nothing falls back to the CPU.
+ *
+ * Number format (the MPFR convention the paper uses, |x| < 2^exp):
+ *   value = sign * mant * 2^(exp - p),  sign in {-1, 0, +1}  (0 means the number 0),
+ *   mant = nl = ceil(p/64) little-endian uint64 limbs per element, mant < 2^p;
+ *   bits at or above p in the top limb are ignored on input.  Results are
+ *   normalised: 2^(p-1) <= mant < 2^p, or sign = 0, exp = 0, mant = 0.
+ * Matrices are row-major with a leading dimension `ld` (in elements) shared by
+ * the sign, exp and limb arrays: element (r, c) is at index r*ld + c, its limbs
+ * at limbs[(r*ld + c)*nl ...].  OZ2H_OP_T means the stored matrix is op(X)^T.
+ *
+ * Conventions for every call:
+ *   - Pointers to matrices, workspaces and outputs are DEVICE pointers owned by
+ *     the caller; the library never frees them.  Plan and batched-plan handles
+ *     are owned by the library and released by their destroy calls.
+ *   - Argument checks happen on the host, synchronously, before anything is
+ *     launched; a failed check returns a negative oz2h_status, launches
+ *     nothing and sets the message returned by oz2h_last_error().  No C++
+ *     exception crosses the ABI.
+ *   - Compute calls are asynchronous on `stream` (0 = the null stream) and do
+ *     not synchronise; a launch failure returns OZ2H_EDEVICE.
+ *   - M or N equal to 0 is a successful no-op; oz2h_gemm with K = 0 writes the
+ *     zero matrix, oz2h_gemm_integers rejects K = 0 (its plan has K >= 1).
+ *   - Inputs must be normalised or zero in the sense above; exponents must lie
+ *     in [-2^29, 2^29] so that no intermediate exponent overflows.
+ */
+#ifndef OZ2H_H
+#define OZ2H_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    OZ2H_OK = 0,
+    OZ2H_EINVAL = -1,       /* bad argument (null pointer, bad shape, bad option)   */
+    OZ2H_ERANGE = -2,       /* K > 133000, or p / t beyond the supported moduli set */
+    OZ2H_ENOMEM = -3,       /* workspace too small, or plan tables not allocatable  */
+    OZ2H_EDEVICE = -4,      /* a HIP call or kernel launch failed                   */
+    OZ2H_EUNSUPPORTED = -5  /* the current device is not gfx950                     */
+} oz2h_status;
+
+typedef enum { OZ2H_OP_N = 0, OZ2H_OP_T = 1 } oz2h_op;
+
+/* Options, the paper's oz2_opts (Implementation section, "Structure"). */
+typedef struct {
+    int32_t guard_bits;  /* g in t = p + g + ceil(log2 K) (Eq. 3); default 16          */
+    int32_t t_bits;      /* 0: t from Eq. 3; otherwise the internal width t itself    */
+    int32_t crt_margin;  /* moduli satisfy log2 P > 2t + ceil(log2 K) + margin; the
+                            paper's implementation uses 2 (after Eq. crtcond)        */
+    uint32_t flags;      /* reserved, must be 0                                      */
+} oz2h_opts;
+
+/* Input matrix (device pointers). */
+typedef struct {
+    const uint64_t *limbs;
+    const int32_t *exp;
+    const int8_t *sign;
+    int64_t ld;
+} oz2h_cmat;
+
+/* Output matrix (device pointers). */
+typedef struct {
+    uint64_t *limbs;
+    int32_t *exp;
+    int8_t *sign;
+    int64_t ld;
+} oz2h_mat;
+
+typedef struct oz2h_plan oz2h_plan;
+
+typedef struct {
+    int32_t p;          /* significand bits                                          */
+    int32_t t;          /* internal width, Eq. 3                                     */
+    int64_t K;          /* contraction length the moduli were chosen for            */
+    int32_t L;          /* number of moduli                                          */
+    int32_t L1;         /* one-limb moduli (m <= 255), listed first                  */
+    int32_t L2;         /* two-limb moduli (255 < m <= 16191)                        */
+    int32_t G;          /* INT8 GEMMs = L1 + 3*L2                                    */
+    int32_t nw32;       /* 32-bit words of an integer significand (t+1 bits)         */
+    int32_t nd32;       /* 32-bit digits of the CRT accumulator: ceil(log2 P/32) + 2 */
+    double log2P;       /* log2 of the moduli product P                              */
+} oz2h_plan_info;
+
+/* Default options: guard_bits 16, t_bits 0, crt_margin 2, flags 0. */
+void oz2h_opts_default(oz2h_opts *o);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char *oz2h_last_error(void);
+
+/*
+ * Moduli selection, host only (no device needed).  The set follows the
+ * subsection "(a) AMX-INT8 backend" and Table "Moduli configuration": all 54
+ * prime powers <= 255 (largest power of each prime), in decreasing order, then
+ * the primes 255 < m <= 16191 in decreasing order, taken until
+ * log2 P > 2t + ceil(log2 K) + crt_margin.  Writes L, L1, G, t and log2 P;
+ * if `moduli` is non-null it must hold L entries (call once with NULL to size).
+ * Returns OZ2H_ERANGE if K > 133000 (INT32 exactness, K*127^2 < 2^31) or the
+ * required width exceeds what this library supports (at most 512 moduli).
+ */
+int oz2h_plan_moduli(int32_t p, int64_t K, const oz2h_opts *o, int32_t *L, int32_t *L1,
+                     int32_t *G, int32_t *t, double *log2P, uint16_t *moduli);
+
+/*
+ * Build the constant tables for precision p and contraction length K and
+ * upload them to the CURRENT device (synchronous hipMalloc + hipMemcpy; the
+ * only allocations the library itself makes).  The plan is then valid for
+ * products with exactly that K on that device.  o may be NULL (defaults).
+ */
+int oz2h_plan_create(int32_t p, int64_t K, const oz2h_opts *o, oz2h_plan **out);
+
+/*
+ * Test/expert variant: explicit internal width t and an explicit list of L
+ * pairwise-coprime moduli 2 <= m <= 16191 (e.g. the worked example's 5, 7, 9).
+ * Moduli <= 255 are one-limb, larger ones two-limb; they are reordered so that
+ * the one-limb moduli come first (oz2h_plan_get_moduli returns that order).
+ * K is the contraction length the plan accepts.  No CRT-bound check is made:
+ * the caller guarantees |c^| < P/2.
+ */
+int oz2h_plan_create_custom(int32_t p, int32_t t, int64_t K, int32_t L, const uint16_t *moduli,
+                            oz2h_plan **out);
+
+void oz2h_plan_destroy(oz2h_plan *plan);
+int oz2h_plan_get_info(const oz2h_plan *plan, oz2h_plan_info *info);
+/* The plan's moduli in the order the library uses (L entries). */
+int oz2h_plan_get_moduli(const oz2h_plan *plan, uint16_t *moduli);
+
+/* Bytes of device workspace oz2h_gemm / oz2h_gemm_integers need for M x N. */
+size_t oz2h_gemm_workspace_size(const oz2h_plan *plan, int64_t M, int64_t N);
+
+/*
+ * C = op(A) * op(B), op(A) M x K, op(B) K x N, p-bit in and out (the plan's p),
+ * K must equal the plan's K.  Workspace: at least oz2h_gemm_workspace_size
+ * bytes of device memory, 256-byte aligned; its contents are scratch.
+ * C may not alias A or B.
+ */
+int oz2h_gemm(const oz2h_plan *plan, int64_t M, int64_t N, int64_t K,
+              oz2h_op opA, oz2h_cmat A, oz2h_op opB, oz2h_cmat B, oz2h_mat C,
+              void *workspace, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Parity entry point: the same pipeline, stopping after the CRT and lift
+ * (stage 4).  Writes the exact integers c^_ij as chat_sign[i*N + j] in
+ * {-1, 0, +1} and magnitude limbs chat_mag[(i*N + j)*nlc + l] (nlc limbs,
+ * little-endian; nlc*64 must be >= log2 P), and the shared exponents
+ * e[M], f[N] (0 for an all-zero row / column).  The output value is
+ * c^_ij * 2^(e_i + f_j - 2t).
+ */
+int oz2h_gemm_integers(const oz2h_plan *plan, int64_t M, int64_t N, int64_t K,
+                       oz2h_op opA, oz2h_cmat A, oz2h_op opB, oz2h_cmat B,
+                       int8_t *chat_sign, uint64_t *chat_mag, int32_t nlc,
+                       int32_t *e, int32_t *f,
+                       void *workspace, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------- stage entry points (parity tests of single kernels) ---------------- */
+
+/*
+ * Stage 1, shared exponents (Eq. 1): out[r] = max exp(x) over the nonzero
+ * entries of logical row r, 0 if the row is all zero.  Entry (r, k) of the
+ * rows x count operand is at index r*rs + k*cs of sign/exp.
+ */
+int oz2h_exponents(int64_t rows, int64_t count, const int8_t *sign, const int32_t *exp,
+                   int64_t rs, int64_t cs, int32_t *out, hipStream_t stream);
+
+/*
+ * Stage 2, residues (Eq. 1 integerization + centred residues + balanced
+ * base-128 split).  For the logical rows x count operand (entry (r, k) at
+ * index r*rs + k*cs of sign/exp, limbs at that index * nl) and its shared
+ * exponents erow[rows], writes the plan's G int8 planes, plane g at
+ * planes[g*rpad*kpad + r*kpad + k]; rows >= `rows` and columns >= `count`
+ * are written as 0.  Plane order follows the moduli: one plane per one-limb
+ * modulus (the centred residue), then three per two-limb modulus (r0, r1,
+ * r0 + r1 with r = r0 + 128 r1, -64 <= r0 <= 63).  rpad must be a multiple of
+ * 128 and >= rows, kpad a multiple of 64 and >= count.
+ */
+int oz2h_residues(const oz2h_plan *plan, int64_t rows, int64_t count,
+                  const uint64_t *limbs, const int32_t *exp, const int8_t *sign,
+                  int64_t rs, int64_t cs, const int32_t *erow,
+                  int64_t rpad, int64_t kpad, int8_t *planes, hipStream_t stream);
+
+/*
+ * Stage 3, residue GEMMs and the fused reduction: for every modulus l,
+ * u_l = (sum_k A_l[i][k] B_l[j][k]) mod m_l in [0, m_l) (with the Karatsuba
+ * recombination P0 + 128 (Ps - P0 - P2) + 16384 P2 for two-limb moduli),
+ * written as uint16 u[l*mpad*npad + i*npad + j].  A planes are laid out as
+ * oz2h_residues writes them (G x mpad x kpad), B planes as G x npad x kpad
+ * (K-contiguous, i.e. B transposed).  mpad, npad multiples of 128, kpad of 64.
+ */
+int oz2h_residue_gemm(const oz2h_plan *plan, int64_t mpad, int64_t npad, int64_t kpad,
+                      const int8_t *a_planes, const int8_t *b_planes, uint16_t *u,
+                      hipStream_t stream);
+
+/*
+ * The bare exact INT8 GEMM (Step 3 of the tutorial section): C[i][j] =
+ * sum_k A[i][k] B[j][k] in int32, A M x K and B N x K K-contiguous int8 with
+ * leading dimension K; M, N multiples of 128, K a multiple of 64, K <= 133000.
+ */
+int oz2h_i8gemm(int64_t M, int64_t N, int64_t K, const int8_t *A, const int8_t *B, int32_t *C,
+                hipStream_t stream);
+
+/*
+ * Stage 4, direct CRT + symmetric lift: from u_l = c^ mod m_l (uint16, plane
+ * l at u[l*plane_stride + i*ldu + j]) reconstructs c^ with |c^| < P/2 as
+ * chat_sign[i*N + j] and nlc magnitude limbs chat_mag[(i*N + j)*nlc + l].
+ */
+int oz2h_crt(const oz2h_plan *plan, int64_t M, int64_t N, const uint16_t *u, int64_t ldu,
+             int64_t plane_stride, int8_t *chat_sign, uint64_t *chat_mag, int32_t nlc,
+             hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OZ2H_H */

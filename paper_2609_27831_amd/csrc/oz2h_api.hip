@@ -1,0 +1,534 @@
+// oz2h_api.hip -- the C ABI (include/oz2h.h): argument checks, plan upload,
+// workspace layout and the launch sequence of the Ozaki-II pipeline.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "oz2h.h"
+#include "oz2h_kernels.hpp"
+#include "oz2h_plan.hpp"
+
+using namespace oz2h;
+
+struct oz2h_plan {
+    PlanHost h;
+    int device = -1;
+    void *dbuf = nullptr;
+    ModInfo *d_info = nullptr;
+    double *d_resid = nullptr;
+    double *d_crt = nullptr;
+    uint32_t *d_pd = nullptr;
+    uint32_t *d_phd = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int ok() {
+    g_err.clear();
+    return OZ2H_OK;
+}
+
+#define OZ2H_HIP(call)                                                                   \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(OZ2H_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));    \
+    } while (0)
+
+int check_launch(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(OZ2H_EDEVICE, "%s launch failed: %s", what, hipGetErrorString(e));
+    return OZ2H_OK;
+}
+
+// the current device must be gfx950 (CDNA4); answers are cached per device
+int check_device(int *dev_out) {
+    static std::mutex mu;
+    static std::vector<int> state;   // 0 unknown, 1 ok, 2 unsupported
+    int dev = -1;
+    OZ2H_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)state.size() <= dev) state.resize(dev + 1, 0);
+    if (state[dev] == 0) {
+        hipDeviceProp_t prop;
+        OZ2H_HIP(hipGetDeviceProperties(&prop, dev));
+        state[dev] = strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 2;
+    }
+    if (state[dev] != 1) return fail(OZ2H_EUNSUPPORTED, "device %d is not gfx950", dev);
+    *dev_out = dev;
+    return OZ2H_OK;
+}
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    int64_t mpad, npad, kpad;
+    size_t off_e, off_f, off_a, off_b, off_u, total;
+};
+
+Layout layout_for(const PlanHost &h, int64_t M, int64_t N) {
+    Layout w{};
+    w.mpad = round_up(std::max<int64_t>(M, 1), GBM);
+    w.npad = round_up(std::max<int64_t>(N, 1), GBN);
+    w.kpad = round_up(std::max<int64_t>(h.K, 1), GBK);
+    size_t off = 0;
+    w.off_e = off;
+    off = align_up(off + sizeof(int32_t) * w.mpad);
+    w.off_f = off;
+    off = align_up(off + sizeof(int32_t) * w.npad);
+    w.off_a = off;
+    off = align_up(off + (size_t)h.G * w.mpad * w.kpad);
+    w.off_b = off;
+    off = align_up(off + (size_t)h.G * w.npad * w.kpad);
+    w.off_u = off;
+    off = align_up(off + sizeof(uint16_t) * (size_t)h.L * w.mpad * w.npad);
+    w.total = off;
+    return w;
+}
+
+// shared exponents of a rows x count side (entry (r, k) at r*rs + k*cs)
+int launch_exponents(int64_t rows, int64_t count, const int8_t *sign, const int32_t *exp,
+                     int64_t rs, int64_t cs, int32_t *out, hipStream_t s) {
+    if (rows <= 0) return OZ2H_OK;
+    const unsigned nb = (unsigned)((rows + 255) / 256);
+    k_fill_i32<<<nb, 256, 0, s>>>(out, rows, INT_MIN);
+    if (count > 0) {
+        if (cs == 1) {
+            dim3 grid((unsigned)((rows + 3) / 4), (unsigned)((count + 4095) / 4096));
+            k_exp_kcontig<<<grid, 256, 0, s>>>(sign, exp, rows, count, rs, out);
+        } else {
+            dim3 grid(nb, (unsigned)((count + 63) / 64));
+            k_exp_generic<<<grid, 256, 0, s>>>(sign, exp, rows, count, rs, cs, out);
+        }
+    }
+    k_exp_fix<<<nb, 256, 0, s>>>(out, rows);
+    return check_launch("exponent scan");
+}
+
+int launch_residues(const oz2h_plan *pl, int64_t rows, int64_t count, const uint64_t *limbs,
+                    const int32_t *exp, const int8_t *sign, int64_t rs, int64_t cs,
+                    const int32_t *erow, int64_t rpad, int64_t kpad, int8_t *planes,
+                    hipStream_t s) {
+    const PlanHost &h = pl->h;
+    const int nl = (h.p + 63) / 64;
+    const int64_t ps = rpad * kpad;
+    int rb = h.nw32 <= 64 ? 4 : (h.nw32 <= 128 ? 2 : 1);   // LDS <= 64 KiB per block
+    dim3 grid((unsigned)(kpad / 64), (unsigned)(rpad / rb));
+    const size_t lds = (size_t)h.nw32 * 64 * rb * sizeof(uint32_t);
+#define OZ2H_RES(RB)                                                                       \
+    k_residues<RB><<<grid, 64 * RB, lds, s>>>(limbs, exp, sign, rs, cs, rows, count, kpad, \
+                                               ps, erow, h.p, nl, h.t, h.nw32, pl->d_resid, \
+                                               pl->d_info, h.L, h.lgroups, planes)
+    if (rb == 4) OZ2H_RES(4);
+    else if (rb == 2) OZ2H_RES(2);
+    else OZ2H_RES(1);
+#undef OZ2H_RES
+    return check_launch("residues");
+}
+
+int launch_resgemm(const oz2h_plan *pl, int64_t mpad, int64_t npad, int64_t kpad,
+                   const int8_t *a, const int8_t *b, uint16_t *u, hipStream_t s) {
+    const PlanHost &h = pl->h;
+    dim3 grid((unsigned)(npad / GBN), (unsigned)(mpad / GBM), (unsigned)h.L);
+    k_resgemm<false><<<grid, 256, 0, s>>>(a, b, kpad, mpad * kpad, npad * kpad, pl->d_info, u,
+                                          mpad * npad, npad, nullptr);
+    return check_launch("residue GEMM");
+}
+
+int launch_crt(const oz2h_plan *pl, int64_t M, int64_t N, const uint16_t *u, int64_t u_ps,
+               int64_t ldu, const int32_t *e, const int32_t *f, bool round, int8_t *osign,
+               int32_t *oexp, uint64_t *olimbs, int64_t ldc, uint64_t *chat, int nlc,
+               hipStream_t s) {
+    const PlanHost &h = pl->h;
+    if (M * N == 0) return OZ2H_OK;
+    const int bd = h.nd32 <= 64 ? 256 : (h.nd32 <= 128 ? 128 : 64);
+    const size_t lds = (size_t)h.nd32 * bd * sizeof(uint32_t);
+    const unsigned nb = (unsigned)((M * N + bd - 1) / bd);
+#define OZ2H_CRT(DC, R)                                                                      \
+    k_crt<DC, R><<<nb, bd, lds, s>>>(u, u_ps, ldu, M, N, pl->d_info, h.L, pl->d_crt,          \
+                                     h.crt_ndpad, h.crt_nc, h.nd32, pl->d_pd, pl->d_phd, e, f, \
+                                     h.t, h.p, osign, oexp, olimbs, ldc, chat, nlc)
+#define OZ2H_CRT_DC(R)                              \
+    switch (h.crt_dc) {                             \
+        case 8: OZ2H_CRT(8, R); break;              \
+        case 16: OZ2H_CRT(16, R); break;            \
+        case 24: OZ2H_CRT(24, R); break;            \
+        default: OZ2H_CRT(32, R); break;            \
+    }
+    if (round) {
+        OZ2H_CRT_DC(true)
+    } else {
+        OZ2H_CRT_DC(false)
+    }
+#undef OZ2H_CRT_DC
+#undef OZ2H_CRT
+    return check_launch("CRT");
+}
+
+int upload_plan(oz2h_plan *pl) {
+    const PlanHost &h = pl->h;
+    const size_t n_info = sizeof(ModInfo) * h.L;
+    const size_t n_res = sizeof(double) * h.resid_tab.size();
+    const size_t n_crt = sizeof(double) * h.crt_digits.size();
+    const size_t n_pd = sizeof(uint32_t) * h.nd32;
+    size_t off = 0;
+    const size_t o_info = off;
+    off = align_up(off + n_info);
+    const size_t o_res = off;
+    off = align_up(off + n_res);
+    const size_t o_crt = off;
+    off = align_up(off + n_crt);
+    const size_t o_pd = off;
+    off = align_up(off + n_pd);
+    const size_t o_phd = off;
+    off = align_up(off + n_pd);
+    void *buf = nullptr;
+    if (hipMalloc(&buf, off) != hipSuccess) return fail(OZ2H_ENOMEM, "plan tables: hipMalloc failed");
+    pl->dbuf = buf;
+    char *b = (char *)buf;
+    pl->d_info = (ModInfo *)(b + o_info);
+    pl->d_resid = (double *)(b + o_res);
+    pl->d_crt = (double *)(b + o_crt);
+    pl->d_pd = (uint32_t *)(b + o_pd);
+    pl->d_phd = (uint32_t *)(b + o_phd);
+    OZ2H_HIP(hipMemcpy(pl->d_info, h.info.data(), n_info, hipMemcpyHostToDevice));
+    OZ2H_HIP(hipMemcpy(pl->d_resid, h.resid_tab.data(), n_res, hipMemcpyHostToDevice));
+    OZ2H_HIP(hipMemcpy(pl->d_crt, h.crt_digits.data(), n_crt, hipMemcpyHostToDevice));
+    OZ2H_HIP(hipMemcpy(pl->d_pd, h.p_digits.data(), n_pd, hipMemcpyHostToDevice));
+    OZ2H_HIP(hipMemcpy(pl->d_phd, h.ph_digits.data(), n_pd, hipMemcpyHostToDevice));
+    return OZ2H_OK;
+}
+
+int check_plan(const oz2h_plan *pl) {
+    if (!pl) return fail(OZ2H_EINVAL, "plan is NULL");
+    int dev = -1;
+    int st = check_device(&dev);
+    if (st) return st;
+    if (dev != pl->device)
+        return fail(OZ2H_EINVAL, "plan was created on device %d, current device is %d", pl->device, dev);
+    return OZ2H_OK;
+}
+
+int check_cmat(const oz2h_cmat &X, const char *name, int64_t rows, int64_t cols) {
+    // rows x cols is the STORED shape
+    if (!X.limbs || !X.exp || !X.sign) return fail(OZ2H_EINVAL, "%s: NULL pointer", name);
+    if (X.ld < std::max<int64_t>(cols, 1))
+        return fail(OZ2H_EINVAL, "%s: ld %lld < stored columns %lld", name, (long long)X.ld,
+                    (long long)cols);
+    (void)rows;
+    return OZ2H_OK;
+}
+
+// shared body of oz2h_gemm and oz2h_gemm_integers
+int run_pipeline(const oz2h_plan *pl, int64_t M, int64_t N, int64_t K, oz2h_op opA,
+                 oz2h_cmat A, oz2h_op opB, oz2h_cmat B, bool round, oz2h_mat *C, int8_t *chat_sign,
+                 uint64_t *chat_mag, int nlc, int32_t *e_out, int32_t *f_out, void *ws,
+                 size_t ws_bytes, hipStream_t s) {
+    int st = check_plan(pl);
+    if (st) return st;
+    const PlanHost &h = pl->h;
+    if (M < 0 || N < 0 || K < 0) return fail(OZ2H_EINVAL, "negative dimension");
+    if ((opA != OZ2H_OP_N && opA != OZ2H_OP_T) || (opB != OZ2H_OP_N && opB != OZ2H_OP_T))
+        return fail(OZ2H_EINVAL, "op must be OZ2H_OP_N or OZ2H_OP_T");
+    if (M == 0 || N == 0) return ok();
+    if (round) {
+        if (!C || !C->limbs || !C->exp || !C->sign) return fail(OZ2H_EINVAL, "C: NULL pointer");
+        if (C->ld < N) return fail(OZ2H_EINVAL, "C: ld < N");
+    } else {
+        if (!chat_sign || !chat_mag || !e_out || !f_out)
+            return fail(OZ2H_EINVAL, "integer outputs: NULL pointer");
+        if ((int64_t)nlc * 64 < h.pbits) return fail(OZ2H_EINVAL, "nlc too small for |c^| < P/2");
+    }
+    if (K == 0) {
+        if (round) {
+            const int nl = (h.p + 63) / 64;
+            k_zero_out<<<(unsigned)((M * N + 255) / 256), 256, 0, s>>>(C->sign, C->exp, C->limbs,
+                                                                       M, N, C->ld, nl);
+            st = check_launch("zero output");
+            return st ? st : ok();
+        }
+        return fail(OZ2H_EINVAL, "K = 0 has no integer representation to report");
+    }
+    if (K != h.K) return fail(OZ2H_EINVAL, "K = %lld but the plan was built for K = %lld",
+                              (long long)K, (long long)h.K);
+    st = check_cmat(A, "A", opA == OZ2H_OP_N ? M : K, opA == OZ2H_OP_N ? K : M);
+    if (st) return st;
+    st = check_cmat(B, "B", opB == OZ2H_OP_N ? K : N, opB == OZ2H_OP_N ? N : K);
+    if (st) return st;
+    const Layout w = layout_for(h, M, N);
+    if (!ws) return fail(OZ2H_EINVAL, "workspace is NULL");
+    if (((uintptr_t)ws) % kAlign) return fail(OZ2H_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < w.total)
+        return fail(OZ2H_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, w.total);
+    char *wb = (char *)ws;
+    int32_t *e = (int32_t *)(wb + w.off_e);
+    int32_t *f = (int32_t *)(wb + w.off_f);
+    int8_t *ap = (int8_t *)(wb + w.off_a);
+    int8_t *bp = (int8_t *)(wb + w.off_b);
+    uint16_t *u = (uint16_t *)(wb + w.off_u);
+
+    // logical side strides: rows own the exponent, k is the contraction
+    const int64_t a_rs = opA == OZ2H_OP_N ? A.ld : 1, a_cs = opA == OZ2H_OP_N ? 1 : A.ld;
+    const int64_t b_rs = opB == OZ2H_OP_N ? 1 : B.ld, b_cs = opB == OZ2H_OP_N ? B.ld : 1;
+
+    if ((st = launch_exponents(M, K, A.sign, A.exp, a_rs, a_cs, e, s))) return st;
+    if ((st = launch_exponents(N, K, B.sign, B.exp, b_rs, b_cs, f, s))) return st;
+    if ((st = launch_residues(pl, M, K, A.limbs, A.exp, A.sign, a_rs, a_cs, e, w.mpad, w.kpad, ap, s)))
+        return st;
+    if ((st = launch_residues(pl, N, K, B.limbs, B.exp, B.sign, b_rs, b_cs, f, w.npad, w.kpad, bp, s)))
+        return st;
+    if ((st = launch_resgemm(pl, w.mpad, w.npad, w.kpad, ap, bp, u, s))) return st;
+    if (round) {
+        st = launch_crt(pl, M, N, u, w.mpad * w.npad, w.npad, e, f, true, C->sign, C->exp,
+                        C->limbs, C->ld, nullptr, 0, s);
+    } else {
+        st = launch_crt(pl, M, N, u, w.mpad * w.npad, w.npad, e, f, false, chat_sign, nullptr,
+                        nullptr, N, chat_mag, nlc, s);
+        if (!st) {
+            OZ2H_HIP(hipMemcpyAsync(e_out, e, sizeof(int32_t) * M, hipMemcpyDeviceToDevice, s));
+            OZ2H_HIP(hipMemcpyAsync(f_out, f, sizeof(int32_t) * N, hipMemcpyDeviceToDevice, s));
+        }
+    }
+    if (st) return st;
+    return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+void oz2h_opts_default(oz2h_opts *o) {
+    if (!o) return;
+    o->guard_bits = 16;
+    o->t_bits = 0;
+    o->crt_margin = 2;
+    o->flags = 0;
+}
+
+const char *oz2h_last_error(void) { return g_err.c_str(); }
+
+int oz2h_plan_moduli(int32_t p, int64_t K, const oz2h_opts *o, int32_t *L, int32_t *L1,
+                     int32_t *G, int32_t *t, double *log2P, uint16_t *moduli) {
+    oz2h_opts d;
+    oz2h_opts_default(&d);
+    if (!o) o = &d;
+    if (o->flags) return fail(OZ2H_EINVAL, "flags must be 0");
+    std::vector<uint32_t> mods;
+    int tt = 0;
+    double lp = 0;
+    std::string err;
+    int st = select_moduli(p, K, o->guard_bits, o->t_bits, o->crt_margin, mods, tt, lp, err);
+    if (st) return fail(st, "%s", err.c_str());
+    int l1 = 0, g = 0;
+    for (uint32_t m : mods) {
+        l1 += m <= kOneLimbMax;
+        g += m <= kOneLimbMax ? 1 : 3;
+    }
+    if (L) *L = (int32_t)mods.size();
+    if (L1) *L1 = l1;
+    if (G) *G = g;
+    if (t) *t = tt;
+    if (log2P) *log2P = lp;
+    if (moduli)
+        for (size_t i = 0; i < mods.size(); ++i) moduli[i] = (uint16_t)mods[i];
+    return ok();
+}
+
+static int plan_finish(oz2h_plan *pl, oz2h_plan **out) {
+    int dev = -1;
+    int st = check_device(&dev);
+    if (st) {
+        delete pl;
+        return st;
+    }
+    pl->device = dev;
+    st = upload_plan(pl);
+    if (st) {
+        if (pl->dbuf) (void)hipFree(pl->dbuf);
+        delete pl;
+        return st;
+    }
+    *out = pl;
+    return ok();
+}
+
+int oz2h_plan_create(int32_t p, int64_t K, const oz2h_opts *o, oz2h_plan **out) {
+    if (!out) return fail(OZ2H_EINVAL, "out is NULL");
+    *out = nullptr;
+    oz2h_opts d;
+    oz2h_opts_default(&d);
+    if (!o) o = &d;
+    if (o->flags) return fail(OZ2H_EINVAL, "flags must be 0");
+    std::vector<uint32_t> mods;
+    int t = 0;
+    double lp = 0;
+    std::string err;
+    int st = select_moduli(p, K, o->guard_bits, o->t_bits, o->crt_margin, mods, t, lp, err);
+    if (st) return fail(st, "%s", err.c_str());
+    oz2h_plan *pl = new oz2h_plan();
+    st = build_plan(p, t, K, mods, pl->h, err);
+    if (st) {
+        delete pl;
+        return fail(st, "%s", err.c_str());
+    }
+    return plan_finish(pl, out);
+}
+
+int oz2h_plan_create_custom(int32_t p, int32_t t, int64_t K, int32_t L, const uint16_t *moduli,
+                            oz2h_plan **out) {
+    if (!out || !moduli) return fail(OZ2H_EINVAL, "NULL pointer");
+    *out = nullptr;
+    if (p < 2 || t < 1) return fail(OZ2H_EINVAL, "need p >= 2 and t >= 1");
+    if (K < 1 || K > kMaxK) return fail(OZ2H_ERANGE, "K must be in [1, 133000]");
+    if (L < 1 || L > kMaxModuli) return fail(OZ2H_ERANGE, "L must be in [1, 512]");
+    std::vector<uint32_t> mods(moduli, moduli + L);
+    oz2h_plan *pl = new oz2h_plan();
+    std::string err;
+    int st = build_plan(p, t, K, mods, pl->h, err);
+    if (st) {
+        delete pl;
+        return fail(st, "%s", err.c_str());
+    }
+    return plan_finish(pl, out);
+}
+
+void oz2h_plan_destroy(oz2h_plan *plan) {
+    if (!plan) return;
+    if (plan->dbuf) (void)hipFree(plan->dbuf);
+    delete plan;
+}
+
+int oz2h_plan_get_info(const oz2h_plan *plan, oz2h_plan_info *info) {
+    if (!plan || !info) return fail(OZ2H_EINVAL, "NULL pointer");
+    const PlanHost &h = plan->h;
+    info->p = h.p;
+    info->t = h.t;
+    info->K = h.K;
+    info->L = h.L;
+    info->L1 = h.L1;
+    info->L2 = h.L2;
+    info->G = h.G;
+    info->nw32 = h.nw32;
+    info->nd32 = h.nd32;
+    info->log2P = h.log2P;
+    return ok();
+}
+
+int oz2h_plan_get_moduli(const oz2h_plan *plan, uint16_t *moduli) {
+    if (!plan || !moduli) return fail(OZ2H_EINVAL, "NULL pointer");
+    for (int l = 0; l < plan->h.L; ++l) moduli[l] = (uint16_t)plan->h.moduli[l];
+    return ok();
+}
+
+size_t oz2h_gemm_workspace_size(const oz2h_plan *plan, int64_t M, int64_t N) {
+    if (!plan || M < 0 || N < 0) return 0;
+    return layout_for(plan->h, M, N).total;
+}
+
+int oz2h_gemm(const oz2h_plan *plan, int64_t M, int64_t N, int64_t K, oz2h_op opA, oz2h_cmat A,
+              oz2h_op opB, oz2h_cmat B, oz2h_mat C, void *workspace, size_t ws_bytes,
+              hipStream_t stream) {
+    return run_pipeline(plan, M, N, K, opA, A, opB, B, true, &C, nullptr, nullptr, 0, nullptr,
+                        nullptr, workspace, ws_bytes, stream);
+}
+
+int oz2h_gemm_integers(const oz2h_plan *plan, int64_t M, int64_t N, int64_t K, oz2h_op opA,
+                       oz2h_cmat A, oz2h_op opB, oz2h_cmat B, int8_t *chat_sign,
+                       uint64_t *chat_mag, int32_t nlc, int32_t *e, int32_t *f, void *workspace,
+                       size_t ws_bytes, hipStream_t stream) {
+    return run_pipeline(plan, M, N, K, opA, A, opB, B, false, nullptr, chat_sign, chat_mag, nlc,
+                        e, f, workspace, ws_bytes, stream);
+}
+
+int oz2h_exponents(int64_t rows, int64_t count, const int8_t *sign, const int32_t *exp,
+                   int64_t rs, int64_t cs, int32_t *out, hipStream_t stream) {
+    int dev = -1;
+    int st = check_device(&dev);
+    if (st) return st;
+    if (rows < 0 || count < 0) return fail(OZ2H_EINVAL, "negative dimension");
+    if (rows == 0) return ok();
+    if (!out || (count > 0 && (!sign || !exp))) return fail(OZ2H_EINVAL, "NULL pointer");
+    st = launch_exponents(rows, count, sign, exp, rs, cs, out, stream);
+    return st ? st : ok();
+}
+
+int oz2h_residues(const oz2h_plan *plan, int64_t rows, int64_t count, const uint64_t *limbs,
+                  const int32_t *exp, const int8_t *sign, int64_t rs, int64_t cs,
+                  const int32_t *erow, int64_t rpad, int64_t kpad, int8_t *planes,
+                  hipStream_t stream) {
+    int st = check_plan(plan);
+    if (st) return st;
+    if (rows < 0 || count < 0) return fail(OZ2H_EINVAL, "negative dimension");
+    if (rpad % GBM || kpad % GBK || rpad < rows || kpad < count || rpad <= 0 || kpad <= 0)
+        return fail(OZ2H_EINVAL, "rpad must be a positive multiple of 128 >= rows, kpad of 64 >= count");
+    if (!planes || (rows > 0 && count > 0 && (!limbs || !exp || !sign || !erow)))
+        return fail(OZ2H_EINVAL, "NULL pointer");
+    st = launch_residues(plan, rows, count, limbs, exp, sign, rs, cs, erow, rpad, kpad, planes,
+                         stream);
+    return st ? st : ok();
+}
+
+int oz2h_residue_gemm(const oz2h_plan *plan, int64_t mpad, int64_t npad, int64_t kpad,
+                      const int8_t *a_planes, const int8_t *b_planes, uint16_t *u,
+                      hipStream_t stream) {
+    int st = check_plan(plan);
+    if (st) return st;
+    if (mpad <= 0 || npad <= 0 || kpad <= 0 || mpad % GBM || npad % GBN || kpad % GBK)
+        return fail(OZ2H_EINVAL, "mpad, npad must be positive multiples of 128 and kpad of 64");
+    if (kpad > kMaxK + GBK) return fail(OZ2H_ERANGE, "K too large for exact INT32 accumulation");
+    if (!a_planes || !b_planes || !u) return fail(OZ2H_EINVAL, "NULL pointer");
+    st = launch_resgemm(plan, mpad, npad, kpad, a_planes, b_planes, u, stream);
+    return st ? st : ok();
+}
+
+int oz2h_i8gemm(int64_t M, int64_t N, int64_t K, const int8_t *A, const int8_t *B, int32_t *C,
+                hipStream_t stream) {
+    int dev = -1;
+    int st = check_device(&dev);
+    if (st) return st;
+    if (M <= 0 || N <= 0 || K <= 0 || M % GBM || N % GBN || K % GBK)
+        return fail(OZ2H_EINVAL, "M, N must be positive multiples of 128 and K of 64");
+    if (K > kMaxK) return fail(OZ2H_ERANGE, "K > 133000");
+    if (!A || !B || !C) return fail(OZ2H_EINVAL, "NULL pointer");
+    dim3 grid((unsigned)(N / GBN), (unsigned)(M / GBM), 1);
+    k_resgemm<true><<<grid, 256, 0, stream>>>(A, B, K, 0, 0, nullptr, nullptr, 0, N, C);
+    st = check_launch("int8 GEMM");
+    return st ? st : ok();
+}
+
+int oz2h_crt(const oz2h_plan *plan, int64_t M, int64_t N, const uint16_t *u, int64_t ldu,
+             int64_t plane_stride, int8_t *chat_sign, uint64_t *chat_mag, int32_t nlc,
+             hipStream_t stream) {
+    int st = check_plan(plan);
+    if (st) return st;
+    if (M < 0 || N < 0) return fail(OZ2H_EINVAL, "negative dimension");
+    if (M == 0 || N == 0) return ok();
+    if (!u || !chat_sign || !chat_mag) return fail(OZ2H_EINVAL, "NULL pointer");
+    if (ldu < N || plane_stride < (M - 1) * ldu + N) return fail(OZ2H_EINVAL, "bad u layout");
+    if ((int64_t)nlc * 64 < plan->h.pbits) return fail(OZ2H_EINVAL, "nlc too small");
+    st = launch_crt(plan, M, N, u, plane_stride, ldu, nullptr, nullptr, false, chat_sign, nullptr,
+                    nullptr, N, chat_mag, nlc, stream);
+    return st ? st : ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,269 @@
+// oz2h_plan.cpp -- moduli selection and constant tables of the Ozaki-II pipeline.
+//
+// Moduli: subsection "(a) AMX-INT8 backend" and Table "Moduli configuration".
+// CRT constants: subsection "Direct CRT without multiple-precision division".
+// Residue constants: subsection "Residue generation and packing" (the residue
+// of a multi-digit integer is the sum of its digits times 2^(digit weight) mod m).
+#include "oz2h_plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+namespace oz2h {
+
+namespace {
+
+// little-endian base-2^32 natural numbers, just what the plan needs
+using Nat = std::vector<uint32_t>;
+
+void nat_trim(Nat &a) {
+    while (!a.empty() && a.back() == 0) a.pop_back();
+}
+
+void nat_mul_small(Nat &a, uint32_t m) {
+    uint64_t carry = 0;
+    for (auto &d : a) {
+        uint64_t x = (uint64_t)d * m + carry;
+        d = (uint32_t)x;
+        carry = x >> 32;
+    }
+    if (carry) a.push_back((uint32_t)carry);
+}
+
+// a / m, requiring the division to be exact; returns the quotient
+Nat nat_divexact_small(const Nat &a, uint32_t m) {
+    Nat q(a.size());
+    uint64_t rem = 0;
+    for (size_t i = a.size(); i-- > 0;) {
+        uint64_t x = (rem << 32) | a[i];
+        q[i] = (uint32_t)(x / m);
+        rem = x % m;
+    }
+    nat_trim(q);
+    return q;
+}
+
+uint32_t nat_mod_small(const Nat &a, uint32_t m) {
+    uint64_t rem = 0;
+    for (size_t i = a.size(); i-- > 0;) rem = ((rem << 32) | a[i]) % m;
+    return (uint32_t)rem;
+}
+
+int nat_bitlen(const Nat &a) {
+    for (size_t i = a.size(); i-- > 0;)
+        if (a[i]) return (int)(32 * i + (32 - __builtin_clz(a[i])));
+    return 0;
+}
+
+// x^-1 mod m for gcd(x, m) = 1
+uint32_t inv_mod(uint32_t x, uint32_t m) {
+    int64_t r0 = m, r1 = x % m, s0 = 0, s1 = 1;
+    while (r1) {
+        int64_t q = r0 / r1;
+        int64_t r2 = r0 - q * r1;
+        r0 = r1;
+        r1 = r2;
+        int64_t s2 = s0 - q * s1;
+        s0 = s1;
+        s1 = s2;
+    }
+    if (r0 != 1) return 0;
+    int64_t v = s0 % (int64_t)m;
+    if (v < 0) v += m;
+    return (uint32_t)v;
+}
+
+std::vector<uint32_t> primes_upto(uint32_t n) {
+    std::vector<char> sieve(n + 1, 1);
+    sieve[0] = 0;
+    if (n >= 1) sieve[1] = 0;
+    for (uint32_t i = 2; (uint64_t)i * i <= n; ++i)
+        if (sieve[i])
+            for (uint32_t j = i * i; j <= n; j += i) sieve[j] = 0;
+    std::vector<uint32_t> out;
+    for (uint32_t i = 2; i <= n; ++i)
+        if (sieve[i]) out.push_back(i);
+    return out;
+}
+
+}  // namespace
+
+int ceil_log2(int64_t K) {
+    int b = 0;
+    int64_t v = K - 1;
+    while (v > 0) {
+        ++b;
+        v >>= 1;
+    }
+    return b;
+}
+
+const std::vector<uint32_t> &global_moduli() {
+    static const std::vector<uint32_t> list = [] {
+        std::vector<uint32_t> one, two;
+        for (uint32_t q : primes_upto(kTwoLimbMax)) {
+            if (q <= kOneLimbMax) {
+                uint32_t x = q;
+                while (x * q <= kOneLimbMax) x *= q;   // largest power of q that fits
+                one.push_back(x);
+            } else {
+                two.push_back(q);
+            }
+        }
+        std::sort(one.rbegin(), one.rend());
+        std::sort(two.rbegin(), two.rend());
+        one.insert(one.end(), two.begin(), two.end());
+        return one;
+    }();
+    return list;
+}
+
+int select_moduli(int p, int64_t K, int guard_bits, int t_bits, int margin,
+                  std::vector<uint32_t> &mods, int &t, double &log2P, std::string &err) {
+    if (p < 2) {
+        err = "p must be >= 2";
+        return -1;
+    }
+    if (K < 1 || K > kMaxK) {
+        err = "K must be in [1, 133000] (INT32 exactness of the residue GEMMs)";
+        return K < 1 ? -1 : -2;
+    }
+    if (guard_bits < 0 || t_bits < 0 || margin < 1) {
+        err = "guard_bits and t_bits must be >= 0 and crt_margin >= 1";
+        return -1;
+    }
+    t = t_bits ? t_bits : p + guard_bits + ceil_log2(K);
+    if (t < 1) {
+        err = "internal width t must be >= 1";
+        return -1;
+    }
+    const double need = 2.0 * t + ceil_log2(K) + margin;   // Eq. crtcond with the safety margin
+    mods.clear();
+    log2P = 0;
+    for (uint32_t m : global_moduli()) {
+        if (log2P > need) break;
+        mods.push_back(m);
+        log2P += std::log2((double)m);
+    }
+    if (!(log2P > need) || (int)mods.size() > kMaxModuli) {
+        err = "precision too large for the supported moduli set (at most 512 moduli)";
+        return -2;
+    }
+    return 0;
+}
+
+int build_plan(int p, int t, int64_t K, const std::vector<uint32_t> &mods_in, PlanHost &h,
+               std::string &err) {
+    if (mods_in.empty() || (int)mods_in.size() > kMaxModuli) {
+        err = "need 1..512 moduli";
+        return -1;
+    }
+    std::vector<uint32_t> mods;
+    for (uint32_t m : mods_in)
+        if (m <= kOneLimbMax) mods.push_back(m);
+    for (uint32_t m : mods_in)
+        if (m > kOneLimbMax) mods.push_back(m);
+    for (size_t a = 0; a < mods.size(); ++a) {
+        if (mods[a] < 2 || mods[a] > kTwoLimbMax) {
+            err = "moduli must lie in [2, 16191]";
+            return -1;
+        }
+        for (size_t b = 0; b < a; ++b)
+            if (std::gcd(mods[a], mods[b]) != 1) {
+                err = "moduli must be pairwise coprime";
+                return -1;
+            }
+    }
+    h = PlanHost{};
+    h.p = p;
+    h.t = t;
+    h.K = K;
+    h.L = (int)mods.size();
+    h.moduli = mods;
+    h.nw32 = (t + 1 + 31) / 32;
+    if (h.nw32 > kMaxWords) {
+        err = "internal width t too large for the residue kernel";
+        return -2;
+    }
+
+    // P and the one-limb / two-limb split; plane numbering
+    Nat P{1};
+    h.log2P = 0;
+    uint32_t g = 0;
+    for (uint32_t m : mods) {
+        nat_mul_small(P, m);
+        h.log2P += std::log2((double)m);
+        ModInfo mi{};
+        mi.m = m;
+        mi.g0 = g;
+        mi.nprod = m <= kOneLimbMax ? 1u : 3u;
+        mi.inv_m = 1.0 / (double)m;
+        g += mi.nprod;
+        h.info.push_back(mi);
+        if (mi.nprod == 1) ++h.L1;
+        else ++h.L2;
+    }
+    h.G = (int)g;
+    h.pbits = nat_bitlen(P);
+    h.nd32 = (h.pbits + 31) / 32 + 2;   // two digits of headroom (subsection on the batched CRT)
+
+    // direct-CRT weights: M_l = P / m_l, minv = M_l^-1 mod m_l
+    h.crt_nc = (h.nd32 + 31) / 32;
+    int per = (h.nd32 + h.crt_nc - 1) / h.crt_nc;
+    h.crt_dc = ((per + 7) / 8) * 8;
+    h.crt_ndpad = h.crt_dc * h.crt_nc;
+    h.crt_digits.assign((size_t)h.L * h.crt_ndpad, 0.0);
+    for (int l = 0; l < h.L; ++l) {
+        const uint32_t m = mods[l];
+        Nat Ml = nat_divexact_small(P, m);
+        uint32_t minv = inv_mod(nat_mod_small(Ml, m), m);
+        if (!minv && m != 1) {
+            err = "internal error: M_l not invertible";
+            return -1;
+        }
+        h.info[l].minv = minv;
+        // balanced base-2^32 digits, |d| <= 2^31
+        int64_t carry = 0;
+        for (int k = 0; k < h.crt_ndpad; ++k) {
+            int64_t x = (k < (int)Ml.size() ? (int64_t)Ml[k] : 0) + carry;
+            if (x >= (int64_t)1 << 31) {
+                x -= (int64_t)1 << 32;
+                carry = 1;
+            } else {
+                carry = 0;
+            }
+            h.crt_digits[(size_t)l * h.crt_ndpad + k] = (double)x;
+        }
+        if (carry) {
+            err = "internal error: CRT digit table too short";
+            return -1;
+        }
+    }
+    h.p_digits.assign(h.nd32, 0);
+    h.ph_digits.assign(h.nd32, 0);
+    for (int k = 0; k < h.nd32 && k < (int)P.size(); ++k) h.p_digits[k] = P[k];
+    for (int k = 0; k < h.nd32; ++k) {
+        uint32_t lo = h.p_digits[k] >> 1;
+        uint32_t hi = (k + 1 < h.nd32) ? (h.p_digits[k + 1] & 1u) << 31 : 0;
+        h.ph_digits[k] = lo | hi;
+    }
+
+    // residue weights: centred 2^(32 w) mod m, grouped by kModGroup moduli
+    h.lgroups = (h.L + kModGroup - 1) / kModGroup;
+    h.resid_tab.assign((size_t)h.lgroups * h.nw32 * kModGroup, 0.0);
+    for (int l = 0; l < h.L; ++l) {
+        const uint64_t m = mods[l];
+        uint64_t x = 1 % m;
+        for (int w = 0; w < h.nw32; ++w) {
+            int64_t c = (int64_t)x;
+            if (c > (int64_t)((m - 1) / 2)) c -= (int64_t)m;
+            h.resid_tab[((size_t)(l / kModGroup) * h.nw32 + w) * kModGroup + (l % kModGroup)] =
+                (double)c;
+            x = ((x << 32) % m);
+        }
+    }
+    return 0;
+}
+
+}  // namespace oz2h

@@ -1,0 +1,62 @@
+// oz2h_plan.hpp -- host-side plan of the Ozaki-II pipeline: the moduli set and
+// every constant table the kernels read.  Pure host C++ (no HIP calls).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace oz2h {
+
+constexpr int kModGroup = 8;          // moduli per group in the residue kernel
+constexpr int kMaxModuli = 512;       // fp64-exact CRT digit sums need L * 2^44 < 2^53
+constexpr int kMaxWords = 256;        // fp64-exact residue sums need nw32 * 2^45 < 2^53
+constexpr int64_t kMaxK = 133000;     // K * 127^2 < 2^31, the cap the paper's implementation uses
+constexpr uint32_t kOneLimbMax = 255;    // centred residue fits int8
+constexpr uint32_t kTwoLimbMax = 16191;  // balanced base-128 halves fit int8 (and their sum)
+
+// Per-modulus record read by the kernels (24 bytes, 8-byte aligned).
+struct ModInfo {
+    uint32_t m;      // the modulus
+    uint32_t g0;     // its first INT8 plane
+    uint32_t nprod;  // 1 for a one-limb modulus, 3 for a two-limb modulus (Karatsuba)
+    uint32_t minv;   // (P / m)^-1 mod m, the direct-CRT weight
+    double inv_m;    // fl(1/m)
+};
+
+struct PlanHost {
+    int p = 0, t = 0;
+    int64_t K = 0;
+    int L = 0, L1 = 0, L2 = 0, G = 0;
+    int nw32 = 0;          // 32-bit words of a (t+1)-bit integer significand
+    int nd32 = 0;          // 32-bit digits of the CRT accumulator
+    int lgroups = 0;       // ceil(L / kModGroup)
+    int crt_dc = 0;        // CRT digit chunk (digits accumulated per pass)
+    int crt_nc = 0;        // CRT passes
+    int crt_ndpad = 0;     // crt_dc * crt_nc
+    double log2P = 0;
+    int pbits = 0;         // bit length of P
+    std::vector<uint32_t> moduli;    // L, one-limb first
+    std::vector<ModInfo> info;       // L
+    std::vector<double> resid_tab;   // [lgroups][nw32][kModGroup]: centred 2^(32w) mod m
+    std::vector<double> crt_digits;  // [L][crt_ndpad]: balanced base-2^32 digits of P/m
+    std::vector<uint32_t> p_digits;  // [nd32] digits of P
+    std::vector<uint32_t> ph_digits; // [nd32] digits of floor(P/2)
+};
+
+int ceil_log2(int64_t K);
+
+// The paper's hybrid INT8 moduli list: the 54 prime powers <= 255 in
+// decreasing order, then the primes 255 < m <= 16191 in decreasing order.
+const std::vector<uint32_t> &global_moduli();
+
+// Greedy prefix of the global list until log2 P > 2t + ceil(log2 K) + margin.
+// Returns 0, or a negative oz2h_status with `err` set.
+int select_moduli(int p, int64_t K, int guard_bits, int t_bits, int margin,
+                  std::vector<uint32_t> &mods, int &t, double &log2P, std::string &err);
+
+// Fill every table for the given moduli (one-limb moduli must come first).
+int build_plan(int p, int t, int64_t K, const std::vector<uint32_t> &mods, PlanHost &out,
+               std::string &err);
+
+}  // namespace oz2h

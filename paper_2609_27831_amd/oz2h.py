@@ -1,0 +1,349 @@
+"""Python binding of liboz2h.so (include/oz2h.h): argument marshalling only.
+
+Every step of the product runs in the library's HIP kernels; PyTorch only
+provides device memory and the current stream.  If the built library is
+missing, every call raises -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "liboz2h.so")
+
+OK, EINVAL, ERANGE, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+OP_N, OP_T = 0, 1
+
+
+class Oz2hError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"oz2h error {code}: {msg}")
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("guard_bits", ctypes.c_int32), ("t_bits", ctypes.c_int32),
+                ("crt_margin", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class CMat(ctypes.Structure):
+    _fields_ = [("limbs", ctypes.c_void_p), ("exp", ctypes.c_void_p),
+                ("sign", ctypes.c_void_p), ("ld", ctypes.c_int64)]
+
+
+class Mat(ctypes.Structure):
+    _fields_ = [("limbs", ctypes.c_void_p), ("exp", ctypes.c_void_p),
+                ("sign", ctypes.c_void_p), ("ld", ctypes.c_int64)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("t", ctypes.c_int32), ("K", ctypes.c_int64),
+                ("L", ctypes.c_int32), ("L1", ctypes.c_int32), ("L2", ctypes.c_int32),
+                ("G", ctypes.c_int32), ("nw32", ctypes.c_int32), ("nd32", ctypes.c_int32),
+                ("log2P", ctypes.c_double)]
+
+
+# (name, restype, argtypes) of every exported symbol
+_P, _I32, _I64, _SZ, _D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_double
+SIGNATURES = {
+    "oz2h_opts_default": (None, [ctypes.POINTER(Opts)]),
+    "oz2h_last_error": (ctypes.c_char_p, []),
+    "oz2h_plan_moduli": (ctypes.c_int, [_I32, _I64, ctypes.POINTER(Opts), _P, _P, _P, _P, _P, _P]),
+    "oz2h_plan_create": (ctypes.c_int, [_I32, _I64, ctypes.POINTER(Opts), ctypes.POINTER(_P)]),
+    "oz2h_plan_create_custom": (ctypes.c_int, [_I32, _I32, _I64, _I32, _P, ctypes.POINTER(_P)]),
+    "oz2h_plan_destroy": (None, [_P]),
+    "oz2h_plan_get_info": (ctypes.c_int, [_P, ctypes.POINTER(PlanInfo)]),
+    "oz2h_plan_get_moduli": (ctypes.c_int, [_P, _P]),
+    "oz2h_gemm_workspace_size": (_SZ, [_P, _I64, _I64]),
+    "oz2h_gemm": (ctypes.c_int, [_P, _I64, _I64, _I64, ctypes.c_int, CMat, ctypes.c_int, CMat,
+                                 Mat, _P, _SZ, _P]),
+    "oz2h_gemm_integers": (ctypes.c_int, [_P, _I64, _I64, _I64, ctypes.c_int, CMat, ctypes.c_int,
+                                          CMat, _P, _P, _I32, _P, _P, _P, _SZ, _P]),
+    "oz2h_exponents": (ctypes.c_int, [_I64, _I64, _P, _P, _I64, _I64, _P, _P]),
+    "oz2h_residues": (ctypes.c_int, [_P, _I64, _I64, _P, _P, _P, _I64, _I64, _P, _I64, _I64, _P, _P]),
+    "oz2h_residue_gemm": (ctypes.c_int, [_P, _I64, _I64, _I64, _P, _P, _P, _P]),
+    "oz2h_i8gemm": (ctypes.c_int, [_I64, _I64, _I64, _P, _P, _P, _P]),
+    "oz2h_crt": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _I64, _P, _P, _I32, _P]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load the in-tree library (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is missing: run "
+                               "`python -m paper_2609_27831_amd.build` (or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != OK:
+        raise Oz2hError(code, lib().oz2h_last_error().decode())
+
+
+def default_opts(guard_bits: Optional[int] = None, t_bits: Optional[int] = None,
+                 crt_margin: Optional[int] = None) -> Opts:
+    o = Opts()
+    lib().oz2h_opts_default(ctypes.byref(o))
+    if guard_bits is not None:
+        o.guard_bits = guard_bits
+    if t_bits is not None:
+        o.t_bits = t_bits
+    if crt_margin is not None:
+        o.crt_margin = crt_margin
+    return o
+
+
+def plan_moduli(p: int, K: int, opts: Optional[Opts] = None):
+    """Host-only moduli selection: dict(L, L1, G, t, log2P, moduli)."""
+    L, L1, G, t = (ctypes.c_int32() for _ in range(4))
+    lp = ctypes.c_double()
+    o = opts or default_opts()
+    _check(lib().oz2h_plan_moduli(p, K, ctypes.byref(o), ctypes.addressof(L), ctypes.addressof(L1),
+                                  ctypes.addressof(G), ctypes.addressof(t), ctypes.addressof(lp), None))
+    mods = np.zeros(L.value, np.uint16)
+    _check(lib().oz2h_plan_moduli(p, K, ctypes.byref(o), None, None, None, None, None,
+                                  mods.ctypes.data))
+    return {"L": L.value, "L1": L1.value, "G": G.value, "t": t.value, "log2P": lp.value,
+            "moduli": mods}
+
+
+class Plan:
+    """Moduli set + device constant tables for one (p, K) on the current device."""
+
+    def __init__(self, handle: int):
+        self.handle = handle
+        info = PlanInfo()
+        _check(lib().oz2h_plan_get_info(handle, ctypes.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in PlanInfo._fields_}
+        mods = np.zeros(self.info["L"], np.uint16)
+        _check(lib().oz2h_plan_get_moduli(handle, mods.ctypes.data))
+        self.moduli = mods
+
+    @classmethod
+    def create(cls, p: int, K: int, opts: Optional[Opts] = None) -> "Plan":
+        h = ctypes.c_void_p()
+        o = opts or default_opts()
+        _check(lib().oz2h_plan_create(p, K, ctypes.byref(o), ctypes.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def custom(cls, p: int, t: int, K: int, moduli: Sequence[int]) -> "Plan":
+        m = np.ascontiguousarray(moduli, dtype=np.uint16)
+        h = ctypes.c_void_p()
+        _check(lib().oz2h_plan_create_custom(p, t, K, m.size, m.ctypes.data, ctypes.byref(h)))
+        return cls(h.value)
+
+    def __getattr__(self, k):
+        info = self.__dict__.get("info")
+        if info is not None and k in info:
+            return info[k]
+        raise AttributeError(k)
+
+    def workspace_size(self, M: int, N: int) -> int:
+        return int(lib().oz2h_gemm_workspace_size(self.handle, M, N))
+
+    def destroy(self):
+        if self.handle:
+            lib().oz2h_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ device data
+
+@dataclass
+class DeviceMP:
+    """A p-bit matrix in device memory (torch tensors), rows x cols, row-major."""
+    sign: "object"   # torch.int8 [rows, ld]
+    exp: "object"    # torch.int32 [rows, ld]
+    limbs: "object"  # torch.int64 [rows, ld, nl] (bit pattern of uint64)
+    p: int
+
+    @property
+    def shape(self):
+        return tuple(self.sign.shape)
+
+    @property
+    def ld(self) -> int:
+        return int(self.sign.stride(0))
+
+    def cmat(self) -> CMat:
+        return CMat(self.limbs.data_ptr(), self.exp.data_ptr(), self.sign.data_ptr(), self.ld)
+
+    def mat(self) -> Mat:
+        return Mat(self.limbs.data_ptr(), self.exp.data_ptr(), self.sign.data_ptr(), self.ld)
+
+    def to_host(self):
+        """-> synth.MPMatrix-like numpy arrays (sign, exp, limbs as uint64)."""
+        s = self.sign.cpu().numpy()
+        e = self.exp.cpu().numpy()
+        l = self.limbs.cpu().numpy().view(np.uint64)
+        return s, e, l
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def to_device(X, device="cuda") -> DeviceMP:
+    """Copy a host operand (sign/exp/limbs numpy arrays, e.g. synth.MPMatrix) to the GPU."""
+    torch = _torch()
+    return DeviceMP(torch.from_numpy(np.ascontiguousarray(X.sign)).to(device),
+                    torch.from_numpy(np.ascontiguousarray(X.exp)).to(device),
+                    torch.from_numpy(np.ascontiguousarray(X.limbs).view(np.int64)).to(device),
+                    X.p)
+
+
+def empty_mp(rows: int, cols: int, p: int, device="cuda") -> DeviceMP:
+    torch = _torch()
+    nl = (p + 63) // 64
+    return DeviceMP(torch.empty((rows, cols), dtype=torch.int8, device=device),
+                    torch.empty((rows, cols), dtype=torch.int32, device=device),
+                    torch.empty((rows, cols, nl), dtype=torch.int64, device=device), p)
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def workspace(plan: Plan, M: int, N: int, device="cuda"):
+    torch = _torch()
+    n = plan.workspace_size(M, N)
+    return torch.empty(max(n, 256), dtype=torch.uint8, device=device)
+
+
+def _dims(A: DeviceMP, B: DeviceMP, opA: int, opB: int):
+    M, K = A.shape if opA == OP_N else A.shape[::-1]
+    K2, N = B.shape if opB == OP_N else B.shape[::-1]
+    if K != K2:
+        raise ValueError(f"inner dimensions differ: {K} vs {K2}")
+    return M, N, K
+
+
+def gemm(plan: Plan, A: DeviceMP, B: DeviceMP, opA: int = OP_N, opB: int = OP_N,
+         out: Optional[DeviceMP] = None, ws=None, stream=None) -> DeviceMP:
+    """C = op(A) op(B) at the plan's precision (oz2h_gemm)."""
+    M, N, K = _dims(A, B, opA, opB)
+    if out is None:
+        out = empty_mp(M, N, plan.p, device=A.sign.device)
+    if ws is None:
+        ws = workspace(plan, M, N, device=A.sign.device)
+    _check(lib().oz2h_gemm(plan.handle, M, N, K, opA, A.cmat(), opB, B.cmat(), out.mat(),
+                           ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
+    return out
+
+
+def gemm_integers(plan: Plan, A: DeviceMP, B: DeviceMP, opA: int = OP_N, opB: int = OP_N,
+                  nlc: Optional[int] = None, ws=None, stream=None):
+    """Exact c^ (sign, magnitude limbs) and shared exponents e, f (oz2h_gemm_integers)."""
+    torch = _torch()
+    M, N, K = _dims(A, B, opA, opB)
+    dev = A.sign.device
+    if nlc is None:
+        nlc = (int(np.ceil(plan.log2P)) + 1 + 63) // 64
+    cs = torch.empty((M, N), dtype=torch.int8, device=dev)
+    cm = torch.empty((M, N, nlc), dtype=torch.int64, device=dev)
+    e = torch.empty(M, dtype=torch.int32, device=dev)
+    f = torch.empty(N, dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = workspace(plan, M, N, device=dev)
+    _check(lib().oz2h_gemm_integers(plan.handle, M, N, K, opA, A.cmat(), opB, B.cmat(),
+                                    cs.data_ptr(), cm.data_ptr(), nlc, e.data_ptr(), f.data_ptr(),
+                                    ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
+    return cs, cm, e, f
+
+
+def exponents(sign, exp, rows: int, count: int, rs: int, cs: int, out=None, stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty(rows, dtype=torch.int32, device=sign.device)
+    _check(lib().oz2h_exponents(rows, count, sign.data_ptr(), exp.data_ptr(), rs, cs,
+                                out.data_ptr(), _stream_ptr(stream)))
+    return out
+
+
+def residues(plan: Plan, X: DeviceMP, erow, side: str, rpad: int, kpad: int, stream=None):
+    """Stage-2 planes of one side: side 'A' (rows of X own the exponent) or 'B' (columns)."""
+    torch = _torch()
+    r, c = X.shape
+    if side == "A":
+        rows, count, rs, cs = r, c, X.ld, 1
+    else:
+        rows, count, rs, cs = c, r, 1, X.ld
+    planes = torch.empty((plan.G, rpad, kpad), dtype=torch.int8, device=X.sign.device)
+    _check(lib().oz2h_residues(plan.handle, rows, count, X.limbs.data_ptr(), X.exp.data_ptr(),
+                               X.sign.data_ptr(), rs, cs, erow.data_ptr(), rpad, kpad,
+                               planes.data_ptr(), _stream_ptr(stream)))
+    return planes
+
+
+def residue_gemm(plan: Plan, a_planes, b_planes, stream=None):
+    torch = _torch()
+    G, mpad, kpad = a_planes.shape
+    G2, npad, kpad2 = b_planes.shape
+    assert G == G2 == plan.G and kpad == kpad2
+    u = torch.empty((plan.L, mpad, npad), dtype=torch.int16, device=a_planes.device)
+    _check(lib().oz2h_residue_gemm(plan.handle, mpad, npad, kpad, a_planes.data_ptr(),
+                                   b_planes.data_ptr(), u.data_ptr(), _stream_ptr(stream)))
+    return u
+
+
+def i8gemm(A, B, stream=None):
+    torch = _torch()
+    M, K = A.shape
+    N, K2 = B.shape
+    assert K == K2
+    C = torch.empty((M, N), dtype=torch.int32, device=A.device)
+    _check(lib().oz2h_i8gemm(M, N, K, A.data_ptr(), B.data_ptr(), C.data_ptr(),
+                             _stream_ptr(stream)))
+    return C
+
+
+def crt(plan: Plan, u, M: int, N: int, nlc: Optional[int] = None, stream=None):
+    """u: uint16 planes as a torch int16 tensor [L, rows, ld]."""
+    torch = _torch()
+    L, rows, ldu = u.shape
+    if nlc is None:
+        nlc = (int(np.ceil(plan.log2P)) + 1 + 63) // 64
+    cs = torch.empty((M, N), dtype=torch.int8, device=u.device)
+    cm = torch.empty((M, N, nlc), dtype=torch.int64, device=u.device)
+    _check(lib().oz2h_crt(plan.handle, M, N, u.data_ptr(), ldu, rows * ldu, cs.data_ptr(),
+                          cm.data_ptr(), nlc, _stream_ptr(stream)))
+    return cs, cm
+
+
+def limbs_to_ints(mag: np.ndarray, sign: np.ndarray):
+    """Signed Python ints from (sign, uint64 magnitude limbs) arrays of any leading shape."""
+    mag = mag.view(np.uint64)
+    flat = mag.reshape(-1, mag.shape[-1])
+    sg = sign.reshape(-1)
+    out = []
+    for row, s in zip(flat, sg):
+        v = 0
+        for x in row[::-1]:
+            v = (v << 64) | int(x)
+        out.append(int(s) * v)
+    return out

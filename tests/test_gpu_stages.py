@@ -1,0 +1,193 @@
+"""GPU parity of each stage kernel through the C ABI (marked gpu).
+
+Expected values come from plain numpy / Python-int computations on the same
+inputs, or from the oracle's integerization (oracle/oz2_oracle.c).
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import dev_mp, need_gpu, py_centered_residue
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def oz(request):
+    need_gpu()
+    from paper_2609_27831_amd import oz2h
+    return oz2h
+
+
+def test_i8gemm_exact_random(oz):
+    import torch
+    rng = np.random.default_rng(1)
+    for (M, N, K) in [(128, 128, 64), (256, 384, 1024), (384, 128, 4160)]:
+        A = rng.integers(-127, 128, (M, K), dtype=np.int8)
+        B = rng.integers(-127, 128, (N, K), dtype=np.int8)
+        print(f"i8gemm M={M} N={N} K={K}", flush=True)
+        C = oz.i8gemm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()).cpu().numpy()
+        ref = A.astype(np.int64) @ B.astype(np.int64).T
+        assert np.array_equal(C.astype(np.int64), ref)
+
+
+def test_i8gemm_int32_limit(oz):
+    """K*127^2 < 2^31 at the largest K the kernel takes (Step 3 of the tutorial section)."""
+    import torch
+    K = 132992           # largest multiple of 64 <= 133000
+    A = np.full((128, K), 127, np.int8)
+    B = np.full((128, K), 127, np.int8)
+    B[1::2] = -127
+    print("i8gemm int32 limit", flush=True)
+    C = oz.i8gemm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()).cpu().numpy()
+    assert int(C[0, 0]) == K * 127 * 127
+    assert int(C[0, 1]) == -K * 127 * 127
+
+
+def test_exponent_scan_both_layouts(oz, c_oracle):
+    import torch
+    X = synth.mp_random(3, 300, 517, 128, -50, 50)
+    X.sign[5, :] = 0
+    X.sign[:, 7] = 0
+    X.sign[rng_idx(300, 517, 0.3)] = 0
+    t = 128 + 16 + 10
+    eA, _, _ = c_oracle.integerize(X, t, "A")
+    eB, _, _ = c_oracle.integerize(X, t, "B")
+    sg = torch.from_numpy(X.sign).cuda()
+    ex = torch.from_numpy(X.exp).cuda()
+    print("exponent scan", flush=True)
+    gA = oz.exponents(sg, ex, 300, 517, 517, 1).cpu().numpy()
+    gB = oz.exponents(sg, ex, 517, 300, 1, 517).cpu().numpy()
+    assert np.array_equal(gA, eA)
+    assert np.array_equal(gB, eB)
+    assert gA[5] == 0 and gB[7] == 0
+
+
+def rng_idx(r, c, frac, seed=0):
+    rng = np.random.default_rng(seed)
+    return rng.random((r, c)) < frac
+
+
+@pytest.mark.parametrize("p,lo,hi,side", [(128, -4, 4, "A"), (256, -32, 32, "B"),
+                                          (2048, -16, 16, "A"), (53, -300, 300, "B"),
+                                          (113, -64, 64, "A")])
+def test_residue_planes(oz, c_oracle, p, lo, hi, side):
+    """Stage 2 vs Python-int centred residues of the oracle's integers a^."""
+    import torch
+    R, C = (70, 150) if side == "A" else (150, 70)
+    X = synth.mp_random(11 + p, R, C, p, lo, hi)
+    X.sign[rng_idx(R, C, 0.05, p)] = 0
+    K = C if side == "A" else R
+    plan = oz.Plan.create(p, K)
+    t = plan.t
+    e, sg, mag = c_oracle.integerize(X, t, side)
+    rows = e.size
+    Xd = dev_mp(X)
+    erow = torch.from_numpy(e).cuda()
+    rpad, kpad = 128, 192
+    print(f"residues p={p} side={side}", flush=True)
+    planes = oz.residues(plan, Xd, erow, side, rpad, kpad).cpu().numpy()
+    assert planes.shape == (plan.G, rpad, kpad)
+    # padding is zero
+    assert not planes[:, rows:, :].any() and not planes[:, :, K:].any()
+    ahat = np.array(oz.limbs_to_ints(mag, sg), dtype=object).reshape(rows, K)
+    for li, m in enumerate(plan.moduli.tolist()):
+        res = np.vectorize(lambda v: py_centered_residue(v, m), otypes=[np.int64])(ahat)
+        g0 = li if li < plan.L1 else plan.L1 + 3 * (li - plan.L1)
+        if m <= 255:
+            got = planes[g0, :rows, :K].astype(np.int64)
+            assert np.array_equal(got, res), f"modulus {m}"
+        else:
+            r0 = planes[g0, :rows, :K].astype(np.int64)
+            r1 = planes[g0 + 1, :rows, :K].astype(np.int64)
+            rs = planes[g0 + 2, :rows, :K].astype(np.int64)
+            assert np.array_equal(r0 + 128 * r1, res), f"modulus {m}"
+            assert np.array_equal(rs, r0 + r1)
+            assert r0.min() >= -64 and r0.max() <= 63 and np.abs(r1).max() <= 63
+
+
+def test_residue_gemm_mod_m(oz):
+    """Stage 3 vs int64 numpy products of the same planes, reduced mod m (Karatsuba included)."""
+    import torch
+    plan = oz.Plan.create(256, 320)        # 54 one-limb + 16 two-limb moduli
+    G, L1 = plan.G, plan.L1
+    rng = np.random.default_rng(5)
+    mpad, npad, kpad = 256, 128, 320
+    A = np.zeros((G, mpad, kpad), np.int8)
+    B = np.zeros((G, npad, kpad), np.int8)
+    for li, m in enumerate(plan.moduli.tolist()):
+        g0 = li if li < L1 else L1 + 3 * (li - L1)
+        if m <= 255:
+            h = (m - 1) // 2
+            A[g0] = rng.integers(-(m // 2), h + 1, (mpad, kpad))
+            B[g0] = rng.integers(-(m // 2), h + 1, (npad, kpad))
+        else:
+            for X, rows in ((A, mpad), (B, npad)):
+                r = rng.integers(-(m - 1) // 2, (m - 1) // 2 + 1, (rows, kpad))
+                r0 = ((r + 64) & 127) - 64
+                r1 = (r - r0) // 128
+                X[g0], X[g0 + 1], X[g0 + 2] = r0, r1, r0 + r1
+    print("residue gemm", flush=True)
+    u = oz.residue_gemm(plan, torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda())
+    u = u.cpu().numpy().view(np.uint16).astype(np.int64)
+    for li, m in enumerate(plan.moduli.tolist()):
+        g0 = li if li < L1 else L1 + 3 * (li - L1)
+        if m <= 255:
+            prod = A[g0].astype(np.int64) @ B[g0].astype(np.int64).T
+        else:
+            a = A[g0].astype(np.int64) + 128 * A[g0 + 1].astype(np.int64)
+            b = B[g0].astype(np.int64) + 128 * B[g0 + 1].astype(np.int64)
+            prod = a @ b.T
+        assert np.array_equal(u[li], np.mod(prod, m)), f"modulus {m}"
+
+
+def test_crt_worked_example(oz):
+    """The tutorial's worked example: moduli 5, 7, 9 and residues (0, 3, 1) give 10."""
+    import torch
+    from tests.gpu_util import read_worked_example
+    ex = read_worked_example()
+    plan = oz.Plan.custom(8, 4, 3, [5, 7, 9])
+    assert list(plan.moduli) == [5, 7, 9]
+    u = np.zeros((3, 1, 1), np.uint16)
+    for li, m in enumerate([5, 7, 9]):
+        u[li, 0, 0] = ex["mod"][m]
+    print("crt worked example", flush=True)
+    cs, cm = oz.crt(plan, torch.from_numpy(u.view(np.int16)).cuda(), 1, 1)
+    val = oz.limbs_to_ints(cm.cpu().numpy(), cs.cpu().numpy())[0]
+    assert val == ex["chat"] == 10
+    # and the whole path on the example's vectors: residues -> GEMM -> CRT
+    for li, m in enumerate([5, 7, 9]):
+        ra = [py_centered_residue(v, m) for v in ex["a"]]
+        rb = [py_centered_residue(v, m) for v in ex["b"]]
+        assert ra == ex["ra"][m] and rb == ex["rb"][m]
+        assert sum(x * y for x, y in zip(ra, rb)) == ex["dot"][m]
+
+
+@pytest.mark.parametrize("t", list(range(40, 1121, 8)))
+def test_crt_random_exact_integers(oz, t):
+    """Direct CRT sweep over t = 40..1120 in steps of 8 (Correctness section)."""
+    import torch
+    plan = oz.Plan.create(max(2, t - 28), 4096, oz.default_opts(t_bits=t))
+    P = 1
+    for m in plan.moduli.tolist():
+        P *= m
+    rng = np.random.default_rng(t)
+    M, N = 3, 43
+    bound = (1 << (2 * t)) * 4096
+    vals = []
+    for k in range(M * N):
+        bits = int(rng.integers(1, 2 * t + 13))
+        v = int.from_bytes(rng.bytes((bits + 7) // 8), "little") % (1 << bits)
+        v = min(v, bound)
+        if k % 7 == 3:
+            v = bound                       # the extreme |c^| = K 2^(2t)
+        if k % 11 == 5:
+            v = 0
+        vals.append(-v if rng.integers(0, 2) else v)
+    u = np.zeros((plan.L, M, N), np.uint16)
+    for li, m in enumerate(plan.moduli.tolist()):
+        u[li] = np.array([v % m for v in vals], np.uint16).reshape(M, N)
+    print(f"crt sweep t={t}", flush=True)
+    cs, cm = oz.crt(plan, torch.from_numpy(u.view(np.int16)).cuda(), M, N)
+    got = oz.limbs_to_ints(cm.cpu().numpy(), cs.cpu().numpy())
+    assert got == vals
