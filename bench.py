@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Benchmark of the Ozaki-II p-bit matrix product on one MI355X.
+
+One step = one full pass of the hot path (shared exponents, residues, INT8
+MFMA residue GEMMs with the fused reduction, direct CRT + lift + rounding)
+over one synthetic input already resident in HBM.  The default workload is
+the plain square product M = N = K = 2048 at p = 256 bits with exponents
+uniform in [-32, 32].  Prints ONE JSON line (rank 0, N = 1 GPU).
+
+  python bench.py [--steps K] [--warmup W] [--config cfg2] [--cpu-seconds S]
+
+Per-stage times come from HIP events that the library records on the launch
+stream between stages (oz2h_gemm_timed); the end-to-end time is wall clock
+over exactly K steps bracketed by torch.cuda.synchronize().
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "effective p-bit GEMM GFlop/s (2MNK/s) at ≤1 ulp; INT8 MFMA % of peak"
+
+# name: (workload, M, N, K, p, elo, ehi, seed offset)
+CONFIGS = {
+    "cfg1": ("plain Ozaki-II, M=N=K=256, p=128, exponents U[-4,4]", 256, 256, 256, 128, -4, 4, 1),
+    "cfg2": ("plain Ozaki-II, M=N=K=2048, p=256, exponents U[-32,32]", 2048, 2048, 2048, 256, -32, 32, 2),
+    "cfg3a": ("plain Ozaki-II, M=N=K=4096, p=2048, exponents U[-16,16]", 4096, 4096, 4096, 2048, -16, 16, 31),
+    "cfg3b": ("plain Ozaki-II, M=N=K=8192, p=113, exponents U[-16,16]", 8192, 8192, 8192, 113, -16, 16, 32),
+}
+
+# MI355X published peaks
+PEAK_INT8_TOPS = 5000.0      # dense INT8 MFMA, TOP/s
+PEAK_HBM_GBS = 8000.0        # HBM3E, GB/s
+PEAK_FP64_TFLOPS = 78.6      # FP64 vector, TFLOP/s (FMA = 2 flops)
+
+CSRC = os.path.join(ROOT, "paper_2609_27831_amd", "csrc")
+
+
+class Hip:
+    """The few HIP runtime calls the bench needs for events."""
+
+    def __init__(self):
+        self.h = ctypes.CDLL("libamdhip64.so")
+        self.h.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.h.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.h.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
+                                               ctypes.c_void_p]
+        self.h.hipEventSynchronize.argtypes = [ctypes.c_void_p]
+
+    def events(self, n):
+        arr = (ctypes.c_void_p * n)()
+        for i in range(n):
+            ev = ctypes.c_void_p()
+            assert self.h.hipEventCreate(ctypes.byref(ev)) == 0
+            arr[i] = ev
+        return arr
+
+    def elapsed_ms(self, a, b) -> float:
+        assert self.h.hipEventSynchronize(b) == 0
+        ms = ctypes.c_float()
+        assert self.h.hipEventElapsedTime(ctypes.byref(ms), a, b) == 0
+        return ms.value
+
+    def destroy(self, arr):
+        for ev in arr:
+            self.h.hipEventDestroy(ev)
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, config: str):
+    """HBM bytes per launch from a committed rocprofv3 PMC summary, if it matches these sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{config}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_digest") != source_digest():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(A, B, seconds: float):
+    """The oracle on the host cores over a bounded sample: the first r rows of C."""
+    import numpy as np
+
+    from oracle import c_oracle
+    M, K = A.sign.shape
+    N = B.sign.shape[1]
+
+    def run(r):
+        si = np.repeat(np.arange(r, dtype=np.int64), N)
+        sj = np.tile(np.arange(N, dtype=np.int64), r)
+        t0 = time.perf_counter()
+        c_oracle.gemm(A, B, sel=(si, sj), want_chat=False)
+        return time.perf_counter() - t0
+
+    r = 1
+    t = run(r)
+    while t < seconds / 8 and r < M:
+        r = min(M, r * 4)
+        t = run(r)
+    if t < seconds / 2 and r < M:
+        r = min(M, max(r + 1, int(r * seconds / max(t, 1e-3))))
+        t = run(r)
+    return {"value": round(2.0 * r * N * K / t / 1e9, 4), "unit": "GFlop/s",
+            "cores": c_oracle.num_threads(), "kind": "oracle",
+            "sample": f"rows 0..{r - 1} of C ({r}x{N} entries, K={K}); exact bignum c^ plus "
+                      f"nearest-even rounding, including the integerization of those rows "
+                      f"and of every column of B; {t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="cfg2", choices=sorted(CONFIGS))
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one MI355X only; --gpus N > 1 is not supported "
+              "(the multi-GPU sharding is a design, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2609_27831_amd import oz2h
+
+    workload, M, N, K, p, elo, ehi, soff = CONFIGS[args.config]
+    torch.cuda.set_device(0)
+    A, B = synth.operands_for(synth.CONFIG_SEED_BASE + soff, M, N, K, p, elo, ehi)
+    Ad, Bd = oz2h.to_device(A), oz2h.to_device(B)
+    plan = oz2h.Plan.create(p, K)
+    ws = oz2h.workspace(plan, M, N)
+    out = oz2h.empty_mp(M, N, p)
+    hip = Hip()
+    stream = torch.cuda.current_stream()
+    evs = [hip.events(5) for _ in range(args.steps)]
+    wev = hip.events(5)
+
+    for _ in range(args.warmup):
+        oz2h.gemm_timed(plan, Ad, Bd, out, ws, wev, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        oz2h.gemm_timed(plan, Ad, Bd, out, ws, evs[s], stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+
+    names = ["exponents", "residues", "gemm", "crt"]
+    phase_ms = {n: float(np.mean([hip.elapsed_ms(e[k], e[k + 1]) for e in evs]))
+                for k, n in enumerate(names)}
+    for e in evs + [wev]:
+        hip.destroy(e)
+
+    flops = 2.0 * M * N * K
+    nl = (p + 63) // 64
+    L, G, nd32 = plan.L, plan.G, plan.nd32
+    gemm_ops = G * 2.0 * M * N * K
+    gemm_tops = gemm_ops / (phase_ms["gemm"] * 1e-3) / 1e12
+    res_bytes = (M * K + K * N) * (8 * nl + 5 + 4) + (M * K + K * N) * G
+    crt_bytes = L * M * N * 2 + M * N * (8 * nl + 5)
+    crt_flops = 2.0 * M * N * L * (nd32 + 1)
+    res_flops = 2.0 * (M * K + K * N) * L * plan.nw32
+    phases = {
+        n: {"ms": round(phase_ms[n], 4),
+            "effective_gflops": round(flops / (phase_ms[n] * 1e-3) / 1e9, 2)} for n in names}
+    phases["residues"]["hbm_gbs"] = round(res_bytes / (phase_ms["residues"] * 1e-3) / 1e9, 1)
+    phases["residues"]["fp64_tflops"] = round(res_flops / (phase_ms["residues"] * 1e-3) / 1e12, 2)
+    phases["gemm"]["int8_tops"] = round(gemm_tops, 1)
+    phases["crt"]["hbm_gbs"] = round(crt_bytes / (phase_ms["crt"] * 1e-3) / 1e9, 1)
+    phases["crt"]["fp64_tflops"] = round(crt_flops / (phase_ms["crt"] * 1e-3) / 1e12, 2)
+
+    dominant = max(("residues", "gemm", "crt"), key=lambda n: phase_ms[n])
+    if dominant == "gemm":
+        roof = {"kernel": "k_resgemm", "bound": "mfma", "achieved": round(gemm_tops, 2),
+                "peak": PEAK_INT8_TOPS, "unit": "TFLOP/s",
+                "frac": round(gemm_tops / PEAK_INT8_TOPS, 4)}
+    elif dominant == "crt":
+        a = crt_flops / (phase_ms["crt"] * 1e-3) / 1e12
+        roof = {"kernel": "k_crt", "bound": "alu", "achieved": round(a, 3),
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(a / PEAK_FP64_TFLOPS, 4)}
+    else:
+        a = res_flops / (phase_ms["residues"] * 1e-3) / 1e12
+        roof = {"kernel": "k_residues", "bound": "alu", "achieved": round(a, 3),
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(a / PEAK_FP64_TFLOPS, 4)}
+    roof["traffic"] = measured_traffic(roof["kernel"], args.config)
+
+    line = {
+        "metric": METRIC,
+        "value": round(flops / (ms_per_step * 1e-3) / 1e9, 3),
+        "unit": "GFlop/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i8",
+        "data": "synthetic",
+        "config": {"workload": workload, "M": M, "N": N, "K": K, "p": p, "t": plan.t,
+                   "moduli": L, "int8_gemms": G, "exponent_range": [elo, ehi]},
+        "int8_mfma_pct_of_peak": round(100.0 * gemm_tops / PEAK_INT8_TOPS, 2),
+        "phases": phases,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(A, B, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

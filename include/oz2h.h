@@ -158,6 +158,18 @@ int oz2h_gemm(const oz2h_plan *plan, int64_t M, int64_t N, int64_t K,
               void *workspace, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * oz2h_gemm that also records five caller-created HIP events on `stream`:
+ * events[0] before stage 1 (shared exponents), [1] before stage 2 (residues),
+ * [2] before stage 3 (residue GEMMs), [3] before stages 4-5 (CRT and
+ * rounding), [4] after the last kernel.  For per-stage timing; the events
+ * must have been created on the current device and stay owned by the caller.
+ * For M or N = 0 or K = 0 no event is recorded.
+ */
+int oz2h_gemm_timed(const oz2h_plan *plan, int64_t M, int64_t N, int64_t K,
+                    oz2h_op opA, oz2h_cmat A, oz2h_op opB, oz2h_cmat B, oz2h_mat C,
+                    void *workspace, size_t ws_bytes, hipStream_t stream, hipEvent_t *events);
+
+/*
  * Parity entry point: the same pipeline, stopping after the CRT and lift
  * (stage 4).  Writes the exact integers c^_ij as chat_sign[i*N + j] in
  * {-1, 0, +1} and magnitude limbs chat_mag[(i*N + j)*nlc + l] (nlc limbs,

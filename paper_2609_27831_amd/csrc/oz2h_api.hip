@@ -243,7 +243,7 @@ int check_cmat(const oz2h_cmat &X, const char *name, int64_t rows, int64_t cols)
 int run_pipeline(const oz2h_plan *pl, int64_t M, int64_t N, int64_t K, oz2h_op opA,
                  oz2h_cmat A, oz2h_op opB, oz2h_cmat B, bool round, oz2h_mat *C, int8_t *chat_sign,
                  uint64_t *chat_mag, int nlc, int32_t *e_out, int32_t *f_out, void *ws,
-                 size_t ws_bytes, hipStream_t s) {
+                 size_t ws_bytes, hipStream_t s, hipEvent_t *ev = nullptr) {
     int st = check_plan(pl);
     if (st) return st;
     const PlanHost &h = pl->h;
@@ -291,13 +291,17 @@ int run_pipeline(const oz2h_plan *pl, int64_t M, int64_t N, int64_t K, oz2h_op o
     const int64_t a_rs = opA == OZ2H_OP_N ? A.ld : 1, a_cs = opA == OZ2H_OP_N ? 1 : A.ld;
     const int64_t b_rs = opB == OZ2H_OP_N ? 1 : B.ld, b_cs = opB == OZ2H_OP_N ? B.ld : 1;
 
+    if (ev) OZ2H_HIP(hipEventRecord(ev[0], s));
     if ((st = launch_exponents(M, K, A.sign, A.exp, a_rs, a_cs, e, s))) return st;
     if ((st = launch_exponents(N, K, B.sign, B.exp, b_rs, b_cs, f, s))) return st;
+    if (ev) OZ2H_HIP(hipEventRecord(ev[1], s));
     if ((st = launch_residues(pl, M, K, A.limbs, A.exp, A.sign, a_rs, a_cs, e, w.mpad, w.kpad, ap, s)))
         return st;
     if ((st = launch_residues(pl, N, K, B.limbs, B.exp, B.sign, b_rs, b_cs, f, w.npad, w.kpad, bp, s)))
         return st;
+    if (ev) OZ2H_HIP(hipEventRecord(ev[2], s));
     if ((st = launch_resgemm(pl, w.mpad, w.npad, w.kpad, ap, bp, u, s))) return st;
+    if (ev) OZ2H_HIP(hipEventRecord(ev[3], s));
     if (round) {
         st = launch_crt(pl, M, N, u, w.mpad * w.npad, w.npad, e, f, true, C->sign, C->exp,
                         C->limbs, C->ld, nullptr, 0, s);
@@ -310,6 +314,7 @@ int run_pipeline(const oz2h_plan *pl, int64_t M, int64_t N, int64_t K, oz2h_op o
         }
     }
     if (st) return st;
+    if (ev) OZ2H_HIP(hipEventRecord(ev[4], s));
     return ok();
 }
 
@@ -450,6 +455,16 @@ int oz2h_gemm(const oz2h_plan *plan, int64_t M, int64_t N, int64_t K, oz2h_op op
               hipStream_t stream) {
     return run_pipeline(plan, M, N, K, opA, A, opB, B, true, &C, nullptr, nullptr, 0, nullptr,
                         nullptr, workspace, ws_bytes, stream);
+}
+
+int oz2h_gemm_timed(const oz2h_plan *plan, int64_t M, int64_t N, int64_t K, oz2h_op opA,
+                    oz2h_cmat A, oz2h_op opB, oz2h_cmat B, oz2h_mat C, void *workspace,
+                    size_t ws_bytes, hipStream_t stream, hipEvent_t *events) {
+    if (!events) return fail(OZ2H_EINVAL, "events is NULL");
+    for (int k = 0; k < 5; ++k)
+        if (!events[k]) return fail(OZ2H_EINVAL, "events[%d] is NULL", k);
+    return run_pipeline(plan, M, N, K, opA, A, opB, B, true, &C, nullptr, nullptr, 0, nullptr,
+                        nullptr, workspace, ws_bytes, stream, events);
 }
 
 int oz2h_gemm_integers(const oz2h_plan *plan, int64_t M, int64_t N, int64_t K, oz2h_op opA,

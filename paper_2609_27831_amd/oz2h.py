@@ -62,6 +62,8 @@ SIGNATURES = {
     "oz2h_gemm_workspace_size": (_SZ, [_P, _I64, _I64]),
     "oz2h_gemm": (ctypes.c_int, [_P, _I64, _I64, _I64, ctypes.c_int, CMat, ctypes.c_int, CMat,
                                  Mat, _P, _SZ, _P]),
+    "oz2h_gemm_timed": (ctypes.c_int, [_P, _I64, _I64, _I64, ctypes.c_int, CMat, ctypes.c_int, CMat,
+                                       Mat, _P, _SZ, _P, _P]),
     "oz2h_gemm_integers": (ctypes.c_int, [_P, _I64, _I64, _I64, ctypes.c_int, CMat, ctypes.c_int,
                                           CMat, _P, _P, _I32, _P, _P, _P, _SZ, _P]),
     "oz2h_exponents": (ctypes.c_int, [_I64, _I64, _P, _P, _I64, _I64, _P, _P]),
@@ -253,6 +255,16 @@ def gemm(plan: Plan, A: DeviceMP, B: DeviceMP, opA: int = OP_N, opB: int = OP_N,
         ws = workspace(plan, M, N, device=A.sign.device)
     _check(lib().oz2h_gemm(plan.handle, M, N, K, opA, A.cmat(), opB, B.cmat(), out.mat(),
                            ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
+    return out
+
+
+def gemm_timed(plan: Plan, A: DeviceMP, B: DeviceMP, out: DeviceMP, ws, events_array,
+               opA: int = OP_N, opB: int = OP_N, stream=None) -> DeviceMP:
+    """oz2h_gemm recording five stage events (a ctypes array of hipEvent_t)."""
+    M, N, K = _dims(A, B, opA, opB)
+    _check(lib().oz2h_gemm_timed(plan.handle, M, N, K, opA, A.cmat(), opB, B.cmat(), out.mat(),
+                                 ws.data_ptr(), ws.numel(), _stream_ptr(stream),
+                                 ctypes.cast(events_array, ctypes.c_void_p)))
     return out
 
 
