@@ -61,12 +61,21 @@ typedef enum {
 
 typedef enum { OZ2H_OP_N = 0, OZ2H_OP_T = 1 } oz2h_op;
 
+/* Block tile of the INT8 residue GEMMs (output rows x columns per block). */
+typedef enum {
+    OZ2H_TILE_AUTO = 0,     /* chosen from M and N (padding, occupancy)                 */
+    OZ2H_TILE_128x128 = 1,  /* four waves of 64 x 64                                    */
+    OZ2H_TILE_256x128 = 2,  /* four waves of 128 x 64                                   */
+    OZ2H_TILE_128x256 = 3   /* four waves of 64 x 128                                   */
+} oz2h_tile;
+
 /* Options, the paper's oz2_opts (Implementation section, "Structure"). */
 typedef struct {
     int32_t guard_bits;  /* g in t = p + g + ceil(log2 K) (Eq. 3); default 16          */
     int32_t t_bits;      /* 0: t from Eq. 3; otherwise the internal width t itself    */
     int32_t crt_margin;  /* moduli satisfy log2 P > 2t + ceil(log2 K) + margin; the
                             paper's implementation uses 2 (after Eq. crtcond)        */
+    int32_t tile;        /* oz2h_tile of the residue GEMMs; default OZ2H_TILE_AUTO    */
     uint32_t flags;      /* reserved, must be 0                                      */
 } oz2h_opts;
 
@@ -101,7 +110,7 @@ typedef struct {
     double log2P;       /* log2 of the moduli product P                              */
 } oz2h_plan_info;
 
-/* Default options: guard_bits 16, t_bits 0, crt_margin 2, flags 0. */
+/* Default options: guard_bits 16, t_bits 0, crt_margin 2, tile AUTO, flags 0. */
 void oz2h_opts_default(oz2h_opts *o);
 
 /* Message for the last failed call on this thread ("" if none). */
@@ -202,7 +211,7 @@ int oz2h_exponents(int64_t rows, int64_t count, const int8_t *sign, const int32_
  * are written as 0.  Plane order follows the moduli: one plane per one-limb
  * modulus (the centred residue), then three per two-limb modulus (r0, r1,
  * r0 + r1 with r = r0 + 128 r1, -64 <= r0 <= 63).  rpad must be a multiple of
- * 128 and >= rows, kpad a multiple of 64 and >= count.
+ * 128 and >= rows, kpad a multiple of 128 and >= count.
  */
 int oz2h_residues(const oz2h_plan *plan, int64_t rows, int64_t count,
                   const uint64_t *limbs, const int32_t *exp, const int8_t *sign,
@@ -210,31 +219,36 @@ int oz2h_residues(const oz2h_plan *plan, int64_t rows, int64_t count,
                   int64_t rpad, int64_t kpad, int8_t *planes, hipStream_t stream);
 
 /*
- * Stage 3, residue GEMMs and the fused reduction: for every modulus l,
- * u_l = (sum_k A_l[i][k] B_l[j][k]) mod m_l in [0, m_l) (with the Karatsuba
- * recombination P0 + 128 (Ps - P0 - P2) + 16384 P2 for two-limb moduli),
- * written as uint16 u[l*mpad*npad + i*npad + j].  A planes are laid out as
- * oz2h_residues writes them (G x mpad x kpad), B planes as G x npad x kpad
- * (K-contiguous, i.e. B transposed).  mpad, npad multiples of 128, kpad of 64.
+ * Stage 3, residue GEMMs, the fused reduction and the first step of the direct
+ * CRT: for every modulus l, with c_l = sum_k A_l[i][k] B_l[j][k] (and, for a
+ * two-limb modulus, the Karatsuba recombination P0 + 128 (Ps - P0 - P2) +
+ * 16384 P2 of its three planes r0, r1, r0 + r1), writes
+ *   v_l = c_l * (P/m_l)^-1 mod m_l   as a centred int16, |v_l| <= m_l / 2,
+ * at v[l*mpad*npad + i*npad + j].  A planes are laid out as oz2h_residues
+ * writes them (G x mpad x kpad), B planes as G x npad x kpad (K-contiguous,
+ * i.e. B transposed).  mpad, npad multiples of the plan's tile (128 for
+ * OZ2H_TILE_AUTO, which then picks a tile dividing them), kpad of 128.
  */
 int oz2h_residue_gemm(const oz2h_plan *plan, int64_t mpad, int64_t npad, int64_t kpad,
-                      const int8_t *a_planes, const int8_t *b_planes, uint16_t *u,
+                      const int8_t *a_planes, const int8_t *b_planes, int16_t *v,
                       hipStream_t stream);
 
 /*
  * The bare exact INT8 GEMM (Step 3 of the tutorial section): C[i][j] =
  * sum_k A[i][k] B[j][k] in int32, A M x K and B N x K K-contiguous int8 with
- * leading dimension K; M, N multiples of 128, K a multiple of 64, K <= 133000.
+ * leading dimension K; M, N multiples of the block tile (OZ2H_TILE_AUTO: 128),
+ * K a multiple of 128, K <= 133000.
  */
 int oz2h_i8gemm(int64_t M, int64_t N, int64_t K, const int8_t *A, const int8_t *B, int32_t *C,
-                hipStream_t stream);
+                int32_t tile, hipStream_t stream);
 
 /*
- * Stage 4, direct CRT + symmetric lift: from u_l = c^ mod m_l (uint16, plane
- * l at u[l*plane_stride + i*ldu + j]) reconstructs c^ with |c^| < P/2 as
+ * Stage 4, direct CRT + symmetric lift from plain residues: from
+ * u_l = c^ mod m_l (int16, any representative with |u_l| < m_l, plane l at
+ * u[l*plane_stride + i*ldu + j]) reconstructs c^ with |c^| < P/2 as
  * chat_sign[i*N + j] and nlc magnitude limbs chat_mag[(i*N + j)*nlc + l].
  */
-int oz2h_crt(const oz2h_plan *plan, int64_t M, int64_t N, const uint16_t *u, int64_t ldu,
+int oz2h_crt(const oz2h_plan *plan, int64_t M, int64_t N, const int16_t *u, int64_t ldu,
              int64_t plane_stride, int8_t *chat_sign, uint64_t *chat_mag, int32_t nlc,
              hipStream_t stream);
 

@@ -81,15 +81,43 @@ int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// residue GEMM block tiles (output rows x columns): 128 x 128 (waves of 64 x 64),
+// 256 x 128 (waves of 128 x 64) and 128 x 256 (waves of 64 x 128)
+struct GemmCfg {
+    int bm, bn;
+};
+
+GemmCfg tile_cfg(int tile) {
+    switch (tile) {
+        case OZ2H_TILE_256x128: return {256, 128};
+        case OZ2H_TILE_128x256: return {128, 256};
+        default: return {128, 128};
+    }
+}
+
+// automatic choice: the larger tile when it pads the output by at most 1/16 more
+// than 128 x 128 and still leaves at least two blocks per compute unit per modulus
+// batch of 8 moduli; otherwise 128 x 128
+GemmCfg choose_gemm(int64_t M, int64_t N, int tile) {
+    if (tile != OZ2H_TILE_AUTO) return tile_cfg(tile);
+    const int64_t a128 = round_up(M, 128) * round_up(N, 128);
+    const int64_t a256 = round_up(M, 256) * round_up(N, 128);
+    const int64_t blocks = a256 / (256 * 128);
+    if (M >= 256 && a256 * 16 <= a128 * 17 && blocks * 8 >= 2 * 256) return {256, 128};
+    return {128, 128};
+}
+
 struct Layout {
+    GemmCfg cfg;
     int64_t mpad, npad, kpad;
     size_t off_e, off_f, off_a, off_b, off_u, total;
 };
 
 Layout layout_for(const PlanHost &h, int64_t M, int64_t N) {
     Layout w{};
-    w.mpad = round_up(std::max<int64_t>(M, 1), GBM);
-    w.npad = round_up(std::max<int64_t>(N, 1), GBN);
+    w.cfg = choose_gemm(std::max<int64_t>(M, 1), std::max<int64_t>(N, 1), h.tile);
+    w.mpad = round_up(std::max<int64_t>(M, 1), w.cfg.bm);
+    w.npad = round_up(std::max<int64_t>(N, 1), w.cfg.bn);
     w.kpad = round_up(std::max<int64_t>(h.K, 1), GBK);
     size_t off = 0;
     w.off_e = off;
@@ -101,7 +129,7 @@ Layout layout_for(const PlanHost &h, int64_t M, int64_t N) {
     w.off_b = off;
     off = align_up(off + (size_t)h.G * w.npad * w.kpad);
     w.off_u = off;
-    off = align_up(off + sizeof(uint16_t) * (size_t)h.L * w.mpad * w.npad);
+    off = align_up(off + sizeof(int16_t) * (size_t)h.L * w.mpad * w.npad);
     w.total = off;
     return w;
 }
@@ -146,39 +174,53 @@ int launch_residues(const oz2h_plan *pl, int64_t rows, int64_t count, const uint
     return check_launch("residues");
 }
 
-int launch_resgemm(const oz2h_plan *pl, int64_t mpad, int64_t npad, int64_t kpad,
-                   const int8_t *a, const int8_t *b, uint16_t *u, hipStream_t s) {
-    const PlanHost &h = pl->h;
-    dim3 grid((unsigned)(npad / GBN), (unsigned)(mpad / GBM), (unsigned)h.L);
-    k_resgemm<false><<<grid, 256, 0, s>>>(a, b, kpad, mpad * kpad, npad * kpad, pl->d_info, u,
-                                          mpad * npad, npad, nullptr);
+template <bool RAW>
+int launch_gemm_kernel(GemmCfg cfg, dim3 grid, const int8_t *a, const int8_t *b, int64_t kpad,
+                       int64_t a_ps, int64_t b_ps, const ModInfo *mi, int L, int16_t *v,
+                       int64_t v_ps, int64_t ldv, int32_t *craw, hipStream_t s) {
+    if (cfg.bm == 256 && cfg.bn == 128)
+        k_resgemm<128, 64, RAW><<<grid, 256, 0, s>>>(a, b, kpad, a_ps, b_ps, mi, L, v, v_ps, ldv, craw);
+    else if (cfg.bm == 128 && cfg.bn == 256)
+        k_resgemm<64, 128, RAW><<<grid, 256, 0, s>>>(a, b, kpad, a_ps, b_ps, mi, L, v, v_ps, ldv, craw);
+    else
+        k_resgemm<64, 64, RAW><<<grid, 256, 0, s>>>(a, b, kpad, a_ps, b_ps, mi, L, v, v_ps, ldv, craw);
     return check_launch("residue GEMM");
 }
 
-int launch_crt(const oz2h_plan *pl, int64_t M, int64_t N, const uint16_t *u, int64_t u_ps,
-               int64_t ldu, const int32_t *e, const int32_t *f, bool round, int8_t *osign,
-               int32_t *oexp, uint64_t *olimbs, int64_t ldc, uint64_t *chat, int nlc,
-               hipStream_t s) {
+int launch_resgemm(const oz2h_plan *pl, GemmCfg cfg, int64_t mpad, int64_t npad, int64_t kpad,
+                   const int8_t *a, const int8_t *b, int16_t *v, hipStream_t s) {
+    const PlanHost &h = pl->h;
+    dim3 grid((unsigned)(npad / cfg.bn), (unsigned)(mpad / cfg.bm), (unsigned)h.L);
+    return launch_gemm_kernel<false>(cfg, grid, a, b, kpad, mpad * kpad, npad * kpad, pl->d_info,
+                                     h.L, v, mpad * npad, npad, nullptr, s);
+}
+
+int launch_crt(const oz2h_plan *pl, int64_t M, int64_t N, const int16_t *u, int64_t u_ps,
+               int64_t ldu, const int32_t *e, const int32_t *f, bool round, bool weight,
+               int8_t *osign, int32_t *oexp, uint64_t *olimbs, int64_t ldc, uint64_t *chat,
+               int nlc, hipStream_t s) {
     const PlanHost &h = pl->h;
     if (M * N == 0) return OZ2H_OK;
     const int bd = h.nd32 <= 64 ? 256 : (h.nd32 <= 128 ? 128 : 64);
     const size_t lds = (size_t)h.nd32 * bd * sizeof(uint32_t);
     const unsigned nb = (unsigned)((M * N + bd - 1) / bd);
-#define OZ2H_CRT(DC, R)                                                                      \
-    k_crt<DC, R><<<nb, bd, lds, s>>>(u, u_ps, ldu, M, N, pl->d_info, h.L, pl->d_crt,          \
-                                     h.crt_ndpad, h.crt_nc, h.nd32, pl->d_pd, pl->d_phd, e, f, \
-                                     h.t, h.p, osign, oexp, olimbs, ldc, chat, nlc)
-#define OZ2H_CRT_DC(R)                              \
+#define OZ2H_CRT(DC, R, W)                                                                   \
+    k_crt<DC, R, W><<<nb, bd, lds, s>>>(u, u_ps, ldu, M, N, pl->d_info, h.L, pl->d_crt,       \
+                                        h.crt_ndpad, h.crt_nc, h.nd32, pl->d_pd, pl->d_phd, e, \
+                                        f, h.t, h.p, osign, oexp, olimbs, ldc, chat, nlc)
+#define OZ2H_CRT_DC(R, W)                           \
     switch (h.crt_dc) {                             \
-        case 8: OZ2H_CRT(8, R); break;              \
-        case 16: OZ2H_CRT(16, R); break;            \
-        case 24: OZ2H_CRT(24, R); break;            \
-        default: OZ2H_CRT(32, R); break;            \
+        case 8: OZ2H_CRT(8, R, W); break;           \
+        case 16: OZ2H_CRT(16, R, W); break;         \
+        case 24: OZ2H_CRT(24, R, W); break;         \
+        default: OZ2H_CRT(32, R, W); break;         \
     }
-    if (round) {
-        OZ2H_CRT_DC(true)
+    if (weight) {
+        OZ2H_CRT_DC(false, true)
+    } else if (round) {
+        OZ2H_CRT_DC(true, false)
     } else {
-        OZ2H_CRT_DC(false)
+        OZ2H_CRT_DC(false, false)
     }
 #undef OZ2H_CRT_DC
 #undef OZ2H_CRT
@@ -285,7 +327,7 @@ int run_pipeline(const oz2h_plan *pl, int64_t M, int64_t N, int64_t K, oz2h_op o
     int32_t *f = (int32_t *)(wb + w.off_f);
     int8_t *ap = (int8_t *)(wb + w.off_a);
     int8_t *bp = (int8_t *)(wb + w.off_b);
-    uint16_t *u = (uint16_t *)(wb + w.off_u);
+    int16_t *u = (int16_t *)(wb + w.off_u);
 
     // logical side strides: rows own the exponent, k is the contraction
     const int64_t a_rs = opA == OZ2H_OP_N ? A.ld : 1, a_cs = opA == OZ2H_OP_N ? 1 : A.ld;
@@ -300,14 +342,14 @@ int run_pipeline(const oz2h_plan *pl, int64_t M, int64_t N, int64_t K, oz2h_op o
     if ((st = launch_residues(pl, N, K, B.limbs, B.exp, B.sign, b_rs, b_cs, f, w.npad, w.kpad, bp, s)))
         return st;
     if (ev) OZ2H_HIP(hipEventRecord(ev[2], s));
-    if ((st = launch_resgemm(pl, w.mpad, w.npad, w.kpad, ap, bp, u, s))) return st;
+    if ((st = launch_resgemm(pl, w.cfg, w.mpad, w.npad, w.kpad, ap, bp, u, s))) return st;
     if (ev) OZ2H_HIP(hipEventRecord(ev[3], s));
     if (round) {
-        st = launch_crt(pl, M, N, u, w.mpad * w.npad, w.npad, e, f, true, C->sign, C->exp,
-                        C->limbs, C->ld, nullptr, 0, s);
+        st = launch_crt(pl, M, N, u, w.mpad * w.npad, w.npad, e, f, true, false, C->sign,
+                        C->exp, C->limbs, C->ld, nullptr, 0, s);
     } else {
-        st = launch_crt(pl, M, N, u, w.mpad * w.npad, w.npad, e, f, false, chat_sign, nullptr,
-                        nullptr, N, chat_mag, nlc, s);
+        st = launch_crt(pl, M, N, u, w.mpad * w.npad, w.npad, e, f, false, false, chat_sign,
+                        nullptr, nullptr, N, chat_mag, nlc, s);
         if (!st) {
             OZ2H_HIP(hipMemcpyAsync(e_out, e, sizeof(int32_t) * M, hipMemcpyDeviceToDevice, s));
             OZ2H_HIP(hipMemcpyAsync(f_out, f, sizeof(int32_t) * N, hipMemcpyDeviceToDevice, s));
@@ -327,6 +369,7 @@ void oz2h_opts_default(oz2h_opts *o) {
     o->guard_bits = 16;
     o->t_bits = 0;
     o->crt_margin = 2;
+    o->tile = OZ2H_TILE_AUTO;
     o->flags = 0;
 }
 
@@ -390,12 +433,14 @@ int oz2h_plan_create(int32_t p, int64_t K, const oz2h_opts *o, oz2h_plan **out) 
     std::string err;
     int st = select_moduli(p, K, o->guard_bits, o->t_bits, o->crt_margin, mods, t, lp, err);
     if (st) return fail(st, "%s", err.c_str());
+    if (o->tile < OZ2H_TILE_AUTO || o->tile > OZ2H_TILE_128x256) return fail(OZ2H_EINVAL, "bad tile");
     oz2h_plan *pl = new oz2h_plan();
     st = build_plan(p, t, K, mods, pl->h, err);
     if (st) {
         delete pl;
         return fail(st, "%s", err.c_str());
     }
+    pl->h.tile = o->tile;
     return plan_finish(pl, out);
 }
 
@@ -494,8 +539,8 @@ int oz2h_residues(const oz2h_plan *plan, int64_t rows, int64_t count, const uint
     int st = check_plan(plan);
     if (st) return st;
     if (rows < 0 || count < 0) return fail(OZ2H_EINVAL, "negative dimension");
-    if (rpad % GBM || kpad % GBK || rpad < rows || kpad < count || rpad <= 0 || kpad <= 0)
-        return fail(OZ2H_EINVAL, "rpad must be a positive multiple of 128 >= rows, kpad of 64 >= count");
+    if (rpad % 128 || kpad % GBK || rpad < rows || kpad < count || rpad <= 0 || kpad <= 0)
+        return fail(OZ2H_EINVAL, "rpad must be a positive multiple of 128 >= rows, kpad of 128 >= count");
     if (!planes || (rows > 0 && count > 0 && (!limbs || !exp || !sign || !erow)))
         return fail(OZ2H_EINVAL, "NULL pointer");
     st = launch_residues(plan, rows, count, limbs, exp, sign, rs, cs, erow, rpad, kpad, planes,
@@ -504,34 +549,40 @@ int oz2h_residues(const oz2h_plan *plan, int64_t rows, int64_t count, const uint
 }
 
 int oz2h_residue_gemm(const oz2h_plan *plan, int64_t mpad, int64_t npad, int64_t kpad,
-                      const int8_t *a_planes, const int8_t *b_planes, uint16_t *u,
+                      const int8_t *a_planes, const int8_t *b_planes, int16_t *v,
                       hipStream_t stream) {
     int st = check_plan(plan);
     if (st) return st;
-    if (mpad <= 0 || npad <= 0 || kpad <= 0 || mpad % GBM || npad % GBN || kpad % GBK)
-        return fail(OZ2H_EINVAL, "mpad, npad must be positive multiples of 128 and kpad of 64");
+    if (mpad <= 0 || npad <= 0 || kpad <= 0 || mpad % 128 || npad % 128 || kpad % GBK)
+        return fail(OZ2H_EINVAL, "mpad, npad must be positive multiples of 128 and kpad of 128");
     if (kpad > kMaxK + GBK) return fail(OZ2H_ERANGE, "K too large for exact INT32 accumulation");
-    if (!a_planes || !b_planes || !u) return fail(OZ2H_EINVAL, "NULL pointer");
-    st = launch_resgemm(plan, mpad, npad, kpad, a_planes, b_planes, u, stream);
+    if (!a_planes || !b_planes || !v) return fail(OZ2H_EINVAL, "NULL pointer");
+    GemmCfg cfg = tile_cfg(plan->h.tile);
+    if (plan->h.tile == OZ2H_TILE_AUTO && mpad % 256 == 0) cfg = {256, 128};
+    if (mpad % cfg.bm || npad % cfg.bn)
+        return fail(OZ2H_EINVAL, "mpad, npad must be multiples of the %dx%d tile", cfg.bm, cfg.bn);
+    st = launch_resgemm(plan, cfg, mpad, npad, kpad, a_planes, b_planes, v, stream);
     return st ? st : ok();
 }
 
 int oz2h_i8gemm(int64_t M, int64_t N, int64_t K, const int8_t *A, const int8_t *B, int32_t *C,
-                hipStream_t stream) {
+                int32_t tile, hipStream_t stream) {
     int dev = -1;
     int st = check_device(&dev);
     if (st) return st;
-    if (M <= 0 || N <= 0 || K <= 0 || M % GBM || N % GBN || K % GBK)
-        return fail(OZ2H_EINVAL, "M, N must be positive multiples of 128 and K of 64");
+    if (tile < OZ2H_TILE_AUTO || tile > OZ2H_TILE_128x256) return fail(OZ2H_EINVAL, "bad tile");
+    const GemmCfg cfg = tile_cfg(tile);
+    if (M <= 0 || N <= 0 || K <= 0 || M % cfg.bm || N % cfg.bn || K % GBK)
+        return fail(OZ2H_EINVAL, "M, N must be positive multiples of the %dx%d tile and K of 128",
+                    cfg.bm, cfg.bn);
     if (K > kMaxK) return fail(OZ2H_ERANGE, "K > 133000");
     if (!A || !B || !C) return fail(OZ2H_EINVAL, "NULL pointer");
-    dim3 grid((unsigned)(N / GBN), (unsigned)(M / GBM), 1);
-    k_resgemm<true><<<grid, 256, 0, stream>>>(A, B, K, 0, 0, nullptr, nullptr, 0, N, C);
-    st = check_launch("int8 GEMM");
+    dim3 grid((unsigned)(N / cfg.bn), (unsigned)(M / cfg.bm), 1);
+    st = launch_gemm_kernel<true>(cfg, grid, A, B, K, 0, 0, nullptr, 1, nullptr, 0, N, C, stream);
     return st ? st : ok();
 }
 
-int oz2h_crt(const oz2h_plan *plan, int64_t M, int64_t N, const uint16_t *u, int64_t ldu,
+int oz2h_crt(const oz2h_plan *plan, int64_t M, int64_t N, const int16_t *u, int64_t ldu,
              int64_t plane_stride, int8_t *chat_sign, uint64_t *chat_mag, int32_t nlc,
              hipStream_t stream) {
     int st = check_plan(plan);
@@ -541,8 +592,8 @@ int oz2h_crt(const oz2h_plan *plan, int64_t M, int64_t N, const uint16_t *u, int
     if (!u || !chat_sign || !chat_mag) return fail(OZ2H_EINVAL, "NULL pointer");
     if (ldu < N || plane_stride < (M - 1) * ldu + N) return fail(OZ2H_EINVAL, "bad u layout");
     if ((int64_t)nlc * 64 < plan->h.pbits) return fail(OZ2H_EINVAL, "nlc too small");
-    st = launch_crt(plan, M, N, u, plane_stride, ldu, nullptr, nullptr, false, chat_sign, nullptr,
-                    nullptr, N, chat_mag, nlc, stream);
+    st = launch_crt(plan, M, N, u, plane_stride, ldu, nullptr, nullptr, false, true, chat_sign,
+                    nullptr, nullptr, N, chat_mag, nlc, stream);
     return st ? st : ok();
 }
 

@@ -205,146 +205,175 @@ __global__ __launch_bounds__(64 * RB) void k_residues(
 
 // ---------------------------------------------------------------- stage 3
 
-constexpr int GBM = 128, GBN = 128, GBK = 64, GLDS = 80;   // 80-byte LDS rows: conflict-free b128 reads
+constexpr int GBK = 128;   // k padding granule of the residue planes = the GEMM k-tile
+constexpr int TBK = 128;   // k-tile of the GEMM kernel: one 128-byte LDS row per output row
 
-// u = (coef * acc + part) mod m in [0, m); |coef * acc + part| < 2^45 is exact in fp64
-__device__ __forceinline__ int32_t fold_mod(int32_t acc, double coef, int32_t part, double md,
-                                            double inv_m) {
-    const double y = fma(coef, (double)acc, (double)part);
-    const double q = floor(y * inv_m);
-    int32_t r = (int32_t)fma(-q, md, y);
-    const int32_t m = (int32_t)md;
-    if (r < 0) r += m;
-    else if (r >= m) r -= m;
-    return r;
+// centred residue x - rint(x/m) m of an exact fp64 integer x (|x| < 2^52)
+__device__ __forceinline__ int32_t centred_mod(double x, double md, double inv_m) {
+    return (int32_t)fma(-rint(x * inv_m), md, x);
 }
 
-// One 128x128 output tile of one modulus per block; four waves in 2x2, each
-// a 64x64 sub-tile of 2x2 v_mfma_i32_32x32x32_i8 blocks.  A/B k-tiles of 64
-// bytes are staged through double-buffered LDS.  For a two-limb modulus the
-// three Karatsuba products run one after another and are folded into a
-// per-element residue: sum r_a r_b = -127 P0 + 128 Ps + 16256 P2.
+// s_waitcnt immediate: wait until at most `lgkm` LDS/scalar ops are outstanding,
+// leaving vector-memory loads in flight (gfx9 encoding, vmcnt and expcnt at max)
+constexpr int lgkmcnt_imm(int lgkm) { return 0xF | (3 << 14) | (0x7 << 4) | ((lgkm & 0xF) << 8); }
+
+// One (2 WM) x (2 WN) output tile of one modulus per block; four waves in 2x2,
+// each a WM x WN sub-tile of v_mfma_i32_32x32x32_i8 blocks (exact int32 sums,
+// K * 127^2 < 2^31).  k-tiles of 128 bytes are prefetched two tiles ahead into
+// registers and stored to a double-buffered LDS ring; a tile row is 128 bytes
+// = eight 16-byte chunks, chunk c of row r stored at c ^ (r & 7), so the MFMA
+// fragment reads of 8 consecutive rows hit 8 different bank groups.
+// The output is v_l = c_l (P/m_l)^-1 mod m_l as a centred int16: the reduction
+// mod m_l and the first step of the direct CRT are fused here.
+// A two-limb modulus runs its three Karatsuba products (planes r0, r1, r0 + r1:
+// P0, P2, Ps) as one continuous k-loop into the SAME accumulators: we want
+// c0 P0 + c2 P2 + cs Ps mod m with the weighted coefficients
+// (c0, c2, cs) = (-127, 16256, 128) (P/m)^-1, and fold in place at the end of
+// each product with w0 = c2^-1 c0, w1 = cs^-1 c2, w2 = cs (m is prime, so the
+// inverses exist): acc = P0 w0 -> + P2 -> * w1 -> + Ps -> * w2.  Between the
+// products |acc| <= m/2, so acc + K 127^2 < 2^31 stays exact.
+// Blocks run the two-limb moduli first (they are three times longer).
 // RAW = true: plain int32 output of a single plane (exactness tests).
-template <bool RAW>
+template <int WM, int WN, bool RAW>
 __global__ __launch_bounds__(256) void k_resgemm(const int8_t *__restrict__ A,
                                                  const int8_t *__restrict__ B, int64_t kpad,
                                                  int64_t a_ps, int64_t b_ps,
-                                                 const ModInfo *__restrict__ mi,
-                                                 uint16_t *__restrict__ U, int64_t u_ps,
-                                                 int64_t ldu, int32_t *__restrict__ Craw) {
-    __shared__ __attribute__((aligned(16))) int8_t sA[2][GBM * GLDS];
-    __shared__ __attribute__((aligned(16))) int8_t sB[2][GBN * GLDS];
+                                                 const ModInfo *__restrict__ mi, int L,
+                                                 int16_t *__restrict__ V, int64_t v_ps,
+                                                 int64_t ldv, int32_t *__restrict__ Craw) {
+    constexpr int BM = 2 * WM, BN = 2 * WN, FM = WM / 32, FN = WN / 32;
+    constexpr int AP = BM / 32, BP = BN / 32;   // 32 rows x 128 bytes per pass of 256 lanes
+    __shared__ __attribute__((aligned(1024))) int8_t sA0[BM * TBK];
+    __shared__ __attribute__((aligned(1024))) int8_t sA1[BM * TBK];
+    __shared__ __attribute__((aligned(1024))) int8_t sB0[BN * TBK];
+    __shared__ __attribute__((aligned(1024))) int8_t sB1[BN * TBK];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
-    const int64_t m0 = (int64_t)blockIdx.y * GBM, n0 = (int64_t)blockIdx.x * GBN;
+    const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+    const int l = RAW ? 0 : L - 1 - (int)blockIdx.z;
 
     uint32_t g0 = 0, nprod = 1;
     double md = 1.0, inv_m = 1.0;
+    int32_t kc[3] = {1, 1, 1};
     if (!RAW) {
-        const ModInfo info = mi[blockIdx.z];
+        const ModInfo info = mi[l];
         g0 = info.g0;
         nprod = info.nprod;
         md = (double)info.m;
         inv_m = info.inv_m;
+        kc[0] = info.kc[0];
+        kc[1] = info.kc[1];
+        kc[2] = info.kc[2];
     }
+    const int nk = (int)(kpad / TBK);   // kpad is a multiple of 128
+    const int ntile = (int)nprod * nk;
 
-    int32_t part[2][2][16];
+    // global -> register -> LDS: thread t moves row t/8 (+32 per pass), chunk t%8
+    const int grow = tid >> 3, gch = tid & 7;
+    const int64_t g_off = (int64_t)grow * kpad + gch * 16;
+    const int s_off = grow * TBK + ((gch ^ (grow & 7)) << 4);   // (grow + 32 i) & 7 == grow & 7
+    v4i ra[2][AP], rb[2][BP];
+    auto gload = [&](int T, int slot) {
+        const int prod = T / nk, kt = T - prod * nk;
+        const int64_t ko = (int64_t)kt * TBK;
+        const int8_t *Ag = A + (int64_t)(g0 + prod) * a_ps + m0 * kpad + ko + g_off;
+        const int8_t *Bg = B + (int64_t)(g0 + prod) * b_ps + n0 * kpad + ko + g_off;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+        for (int i = 0; i < AP; ++i) ra[slot][i] = *(const v4i *)(Ag + (int64_t)(32 * i) * kpad);
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int i = 0; i < BP; ++i) rb[slot][i] = *(const v4i *)(Bg + (int64_t)(32 * i) * kpad);
+    };
+    auto sstore = [&](int slot, int8_t *dA, int8_t *dB) {
 #pragma unroll
-            for (int e = 0; e < 16; ++e) part[a][b][e] = 0;
+        for (int i = 0; i < AP; ++i) *(v4i *)(dA + s_off + 32 * i * TBK) = ra[slot][i];
+#pragma unroll
+        for (int i = 0; i < BP; ++i) *(v4i *)(dB + s_off + 32 * i * TBK) = rb[slot][i];
+    };
 
-    const int ldrow = tid >> 2, ldchunk = (tid & 3) * 16;   // global->LDS: 4 lanes per 64-byte row
-    const int nk = (int)(kpad / GBK);
+    v16i acc[FM][FN];
+#pragma unroll
+    for (int x = 0; x < FM; ++x)
+#pragma unroll
+        for (int y = 0; y < FN; ++y) acc[x][y] = v16i{};
 
-    for (uint32_t prod = 0; prod < nprod; ++prod) {
-        const int8_t *Ag = A + (int64_t)(g0 + prod) * a_ps + m0 * kpad;
-        const int8_t *Bg = B + (int64_t)(g0 + prod) * b_ps + n0 * kpad;
-        v16i acc[2][2];
+    // fragment reads: row R = (multiple of 32) + lane%32, logical chunk c = 2 s + lane/32;
+    // R & 7 only depends on lane, so each k-step's swizzled offset is a per-lane constant
+    const int frow = lane & 31;
+    auto compute = [&](const int8_t *cA, const int8_t *cB) {
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int ks = 0; ks < TBK / 32; ++ks) {
+            const int fo = frow * TBK + (((2 * ks + (lane >> 5)) ^ (frow & 7)) << 4);
+            v4i fa[FM], fb[FN];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) acc[a][b] = v16i{};
-
-        v4i ga0, ga1, gb0, gb1;
-        auto gload = [&](int kt) {
-            const int64_t ko = (int64_t)kt * GBK + ldchunk;
-            ga0 = *(const v4i *)(Ag + (int64_t)ldrow * kpad + ko);
-            ga1 = *(const v4i *)(Ag + (int64_t)(ldrow + 64) * kpad + ko);
-            gb0 = *(const v4i *)(Bg + (int64_t)ldrow * kpad + ko);
-            gb1 = *(const v4i *)(Bg + (int64_t)(ldrow + 64) * kpad + ko);
-        };
-        auto sstore = [&](int buf) {
-            *(v4i *)(&sA[buf][ldrow * GLDS + ldchunk]) = ga0;
-            *(v4i *)(&sA[buf][(ldrow + 64) * GLDS + ldchunk]) = ga1;
-            *(v4i *)(&sB[buf][ldrow * GLDS + ldchunk]) = gb0;
-            *(v4i *)(&sB[buf][(ldrow + 64) * GLDS + ldchunk]) = gb1;
-        };
-
-        gload(0);
-        sstore(0);
-        __syncthreads();
-        for (int kt = 0; kt < nk; ++kt) {
-            const int cur = kt & 1;
-            if (kt + 1 < nk) gload(kt + 1);
+            for (int x = 0; x < FM; ++x) fa[x] = *(const v4i *)(cA + (wr * WM + x * 32) * TBK + fo);
 #pragma unroll
-            for (int kh = 0; kh < 2; ++kh) {
-                v4i fa[2], fb[2];
-                const int koff = kh * 32 + (lane >> 5) * 16;
+            for (int y = 0; y < FN; ++y) fb[y] = *(const v4i *)(cB + (wc * WN + y * 32) * TBK + fo);
 #pragma unroll
-                for (int x = 0; x < 2; ++x) {
-                    fa[x] = *(const v4i *)(&sA[cur][(wr * 64 + x * 32 + (lane & 31)) * GLDS + koff]);
-                    fb[x] = *(const v4i *)(&sB[cur][(wc * 64 + x * 32 + (lane & 31)) * GLDS + koff]);
-                }
+            for (int x = 0; x < FM; ++x)
 #pragma unroll
-                for (int a = 0; a < 2; ++a)
-#pragma unroll
-                    for (int b = 0; b < 2; ++b)
-                        acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[b], acc[a][b],
-                                                                          0, 0, 0);
-            }
-            if (kt + 1 < nk) sstore(cur ^ 1);
-            __syncthreads();
+                for (int y = 0; y < FN; ++y)
+                    acc[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[x], fb[y], acc[x][y], 0, 0, 0);
         }
-
-        if (RAW) {
+    };
+    // end of a product: acc = acc * w mod m, centred (|x| < 2^45 is exact in fp64)
+    auto fold = [&](int prod) {
+        const double w = (double)kc[prod];
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+        for (int x = 0; x < FM; ++x)
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
-#pragma unroll
-                    for (int e = 0; e < 16; ++e) {
-                        const int64_t row =
-                            m0 + wr * 64 + a * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-                        const int64_t col = n0 + wc * 64 + b * 32 + (lane & 31);
-                        Craw[row * ldu + col] = acc[a][b][e];
-                    }
-            return;
-        }
-        // planes are (r0, r1, r0 + r1): products P0, P2, Ps in that order
-        const double coef = nprod == 1 ? 1.0 : (prod == 0 ? -127.0 : (prod == 1 ? 16256.0 : 128.0));
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
+            for (int y = 0; y < FN; ++y)
 #pragma unroll
                 for (int e = 0; e < 16; ++e)
-                    part[a][b][e] = fold_mod(acc[a][b][e], coef, part[a][b][e], md, inv_m);
-    }
+                    acc[x][y][e] = centred_mod((double)acc[x][y][e] * w, md, inv_m);
+    };
+    // one k-tile: LDS (c) holds tile T, registers `slot ^ 1` hold (or will hold) tile T + 1;
+    // tile T + 2 is fetched into `slot` while T is multiplied, T + 1 goes to LDS (n) after.
+    // Loads and stores are unconditional (indices clamped at the end) so that the
+    // compiler can count the loads in flight and keep two tiles of prefetch.
+    const int last = ntile - 1;
+    auto step = [&](int T, int slot, const int8_t *cA, const int8_t *cB, int8_t *nA, int8_t *nB) {
+        gload(min(T + 2, last), slot);
+        compute(cA, cB);
+        if (!RAW && (T + 1) % nk == 0) fold(T / nk);
+        sstore(slot ^ 1, nA, nB);
+        __builtin_amdgcn_s_waitcnt(lgkmcnt_imm(0));   // own LDS stores done (loads stay in flight)
+        __builtin_amdgcn_s_barrier();
+    };
 
-    uint16_t *Ul = U + (int64_t)blockIdx.z * u_ps;
+    gload(0, 0);
+    gload(min(1, last), 1);
+    sstore(0, sA0, sB0);
+    __builtin_amdgcn_s_waitcnt(lgkmcnt_imm(0));
+    __builtin_amdgcn_s_barrier();
+    int T = 0;
+    for (; T + 1 < ntile; T += 2) {
+        step(T, 0, sA0, sB0, sA1, sB1);
+        step(T + 1, 1, sA1, sB1, sA0, sB0);
+    }
+    if (T < ntile) step(T, 0, sA0, sB0, sA1, sB1);
+
+    // output element e of block (x, y): row 8*(e/4) + 4*(lane/32) + e%4, column lane%32;
+    // the per-element row offsets are uniform, only the lane base is per lane
+    const int64_t lane_off = (m0 + wr * WM + 4 * (lane >> 5)) * ldv + n0 + wc * WN + (lane & 31);
+    if (RAW) {
+        int32_t *base = Craw + lane_off;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+        for (int x = 0; x < FM; ++x)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+            for (int y = 0; y < FN; ++y)
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int64_t row = m0 + wr * 64 + a * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-                const int64_t col = n0 + wc * 64 + b * 32 + (lane & 31);
-                Ul[row * ldu + col] = (uint16_t)part[a][b][e];
-            }
+                for (int e = 0; e < 16; ++e)
+                    base[(int64_t)(x * 32 + 8 * (e >> 2) + (e & 3)) * ldv + y * 32] = acc[x][y][e];
+        return;
+    }
+    int16_t *base = V + (int64_t)l * v_ps + lane_off;
+#pragma unroll
+    for (int x = 0; x < FM; ++x)
+#pragma unroll
+        for (int y = 0; y < FN; ++y)
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                base[(int64_t)(x * 32 + 8 * (e >> 2) + (e & 3)) * ldv + y * 32] = (int16_t)acc[x][y][e];
 }
 
 // ---------------------------------------------------------------- stage 4 + 5
@@ -365,9 +394,11 @@ __device__ __forceinline__ uint32_t dig_bits32(const uint32_t *__restrict__ sd, 
 // floor(sum v_l / m_l) in binary64; R = S - (alpha - 1) P is carried into
 // 32-bit digits in an LDS column.  Then at most two subtractions of P give x0,
 // the lift compares with floor(P/2), and (ROUND) the magnitude is rounded once
-// to p bits with its scale 2^(e_i + f_j - 2t).
-template <int DC, bool ROUND>
-__global__ void k_crt(const uint16_t *__restrict__ U, int64_t u_ps, int64_t ldu, int64_t M,
+// to p bits with its scale 2^(e_i + f_j - 2t).  The input planes hold
+// v_l = u_l (P/m_l)^-1 mod m_l as centred int16 (the residue GEMM applies the
+// weight); WEIGHT = true takes plain residues u_l and applies it here.
+template <int DC, bool ROUND, bool WEIGHT>
+__global__ void k_crt(const int16_t *__restrict__ V, int64_t v_ps, int64_t ldv, int64_t M,
                       int64_t N, const ModInfo *__restrict__ mi, int L,
                       const double *__restrict__ dig, int ndpad, int nc, int nd32,
                       const uint32_t *__restrict__ Pd, const uint32_t *__restrict__ Phd,
@@ -380,7 +411,7 @@ __global__ void k_crt(const uint16_t *__restrict__ U, int64_t u_ps, int64_t ldu,
     const int64_t idx = (int64_t)blockIdx.x * bd + tid;
     if (idx >= M * N) return;
     const int64_t i = idx / N, j = idx - i * N;
-    const uint16_t *up = U + i * ldu + j;
+    const int16_t *vp = V + i * ldv + j;
     uint32_t *sd = sdig + tid;
 
     int64_t beta = 0, carry = 0;
@@ -390,21 +421,25 @@ __global__ void k_crt(const uint16_t *__restrict__ U, int64_t u_ps, int64_t ldu,
         for (int d = 0; d < DC; ++d) acc[d] = 0.0;
         double asum = 0.0;
         const double *dc = dig + c * DC;
-        for (int l = 0; l < L; ++l) {
+        auto step = [&](int l, int raw) {
             const ModInfo info = mi[l];
-            const uint32_t x = (uint32_t)up[(int64_t)l * u_ps] * info.minv;   // < 2^28
-            const double xd = (double)x, md = (double)info.m;
-            const double q = floor(xd * info.inv_m);
-            int v = (int)fma(-q, md, xd);
-            if (v < 0) v += (int)info.m;
-            else if (v >= (int)info.m) v -= (int)info.m;
-            if (v > (int)((info.m - 1) >> 1)) v -= (int)info.m;   // centred v_l
-            const double vd = (double)v;
+            double vd;
+            if (WEIGHT) vd = (double)centred_mod((double)raw * (double)info.minv, (double)info.m, info.inv_m);
+            else vd = (double)raw;
             if (c == 0) asum = fma(vd, info.inv_m, asum);
             const double *dl = dc + (size_t)l * ndpad;
 #pragma unroll
             for (int d = 0; d < DC; ++d) acc[d] = fma(vd, dl[d], acc[d]);
+        };
+        int l = 0;
+        for (; l + 8 <= L; l += 8) {   // eight loads in flight before their use
+            int raw[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) raw[q] = vp[(int64_t)(l + q) * v_ps];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) step(l + q, raw[q]);
         }
+        for (; l < L; ++l) step(l, vp[(int64_t)l * v_ps]);
         if (c == 0) beta = (int64_t)floor(asum) - 1;   // alpha - 1
 #pragma unroll
         for (int d = 0; d < DC; ++d) {

@@ -223,6 +223,30 @@ int build_plan(int p, int t, int64_t K, const std::vector<uint32_t> &mods_in, Pl
             return -1;
         }
         h.info[l].minv = minv;
+        auto centred = [m](int64_t x) {
+            int64_t r = x % (int64_t)m;
+            if (r < 0) r += m;
+            if (r > (int64_t)((m - 1) / 2)) r -= m;
+            return (int32_t)r;
+        };
+        if (h.info[l].nprod == 1) {
+            h.info[l].kc[0] = centred(minv);
+            h.info[l].kc[1] = h.info[l].kc[2] = 0;
+        } else {
+            // sum r_a r_b = -127 P0 + 16256 P2 + 128 Ps (Karatsuba on balanced base-128
+            // halves); weighted by minv, folded after each product (see k_resgemm)
+            const int64_t c0 = (-127 * (int64_t)minv) % m, c2 = (16256 * (int64_t)minv) % m,
+                          cs = (128 * (int64_t)minv) % m;
+            const uint32_t c2i = inv_mod((uint32_t)((c2 + m) % m), m);
+            const uint32_t csi = inv_mod((uint32_t)((cs + m) % m), m);
+            if (!c2i || !csi) {
+                err = "two-limb moduli must be odd primes";
+                return -1;
+            }
+            h.info[l].kc[0] = centred(((c0 + m) % m) * (int64_t)c2i);
+            h.info[l].kc[1] = centred(((c2 + m) % m) * (int64_t)csi);
+            h.info[l].kc[2] = centred(cs);
+        }
         // balanced base-2^32 digits, |d| <= 2^31
         int64_t carry = 0;
         for (int k = 0; k < h.crt_ndpad; ++k) {

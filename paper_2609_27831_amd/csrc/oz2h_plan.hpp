@@ -15,17 +15,21 @@ constexpr int64_t kMaxK = 133000;     // K * 127^2 < 2^31, the cap the paper's i
 constexpr uint32_t kOneLimbMax = 255;    // centred residue fits int8
 constexpr uint32_t kTwoLimbMax = 16191;  // balanced base-128 halves fit int8 (and their sum)
 
-// Per-modulus record read by the kernels (24 bytes, 8-byte aligned).
+// Per-modulus record read by the kernels (40 bytes, 8-byte aligned).
 struct ModInfo {
     uint32_t m;      // the modulus
     uint32_t g0;     // its first INT8 plane
     uint32_t nprod;  // 1 for a one-limb modulus, 3 for a two-limb modulus (Karatsuba)
     uint32_t minv;   // (P / m)^-1 mod m, the direct-CRT weight
     double inv_m;    // fl(1/m)
+    int32_t kc[3];   // centred in-place fold factors of the GEMM accumulator after
+                     // each product: minv (one-limb), or w0, w1, w2 (two-limb, k_resgemm)
+    int32_t pad;
 };
 
 struct PlanHost {
     int p = 0, t = 0;
+    int tile = 0;          // oz2h_tile hint of the residue GEMMs (0 = automatic)
     int64_t K = 0;
     int L = 0, L1 = 0, L2 = 0, G = 0;
     int nw32 = 0;          // 32-bit words of a (t+1)-bit integer significand

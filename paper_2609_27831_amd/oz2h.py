@@ -26,9 +26,14 @@ class Oz2hError(RuntimeError):
         self.code = code
 
 
+TILE_AUTO, TILE_128x128, TILE_256x128, TILE_128x256 = 0, 1, 2, 3
+TILE_SHAPES = {TILE_128x128: (128, 128), TILE_256x128: (256, 128), TILE_128x256: (128, 256)}
+
+
 class Opts(ctypes.Structure):
     _fields_ = [("guard_bits", ctypes.c_int32), ("t_bits", ctypes.c_int32),
-                ("crt_margin", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("crt_margin", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
 
 
 class CMat(ctypes.Structure):
@@ -69,7 +74,7 @@ SIGNATURES = {
     "oz2h_exponents": (ctypes.c_int, [_I64, _I64, _P, _P, _I64, _I64, _P, _P]),
     "oz2h_residues": (ctypes.c_int, [_P, _I64, _I64, _P, _P, _P, _I64, _I64, _P, _I64, _I64, _P, _P]),
     "oz2h_residue_gemm": (ctypes.c_int, [_P, _I64, _I64, _I64, _P, _P, _P, _P]),
-    "oz2h_i8gemm": (ctypes.c_int, [_I64, _I64, _I64, _P, _P, _P, _P]),
+    "oz2h_i8gemm": (ctypes.c_int, [_I64, _I64, _I64, _P, _P, _P, _I32, _P]),
     "oz2h_crt": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _I64, _P, _P, _I32, _P]),
 }
 
@@ -98,9 +103,11 @@ def _check(code: int):
 
 
 def default_opts(guard_bits: Optional[int] = None, t_bits: Optional[int] = None,
-                 crt_margin: Optional[int] = None) -> Opts:
+                 crt_margin: Optional[int] = None, tile: Optional[int] = None) -> Opts:
     o = Opts()
     lib().oz2h_opts_default(ctypes.byref(o))
+    if tile is not None:
+        o.tile = tile
     if guard_bits is not None:
         o.guard_bits = guard_bits
     if t_bits is not None:
@@ -323,13 +330,13 @@ def residue_gemm(plan: Plan, a_planes, b_planes, stream=None):
     return u
 
 
-def i8gemm(A, B, stream=None):
+def i8gemm(A, B, tile: int = TILE_AUTO, stream=None):
     torch = _torch()
     M, K = A.shape
     N, K2 = B.shape
     assert K == K2
     C = torch.empty((M, N), dtype=torch.int32, device=A.device)
-    _check(lib().oz2h_i8gemm(M, N, K, A.data_ptr(), B.data_ptr(), C.data_ptr(),
+    _check(lib().oz2h_i8gemm(M, N, K, A.data_ptr(), B.data_ptr(), C.data_ptr(), tile,
                              _stream_ptr(stream)))
     return C
 

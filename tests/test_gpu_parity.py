@@ -67,12 +67,16 @@ CASES = [
     ("p1024_two_limb", 107, 64, 70, 33, 1024, -40, 40, 0.0, 0, 0),
     ("p2048_small", 108, 20, 30, 17, 2048, -16, 16, 0.0, 0, 0),
     ("p113_K_odd", 109, 140, 129, 1001, 113, -16, 16, 0.01, 0, 0),
+    ("tile256x128_p256", 110, 300, 200, 150, 256, -32, 32, 0.02, 0, 0, 2),
+    ("tile128x256_p512", 111, 130, 260, 70, 512, -32, 32, 0.0, 0, 1, 3),
+    ("tile128x128_p113", 112, 260, 140, 333, 113, -16, 16, 0.0, 1, 0, 1),
 ]
 
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_gemm_matches_oracle_elementwise(oz, c_oracle, case):
-    name, seed, M, N, K, p, lo, hi, zf, opA, opB = case
+    name, seed, M, N, K, p, lo, hi, zf, opA, opB = case[:11]
+    tile = case[11] if len(case) > 11 else 0
     A, B = synth.operands_for(seed, M, N, K, p, lo, hi)
     if zf:
         _zeros(A, zf, seed)
@@ -80,8 +84,8 @@ def test_gemm_matches_oracle_elementwise(oz, c_oracle, case):
     if M > 3 and N > 3:
         A.sign[M // 2, :] = 0       # an all-zero row of A and column of B
         B.sign[:, N // 3] = 0
-    print(f"parity {name}: M={M} N={N} K={K} p={p}", flush=True)
-    plan = oz.Plan.create(p, K)
+    print(f"parity {name}: M={M} N={N} K={K} p={p} tile={tile}", flush=True)
+    plan = oz.Plan.create(p, K, oz.default_opts(tile=tile))
     ref = c_oracle.gemm(A, B)
     got = _run_gpu(oz, plan, A, B, opA, opB)
     _compare_full(got, ref, ref["nlc"])

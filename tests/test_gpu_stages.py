@@ -19,14 +19,16 @@ def oz(request):
     return oz2h
 
 
-def test_i8gemm_exact_random(oz):
+@pytest.mark.parametrize("tile", [1, 2, 3])
+def test_i8gemm_exact_random(oz, tile):
     import torch
     rng = np.random.default_rng(1)
-    for (M, N, K) in [(128, 128, 64), (256, 384, 1024), (384, 128, 4160)]:
+    bm, bn = oz.TILE_SHAPES[tile]
+    for (M, N, K) in [(bm, bn, 128), (2 * bm, 3 * bn, 1024), (3 * bm, bn, 4224), (bm, 2 * bn, 256)]:
         A = rng.integers(-127, 128, (M, K), dtype=np.int8)
         B = rng.integers(-127, 128, (N, K), dtype=np.int8)
-        print(f"i8gemm M={M} N={N} K={K}", flush=True)
-        C = oz.i8gemm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()).cpu().numpy()
+        print(f"i8gemm tile={tile} M={M} N={N} K={K}", flush=True)
+        C = oz.i8gemm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), tile).cpu().numpy()
         ref = A.astype(np.int64) @ B.astype(np.int64).T
         assert np.array_equal(C.astype(np.int64), ref)
 
@@ -34,7 +36,7 @@ def test_i8gemm_exact_random(oz):
 def test_i8gemm_int32_limit(oz):
     """K*127^2 < 2^31 at the largest K the kernel takes (Step 3 of the tutorial section)."""
     import torch
-    K = 132992           # largest multiple of 64 <= 133000
+    K = 132992           # largest multiple of 128 <= 133000
     A = np.full((128, K), 127, np.int8)
     B = np.full((128, K), 127, np.int8)
     B[1::2] = -127
@@ -84,7 +86,7 @@ def test_residue_planes(oz, c_oracle, p, lo, hi, side):
     rows = e.size
     Xd = dev_mp(X)
     erow = torch.from_numpy(e).cuda()
-    rpad, kpad = 128, 192
+    rpad, kpad = 128, 256
     print(f"residues p={p} side={side}", flush=True)
     planes = oz.residues(plan, Xd, erow, side, rpad, kpad).cpu().numpy()
     assert planes.shape == (plan.G, rpad, kpad)
@@ -106,13 +108,16 @@ def test_residue_planes(oz, c_oracle, p, lo, hi, side):
             assert r0.min() >= -64 and r0.max() <= 63 and np.abs(r1).max() <= 63
 
 
-def test_residue_gemm_mod_m(oz):
-    """Stage 3 vs int64 numpy products of the same planes, reduced mod m (Karatsuba included)."""
+@pytest.mark.parametrize("mpad,npad,kpad,tile", [(256, 128, 384, 0), (512, 256, 256, 0),
+                                               (128, 384, 128, 1), (256, 256, 256, 2),
+                                               (128, 512, 128, 3)])
+def test_residue_gemm_mod_m(oz, mpad, npad, kpad, tile):
+    """Stage 3 vs int64 numpy products of the same planes, reduced mod m (Karatsuba included)
+    and weighted by the direct-CRT factor (P/m)^-1 mod m."""
     import torch
-    plan = oz.Plan.create(256, 320)        # 54 one-limb + 16 two-limb moduli
+    plan = oz.Plan.create(256, 320, oz.default_opts(tile=tile))   # 54 one-limb + 16 two-limb
     G, L1 = plan.G, plan.L1
-    rng = np.random.default_rng(5)
-    mpad, npad, kpad = 256, 128, 320
+    rng = np.random.default_rng(5 + mpad)
     A = np.zeros((G, mpad, kpad), np.int8)
     B = np.zeros((G, npad, kpad), np.int8)
     for li, m in enumerate(plan.moduli.tolist()):
@@ -128,9 +133,13 @@ def test_residue_gemm_mod_m(oz):
                 r1 = (r - r0) // 128
                 X[g0], X[g0 + 1], X[g0 + 2] = r0, r1, r0 + r1
     print("residue gemm", flush=True)
-    u = oz.residue_gemm(plan, torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda())
-    u = u.cpu().numpy().view(np.uint16).astype(np.int64)
+    v = oz.residue_gemm(plan, torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda())
+    v = v.cpu().numpy().astype(np.int64)
+    P = 1
+    for m in plan.moduli.tolist():
+        P *= m
     for li, m in enumerate(plan.moduli.tolist()):
+        minv = pow((P // m) % m, -1, m)
         g0 = li if li < L1 else L1 + 3 * (li - L1)
         if m <= 255:
             prod = A[g0].astype(np.int64) @ B[g0].astype(np.int64).T
@@ -138,7 +147,8 @@ def test_residue_gemm_mod_m(oz):
             a = A[g0].astype(np.int64) + 128 * A[g0 + 1].astype(np.int64)
             b = B[g0].astype(np.int64) + 128 * B[g0 + 1].astype(np.int64)
             prod = a @ b.T
-        assert np.array_equal(u[li], np.mod(prod, m)), f"modulus {m}"
+        assert np.abs(v[li]).max() <= m // 2, f"modulus {m}: not centred"
+        assert np.array_equal(np.mod(v[li], m), np.mod(np.mod(prod, m) * minv, m)), f"modulus {m}"
 
 
 def test_crt_worked_example(oz):
