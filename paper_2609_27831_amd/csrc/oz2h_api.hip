@@ -160,7 +160,7 @@ int launch_residues(const oz2h_plan *pl, int64_t rows, int64_t count, const uint
     const PlanHost &h = pl->h;
     const int nl = (h.p + 63) / 64;
     const int64_t ps = rpad * kpad;
-    int rb = h.nw32 <= 64 ? 4 : (h.nw32 <= 128 ? 2 : 1);   // LDS <= 64 KiB per block
+    int rb = h.nw32 <= 64 ? 4 : (h.nw32 <= 128 ? 2 : 1);   // word columns <= 64 KiB per block
     dim3 grid((unsigned)(kpad / 64), (unsigned)(rpad / rb));
     const size_t lds = (size_t)h.nw32 * 64 * rb * sizeof(uint32_t);
 #define OZ2H_RES(RB)                                                                       \
@@ -201,19 +201,28 @@ int launch_crt(const oz2h_plan *pl, int64_t M, int64_t N, const int16_t *u, int6
                int nlc, hipStream_t s) {
     const PlanHost &h = pl->h;
     if (M * N == 0) return OZ2H_OK;
-    const int bd = h.nd32 <= 64 ? 256 : (h.nd32 <= 128 ? 128 : 64);
-    const size_t lds = (size_t)h.nd32 * bd * sizeof(uint32_t);
-    const unsigned nb = (unsigned)((M * N + bd - 1) / bd);
-#define OZ2H_CRT(DC, R, W)                                                                   \
-    k_crt<DC, R, W><<<nb, bd, lds, s>>>(u, u_ps, ldu, M, N, pl->d_info, h.L, pl->d_crt,       \
-                                        h.crt_ndpad, h.crt_nc, h.nd32, pl->d_pd, pl->d_phd, e, \
-                                        f, h.t, h.p, osign, oexp, olimbs, ldc, chat, nlc)
-#define OZ2H_CRT_DC(R, W)                           \
-    switch (h.crt_dc) {                             \
-        case 8: OZ2H_CRT(8, R, W); break;           \
-        case 16: OZ2H_CRT(16, R, W); break;         \
-        case 24: OZ2H_CRT(24, R, W); break;         \
-        default: OZ2H_CRT(32, R, W); break;         \
+    // two entries per thread; the LDS digit columns (nd32 words per entry) stay <= 64 KiB
+    const int ept = h.nd32 <= 64 ? 2 : 1;
+    int bd = 256;
+    while (bd > 64 && (size_t)h.nd32 * bd * ept * sizeof(uint32_t) > 49152) bd /= 2;
+    // digit columns, then a slice of LB moduli x crt_dc digit constants and LB reciprocals
+    const size_t cols = (((size_t)h.nd32 * bd * ept + 3) & ~(size_t)3) * sizeof(uint32_t);
+    const int LB = std::max(1, std::min(h.L, (int)((65536 - cols) / (sizeof(double) * (h.crt_dc + 1)))));
+    const size_t lds = cols + (size_t)LB * (h.crt_dc + 1) * sizeof(double);
+    const unsigned nb = (unsigned)((M * N + (int64_t)bd * ept - 1) / ((int64_t)bd * ept));
+#define OZ2H_CRT(DC, E, R, W)                                                                   \
+    k_crt<DC, E, R, W><<<nb, bd, lds, s>>>(u, u_ps, ldu, M, N, pl->d_info, h.L, pl->d_crt,      \
+                                           h.crt_ndpad, h.crt_nc, h.nd32, pl->d_pd, pl->d_phd, \
+                                           e, f, h.t, h.p, osign, oexp, olimbs, ldc, chat, nlc, LB)
+#define OZ2H_CRT_E(DC, R, W)          \
+    if (ept == 2) OZ2H_CRT(DC, 2, R, W); \
+    else OZ2H_CRT(DC, 1, R, W);
+#define OZ2H_CRT_DC(R, W)                             \
+    switch (h.crt_dc) {                               \
+        case 8: OZ2H_CRT_E(8, R, W) break;            \
+        case 16: OZ2H_CRT_E(16, R, W) break;          \
+        case 24: OZ2H_CRT_E(24, R, W) break;          \
+        default: OZ2H_CRT_E(32, R, W) break;          \
     }
     if (weight) {
         OZ2H_CRT_DC(false, true)
@@ -223,6 +232,7 @@ int launch_crt(const oz2h_plan *pl, int64_t M, int64_t N, const int16_t *u, int6
         OZ2H_CRT_DC(false, false)
     }
 #undef OZ2H_CRT_DC
+#undef OZ2H_CRT_E
 #undef OZ2H_CRT
     return check_launch("CRT");
 }

@@ -107,12 +107,72 @@ __device__ __forceinline__ int mant_any_below(const uint64_t *__restrict__ base,
     return 0;
 }
 
-// One thread per entry (r, k) of a rows x count operand side; a block covers 64
-// consecutive k of RB rows, so the int8 plane stores of a wave are 64
-// contiguous bytes.  The (t+1)-bit integer a^ is built once per entry into a
-// per-thread LDS column of 32-bit words; the moduli are then swept in groups
-// of 8 with fp64 FMAs against centred 2^(32w) mod m weights (exact: every
-// partial sum stays below 2^53), one rint-based reduction per modulus.
+// limb i of a significand (bits at or above p masked off; out of range -> 0),
+// branch-free: the index is clamped and the value selected, so that the
+// compiler can issue the loads of all words back to back
+__device__ __forceinline__ uint64_t glimb(const uint64_t *__restrict__ sl, int nl, uint64_t topmask,
+                                          int64_t i) {
+    const int ii = (int)min(max(i, (int64_t)0), (int64_t)(nl - 1));
+    uint64_t v = sl[ii];
+    v &= (ii == nl - 1) ? topmask : ~0ull;
+    return (i >= 0 && i < nl) ? v : 0ull;
+}
+__device__ __forceinline__ uint32_t gbits32(const uint64_t *__restrict__ sl, int nl, uint64_t topmask,
+                                            int64_t off) {
+    const int64_t q = off >> 6;
+    const int r = (int)(off & 63);
+    const uint64_t lo = glimb(sl, nl, topmask, q), hi = glimb(sl, nl, topmask, q + 1);
+    return (uint32_t)(r ? ((lo >> r) | (hi << (64 - r))) : lo);
+}
+
+// The (t+1)-bit integer a^ = RNE(mant * 2^sh) of one entry as 32-bit words into
+// an LDS column (stride st); returns the sign after rounding (0 if a^ = 0).
+// sh = t - p + exp - e <= t - p (Eq. 1).
+__device__ __forceinline__ int build_words(const uint64_t *__restrict__ sl, int s, int64_t sh,
+                                           int p, int nl, int nw32, uint32_t *col, int st) {
+    if (s == 0) return 0;
+    const int topbits = p - 64 * (nl - 1);
+    const uint64_t topmask = topbits >= 64 ? ~0ull : ((1ull << topbits) - 1);
+    if (sh >= 0) {
+        for (int w = 0; w < nw32; ++w) col[w * st] = gbits32(sl, nl, topmask, 32 * (int64_t)w - sh);
+        return s;
+    }
+    const int64_t rsh = -sh;   // round to nearest even on the dropped bits
+    uint32_t nz = 0;
+    for (int w = 0; w < nw32; ++w) {
+        const uint32_t v = gbits32(sl, nl, topmask, 32 * (int64_t)w + rsh);
+        col[w * st] = v;
+        nz |= v;
+    }
+    const int64_t rpos = rsh - 1;   // round bit position, sticky = any bit below it
+    const int rbit = (int)((glimb(sl, nl, topmask, rpos >> 6) >> (rpos & 63)) & 1u);
+    if (rbit) {
+        bool sticky = false;
+        const int64_t full = rpos >> 6;
+        for (int64_t i = 0; i < full && i < nl; ++i) sticky |= glimb(sl, nl, topmask, i) != 0;
+        const int rr = (int)(rpos & 63);
+        if (rr && full < nl) sticky |= (glimb(sl, nl, topmask, full) & ((1ull << rr) - 1)) != 0;
+        if (sticky || (col[0] & 1u)) {
+            for (int w = 0; w < nw32; ++w) {
+                const uint32_t v = col[w * st] + 1u;
+                col[w * st] = v;
+                if (v) break;
+            }
+            nz = 1;
+        }
+    }
+    return nz ? s : 0;
+}
+
+// Residues of a^ (stage 2).  One thread per entry (r, k) of a rows x count
+// operand side; a block covers 64 consecutive k of RB rows, so a wave stores
+// 64 contiguous int8 per plane.  The integer a^ of the entry is built once into
+// an LDS column of 32-bit words; the moduli are then swept in groups of 8 with
+// fp64 FMAs against centred 2^(32 w) mod m weights (every partial sum is an
+// exact integer below 2^53), read with wave-uniform scalar loads.  Reduction:
+// r = a - rint(a/m) m (the rint quotient is off by at most one, so one
+// correction step gives the canonical centred residue in [-floor(m/2), (m-1)/2]),
+// and for two-limb moduli the balanced base-128 split r = r0 + 128 r1.
 template <int RB>
 __global__ __launch_bounds__(64 * RB) void k_residues(
     const uint64_t *__restrict__ limbs, const int32_t *__restrict__ exps,
@@ -126,54 +186,26 @@ __global__ __launch_bounds__(64 * RB) void k_residues(
     const int64_t k = (int64_t)blockIdx.x * 64 + (tid & 63);
     const int64_t r = (int64_t)blockIdx.y * RB + (tid >> 6);
 
+    uint32_t *col = words + tid;
     int s = 0;
+    int64_t sh = 0, idx = 0;
     if (r < rows && k < count) {
-        const int64_t idx = r * rs + k * cs;
+        idx = r * rs + k * cs;
         s = signs[idx];
-        if (s != 0) {
-            const uint64_t *base = limbs + idx * nl;
-            const int topbits = p - 64 * (nl - 1);
-            const uint64_t topmask = topbits >= 64 ? ~0ull : ((1ull << topbits) - 1);
-            // a * 2^(t - e) = sign * mant * 2^sh, sh <= t - p  (Eq. 1)
-            const int64_t sh = (int64_t)t - p + exps[idx] - erow[r];
-            if (sh >= 0) {
-                for (int w = 0; w < nw32; ++w)
-                    words[w * BD + tid] = mant_bits32(base, nl, topmask, 32 * (int64_t)w - sh);
-            } else {
-                const int64_t rsh = -sh;   // round to nearest even on the dropped bits
-                uint32_t nz = 0;
-                for (int w = 0; w < nw32; ++w) {
-                    const uint32_t v = mant_bits32(base, nl, topmask, 32 * (int64_t)w + rsh);
-                    words[w * BD + tid] = v;
-                    nz |= v;
-                }
-                const int rb = mant_bit(base, nl, topmask, rsh - 1);
-                if (rb) {
-                    const int st = mant_any_below(base, nl, topmask, rsh - 1);
-                    if (st || (words[tid] & 1u)) {
-                        for (int w = 0; w < nw32; ++w) {
-                            const uint32_t v = words[w * BD + tid] + 1u;
-                            words[w * BD + tid] = v;
-                            if (v) break;
-                        }
-                        nz = 1;
-                    }
-                }
-                if (!nz) s = 0;
-            }
-        }
+        sh = (int64_t)t - p + exps[idx] - erow[r];
     }
+    s = build_words(limbs + idx * nl, s, sh, p, nl, nw32, col, BD);
     if (s == 0)
-        for (int w = 0; w < nw32; ++w) words[w * BD + tid] = 0;
+        for (int w = 0; w < nw32; ++w) col[w * BD] = 0;
 
     int8_t *out = planes + r * kpad + k;
     for (int grp = 0; grp < lgroups; ++grp) {
         double acc[kModGroup];
 #pragma unroll
         for (int g = 0; g < kModGroup; ++g) acc[g] = 0.0;
-        const double *c = tab + (size_t)grp * nw32 * kModGroup;
+        const double *c = tab + (size_t)grp * nw32 * kModGroup;   // uniform: scalar loads
         for (int w = 0; w < nw32; ++w) {
-            const double x = (double)words[w * BD + tid];
+            const double x = (double)col[w * BD];
 #pragma unroll
             for (int g = 0; g < kModGroup; ++g) acc[g] = fma(x, c[w * kModGroup + g], acc[g]);
         }
@@ -182,17 +214,15 @@ __global__ __launch_bounds__(64 * RB) void k_residues(
             const int l = grp * kModGroup + g;
             if (l >= L) break;
             const ModInfo info = mi[l];
+            const int hi = (int)((info.m - 1) >> 1);
             const double a = s < 0 ? -acc[g] : acc[g];
-            const double md = (double)info.m;
-            const double q = rint(a * info.inv_m);
-            int ri = (int)fma(-q, md, a);
-            const int hi = (int)((info.m - 1) >> 1), lo = -(int)(info.m >> 1);
+            int ri = (int)fma(-rint(a * info.inv_m), (double)info.m, a);
             if (ri > hi) ri -= (int)info.m;
-            else if (ri < lo) ri += (int)info.m;
             int8_t *o = out + (int64_t)info.g0 * plane_stride;
             if (info.nprod == 1) {
                 o[0] = (int8_t)ri;
             } else {
+                if (ri < -hi) ri += (int)info.m;
                 const int r0 = ((ri + 64) & 127) - 64;   // balanced base-128 split
                 const int r1 = (ri - r0) >> 7;
                 o[0] = (int8_t)r0;
@@ -388,167 +418,273 @@ __device__ __forceinline__ uint32_t dig_bits32(const uint32_t *__restrict__ sd, 
     return (uint32_t)(((hi << 32) | lo) >> r);
 }
 
-// One thread per output entry.  Pass c accumulates digits [c*DC, (c+1)*DC) of
-// S = sum_l v_l M_l over all moduli (centred v_l, balanced digits of M_l, so
-// each column sum is an exact fp64 integer), pass 0 also forms alpha =
-// floor(sum v_l / m_l) in binary64; R = S - (alpha - 1) P is carried into
-// 32-bit digits in an LDS column.  Then at most two subtractions of P give x0,
-// the lift compares with floor(P/2), and (ROUND) the magnitude is rounded once
-// to p bits with its scale 2^(e_i + f_j - 2t).  The input planes hold
-// v_l = u_l (P/m_l)^-1 mod m_l as centred int16 (the residue GEMM applies the
-// weight); WEIGHT = true takes plain residues u_l and applies it here.
-template <int DC, bool ROUND, bool WEIGHT>
-__global__ void k_crt(const int16_t *__restrict__ V, int64_t v_ps, int64_t ldv, int64_t M,
-                      int64_t N, const ModInfo *__restrict__ mi, int L,
-                      const double *__restrict__ dig, int ndpad, int nc, int nd32,
-                      const uint32_t *__restrict__ Pd, const uint32_t *__restrict__ Phd,
-                      const int32_t *__restrict__ erow, const int32_t *__restrict__ fcol, int t,
-                      int p, int8_t *__restrict__ osign, int32_t *__restrict__ oexp,
-                      uint64_t *__restrict__ olimbs, int64_t ldc, uint64_t *__restrict__ chat_mag,
-                      int nlc) {
-    extern __shared__ uint32_t sdig[];
-    const int tid = threadIdx.x, bd = blockDim.x;
-    const int64_t idx = (int64_t)blockIdx.x * bd + tid;
-    if (idx >= M * N) return;
-    const int64_t i = idx / N, j = idx - i * N;
-    const int16_t *vp = V + i * ldv + j;
-    uint32_t *sd = sdig + tid;
-
-    int64_t beta = 0, carry = 0;
-    for (int c = 0; c < nc; ++c) {
-        double acc[DC];
-#pragma unroll
-        for (int d = 0; d < DC; ++d) acc[d] = 0.0;
-        double asum = 0.0;
-        const double *dc = dig + c * DC;
-        auto step = [&](int l, int raw) {
-            const ModInfo info = mi[l];
-            double vd;
-            if (WEIGHT) vd = (double)centred_mod((double)raw * (double)info.minv, (double)info.m, info.inv_m);
-            else vd = (double)raw;
-            if (c == 0) asum = fma(vd, info.inv_m, asum);
-            const double *dl = dc + (size_t)l * ndpad;
-#pragma unroll
-            for (int d = 0; d < DC; ++d) acc[d] = fma(vd, dl[d], acc[d]);
-        };
-        int l = 0;
-        for (; l + 8 <= L; l += 8) {   // eight loads in flight before their use
-            int raw[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) raw[q] = vp[(int64_t)(l + q) * v_ps];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) step(l + q, raw[q]);
-        }
-        for (; l < L; ++l) step(l, vp[(int64_t)l * v_ps]);
-        if (c == 0) beta = (int64_t)floor(asum) - 1;   // alpha - 1
-#pragma unroll
-        for (int d = 0; d < DC; ++d) {
-            const int k = c * DC + d;
-            if (k < nd32) {
-                const int64_t x = (int64_t)acc[d] - beta * (int64_t)Pd[k] + carry;
-                sd[k * bd] = (uint32_t)x;
-                carry = x >> 32;
-            }
-        }
-    }
-
-    // R in [0, 3P): at most two subtractions of P
-    for (int rep = 0; rep < 2; ++rep) {
-        int64_t br = 0;
-        for (int k = 0; k < nd32; ++k) {
-            const int64_t d = (int64_t)sd[k * bd] - (int64_t)Pd[k] - br;
-            br = d < 0;
-        }
-        if (br) break;
-        br = 0;
-        for (int k = 0; k < nd32; ++k) {
-            const int64_t d = (int64_t)sd[k * bd] - (int64_t)Pd[k] - br;
-            sd[k * bd] = (uint32_t)d;
-            br = d < 0;
-        }
-    }
-    // symmetric lift: x0 > floor(P/2) means c^ = x0 - P < 0
+// multi-digit helpers on an LDS digit column (stride `st` words between digits)
+__device__ __forceinline__ bool dig_ge(const uint32_t *sd, int st, const uint32_t *__restrict__ Q,
+                                       int nd) {   // column >= Q ?
     int64_t br = 0;
-    for (int k = 0; k < nd32; ++k) {
-        const int64_t d = (int64_t)Phd[k] - (int64_t)sd[k * bd] - br;
+    for (int k = 0; k < nd; ++k) br = ((int64_t)sd[k * st] - (int64_t)Q[k] - br) < 0;
+    return br == 0;
+}
+__device__ __forceinline__ void dig_sub(uint32_t *sd, int st, const uint32_t *__restrict__ Q,
+                                        int nd) {   // column -= Q
+    int64_t br = 0;
+    for (int k = 0; k < nd; ++k) {
+        const int64_t d = (int64_t)sd[k * st] - (int64_t)Q[k] - br;
+        sd[k * st] = (uint32_t)d;
         br = d < 0;
     }
-    const bool neg = br != 0;
-    if (neg) {
-        br = 0;
-        for (int k = 0; k < nd32; ++k) {
-            const int64_t d = (int64_t)Pd[k] - (int64_t)sd[k * bd] - br;
-            sd[k * bd] = (uint32_t)d;
-            br = d < 0;
-        }
+}
+__device__ __forceinline__ void dig_rsub(uint32_t *sd, int st, const uint32_t *__restrict__ Q,
+                                         int nd) {   // column = Q - column
+    int64_t br = 0;
+    for (int k = 0; k < nd; ++k) {
+        const int64_t d = (int64_t)Q[k] - (int64_t)sd[k * st] - br;
+        sd[k * st] = (uint32_t)d;
+        br = d < 0;
     }
-    int top = nd32 - 1;
-    while (top >= 0 && sd[top * bd] == 0) --top;
+}
+__device__ __forceinline__ void dig_add(uint32_t *sd, int st, const uint32_t *__restrict__ Q,
+                                        int nd) {   // column += Q (mod 2^(32 nd))
+    uint64_t cy = 0;
+    for (int k = 0; k < nd; ++k) {
+        const uint64_t d = (uint64_t)sd[k * st] + Q[k] + cy;
+        sd[k * st] = (uint32_t)d;
+        cy = d >> 32;
+    }
+}
+__device__ __forceinline__ void dig_neg(uint32_t *sd, int st, int nd) {   // two's complement
+    uint64_t cy = 1;
+    for (int k = 0; k < nd; ++k) {
+        const uint64_t d = (uint64_t)(uint32_t)~sd[k * st] + cy;
+        sd[k * st] = (uint32_t)d;
+        cy = d >> 32;
+    }
+}
 
-    if (!ROUND) {
-        uint64_t *o = chat_mag + idx * nlc;
-        for (int l = 0; l < nlc; ++l) {
-            const uint64_t lo = (2 * l < nd32) ? sd[2 * l * bd] : 0u;
-            const uint64_t hi = (2 * l + 1 < nd32) ? sd[(2 * l + 1) * bd] : 0u;
-            o[l] = lo | (hi << 32);
+// Direct CRT (subsection "Direct CRT without multiple-precision division").
+// Each thread reconstructs EPT output entries (entries tid + q*blockDim of the
+// block's range, so every load is coalesced).  Pass c accumulates digits
+// [c*DC, (c+1)*DC) of S = sum_l v_l M_l over all moduli: v_l centred, M_l in
+// balanced base-2^32 digits, so each column sum is an exact fp64 integer and
+// the DC digit constants of modulus l are shared by the EPT entries.  Pass 0
+// also forms sum_l v_l / m_l in binary64, an estimate of S/P = n + c^/P.
+// Since |c^| < P/2, the nearest integer beta of that estimate is n unless the
+// estimate lies within 2^-30 of a half-integer (never, when the CRT margin is
+// at least 2, because then |c^| < P/4); in that case c^ = S - beta P comes out
+// of one signed carry pass, already lifted.  Otherwise the paper's sequence is
+// used: R = S - (alpha - 1) P with alpha = floor(estimate), R in [0, 3P), at
+// most two subtractions of P, and the symmetric lift against floor(P/2).
+// The magnitude digits sit in an LDS column; (ROUND) they are rounded once,
+// nearest-even, to p bits with the scale 2^(e_i + f_j - 2t).
+// The planes hold v_l = u_l (P/m_l)^-1 mod m_l as centred int16 (the residue
+// GEMM applies the weight); WEIGHT = true takes plain residues u_l instead.
+// The digit constants of a block of LB moduli (and their 1/m_l) are staged in
+// LDS and read with wave-uniform addresses (broadcast), two per ds_read_b128.
+template <int DC, int EPT, bool ROUND, bool WEIGHT>
+__global__ __launch_bounds__(256) void k_crt(
+    const int16_t *__restrict__ V, int64_t v_ps, int64_t ldv, int64_t M, int64_t N,
+    const ModInfo *__restrict__ mi, int L, const double *__restrict__ dig, int ndpad, int nc,
+    int nd32, const uint32_t *__restrict__ Pd, const uint32_t *__restrict__ Phd,
+    const int32_t *__restrict__ erow, const int32_t *__restrict__ fcol, int t, int p,
+    int8_t *__restrict__ osign, int32_t *__restrict__ oexp, uint64_t *__restrict__ olimbs,
+    int64_t ldc, uint64_t *__restrict__ chat_mag, int nlc, int LB) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t sdig[];
+    const int tid = threadIdx.x, bd = blockDim.x, st = bd * EPT;
+    double *stab = (double *)(sdig + (((size_t)nd32 * st + 3) & ~(size_t)3));   // LB x DC digits
+    double *sinv = stab + (size_t)LB * DC;                                      // LB x 1/m
+    const int64_t MN = M * N;
+    int64_t idx[EPT];
+    const int16_t *vp[EPT];
+    bool live[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        idx[q] = (int64_t)blockIdx.x * st + q * bd + tid;
+        live[q] = idx[q] < MN;
+        // a dead lane reads entry 0 (always valid) and writes nothing: no branch around loads
+        const int64_t ii = live[q] ? idx[q] / N : 0, jj = live[q] ? idx[q] - ii * N : 0;
+        vp[q] = V + ii * ldv + jj;
+    }
+
+    int64_t beta[EPT], carry[EPT];
+    bool slow[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        beta[q] = 0;
+        carry[q] = 0;
+        slow[q] = false;
+    }
+    for (int c = 0; c < nc; ++c) {
+        double acc[EPT][DC], asum[EPT];
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            asum[q] = 0.0;
+#pragma unroll
+            for (int d = 0; d < DC; ++d) acc[q][d] = 0.0;
         }
-        osign[idx] = top < 0 ? 0 : (neg ? -1 : 1);
-        return;
+        const double *dc = dig + c * DC;
+        for (int l0 = 0; l0 < L; l0 += LB) {
+            const int nlb = min(LB, L - l0);
+            __syncthreads();   // the previous slice has been consumed by every thread
+            for (int e = tid; e < nlb * DC; e += bd) {
+                const int ll = e / DC, d = e - ll * DC;
+                stab[e] = dc[(size_t)(l0 + ll) * ndpad + d];
+            }
+            for (int e = tid; e < nlb; e += bd) sinv[e] = mi[l0 + e].inv_m;
+            __syncthreads();
+            // v_l of the next PF moduli are loaded ahead (unconditional, clamped at the end)
+            constexpr int PF = 4;
+            int ring[PF][EPT];
+#pragma unroll
+            for (int f = 0; f < PF; ++f)
+#pragma unroll
+                for (int q = 0; q < EPT; ++q) ring[f][q] = vp[q][(int64_t)(l0 + min(f, nlb - 1)) * v_ps];
+            for (int lb = 0; lb < nlb; lb += PF) {
+#pragma unroll
+            for (int f = 0; f < PF; ++f) {
+                const int ll = lb + f;
+                if (ll >= nlb) break;
+                const int l = l0 + ll;
+                const double inv_m = sinv[ll];
+                int cur[EPT];
+#pragma unroll
+                for (int q = 0; q < EPT; ++q) {
+                    cur[q] = ring[f][q];
+                    ring[f][q] = vp[q][(int64_t)(l0 + min(ll + PF, nlb - 1)) * v_ps];
+                }
+                double vd[EPT];
+#pragma unroll
+                for (int q = 0; q < EPT; ++q) {
+                    const int raw = cur[q];
+                    if (WEIGHT) {
+                        const ModInfo info = mi[l];
+                        vd[q] = (double)centred_mod((double)raw * (double)info.minv, (double)info.m, inv_m);
+                    } else {
+                        vd[q] = (double)raw;
+                    }
+                    if (c == 0) asum[q] = fma(vd[q], inv_m, asum[q]);
+                }
+                const double *dl = stab + (size_t)ll * DC;
+#pragma unroll
+                for (int d = 0; d < DC; d += 2) {
+                    const double2 w = *(const double2 *)(dl + d);
+#pragma unroll
+                    for (int q = 0; q < EPT; ++q) {
+                        acc[q][d] = fma(vd[q], w.x, acc[q][d]);
+                        acc[q][d + 1] = fma(vd[q], w.y, acc[q][d + 1]);
+                    }
+                }
+            }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            if (c == 0) {
+                const double r = rint(asum[q]);
+                slow[q] = fabs(asum[q] - r) > 0.5 - 0x1p-30;
+                beta[q] = slow[q] ? (int64_t)floor(asum[q]) - 1 : (int64_t)r;   // alpha - 1 when slow
+            }
+            uint32_t *sd = sdig + q * bd + tid;
+#pragma unroll
+            for (int d = 0; d < DC; ++d) {
+                const int k = c * DC + d;
+                if (k < nd32) {
+                    const int64_t x = (int64_t)acc[q][d] - beta[q] * (int64_t)Pd[k] + carry[q];
+                    sd[k * st] = (uint32_t)x;
+                    carry[q] = x >> 32;
+                }
+            }
+        }
     }
 
     const int nl = (p + 63) / 64;
-    const int64_t oi = i * ldc + j;
-    uint64_t *o = olimbs + oi * nl;
-    if (top < 0) {
-        for (int l = 0; l < nl; ++l) o[l] = 0;
-        osign[oi] = 0;
-        oexp[oi] = 0;
-        return;
-    }
-    int64_t nb = 32 * (int64_t)top + (32 - __builtin_clz(sd[top * bd]));
-    const int64_t sh = nb - p;   // mant = RNE(mag / 2^sh)
-    bool inc = false;
-    if (sh > 0) {
-        const int64_t rpos = sh - 1;
-        const int rb = (int)((sd[(rpos >> 5) * bd] >> (rpos & 31)) & 1u);
-        if (rb) {
-            bool st = false;
-            const int64_t full = rpos >> 5;
-            for (int64_t k = 0; k < full && !st; ++k) st = sd[k * bd] != 0;
-            const int rr = (int)(rpos & 31);
-            if (!st && rr) st = (sd[full * bd] & ((1u << rr) - 1)) != 0;
-            const uint32_t lsb = dig_bits32(sd, bd, nd32, sh) & 1u;
-            inc = st || lsb;
-        }
-    }
-    bool allones = inc;
-    if (inc) {   // mant = 2^p - 1 rounds up to 2^p: renormalise
-        for (int l = 0; l < nl && allones; ++l) {
-            const uint64_t v = (uint64_t)dig_bits32(sd, bd, nd32, 64 * (int64_t)l + sh) |
-                               ((uint64_t)dig_bits32(sd, bd, nd32, 64 * (int64_t)l + 32 + sh) << 32);
-            const int bits = (l == nl - 1) ? p - 64 * (nl - 1) : 64;
-            const uint64_t mask = bits >= 64 ? ~0ull : ((1ull << bits) - 1);
-            allones = v == mask;
-        }
-    }
-    if (allones) {
-        for (int l = 0; l < nl; ++l) o[l] = 0;
-        o[(p - 1) >> 6] = 1ull << ((p - 1) & 63);
-        nb += 1;
-    } else {
-        bool cy = inc;
-        for (int l = 0; l < nl; ++l) {
-            uint64_t v = (uint64_t)dig_bits32(sd, bd, nd32, 64 * (int64_t)l + sh) |
-                         ((uint64_t)dig_bits32(sd, bd, nd32, 64 * (int64_t)l + 32 + sh) << 32);
-            if (cy) {
-                v += 1;
-                cy = v == 0;
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        if (!live[q]) continue;
+        uint32_t *sd = sdig + q * bd + tid;
+        bool neg;
+        if (!slow[q]) {
+            neg = carry[q] < 0;   // two's complement c^ over nd32 digits
+            if (neg) dig_neg(sd, st, nd32);
+        } else {
+            // R in [0, 3P): at most two subtractions of P, then the symmetric lift
+            if (dig_ge(sd, st, Pd, nd32)) dig_sub(sd, st, Pd, nd32);
+            if (dig_ge(sd, st, Pd, nd32)) dig_sub(sd, st, Pd, nd32);
+            neg = !dig_ge(sd, st, Phd, nd32) ? false : true;   // x0 >= floor(P/2) ...
+            if (neg) {                                         // ... and x0 != floor(P/2)
+                dig_sub(sd, st, Phd, nd32);
+                bool eq = true;
+                for (int k = 0; k < nd32 && eq; ++k) eq = sd[k * st] == 0;
+                dig_add(sd, st, Phd, nd32);
+                neg = !eq;
             }
-            o[l] = v;
+            if (neg) dig_rsub(sd, st, Pd, nd32);   // |c^| = P - x0
         }
+        int top = nd32 - 1;
+        while (top >= 0 && sd[top * st] == 0) --top;
+        const int64_t i = idx[q] / N, j = idx[q] - i * N;
+
+        if (!ROUND) {
+            uint64_t *o = chat_mag + idx[q] * nlc;
+            for (int w = 0; w < nlc; ++w) {
+                const uint64_t lo = (2 * w < nd32) ? sd[2 * w * st] : 0u;
+                const uint64_t hi = (2 * w + 1 < nd32) ? sd[(2 * w + 1) * st] : 0u;
+                o[w] = lo | (hi << 32);
+            }
+            osign[idx[q]] = top < 0 ? 0 : (neg ? -1 : 1);
+            continue;
+        }
+        const int64_t oi = i * ldc + j;
+        uint64_t *o = olimbs + oi * nl;
+        if (top < 0) {
+            for (int w = 0; w < nl; ++w) o[w] = 0;
+            osign[oi] = 0;
+            oexp[oi] = 0;
+            continue;
+        }
+        int64_t nb = 32 * (int64_t)top + (32 - __builtin_clz(sd[top * st]));
+        const int64_t sh = nb - p;   // mant = RNE(mag / 2^sh)
+        bool inc = false;
+        if (sh > 0) {
+            const int64_t rpos = sh - 1;
+            const int rbit = (int)((sd[(rpos >> 5) * st] >> (rpos & 31)) & 1u);
+            if (rbit) {
+                bool sticky = false;
+                const int64_t full = rpos >> 5;
+                for (int64_t k = 0; k < full && !sticky; ++k) sticky = sd[k * st] != 0;
+                const int rr = (int)(rpos & 31);
+                if (!sticky && rr) sticky = (sd[full * st] & ((1u << rr) - 1)) != 0;
+                inc = sticky || (dig_bits32(sd, st, nd32, sh) & 1u);
+            }
+        }
+        bool allones = inc;
+        if (inc) {   // mant = 2^p - 1 rounds up to 2^p: renormalise
+            for (int w = 0; w < nl && allones; ++w) {
+                const uint64_t v = (uint64_t)dig_bits32(sd, st, nd32, 64 * (int64_t)w + sh) |
+                                   ((uint64_t)dig_bits32(sd, st, nd32, 64 * (int64_t)w + 32 + sh) << 32);
+                const int bits = (w == nl - 1) ? p - 64 * (nl - 1) : 64;
+                const uint64_t mask = bits >= 64 ? ~0ull : ((1ull << bits) - 1);
+                allones = v == mask;
+            }
+        }
+        if (allones) {
+            for (int w = 0; w < nl; ++w) o[w] = 0;
+            o[(p - 1) >> 6] = 1ull << ((p - 1) & 63);
+            nb += 1;
+        } else {
+            bool cy = inc;
+            for (int w = 0; w < nl; ++w) {
+                uint64_t v = (uint64_t)dig_bits32(sd, st, nd32, 64 * (int64_t)w + sh) |
+                             ((uint64_t)dig_bits32(sd, st, nd32, 64 * (int64_t)w + 32 + sh) << 32);
+                if (cy) {
+                    v += 1;
+                    cy = v == 0;
+                }
+                o[w] = v;
+            }
+        }
+        osign[oi] = neg ? -1 : 1;
+        oexp[oi] = (int32_t)(nb + (int64_t)erow[i] + fcol[j] - 2 * (int64_t)t);
     }
-    osign[oi] = neg ? -1 : 1;
-    oexp[oi] = (int32_t)(nb + (int64_t)erow[i] + fcol[j] - 2 * (int64_t)t);
 }
 
 // zero output for K = 0
