@@ -252,6 +252,66 @@ int oz2h_crt(const oz2h_plan *plan, int64_t M, int64_t N, const int16_t *u, int6
              int64_t plane_stride, int8_t *chat_sign, uint64_t *chat_mag, int32_t nlc,
              hipStream_t stream);
 
+/* ---------------- batched form ---------------- */
+
+/* One product of a batch: C = op(A) op(B) at precision p (device pointers). */
+typedef struct {
+    int64_t M, N, K;   /* op(A) is M x K, op(B) K x N; all >= 1, K <= 133000 */
+    int32_t p;         /* significand bits of this product's A, B and C */
+    int32_t opA, opB;  /* oz2h_op */
+    oz2h_cmat A, B;
+    oz2h_mat C;
+} oz2h_problem;
+
+typedef struct oz2h_batched_plan oz2h_batched_plan;
+
+/*
+ * Plan for `count` independent products (1 <= count <= 65535) of uneven
+ * M, N, K and p.  Each product gets its own moduli set (the prefix of the list
+ * of oz2h_plan_moduli that its p and K need) and constant tables, uploaded to
+ * the current device now.  The pointers in `probs` are captured: the plan
+ * always reads those inputs and writes those outputs.  A run executes, for all
+ * products at once, one grouped launch per stage (shared exponents, residues,
+ * and the CRT/rounding, the latter one launch per digit-chunk class) and the
+ * residue GEMMs of all products and moduli as ONE persistent grouped launch
+ * over a cost-sorted list of (product, modulus, output tile) work items.
+ * o->tile fixes the block tile; OZ2H_TILE_AUTO takes a previously tuned
+ * configuration for the same shapes if the process has one (see
+ * oz2h_batched_tune), else 128 x 128 with 2 blocks per compute unit.
+ */
+int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2h_opts *o,
+                             oz2h_batched_plan **out);
+/* Device workspace bytes a run needs (256-byte aligned, contents scratch). */
+size_t oz2h_batched_workspace_size(const oz2h_batched_plan *plan);
+/*
+ * Autotuner: runs stages 1-2 once, then times the grouped GEMM for every
+ * block tile (128x128, 256x128, 128x256) and every persistent schedule (1, 2
+ * or 4 resident blocks per compute unit), keeps the fastest and records it in
+ * an in-process cache keyed by the batch's shapes (and, if the environment
+ * variable OZ2H_TUNE_CACHE names a file, appends it there; plans created later
+ * with OZ2H_TILE_AUTO pick it up).  Synchronizes `stream`; the outputs C are
+ * not written.
+ */
+int oz2h_batched_tune(oz2h_batched_plan *plan, void *workspace, size_t ws_bytes,
+                      hipStream_t stream);
+/*
+ * Runs the whole batch as a HIP graph: the launch sequence is captured on a
+ * private stream at the first call (and again whenever the workspace pointer or
+ * the configuration changes) and replayed on `stream`.  Asynchronous.
+ * Runs of one plan must not overlap (they share the workspace and outputs).
+ */
+int oz2h_batched_run(oz2h_batched_plan *plan, void *workspace, size_t ws_bytes,
+                     hipStream_t stream);
+/* The same launches issued directly on `stream` (no graph). */
+int oz2h_batched_run_eager(oz2h_batched_plan *plan, void *workspace, size_t ws_bytes,
+                           hipStream_t stream);
+/* Current block tile (oz2h_tile), resident blocks per compute unit, GEMM work items. */
+int oz2h_batched_get_config(const oz2h_batched_plan *plan, int32_t *tile, int32_t *blocks_per_cu,
+                            int64_t *gemm_items);
+/* Sets the tile (1..3) and blocks per compute unit (1..16) by hand. */
+int oz2h_batched_set_config(oz2h_batched_plan *plan, int32_t tile, int32_t blocks_per_cu);
+void oz2h_batched_plan_destroy(oz2h_batched_plan *plan);
+
 #ifdef __cplusplus
 }
 #endif

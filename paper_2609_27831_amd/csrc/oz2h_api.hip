@@ -9,7 +9,15 @@
 #include <string>
 #include <vector>
 
+#include <algorithm>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <sstream>
+
 #include "oz2h.h"
+#include "oz2h_batched.hpp"
 #include "oz2h_kernels.hpp"
 #include "oz2h_plan.hpp"
 
@@ -163,14 +171,11 @@ int launch_residues(const oz2h_plan *pl, int64_t rows, int64_t count, const uint
     int rb = h.nw32 <= 64 ? 4 : (h.nw32 <= 128 ? 2 : 1);   // word columns <= 64 KiB per block
     dim3 grid((unsigned)(kpad / 64), (unsigned)(rpad / rb));
     const size_t lds = (size_t)h.nw32 * 64 * rb * sizeof(uint32_t);
-#define OZ2H_RES(RB)                                                                       \
-    k_residues<RB><<<grid, 64 * RB, lds, s>>>(limbs, exp, sign, rs, cs, rows, count, kpad, \
-                                               ps, erow, h.p, nl, h.t, h.nw32, pl->d_resid, \
-                                               pl->d_info, h.L, h.lgroups, planes)
-    if (rb == 4) OZ2H_RES(4);
-    else if (rb == 2) OZ2H_RES(2);
-    else OZ2H_RES(1);
-#undef OZ2H_RES
+    const ResArgs a{limbs, exp, sign, rs, cs, rows, count, kpad, ps, erow, h.p, nl, h.t, h.nw32,
+                    pl->d_resid, pl->d_info, h.L, h.lgroups, planes};
+    if (rb == 4) k_residues<4><<<grid, 256, lds, s>>>(a);
+    else if (rb == 2) k_residues<2><<<grid, 128, lds, s>>>(a);
+    else k_residues<1><<<grid, 64, lds, s>>>(a);
     return check_launch("residues");
 }
 
@@ -178,12 +183,10 @@ template <bool RAW>
 int launch_gemm_kernel(GemmCfg cfg, dim3 grid, const int8_t *a, const int8_t *b, int64_t kpad,
                        int64_t a_ps, int64_t b_ps, const ModInfo *mi, int L, int16_t *v,
                        int64_t v_ps, int64_t ldv, int32_t *craw, hipStream_t s) {
-    if (cfg.bm == 256 && cfg.bn == 128)
-        k_resgemm<128, 64, RAW><<<grid, 256, 0, s>>>(a, b, kpad, a_ps, b_ps, mi, L, v, v_ps, ldv, craw);
-    else if (cfg.bm == 128 && cfg.bn == 256)
-        k_resgemm<64, 128, RAW><<<grid, 256, 0, s>>>(a, b, kpad, a_ps, b_ps, mi, L, v, v_ps, ldv, craw);
-    else
-        k_resgemm<64, 64, RAW><<<grid, 256, 0, s>>>(a, b, kpad, a_ps, b_ps, mi, L, v, v_ps, ldv, craw);
+    const GemmArgs g{a, b, kpad, a_ps, b_ps, mi, v, v_ps, ldv, craw};
+    if (cfg.bm == 256 && cfg.bn == 128) k_resgemm<128, 64, RAW><<<grid, 256, 0, s>>>(g, L);
+    else if (cfg.bm == 128 && cfg.bn == 256) k_resgemm<64, 128, RAW><<<grid, 256, 0, s>>>(g, L);
+    else k_resgemm<64, 64, RAW><<<grid, 256, 0, s>>>(g, L);
     return check_launch("residue GEMM");
 }
 
@@ -210,10 +213,9 @@ int launch_crt(const oz2h_plan *pl, int64_t M, int64_t N, const int16_t *u, int6
     const int LB = std::max(1, std::min(h.L, (int)((65536 - cols) / (sizeof(double) * (h.crt_dc + 1)))));
     const size_t lds = cols + (size_t)LB * (h.crt_dc + 1) * sizeof(double);
     const unsigned nb = (unsigned)((M * N + (int64_t)bd * ept - 1) / ((int64_t)bd * ept));
-#define OZ2H_CRT(DC, E, R, W)                                                                   \
-    k_crt<DC, E, R, W><<<nb, bd, lds, s>>>(u, u_ps, ldu, M, N, pl->d_info, h.L, pl->d_crt,      \
-                                           h.crt_ndpad, h.crt_nc, h.nd32, pl->d_pd, pl->d_phd, \
-                                           e, f, h.t, h.p, osign, oexp, olimbs, ldc, chat, nlc, LB)
+    const CrtArgs ca{u, u_ps, ldu, M, N, pl->d_info, h.L, pl->d_crt, h.crt_ndpad, h.crt_nc, h.nd32,
+                     pl->d_pd, pl->d_phd, e, f, h.t, h.p, osign, oexp, olimbs, ldc, chat, nlc, LB};
+#define OZ2H_CRT(DC, E, R, W) k_crt<DC, E, R, W><<<nb, bd, lds, s>>>(ca)
 #define OZ2H_CRT_E(DC, R, W)          \
     if (ept == 2) OZ2H_CRT(DC, 2, R, W); \
     else OZ2H_CRT(DC, 1, R, W);
@@ -605,6 +607,552 @@ int oz2h_crt(const oz2h_plan *plan, int64_t M, int64_t N, const int16_t *u, int6
     st = launch_crt(plan, M, N, u, plane_stride, ldu, nullptr, nullptr, false, true, chat_sign,
                     nullptr, nullptr, N, chat_mag, nlc, stream);
     return st ? st : ok();
+}
+
+}  // extern "C"
+
+// ====================================================================== batched form
+
+struct oz2h_batched_plan {
+    int count = 0;
+    int device = -1;
+    int ncu = 256;
+    std::vector<oz2h_problem> probs;
+    std::vector<PlanHost> hosts;
+    std::vector<ProbDev> pd;         // host copy of the descriptors
+    // device buffers: tables + descriptors + segment tables, one allocation
+    void *dbuf = nullptr;
+    ProbDev *d_probs = nullptr;
+    Seg *d_exp_segs = nullptr, *d_res_segs = nullptr;
+    int n_exp_segs = 0, n_res_segs = 0;
+    int64_t exp_blocks = 0, res_blocks = 0;
+    int res_rb = 4;
+    size_t res_lds = 0;
+    struct CrtClass {
+        int dc, ept, bd, LB;
+        size_t lds;
+        Seg *d_segs;
+        int nseg;
+        int64_t blocks;
+    };
+    std::vector<CrtClass> crt;
+    // grouped GEMM: work items for the current tile
+    int tile = OZ2H_TILE_128x128;
+    int bpc = 2;
+    GemmItem *d_items = nullptr;
+    int nitems = 0;
+    size_t ws_bytes = 0;
+    // graph
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void *cap_ws = nullptr;
+    uint64_t signature = 0;
+};
+
+namespace {
+
+uint64_t fnv1a(const void *data, size_t n, uint64_t h = 1469598103934665603ull) {
+    const unsigned char *c = (const unsigned char *)data;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= c[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+// autotuner cache: shape signature -> (tile, blocks per CU); optionally mirrored in the
+// text file named by OZ2H_TUNE_CACHE (one "signature tile bpc" line per entry)
+std::mutex g_tune_mu;
+std::map<uint64_t, std::pair<int, int>> g_tune;
+bool g_tune_loaded = false;
+
+void tune_load() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = getenv("OZ2H_TUNE_CACHE");
+    if (!path) return;
+    std::ifstream in(path);
+    uint64_t sig;
+    int tile, bpc;
+    while (in >> std::hex >> sig >> std::dec >> tile >> bpc) g_tune[sig] = {tile, bpc};
+}
+
+void tune_store(uint64_t sig, int tile, int bpc) {
+    g_tune[sig] = {tile, bpc};
+    const char *path = getenv("OZ2H_TUNE_CACHE");
+    if (!path) return;
+    std::ofstream out(path, std::ios::app);
+    out << std::hex << sig << std::dec << " " << tile << " " << bpc << "\n";
+}
+
+// work items of the grouped GEMM for a tile shape, heaviest first (two-limb moduli and
+// long contractions), then product, modulus and tile order for L2 locality
+std::vector<GemmItem> make_items(const oz2h_batched_plan *bp, GemmCfg cfg) {
+    struct Key {
+        int64_t cost;
+        GemmItem it;
+    };
+    std::vector<Key> keys;
+    for (int b = 0; b < bp->count; ++b) {
+        const PlanHost &h = bp->hosts[b];
+        const int64_t tm = (bp->probs[b].M + cfg.bm - 1) / cfg.bm;
+        const int64_t tn = (bp->probs[b].N + cfg.bn - 1) / cfg.bn;
+        for (int l = 0; l < h.L; ++l) {
+            const int64_t cost = (int64_t)h.info[l].nprod * bp->pd[b].kpad;
+            for (int64_t mt = 0; mt < tm; ++mt)
+                for (int64_t nt = 0; nt < tn; ++nt)
+                    keys.push_back({cost, GemmItem{(uint16_t)b, (uint16_t)l, (uint16_t)mt, (uint16_t)nt}});
+        }
+    }
+    std::stable_sort(keys.begin(), keys.end(), [](const Key &a, const Key &b) { return a.cost > b.cost; });
+    std::vector<GemmItem> out;
+    out.reserve(keys.size());
+    for (auto &k : keys) out.push_back(k.it);
+    return out;
+}
+
+int upload_items(oz2h_batched_plan *bp) {
+    std::vector<GemmItem> items = make_items(bp, tile_cfg(bp->tile));
+    if (bp->d_items) (void)hipFree(bp->d_items);
+    bp->d_items = nullptr;
+    bp->nitems = (int)items.size();
+    if (items.empty()) return OZ2H_OK;
+    if (hipMalloc(&bp->d_items, items.size() * sizeof(GemmItem)) != hipSuccess)
+        return fail(OZ2H_ENOMEM, "batched plan: item list allocation failed");
+    OZ2H_HIP(hipMemcpy(bp->d_items, items.data(), items.size() * sizeof(GemmItem), hipMemcpyHostToDevice));
+    return OZ2H_OK;
+}
+
+void drop_graph(oz2h_batched_plan *bp) {
+    if (bp->exec) (void)hipGraphExecDestroy(bp->exec);
+    if (bp->graph) (void)hipGraphDestroy(bp->graph);
+    bp->exec = nullptr;
+    bp->graph = nullptr;
+    bp->cap_ws = nullptr;
+}
+
+int launch_batched_gemm(oz2h_batched_plan *bp, char *ws, hipStream_t s) {
+    if (!bp->nitems) return OZ2H_OK;
+    const int grid = (int)std::min<int64_t>(bp->nitems, (int64_t)bp->ncu * bp->bpc);
+    switch (bp->tile) {
+        case OZ2H_TILE_256x128:
+            k_resgemm_grouped<128, 64><<<grid, 256, 0, s>>>(bp->d_probs, bp->d_items, bp->nitems, ws);
+            break;
+        case OZ2H_TILE_128x256:
+            k_resgemm_grouped<64, 128><<<grid, 256, 0, s>>>(bp->d_probs, bp->d_items, bp->nitems, ws);
+            break;
+        default:
+            k_resgemm_grouped<64, 64><<<grid, 256, 0, s>>>(bp->d_probs, bp->d_items, bp->nitems, ws);
+            break;
+    }
+    return check_launch("grouped residue GEMM");
+}
+
+// stages 1-2 (exponents, residues) for every product
+int launch_batched_front(oz2h_batched_plan *bp, char *ws, hipStream_t s) {
+    if (bp->exp_blocks)
+        k_exp_grouped<<<(unsigned)bp->exp_blocks, 256, 0, s>>>(bp->d_probs, bp->d_exp_segs, bp->n_exp_segs, ws);
+    int st = check_launch("grouped exponents");
+    if (st) return st;
+    if (bp->res_blocks) {
+        const unsigned nb = (unsigned)bp->res_blocks;
+        if (bp->res_rb == 4)
+            k_residues_grouped<4><<<nb, 256, bp->res_lds, s>>>(bp->d_probs, bp->d_res_segs, bp->n_res_segs, ws);
+        else if (bp->res_rb == 2)
+            k_residues_grouped<2><<<nb, 128, bp->res_lds, s>>>(bp->d_probs, bp->d_res_segs, bp->n_res_segs, ws);
+        else
+            k_residues_grouped<1><<<nb, 64, bp->res_lds, s>>>(bp->d_probs, bp->d_res_segs, bp->n_res_segs, ws);
+    }
+    return check_launch("grouped residues");
+}
+
+int launch_batched_crt(oz2h_batched_plan *bp, char *ws, hipStream_t s) {
+    for (auto &c : bp->crt) {
+        if (!c.blocks) continue;
+        const unsigned nb = (unsigned)c.blocks;
+#define OZ2H_GCRT(DC, E) k_crt_grouped<DC, E><<<nb, c.bd, c.lds, s>>>(bp->d_probs, c.d_segs, c.nseg, ws, c.LB)
+        if (c.ept == 2) {
+            switch (c.dc) {
+                case 8: OZ2H_GCRT(8, 2); break;
+                case 16: OZ2H_GCRT(16, 2); break;
+                case 24: OZ2H_GCRT(24, 2); break;
+                default: OZ2H_GCRT(32, 2); break;
+            }
+        } else {
+            switch (c.dc) {
+                case 8: OZ2H_GCRT(8, 1); break;
+                case 16: OZ2H_GCRT(16, 1); break;
+                case 24: OZ2H_GCRT(24, 1); break;
+                default: OZ2H_GCRT(32, 1); break;
+            }
+        }
+#undef OZ2H_GCRT
+        int st = check_launch("grouped CRT");
+        if (st) return st;
+    }
+    return OZ2H_OK;
+}
+
+int launch_batched_all(oz2h_batched_plan *bp, char *ws, hipStream_t s) {
+    int st = launch_batched_front(bp, ws, s);
+    if (!st) st = launch_batched_gemm(bp, ws, s);
+    if (!st) st = launch_batched_crt(bp, ws, s);
+    return st;
+}
+
+int check_batched_run(oz2h_batched_plan *bp, void *ws, size_t ws_bytes) {
+    if (!bp) return fail(OZ2H_EINVAL, "plan is NULL");
+    int dev = -1;
+    int st = check_device(&dev);
+    if (st) return st;
+    if (dev != bp->device) return fail(OZ2H_EINVAL, "batched plan belongs to device %d", bp->device);
+    if (!ws || ((uintptr_t)ws) % kAlign) return fail(OZ2H_EINVAL, "workspace NULL or not 256-byte aligned");
+    if (ws_bytes < bp->ws_bytes)
+        return fail(OZ2H_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, bp->ws_bytes);
+    return OZ2H_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2h_opts *o,
+                             oz2h_batched_plan **out) {
+    if (!out || !probs) return fail(OZ2H_EINVAL, "NULL pointer");
+    *out = nullptr;
+    if (count < 1 || count > 65535) return fail(OZ2H_EINVAL, "count must be in [1, 65535]");
+    oz2h_opts d;
+    oz2h_opts_default(&d);
+    if (!o) o = &d;
+    if (o->flags) return fail(OZ2H_EINVAL, "flags must be 0");
+    int dev = -1;
+    int st = check_device(&dev);
+    if (st) return st;
+    auto bp = std::make_unique<oz2h_batched_plan>();
+    bp->count = count;
+    bp->device = dev;
+    hipDeviceProp_t prop;
+    OZ2H_HIP(hipGetDeviceProperties(&prop, dev));
+    bp->ncu = prop.multiProcessorCount;
+    bp->probs.assign(probs, probs + count);
+    bp->hosts.resize(count);
+
+    // per-product moduli prefix and tables
+    for (int b = 0; b < count; ++b) {
+        const oz2h_problem &q = probs[b];
+        if (q.M < 1 || q.N < 1 || q.K < 1)
+            return fail(OZ2H_EINVAL, "problem %d: M, N, K must be >= 1", b);
+        if (q.M > 65535 * 128 || q.N > 65535 * 128)
+            return fail(OZ2H_ERANGE, "problem %d: M or N too large for the tile index", b);
+        if ((q.opA != OZ2H_OP_N && q.opA != OZ2H_OP_T) || (q.opB != OZ2H_OP_N && q.opB != OZ2H_OP_T))
+            return fail(OZ2H_EINVAL, "problem %d: bad op", b);
+        if ((st = check_cmat(q.A, "A", 0, q.opA == OZ2H_OP_N ? q.K : q.M))) return st;
+        if ((st = check_cmat(q.B, "B", 0, q.opB == OZ2H_OP_N ? q.N : q.K))) return st;
+        if (!q.C.limbs || !q.C.exp || !q.C.sign || q.C.ld < q.N)
+            return fail(OZ2H_EINVAL, "problem %d: bad C", b);
+        std::vector<uint32_t> mods;
+        int t = 0;
+        double lp = 0;
+        std::string err;
+        st = select_moduli(q.p, q.K, o->guard_bits, o->t_bits, o->crt_margin, mods, t, lp, err);
+        if (st) return fail(st, "problem %d: %s", b, err.c_str());
+        st = build_plan(q.p, t, q.K, mods, bp->hosts[b], err);
+        if (st) return fail(st, "problem %d: %s", b, err.c_str());
+    }
+
+    // device table layout
+    size_t off = 0;
+    std::vector<size_t> o_info(count), o_res(count), o_crt(count), o_pd(count), o_phd(count);
+    for (int b = 0; b < count; ++b) {
+        const PlanHost &h = bp->hosts[b];
+        o_info[b] = off;
+        off = align_up(off + sizeof(ModInfo) * h.L);
+        o_res[b] = off;
+        off = align_up(off + sizeof(double) * h.resid_tab.size());
+        o_crt[b] = off;
+        off = align_up(off + sizeof(double) * h.crt_digits.size());
+        o_pd[b] = off;
+        off = align_up(off + sizeof(uint32_t) * h.nd32);
+        o_phd[b] = off;
+        off = align_up(off + sizeof(uint32_t) * h.nd32);
+    }
+    const size_t o_probs = off;
+    off = align_up(off + sizeof(ProbDev) * count);
+
+    // workspace layout: rows padded to 256 (every tile shape divides them), k to 128
+    size_t w = 0;
+    bp->pd.resize(count);
+    for (int b = 0; b < count; ++b) {
+        const oz2h_problem &q = probs[b];
+        const PlanHost &h = bp->hosts[b];
+        ProbDev &P = bp->pd[b];
+        P = ProbDev{};
+        P.limbs[0] = q.A.limbs;
+        P.exps[0] = q.A.exp;
+        P.signs[0] = q.A.sign;
+        P.rs[0] = q.opA == OZ2H_OP_N ? q.A.ld : 1;
+        P.cs[0] = q.opA == OZ2H_OP_N ? 1 : q.A.ld;
+        P.limbs[1] = q.B.limbs;
+        P.exps[1] = q.B.exp;
+        P.signs[1] = q.B.sign;
+        P.rs[1] = q.opB == OZ2H_OP_N ? 1 : q.B.ld;
+        P.cs[1] = q.opB == OZ2H_OP_N ? q.B.ld : 1;
+        P.rows[0] = q.M;
+        P.rows[1] = q.N;
+        P.rpad[0] = round_up(q.M, 256);
+        P.rpad[1] = round_up(q.N, 256);
+        P.K = q.K;
+        P.kpad = round_up(q.K, GBK);
+        P.p = h.p;
+        P.nl = (h.p + 63) / 64;
+        P.t = h.t;
+        P.nw32 = h.nw32;
+        P.L = h.L;
+        P.lgroups = h.lgroups;
+        P.G = h.G;
+        P.nd32 = h.nd32;
+        P.crt_dc = h.crt_dc;
+        P.crt_nc = h.crt_nc;
+        P.crt_ndpad = h.crt_ndpad;
+        P.climbs = q.C.limbs;
+        P.cexp = q.C.exp;
+        P.csign = q.C.sign;
+        P.ldc = q.C.ld;
+        for (int sd = 0; sd < 2; ++sd) {
+            P.erow_off[sd] = w;
+            w = align_up(w + sizeof(int32_t) * P.rpad[sd]);
+        }
+        for (int sd = 0; sd < 2; ++sd) {
+            P.planes_off[sd] = w;
+            w = align_up(w + (size_t)h.G * P.rpad[sd] * P.kpad);
+        }
+        P.v_off = w;
+        w = align_up(w + sizeof(int16_t) * (size_t)h.L * P.rpad[0] * P.rpad[1]);
+    }
+    bp->ws_bytes = w;
+
+    // segment tables
+    std::vector<Seg> exp_segs, res_segs;
+    int maxw = 1;
+    for (int b = 0; b < count; ++b) maxw = std::max(maxw, bp->pd[b].nw32);
+    bp->res_rb = maxw <= 64 ? 4 : (maxw <= 128 ? 2 : 1);
+    bp->res_lds = (size_t)maxw * 64 * bp->res_rb * sizeof(uint32_t);
+    for (int b = 0; b < count; ++b)
+        for (int sd = 0; sd < 2; ++sd) {
+            const ProbDev &P = bp->pd[b];
+            const int64_t nbe = P.cs[sd] == 1 ? (P.rows[sd] + 3) / 4 : (P.rows[sd] + 255) / 256;
+            exp_segs.push_back(Seg{bp->exp_blocks, b, sd, nbe});
+            bp->exp_blocks += nbe;
+            const int64_t nbx = P.kpad / 64, nby = P.rpad[sd] / bp->res_rb;
+            res_segs.push_back(Seg{bp->res_blocks, b, sd, nbx});
+            bp->res_blocks += nbx * nby;
+        }
+    // CRT classes by digit chunk; two entries per thread while the LDS columns allow it
+    std::map<std::pair<int, int>, std::vector<int>> classes;
+    for (int b = 0; b < count; ++b)
+        classes[{bp->hosts[b].crt_dc, bp->hosts[b].nd32 <= 64 ? 2 : 1}].push_back(b);
+    std::vector<std::vector<Seg>> crt_segs;
+    for (auto &kv : classes) {
+        oz2h_batched_plan::CrtClass c{};
+        c.dc = kv.first.first;
+        c.ept = kv.first.second;
+        int maxnd = 1;
+        for (int b : kv.second) maxnd = std::max(maxnd, bp->hosts[b].nd32);
+        c.bd = 256;
+        while (c.bd > 64 && (size_t)maxnd * c.bd * c.ept * 4 > 49152) c.bd /= 2;
+        const size_t cols = (((size_t)maxnd * c.bd * c.ept + 3) & ~(size_t)3) * 4;
+        int maxL = 1;
+        for (int b : kv.second) maxL = std::max(maxL, bp->hosts[b].L);
+        c.LB = std::max(1, std::min(maxL, (int)((65536 - cols) / (sizeof(double) * (c.dc + 1)))));
+        c.lds = cols + (size_t)c.LB * (c.dc + 1) * sizeof(double);
+        std::vector<Seg> segs;
+        for (int b : kv.second) {
+            const int64_t per = (int64_t)c.bd * c.ept;
+            const int64_t nb = (probs[b].M * probs[b].N + per - 1) / per;
+            segs.push_back(Seg{c.blocks, b, 0, nb});
+            c.blocks += nb;
+        }
+        c.nseg = (int)segs.size();
+        bp->crt.push_back(c);
+        crt_segs.push_back(segs);
+    }
+    const size_t o_exp = off;
+    off = align_up(off + sizeof(Seg) * exp_segs.size());
+    const size_t o_rs = off;
+    off = align_up(off + sizeof(Seg) * res_segs.size());
+    std::vector<size_t> o_cs;
+    for (auto &v : crt_segs) {
+        o_cs.push_back(off);
+        off = align_up(off + sizeof(Seg) * v.size());
+    }
+
+    void *buf = nullptr;
+    if (hipMalloc(&buf, off) != hipSuccess) return fail(OZ2H_ENOMEM, "batched plan tables: hipMalloc failed");
+    bp->dbuf = buf;
+    char *db = (char *)buf;
+    for (int b = 0; b < count; ++b) {
+        const PlanHost &h = bp->hosts[b];
+        ProbDev &P = bp->pd[b];
+        P.mi = (const ModInfo *)(db + o_info[b]);
+        P.resid = (const double *)(db + o_res[b]);
+        P.crt = (const double *)(db + o_crt[b]);
+        P.pd = (const uint32_t *)(db + o_pd[b]);
+        P.phd = (const uint32_t *)(db + o_phd[b]);
+        OZ2H_HIP(hipMemcpy(db + o_info[b], h.info.data(), sizeof(ModInfo) * h.L, hipMemcpyHostToDevice));
+        OZ2H_HIP(hipMemcpy(db + o_res[b], h.resid_tab.data(), sizeof(double) * h.resid_tab.size(), hipMemcpyHostToDevice));
+        OZ2H_HIP(hipMemcpy(db + o_crt[b], h.crt_digits.data(), sizeof(double) * h.crt_digits.size(), hipMemcpyHostToDevice));
+        OZ2H_HIP(hipMemcpy(db + o_pd[b], h.p_digits.data(), sizeof(uint32_t) * h.nd32, hipMemcpyHostToDevice));
+        OZ2H_HIP(hipMemcpy(db + o_phd[b], h.ph_digits.data(), sizeof(uint32_t) * h.nd32, hipMemcpyHostToDevice));
+    }
+    bp->d_probs = (ProbDev *)(db + o_probs);
+    OZ2H_HIP(hipMemcpy(bp->d_probs, bp->pd.data(), sizeof(ProbDev) * count, hipMemcpyHostToDevice));
+    bp->d_exp_segs = (Seg *)(db + o_exp);
+    bp->n_exp_segs = (int)exp_segs.size();
+    OZ2H_HIP(hipMemcpy(bp->d_exp_segs, exp_segs.data(), sizeof(Seg) * exp_segs.size(), hipMemcpyHostToDevice));
+    bp->d_res_segs = (Seg *)(db + o_rs);
+    bp->n_res_segs = (int)res_segs.size();
+    OZ2H_HIP(hipMemcpy(bp->d_res_segs, res_segs.data(), sizeof(Seg) * res_segs.size(), hipMemcpyHostToDevice));
+    for (size_t c = 0; c < bp->crt.size(); ++c) {
+        bp->crt[c].d_segs = (Seg *)(db + o_cs[c]);
+        OZ2H_HIP(hipMemcpy(bp->crt[c].d_segs, crt_segs[c].data(), sizeof(Seg) * crt_segs[c].size(), hipMemcpyHostToDevice));
+    }
+
+    // shape signature for the autotuner cache; default schedule unless tuned before
+    uint64_t sig = 1469598103934665603ull;
+    for (int b = 0; b < count; ++b) {
+        const int64_t key[6] = {probs[b].M, probs[b].N, probs[b].K, probs[b].p, probs[b].opA, probs[b].opB};
+        sig = fnv1a(key, sizeof key, sig);
+    }
+    const int32_t okey[3] = {o->guard_bits, o->t_bits, o->crt_margin};
+    bp->signature = fnv1a(okey, sizeof okey, sig);
+    bp->tile = o->tile == OZ2H_TILE_AUTO ? OZ2H_TILE_128x128 : o->tile;
+    bp->bpc = 2;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load();
+        auto it = g_tune.find(bp->signature);
+        if (it != g_tune.end() && o->tile == OZ2H_TILE_AUTO) {
+            bp->tile = it->second.first;
+            bp->bpc = it->second.second;
+        }
+    }
+    if ((st = upload_items(bp.get()))) return st;
+    OZ2H_HIP(hipStreamCreateWithFlags(&bp->cap, hipStreamNonBlocking));
+    *out = bp.release();
+    return ok();
+}
+
+size_t oz2h_batched_workspace_size(const oz2h_batched_plan *plan) { return plan ? plan->ws_bytes : 0; }
+
+int oz2h_batched_get_config(const oz2h_batched_plan *plan, int32_t *tile, int32_t *blocks_per_cu,
+                            int64_t *gemm_items) {
+    if (!plan) return fail(OZ2H_EINVAL, "plan is NULL");
+    if (tile) *tile = plan->tile;
+    if (blocks_per_cu) *blocks_per_cu = plan->bpc;
+    if (gemm_items) *gemm_items = plan->nitems;
+    return ok();
+}
+
+int oz2h_batched_set_config(oz2h_batched_plan *plan, int32_t tile, int32_t blocks_per_cu) {
+    if (!plan) return fail(OZ2H_EINVAL, "plan is NULL");
+    if (tile < OZ2H_TILE_128x128 || tile > OZ2H_TILE_128x256 || blocks_per_cu < 1 || blocks_per_cu > 16)
+        return fail(OZ2H_EINVAL, "bad tile or blocks_per_cu");
+    if (tile != plan->tile || blocks_per_cu != plan->bpc) {
+        plan->tile = tile;
+        plan->bpc = blocks_per_cu;
+        drop_graph(plan);
+        int st = upload_items(plan);
+        if (st) return st;
+    }
+    return ok();
+}
+
+int oz2h_batched_run_eager(oz2h_batched_plan *plan, void *ws, size_t ws_bytes, hipStream_t stream) {
+    int st = check_batched_run(plan, ws, ws_bytes);
+    if (st) return st;
+    st = launch_batched_all(plan, (char *)ws, stream);
+    return st ? st : ok();
+}
+
+int oz2h_batched_run(oz2h_batched_plan *plan, void *ws, size_t ws_bytes, hipStream_t stream) {
+    int st = check_batched_run(plan, ws, ws_bytes);
+    if (st) return st;
+    if (!plan->exec || plan->cap_ws != ws) {
+        drop_graph(plan);
+        OZ2H_HIP(hipStreamBeginCapture(plan->cap, hipStreamCaptureModeThreadLocal));
+        st = launch_batched_all(plan, (char *)ws, plan->cap);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(plan->cap, &g);
+        if (st) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return fail(OZ2H_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        plan->graph = g;
+        OZ2H_HIP(hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0));
+        plan->cap_ws = ws;
+    }
+    OZ2H_HIP(hipGraphLaunch(plan->exec, stream));
+    return ok();
+}
+
+int oz2h_batched_tune(oz2h_batched_plan *plan, void *ws, size_t ws_bytes, hipStream_t stream) {
+    int st = check_batched_run(plan, ws, ws_bytes);
+    if (st) return st;
+    // the residue planes the candidates multiply
+    if ((st = launch_batched_front(plan, (char *)ws, stream))) return st;
+    hipEvent_t e0, e1;
+    OZ2H_HIP(hipEventCreate(&e0));
+    OZ2H_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    int bt = plan->tile, bb = plan->bpc;
+    const int tiles[3] = {OZ2H_TILE_128x128, OZ2H_TILE_256x128, OZ2H_TILE_128x256};
+    const int bpcs[3] = {1, 2, 4};
+    for (int ti : tiles)
+        for (int bc : bpcs) {
+            plan->tile = ti;
+            plan->bpc = bc;
+            if ((st = upload_items(plan))) break;
+            if ((st = launch_batched_gemm(plan, (char *)ws, stream))) break;   // warm-up
+            float acc = 0;
+            for (int rep = 0; rep < 3 && !st; ++rep) {
+                (void)hipEventRecord(e0, stream);
+                st = launch_batched_gemm(plan, (char *)ws, stream);
+                (void)hipEventRecord(e1, stream);
+                if (hipEventSynchronize(e1) != hipSuccess) st = fail(OZ2H_EDEVICE, "tuning run failed");
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                acc += ms;
+            }
+            if (st) break;
+            if (acc < best) {
+                best = acc;
+                bt = ti;
+                bb = bc;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st) return st;
+    plan->tile = bt;
+    plan->bpc = bb;
+    drop_graph(plan);
+    if ((st = upload_items(plan))) return st;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_store(plan->signature, bt, bb);
+    }
+    return ok();
+}
+
+void oz2h_batched_plan_destroy(oz2h_batched_plan *plan) {
+    if (!plan) return;
+    drop_graph(plan);
+    if (plan->cap) (void)hipStreamDestroy(plan->cap);
+    if (plan->d_items) (void)hipFree(plan->d_items);
+    if (plan->dbuf) (void)hipFree(plan->dbuf);
+    delete plan;
 }
 
 }  // extern "C"

@@ -1,0 +1,148 @@
+// oz2h_batched.hpp -- grouped kernels of the batched form: many independent
+// Ozaki-II products of uneven M, N, K and p in one pass per stage.
+//
+// Every product keeps its own moduli set (a prefix of the global list) and
+// constant tables; the stages walk segment tables (one segment per product
+// and operand side) and the residue GEMMs run as ONE persistent grouped launch
+// over a cost-sorted list of (product, modulus, output tile) work items.
+#pragma once
+
+#include "oz2h_kernels.hpp"
+
+namespace oz2h {
+
+// per-product descriptor in device memory; workspace regions are byte offsets
+// from the workspace base passed to every grouped kernel
+struct ProbDev {
+    const uint64_t *limbs[2];   // side 0: A (rows = M), side 1: B (rows = N)
+    const int32_t *exps[2];
+    const int8_t *signs[2];
+    int64_t rs[2], cs[2], rows[2], rpad[2];
+    uint64_t erow_off[2], planes_off[2], v_off;
+    int64_t K, kpad;
+    int32_t p, nl, t, nw32, L, lgroups, G;
+    int32_t nd32, crt_dc, crt_nc, crt_ndpad;
+    const ModInfo *mi;
+    const double *resid, *crt;
+    const uint32_t *pd, *phd;
+    uint64_t *climbs;
+    int32_t *cexp;
+    int8_t *csign;
+    int64_t ldc;
+};
+
+struct Seg {
+    int64_t first;   // first block of the segment
+    int32_t prod, side;
+    int64_t nbx;     // blocks along the fast grid dimension of the segment
+};
+
+// largest i with segs[i].first <= b
+__device__ __forceinline__ int find_seg(const Seg *__restrict__ segs, int nseg, int64_t b) {
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].first <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// stage 1, grouped: segment (prod, side); a side whose contraction is contiguous
+// (cs == 1) gets one wave per row (4 rows per block), any other one thread per
+// row (256 rows per block); each row is reduced completely, so no atomics
+__global__ __launch_bounds__(256) void k_exp_grouped(const ProbDev *__restrict__ probs,
+                                                     const Seg *__restrict__ segs, int nseg,
+                                                     char *ws) {
+    const int si = find_seg(segs, nseg, blockIdx.x);
+    const Seg sg = segs[si];
+    const ProbDev &P = probs[sg.prod];
+    const int side = sg.side;
+    const int64_t lb = (int64_t)blockIdx.x - sg.first;
+    const int8_t *__restrict__ sign = P.signs[side];
+    const int32_t *__restrict__ exps = P.exps[side];
+    const int64_t rows = P.rows[side], K = P.K, rs = P.rs[side], cs = P.cs[side];
+    int32_t *out = (int32_t *)(ws + P.erow_off[side]);
+    if (cs == 1) {
+        const int lane = threadIdx.x & 63;
+        const int64_t r = lb * 4 + (threadIdx.x >> 6);
+        if (r >= rows) return;   // whole wave
+        int m = INT_MIN;
+        for (int64_t k = lane; k < K; k += 64) {
+            const int64_t idx = r * rs + k;
+            if (sign[idx]) m = max(m, exps[idx]);
+        }
+        for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off));
+        if (lane == 0) out[r] = m == INT_MIN ? 0 : m;
+    } else {
+        const int64_t r = lb * 256 + threadIdx.x;
+        if (r >= rows) return;
+        int m = INT_MIN;
+        for (int64_t k = 0; k < K; ++k) {
+            const int64_t idx = r * rs + k * cs;
+            if (sign[idx]) m = max(m, exps[idx]);
+        }
+        out[r] = m == INT_MIN ? 0 : m;
+    }
+}
+
+__device__ __forceinline__ ResArgs res_args(const ProbDev &P, int side, char *ws) {
+    return ResArgs{P.limbs[side], P.exps[side], P.signs[side], P.rs[side], P.cs[side],
+                   P.rows[side], P.K, P.kpad, P.rpad[side] * P.kpad,
+                   (const int32_t *)(ws + P.erow_off[side]), P.p, P.nl, P.t, P.nw32, P.resid,
+                   P.mi, P.L, P.lgroups, (int8_t *)(ws + P.planes_off[side])};
+}
+
+// stage 2, grouped: segment (prod, side) is a (kpad/64) x (rpad/RB) grid of blocks
+template <int RB>
+__global__ __launch_bounds__(64 * RB) void k_residues_grouped(const ProbDev *__restrict__ probs,
+                                                              const Seg *__restrict__ segs,
+                                                              int nseg, char *ws) {
+    extern __shared__ uint32_t words[];
+    const int si = find_seg(segs, nseg, blockIdx.x);
+    const Seg sg = segs[si];
+    const int64_t lb = (int64_t)blockIdx.x - sg.first;
+    const ResArgs a = res_args(probs[sg.prod], sg.side, ws);
+    residue_block<RB>(a, lb % sg.nbx, lb / sg.nbx, words);
+}
+
+// one work item of the grouped GEMM: output tile (mt, nt) of modulus l of product prod
+struct GemmItem {
+    uint16_t prod, l, mt, nt;
+};
+
+// stage 3, persistent grouped launch: a grid of a few blocks per compute unit
+// walks the cost-sorted item list with a grid stride
+template <int WM, int WN>
+__global__ __launch_bounds__(256) void k_resgemm_grouped(const ProbDev *__restrict__ probs,
+                                                         const GemmItem *__restrict__ items,
+                                                         int nitems, char *ws) {
+    __shared__ __attribute__((aligned(1024))) int8_t lds[gemm_lds_bytes<WM, WN>()];
+    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+        const GemmItem it = items[i];
+        const ProbDev &P = probs[it.prod];
+        const GemmArgs g{(const int8_t *)(ws + P.planes_off[0]), (const int8_t *)(ws + P.planes_off[1]),
+                         P.kpad, P.rpad[0] * P.kpad, P.rpad[1] * P.kpad, P.mi,
+                         (int16_t *)(ws + P.v_off), P.rpad[0] * P.rpad[1], P.rpad[1], nullptr};
+        __syncthreads();   // the previous item's LDS tiles are no longer read
+        gemm_tile<WM, WN, false>(g, it.mt, it.nt, it.l, lds);
+    }
+}
+
+// stages 4-5, grouped: segment prod is a 1-D grid of CRT blocks
+template <int DC, int EPT>
+__global__ __launch_bounds__(256) void k_crt_grouped(const ProbDev *__restrict__ probs,
+                                                     const Seg *__restrict__ segs, int nseg,
+                                                     char *ws, int LB) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t sdig[];
+    const int si = find_seg(segs, nseg, blockIdx.x);
+    const Seg sg = segs[si];
+    const ProbDev &P = probs[sg.prod];
+    const CrtArgs a{(const int16_t *)(ws + P.v_off), P.rpad[0] * P.rpad[1], P.rpad[1], P.rows[0],
+                    P.rows[1], P.mi, P.L, P.crt, P.crt_ndpad, P.crt_nc, P.nd32, P.pd, P.phd,
+                    (const int32_t *)(ws + P.erow_off[0]), (const int32_t *)(ws + P.erow_off[1]),
+                    P.t, P.p, P.csign, P.cexp, P.climbs, P.ldc, nullptr, 0, LB};
+    crt_block<DC, EPT, true, false>(a, (int64_t)blockIdx.x - sg.first, sdig);
+}
+
+}  // namespace oz2h

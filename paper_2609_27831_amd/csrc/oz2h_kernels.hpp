@@ -72,41 +72,6 @@ __global__ void k_exp_fix(int32_t *__restrict__ p, int64_t n) {
 
 // ---------------------------------------------------------------- stage 2
 
-__device__ __forceinline__ uint64_t mant_limb(const uint64_t *__restrict__ base, int nl,
-                                              uint64_t topmask, int64_t i) {
-    if (i < 0 || i >= nl) return 0;
-    const uint64_t v = base[i];
-    return i == nl - 1 ? (v & topmask) : v;
-}
-
-// bits [off, off + 32) of the significand (bits outside [0, p) read as 0)
-__device__ __forceinline__ uint32_t mant_bits32(const uint64_t *__restrict__ base, int nl,
-                                                uint64_t topmask, int64_t off) {
-    const int64_t q = off >> 6;
-    const int r = (int)(off & 63);
-    const uint64_t lo = mant_limb(base, nl, topmask, q);
-    const uint64_t hi = mant_limb(base, nl, topmask, q + 1);
-    return (uint32_t)(r ? ((lo >> r) | (hi << (64 - r))) : lo);
-}
-
-__device__ __forceinline__ int mant_bit(const uint64_t *__restrict__ base, int nl,
-                                        uint64_t topmask, int64_t pos) {
-    if (pos < 0) return 0;
-    return (int)((mant_limb(base, nl, topmask, pos >> 6) >> (pos & 63)) & 1u);
-}
-
-// any bit set in [0, pos)
-__device__ __forceinline__ int mant_any_below(const uint64_t *__restrict__ base, int nl,
-                                              uint64_t topmask, int64_t pos) {
-    if (pos <= 0) return 0;
-    const int64_t full = pos >> 6;
-    const int r = (int)(pos & 63);
-    for (int64_t i = 0; i < full && i < nl; ++i)
-        if (mant_limb(base, nl, topmask, i)) return 1;
-    if (r && full < nl && (mant_limb(base, nl, topmask, full) & ((1ull << r) - 1))) return 1;
-    return 0;
-}
-
 // limb i of a significand (bits at or above p masked off; out of range -> 0),
 // branch-free: the index is clamped and the value selected, so that the
 // compiler can issue the loads of all words back to back
@@ -173,37 +138,48 @@ __device__ __forceinline__ int build_words(const uint64_t *__restrict__ sl, int 
 // r = a - rint(a/m) m (the rint quotient is off by at most one, so one
 // correction step gives the canonical centred residue in [-floor(m/2), (m-1)/2]),
 // and for two-limb moduli the balanced base-128 split r = r0 + 128 r1.
+struct ResArgs {
+    const uint64_t *limbs;
+    const int32_t *exps;
+    const int8_t *signs;
+    int64_t rs, cs, rows, count, kpad, plane_stride;
+    const int32_t *erow;
+    int p, nl, t, nw32;
+    const double *tab;
+    const ModInfo *mi;
+    int L, lgroups;
+    int8_t *planes;
+};
+
 template <int RB>
-__global__ __launch_bounds__(64 * RB) void k_residues(
-    const uint64_t *__restrict__ limbs, const int32_t *__restrict__ exps,
-    const int8_t *__restrict__ signs, int64_t rs, int64_t cs, int64_t rows, int64_t count,
-    int64_t kpad, int64_t plane_stride, const int32_t *__restrict__ erow, int p, int nl, int t,
-    int nw32, const double *__restrict__ tab, const ModInfo *__restrict__ mi, int L,
-    int lgroups, int8_t *__restrict__ planes) {
-    extern __shared__ uint32_t words[];
+__device__ __forceinline__ void residue_block(const ResArgs &a, int64_t bx, int64_t by,
+                                              uint32_t *words) {
     constexpr int BD = 64 * RB;
     const int tid = threadIdx.x;
-    const int64_t k = (int64_t)blockIdx.x * 64 + (tid & 63);
-    const int64_t r = (int64_t)blockIdx.y * RB + (tid >> 6);
+    const int64_t k = bx * 64 + (tid & 63);
+    const int64_t r = by * RB + (tid >> 6);
+    const int p = a.p, nl = a.nl, nw32 = a.nw32, L = a.L;
+    const int64_t kpad = a.kpad, plane_stride = a.plane_stride;
+    const ModInfo *__restrict__ mi = a.mi;
 
     uint32_t *col = words + tid;
     int s = 0;
     int64_t sh = 0, idx = 0;
-    if (r < rows && k < count) {
-        idx = r * rs + k * cs;
-        s = signs[idx];
-        sh = (int64_t)t - p + exps[idx] - erow[r];
+    if (r < a.rows && k < a.count) {
+        idx = r * a.rs + k * a.cs;
+        s = a.signs[idx];
+        sh = (int64_t)a.t - p + a.exps[idx] - a.erow[r];
     }
-    s = build_words(limbs + idx * nl, s, sh, p, nl, nw32, col, BD);
+    s = build_words(a.limbs + idx * nl, s, sh, p, nl, nw32, col, BD);
     if (s == 0)
         for (int w = 0; w < nw32; ++w) col[w * BD] = 0;
 
-    int8_t *out = planes + r * kpad + k;
-    for (int grp = 0; grp < lgroups; ++grp) {
+    int8_t *out = a.planes + r * kpad + k;
+    for (int grp = 0; grp < a.lgroups; ++grp) {
         double acc[kModGroup];
 #pragma unroll
         for (int g = 0; g < kModGroup; ++g) acc[g] = 0.0;
-        const double *c = tab + (size_t)grp * nw32 * kModGroup;   // uniform: scalar loads
+        const double *c = a.tab + (size_t)grp * nw32 * kModGroup;   // uniform: scalar loads
         for (int w = 0; w < nw32; ++w) {
             const double x = (double)col[w * BD];
 #pragma unroll
@@ -231,6 +207,12 @@ __global__ __launch_bounds__(64 * RB) void k_residues(
             }
         }
     }
+}
+
+template <int RB>
+__global__ __launch_bounds__(64 * RB) void k_residues(ResArgs a) {
+    extern __shared__ uint32_t words[];
+    residue_block<RB>(a, blockIdx.x, blockIdx.y, words);
 }
 
 // ---------------------------------------------------------------- stage 3
@@ -264,29 +246,37 @@ constexpr int lgkmcnt_imm(int lgkm) { return 0xF | (3 << 14) | (0x7 << 4) | ((lg
 // products |acc| <= m/2, so acc + K 127^2 < 2^31 stays exact.
 // Blocks run the two-limb moduli first (they are three times longer).
 // RAW = true: plain int32 output of a single plane (exactness tests).
+struct GemmArgs {
+    const int8_t *A, *B;
+    int64_t kpad, a_ps, b_ps;
+    const ModInfo *mi;
+    int16_t *V;
+    int64_t v_ps, ldv;
+    int32_t *Craw;
+};
+
+template <int WM, int WN>
+constexpr int gemm_lds_bytes() { return 2 * (2 * WM + 2 * WN) * TBK; }
+
+// one output tile (mt, nt) of modulus l; `lds` holds gemm_lds_bytes<WM, WN>() bytes
 template <int WM, int WN, bool RAW>
-__global__ __launch_bounds__(256) void k_resgemm(const int8_t *__restrict__ A,
-                                                 const int8_t *__restrict__ B, int64_t kpad,
-                                                 int64_t a_ps, int64_t b_ps,
-                                                 const ModInfo *__restrict__ mi, int L,
-                                                 int16_t *__restrict__ V, int64_t v_ps,
-                                                 int64_t ldv, int32_t *__restrict__ Craw) {
+__device__ __forceinline__ void gemm_tile(const GemmArgs &args, int64_t mt, int64_t nt, int l,
+                                          int8_t *lds) {
     constexpr int BM = 2 * WM, BN = 2 * WN, FM = WM / 32, FN = WN / 32;
     constexpr int AP = BM / 32, BP = BN / 32;   // 32 rows x 128 bytes per pass of 256 lanes
-    __shared__ __attribute__((aligned(1024))) int8_t sA0[BM * TBK];
-    __shared__ __attribute__((aligned(1024))) int8_t sA1[BM * TBK];
-    __shared__ __attribute__((aligned(1024))) int8_t sB0[BN * TBK];
-    __shared__ __attribute__((aligned(1024))) int8_t sB1[BN * TBK];
+    int8_t *sA0 = lds, *sA1 = lds + BM * TBK, *sB0 = lds + 2 * BM * TBK, *sB1 = sB0 + BN * TBK;
+    const int8_t *__restrict__ A = args.A;
+    const int8_t *__restrict__ B = args.B;
+    const int64_t kpad = args.kpad, a_ps = args.a_ps, b_ps = args.b_ps, ldv = args.ldv;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
-    const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
-    const int l = RAW ? 0 : L - 1 - (int)blockIdx.z;
+    const int64_t m0 = mt * BM, n0 = nt * BN;
 
     uint32_t g0 = 0, nprod = 1;
     double md = 1.0, inv_m = 1.0;
     int32_t kc[3] = {1, 1, 1};
     if (!RAW) {
-        const ModInfo info = mi[l];
+        const ModInfo info = args.mi[l];
         g0 = info.g0;
         nprod = info.nprod;
         md = (double)info.m;
@@ -386,7 +376,7 @@ __global__ __launch_bounds__(256) void k_resgemm(const int8_t *__restrict__ A,
     // the per-element row offsets are uniform, only the lane base is per lane
     const int64_t lane_off = (m0 + wr * WM + 4 * (lane >> 5)) * ldv + n0 + wc * WN + (lane & 31);
     if (RAW) {
-        int32_t *base = Craw + lane_off;
+        int32_t *base = args.Craw + lane_off;
 #pragma unroll
         for (int x = 0; x < FM; ++x)
 #pragma unroll
@@ -396,7 +386,7 @@ __global__ __launch_bounds__(256) void k_resgemm(const int8_t *__restrict__ A,
                     base[(int64_t)(x * 32 + 8 * (e >> 2) + (e & 3)) * ldv + y * 32] = acc[x][y][e];
         return;
     }
-    int16_t *base = V + (int64_t)l * v_ps + lane_off;
+    int16_t *base = args.V + (int64_t)l * args.v_ps + lane_off;
 #pragma unroll
     for (int x = 0; x < FM; ++x)
 #pragma unroll
@@ -404,6 +394,14 @@ __global__ __launch_bounds__(256) void k_resgemm(const int8_t *__restrict__ A,
 #pragma unroll
             for (int e = 0; e < 16; ++e)
                 base[(int64_t)(x * 32 + 8 * (e >> 2) + (e & 3)) * ldv + y * 32] = (int16_t)acc[x][y][e];
+}
+
+// plain launch: grid (N tiles, M tiles, moduli), two-limb moduli (listed last) first
+template <int WM, int WN, bool RAW>
+__global__ __launch_bounds__(256) void k_resgemm(GemmArgs args, int L) {
+    __shared__ __attribute__((aligned(1024))) int8_t lds[gemm_lds_bytes<WM, WN>()];
+    const int l = RAW ? 0 : L - 1 - (int)blockIdx.z;
+    gemm_tile<WM, WN, RAW>(args, blockIdx.y, blockIdx.x, l, lds);
 }
 
 // ---------------------------------------------------------------- stage 4 + 5
@@ -480,29 +478,46 @@ __device__ __forceinline__ void dig_neg(uint32_t *sd, int st, int nd) {   // two
 // GEMM applies the weight); WEIGHT = true takes plain residues u_l instead.
 // The digit constants of a block of LB moduli (and their 1/m_l) are staged in
 // LDS and read with wave-uniform addresses (broadcast), two per ds_read_b128.
+struct CrtArgs {
+    const int16_t *V;
+    int64_t v_ps, ldv, M, N;
+    const ModInfo *mi;
+    int L;
+    const double *dig;
+    int ndpad, nc, nd32;
+    const uint32_t *Pd, *Phd;
+    const int32_t *erow, *fcol;
+    int t, p;
+    int8_t *osign;
+    int32_t *oexp;
+    uint64_t *olimbs;
+    int64_t ldc;
+    uint64_t *chat_mag;
+    int nlc, LB;
+};
+
+// LDS of a CRT block: bd * EPT digit columns of nd32 words, then LB x (DC + 1) doubles
 template <int DC, int EPT, bool ROUND, bool WEIGHT>
-__global__ __launch_bounds__(256) void k_crt(
-    const int16_t *__restrict__ V, int64_t v_ps, int64_t ldv, int64_t M, int64_t N,
-    const ModInfo *__restrict__ mi, int L, const double *__restrict__ dig, int ndpad, int nc,
-    int nd32, const uint32_t *__restrict__ Pd, const uint32_t *__restrict__ Phd,
-    const int32_t *__restrict__ erow, const int32_t *__restrict__ fcol, int t, int p,
-    int8_t *__restrict__ osign, int32_t *__restrict__ oexp, uint64_t *__restrict__ olimbs,
-    int64_t ldc, uint64_t *__restrict__ chat_mag, int nlc, int LB) {
-    extern __shared__ __attribute__((aligned(16))) uint32_t sdig[];
+__device__ __forceinline__ void crt_block(const CrtArgs &a, int64_t blk, uint32_t *sdig) {
     const int tid = threadIdx.x, bd = blockDim.x, st = bd * EPT;
+    const int nd32 = a.nd32, L = a.L, LB = a.LB, ndpad = a.ndpad, p = a.p;
+    const int64_t N = a.N, v_ps = a.v_ps;
+    const uint32_t *__restrict__ Pd = a.Pd;
+    const uint32_t *__restrict__ Phd = a.Phd;
+    const ModInfo *__restrict__ mi = a.mi;
     double *stab = (double *)(sdig + (((size_t)nd32 * st + 3) & ~(size_t)3));   // LB x DC digits
     double *sinv = stab + (size_t)LB * DC;                                      // LB x 1/m
-    const int64_t MN = M * N;
+    const int64_t MN = a.M * N;
     int64_t idx[EPT];
     const int16_t *vp[EPT];
     bool live[EPT];
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
-        idx[q] = (int64_t)blockIdx.x * st + q * bd + tid;
+        idx[q] = blk * st + q * bd + tid;
         live[q] = idx[q] < MN;
         // a dead lane reads entry 0 (always valid) and writes nothing: no branch around loads
         const int64_t ii = live[q] ? idx[q] / N : 0, jj = live[q] ? idx[q] - ii * N : 0;
-        vp[q] = V + ii * ldv + jj;
+        vp[q] = a.V + ii * a.ldv + jj;
     }
 
     int64_t beta[EPT], carry[EPT];
@@ -513,7 +528,7 @@ __global__ __launch_bounds__(256) void k_crt(
         carry[q] = 0;
         slow[q] = false;
     }
-    for (int c = 0; c < nc; ++c) {
+    for (int c = 0; c < a.nc; ++c) {
         double acc[EPT][DC], asum[EPT];
 #pragma unroll
         for (int q = 0; q < EPT; ++q) {
@@ -521,7 +536,7 @@ __global__ __launch_bounds__(256) void k_crt(
 #pragma unroll
             for (int d = 0; d < DC; ++d) acc[q][d] = 0.0;
         }
-        const double *dc = dig + c * DC;
+        const double *dc = a.dig + c * DC;
         for (int l0 = 0; l0 < L; l0 += LB) {
             const int nlb = min(LB, L - l0);
             __syncthreads();   // the previous slice has been consumed by every thread
@@ -624,21 +639,21 @@ __global__ __launch_bounds__(256) void k_crt(
         const int64_t i = idx[q] / N, j = idx[q] - i * N;
 
         if (!ROUND) {
-            uint64_t *o = chat_mag + idx[q] * nlc;
-            for (int w = 0; w < nlc; ++w) {
+            uint64_t *o = a.chat_mag + idx[q] * a.nlc;
+            for (int w = 0; w < a.nlc; ++w) {
                 const uint64_t lo = (2 * w < nd32) ? sd[2 * w * st] : 0u;
                 const uint64_t hi = (2 * w + 1 < nd32) ? sd[(2 * w + 1) * st] : 0u;
                 o[w] = lo | (hi << 32);
             }
-            osign[idx[q]] = top < 0 ? 0 : (neg ? -1 : 1);
+            a.osign[idx[q]] = top < 0 ? 0 : (neg ? -1 : 1);
             continue;
         }
-        const int64_t oi = i * ldc + j;
-        uint64_t *o = olimbs + oi * nl;
+        const int64_t oi = i * a.ldc + j;
+        uint64_t *o = a.olimbs + oi * nl;
         if (top < 0) {
             for (int w = 0; w < nl; ++w) o[w] = 0;
-            osign[oi] = 0;
-            oexp[oi] = 0;
+            a.osign[oi] = 0;
+            a.oexp[oi] = 0;
             continue;
         }
         int64_t nb = 32 * (int64_t)top + (32 - __builtin_clz(sd[top * st]));
@@ -682,9 +697,15 @@ __global__ __launch_bounds__(256) void k_crt(
                 o[w] = v;
             }
         }
-        osign[oi] = neg ? -1 : 1;
-        oexp[oi] = (int32_t)(nb + (int64_t)erow[i] + fcol[j] - 2 * (int64_t)t);
+        a.osign[oi] = neg ? -1 : 1;
+        a.oexp[oi] = (int32_t)(nb + (int64_t)a.erow[i] + a.fcol[j] - 2 * (int64_t)a.t);
     }
+}
+
+template <int DC, int EPT, bool ROUND, bool WEIGHT>
+__global__ __launch_bounds__(256) void k_crt(CrtArgs a) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t sdig[];
+    crt_block<DC, EPT, ROUND, WEIGHT>(a, blockIdx.x, sdig);
 }
 
 // zero output for K = 0

@@ -53,6 +53,12 @@ class PlanInfo(ctypes.Structure):
                 ("log2P", ctypes.c_double)]
 
 
+class Problem(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int64), ("N", ctypes.c_int64), ("K", ctypes.c_int64),
+                ("p", ctypes.c_int32), ("opA", ctypes.c_int32), ("opB", ctypes.c_int32),
+                ("A", CMat), ("B", CMat), ("C", Mat)]
+
+
 # (name, restype, argtypes) of every exported symbol
 _P, _I32, _I64, _SZ, _D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_double
 SIGNATURES = {
@@ -76,6 +82,14 @@ SIGNATURES = {
     "oz2h_residue_gemm": (ctypes.c_int, [_P, _I64, _I64, _I64, _P, _P, _P, _P]),
     "oz2h_i8gemm": (ctypes.c_int, [_I64, _I64, _I64, _P, _P, _P, _I32, _P]),
     "oz2h_crt": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _I64, _P, _P, _I32, _P]),
+    "oz2h_batched_plan_create": (ctypes.c_int, [_I32, _P, ctypes.POINTER(Opts), ctypes.POINTER(_P)]),
+    "oz2h_batched_workspace_size": (_SZ, [_P]),
+    "oz2h_batched_tune": (ctypes.c_int, [_P, _P, _SZ, _P]),
+    "oz2h_batched_run": (ctypes.c_int, [_P, _P, _SZ, _P]),
+    "oz2h_batched_run_eager": (ctypes.c_int, [_P, _P, _SZ, _P]),
+    "oz2h_batched_get_config": (ctypes.c_int, [_P, _P, _P, _P]),
+    "oz2h_batched_set_config": (ctypes.c_int, [_P, _I32, _I32]),
+    "oz2h_batched_plan_destroy": (None, [_P]),
 }
 
 _lib = None
@@ -366,3 +380,64 @@ def limbs_to_ints(mag: np.ndarray, sign: np.ndarray):
             v = (v << 64) | int(x)
         out.append(int(s) * v)
     return out
+
+
+# ------------------------------------------------------------------ batched form
+
+class BatchedPlan:
+    """Many independent products in one grouped pass per stage (oz2h_batched_*).
+
+    problems: list of (A, B, C, opA, opB) with DeviceMP operands; each product
+    runs at its operands' precision.  The device pointers are captured by the plan.
+    """
+
+    def __init__(self, problems, opts: Optional[Opts] = None):
+        arr = (Problem * len(problems))()
+        self._keep = problems   # the captured tensors must outlive the plan
+        for i, (A, B, C, opA, opB) in enumerate(problems):
+            M, N, K = _dims(A, B, opA, opB)
+            if C.shape != (M, N) or A.p != B.p or C.p != A.p:
+                raise ValueError(f"problem {i}: inconsistent shapes or precisions")
+            arr[i] = Problem(M, N, K, A.p, opA, opB, A.cmat(), B.cmat(), C.mat())
+        h = ctypes.c_void_p()
+        o = opts or default_opts()
+        _check(lib().oz2h_batched_plan_create(len(problems), arr, ctypes.byref(o), ctypes.byref(h)))
+        self.handle = h.value
+        self.count = len(problems)
+
+    def workspace_size(self) -> int:
+        return int(lib().oz2h_batched_workspace_size(self.handle))
+
+    def workspace(self, device="cuda"):
+        torch = _torch()
+        return torch.empty(max(self.workspace_size(), 256), dtype=torch.uint8, device=device)
+
+    def tune(self, ws, stream=None):
+        _check(lib().oz2h_batched_tune(self.handle, ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
+        return self.config()
+
+    def run(self, ws, stream=None):
+        _check(lib().oz2h_batched_run(self.handle, ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
+
+    def run_eager(self, ws, stream=None):
+        _check(lib().oz2h_batched_run_eager(self.handle, ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
+
+    def config(self):
+        t, bc, n = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().oz2h_batched_get_config(self.handle, ctypes.addressof(t), ctypes.addressof(bc),
+                                             ctypes.addressof(n)))
+        return {"tile": t.value, "blocks_per_cu": bc.value, "gemm_items": n.value}
+
+    def set_config(self, tile: int, blocks_per_cu: int):
+        _check(lib().oz2h_batched_set_config(self.handle, tile, blocks_per_cu))
+
+    def destroy(self):
+        if self.handle:
+            lib().oz2h_batched_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

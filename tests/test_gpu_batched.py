@@ -1,0 +1,123 @@
+"""GPU tests of the batched form (marked gpu).
+
+Every product of a batch must equal the plain per-product call on the same
+inputs bit for bit (and hence the oracle); graph replays are checked against
+the eager result several times, with other work and synchronisations between.
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import dev_mp, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def oz():
+    need_gpu()
+    from paper_2609_27831_amd import oz2h
+    return oz2h
+
+
+def make_batch(seed, count, lo, hi, ps=(53, 113, 256, 512), elo=-4, ehi=4):
+    """Log-uniform dimensions in [lo, hi], precision drawn from ps (the batched workload's recipe)."""
+    u = synth.splitmix64(seed, 0, 4 * count).reshape(count, 4)
+    out = []
+    for i in range(count):
+        f = (u[i, :3] >> np.uint64(11)).astype(np.float64) / float(1 << 53)
+        M, N, K = (int(round(lo * (hi / lo) ** x)) for x in f)
+        p = ps[int(u[i, 3] % np.uint64(len(ps)))]
+        A, B = synth.operands_for(seed * 1000 + i, M, N, K, p, elo, ehi)
+        out.append((A, B))
+    return out
+
+
+def _host(C):
+    s, e, l = C.to_host()
+    return s, e, l
+
+
+def test_batched_matches_plain_calls(oz, c_oracle):
+    import torch
+    batch = make_batch(7, 24, 16, 400)
+    probs, devs = [], []
+    for i, (A, B) in enumerate(batch):
+        opA, opB = (i % 2, (i // 2) % 2)
+        Ad = dev_mp(A.transpose() if opA else A)
+        Bd = dev_mp(B.transpose() if opB else B)
+        C = oz.empty_mp(A.shape[0], B.shape[1], A.p)
+        probs.append((Ad, Bd, C, opA, opB))
+    bp = oz.BatchedPlan(probs)
+    ws = bp.workspace()
+    print("batched eager", bp.config(), flush=True)
+    bp.run_eager(ws)
+    torch.cuda.synchronize()
+    eager = [_host(C) for (_, _, C, _, _) in probs]
+    for i, (Ad, Bd, C, opA, opB) in enumerate(probs):
+        plan = oz.Plan.create(Ad.p, batch[i][0].shape[1])
+        Cp = oz.gemm(plan, Ad, Bd, opA, opB)
+        torch.cuda.synchronize()
+        ref = _host(Cp)
+        for a, b in zip(eager[i], ref):
+            assert np.array_equal(a, b), f"product {i}"
+    # the oracle on a few products
+    for i in (0, 5, 11):
+        A, B = batch[i]
+        r = c_oracle.gemm(A, B, want_chat=False)
+        s, e, l = eager[i]
+        assert np.array_equal(s, r["c_sign"]) and np.array_equal(e, r["c_exp"])
+        assert np.array_equal(l, r["c_limbs"])
+    # graph replays, with other work between them
+    for rep in range(3):
+        for (_, _, C, _, _) in probs:
+            C.sign.fill_(0)
+            C.exp.fill_(0)
+            C.limbs.fill_(0)
+        torch.cuda.synchronize()
+        print(f"batched graph replay {rep}", flush=True)
+        bp.run(ws)
+        torch.cuda.synchronize()
+        for i, (_, _, C, _, _) in enumerate(probs):
+            for a, b in zip(_host(C), eager[i]):
+                assert np.array_equal(a, b), f"replay {rep} product {i}"
+    bp.destroy()
+
+
+@pytest.mark.parametrize("tile,bpc", [(1, 1), (2, 2), (3, 4)])
+def test_batched_tiles_and_schedules(oz, tile, bpc):
+    import torch
+    batch = make_batch(11, 10, 100, 700, ps=(113, 512))
+    probs = [(dev_mp(A), dev_mp(B), oz.empty_mp(A.shape[0], B.shape[1], A.p), 0, 0) for A, B in batch]
+    bp = oz.BatchedPlan(probs, oz.default_opts(tile=tile))
+    bp.set_config(tile, bpc)
+    ws = bp.workspace()
+    print(f"batched tile={tile} bpc={bpc}", bp.config(), flush=True)
+    bp.run(ws)
+    torch.cuda.synchronize()
+    for i, (Ad, Bd, C, _, _) in enumerate(probs):
+        Cp = oz.gemm(oz.Plan.create(Ad.p, Ad.shape[1]), Ad, Bd)
+        torch.cuda.synchronize()
+        for a, b in zip(_host(C), _host(Cp)):
+            assert np.array_equal(a, b), f"product {i}"
+
+
+def test_batched_autotune(oz):
+    import torch
+    batch = make_batch(13, 8, 64, 512)
+    probs = [(dev_mp(A), dev_mp(B), oz.empty_mp(A.shape[0], B.shape[1], A.p), 0, 0) for A, B in batch]
+    bp = oz.BatchedPlan(probs)
+    ws = bp.workspace()
+    cfg = bp.tune(ws)
+    print("tuned", cfg, flush=True)
+    assert cfg["tile"] in (1, 2, 3) and cfg["blocks_per_cu"] in (1, 2, 4)
+    bp.run(ws)
+    torch.cuda.synchronize()
+    for i, (Ad, Bd, C, _, _) in enumerate(probs):
+        Cp = oz.gemm(oz.Plan.create(Ad.p, Ad.shape[1]), Ad, Bd)
+        torch.cuda.synchronize()
+        for a, b in zip(_host(C), _host(Cp)):
+            assert np.array_equal(a, b)
+    # a second plan with the same shapes picks the tuned configuration up
+    bp2 = oz.BatchedPlan(probs)
+    assert bp2.config()["tile"] == cfg["tile"] and bp2.config()["blocks_per_cu"] == cfg["blocks_per_cu"]
