@@ -15,6 +15,15 @@
  *   c^_ij = sum_k a^_ik b^_kj                              (Eq. 2, exact)
  *   c_ij  = RNE_p(c^_ij * 2^(e_i + f_j - 2t))              (Eq. 2, one rounding)
  *
+ * The general entry point oz2o_gemm_scaled gives each operand side its own
+ * width t, an optional exponent offset per contraction index and optionally
+ * given (instead of computed) row exponents.  This is how the backward
+ * products of C = A B are integerized when they reuse the forward's integer
+ * matrices (exponent folding, a reading the paper does not state):
+ *   dA = W B^T:  W'_ij = W_ij 2^(f_j), scaled per row with t_w;  B^ as saved,
+ *                i.e. offset -f_j per contraction index j and row exponent 0
+ *   dB = A^T W:  W''_ij = W_ij 2^(e_i), scaled per column with t_w;  A^ as saved
+ *
  * Number format: value = sign * mant * 2^(exp - p), sign in {-1,0,+1} (0 is
  * zero), mant stored as nl = ceil(p/64) little-endian uint64 limbs; bits at
  * or above p are ignored.  Outputs have 2^(p-1) <= mant < 2^p, or are zero.
@@ -158,21 +167,23 @@ static void bn_addmul(uint64_t *acc, int nacc, const uint64_t *a, const uint64_t
 
 /* ---- the method's steps ---- */
 
-/* e = max exp over the nonzero entries of one logical row (step 1, Eq. 1) */
-static int32_t shared_exponent(const opnd *X, int64_t base, int64_t step, int64_t count) {
+/* e = max exp (+ koff[k]) over the nonzero entries of one logical row (step 1, Eq. 1) */
+static int32_t shared_exponent(const opnd *X, int64_t base, int64_t step, int64_t count,
+                               const int32_t *koff) {
     int have = 0;
     int32_t e = 0;
     for (int64_t k = 0; k < count; k++) {
         int64_t idx = base + k * step;
         if (X->sign[idx] == 0) continue;
-        if (!have || X->exp[idx] > e) e = X->exp[idx];
+        int32_t x = X->exp[idx] + (koff ? koff[k] : 0);
+        if (!have || x > e) e = x;
         have = 1;
     }
     return have ? e : 0;
 }
 
-/* a^ = RNE(a * 2^(t - e)) as sign + na-limb magnitude (Eq. 1); returns sign */
-static int integerize_entry(const opnd *X, int64_t idx, int p, int t, int32_t e,
+/* a^ = RNE(a * 2^(t + off - e)) as sign + na-limb magnitude (Eq. 1); returns sign */
+static int integerize_entry(const opnd *X, int64_t idx, int p, int t, int32_t off, int32_t e,
                             uint64_t *mag, int na) {
     memset(mag, 0, sizeof(uint64_t) * na);
     int s = X->sign[idx];
@@ -181,7 +192,7 @@ static int integerize_entry(const opnd *X, int64_t idx, int p, int t, int32_t e,
     memcpy(mant, X->limbs + idx * X->nl, sizeof(uint64_t) * X->nl);
     int topbits = p - 64 * (X->nl - 1);
     if (topbits < 64) mant[X->nl - 1] &= (1ull << topbits) - 1;
-    int64_t sh = (int64_t)t - p + X->exp[idx] - e;
+    int64_t sh = (int64_t)t - p + X->exp[idx] + off - e;
     if (sh >= 0) bn_shl(mant, X->nl, sh, mag, na);
     else bn_shr_rne(mant, X->nl, -sh, mag, na);
     if (bn_bitlen(mag, na) == 0) return 0;
@@ -202,12 +213,12 @@ int oz2o_integerize(int64_t rows, int64_t count, int p, int t,
     if (na * 64 < t + 1) return -1;
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t r = 0; r < rows; r++) {
-        int32_t e = shared_exponent(&X, r * rs, cs, count);
+        int32_t e = shared_exponent(&X, r * rs, cs, count, NULL);
         e_out[r] = e;
         for (int64_t k = 0; k < count; k++) {
             int64_t idx = r * rs + k * cs;
             sign_out[r * count + k] =
-                (int8_t)integerize_entry(&X, idx, p, t, e, mag_out + (r * count + k) * na, na);
+                (int8_t)integerize_entry(&X, idx, p, t, 0, e, mag_out + (r * count + k) * na, na);
         }
     }
     return 0;
@@ -239,24 +250,33 @@ static int round_out(int sgn, const uint64_t *mag, int n, int64_t scale, int p,
 }
 
 /*
- * The whole reference.  A is M x K, B is K x N, given as (sign, exp, limbs)
- * with element strides (a_rs, a_cs), (b_rs, b_cs).  If sel_i is NULL every
- * entry of C is computed (row-major, index i*N + j); else the nsel entries
- * (sel_i[s], sel_j[s]) are computed into slot s.  Optional outputs (NULL to
- * skip): e[M], f[N]; c^ as sign + nlc-limb magnitude; C as sign/exp/nl limbs.
- * Returns 0, -1 for a too-small nlc, -2 for an exponent overflow.
+ * The whole reference, general form.  A is M x K, B is K x N, given as
+ * (sign, exp, limbs) with element strides (a_rs, a_cs), (b_rs, b_cs).  Side A
+ * is integerized with width ta: a^_ik = RNE(a_ik 2^(ta + a_koff[k] - e_i)) with
+ * e_i = a_efix[i] if a_efix is given, else max(exp a_ik + a_koff[k]) over the
+ * nonzero a_ik (0 if none); side B likewise per column with tb, b_koff, b_efix.
+ * Every integer must satisfy |x^| <= 2^t of its side (true whenever the row
+ * exponent is the max; checked otherwise).  c_ij = RNE_p(c^_ij 2^(e_i + f_j -
+ * ta - tb)).  If sel_i is NULL every entry of C is computed (row-major, index
+ * i*N + j); else the nsel entries (sel_i[s], sel_j[s]) are computed into slot
+ * s.  Optional outputs (NULL to skip): e[M], f[N]; c^ as sign + nlc-limb
+ * magnitude; C as sign/exp/nl limbs.  Returns 0, -1 for a too-small nlc, -2
+ * for an exponent overflow, -3 for an integer wider than its t.
  */
-int oz2o_gemm(int64_t M, int64_t N, int64_t K, int p, int t,
-              const int8_t *As, const int32_t *Ae, const uint64_t *Al, int64_t a_rs, int64_t a_cs,
-              const int8_t *Bs, const int32_t *Be, const uint64_t *Bl, int64_t b_rs, int64_t b_cs,
-              int64_t nsel, const int64_t *sel_i, const int64_t *sel_j,
-              int32_t *e_out, int32_t *f_out,
-              int nlc, uint64_t *chat_mag, int8_t *chat_sign,
-              int8_t *c_sign, int32_t *c_exp, uint64_t *c_limbs) {
+int oz2o_gemm_scaled(int64_t M, int64_t N, int64_t K, int p,
+                     int ta, const int8_t *As, const int32_t *Ae, const uint64_t *Al,
+                     int64_t a_rs, int64_t a_cs, const int32_t *a_koff, const int32_t *a_efix,
+                     int tb, const int8_t *Bs, const int32_t *Be, const uint64_t *Bl,
+                     int64_t b_rs, int64_t b_cs, const int32_t *b_koff, const int32_t *b_efix,
+                     int64_t nsel, const int64_t *sel_i, const int64_t *sel_j,
+                     int32_t *e_out, int32_t *f_out,
+                     int nlc, uint64_t *chat_mag, int8_t *chat_sign,
+                     int8_t *c_sign, int32_t *c_exp, uint64_t *c_limbs) {
     opnd A = {As, Ae, Al, a_rs, a_cs, (p + 63) / 64};
     opnd B = {Bs, Be, Bl, b_rs, b_cs, (p + 63) / 64};
-    int na = (t + 1 + 63) / 64;
-    int nacc = (2 * t + ceil_log2_i64(K) + 2 + 63) / 64 + 1;
+    int tmax = ta > tb ? ta : tb;
+    int na = (tmax + 1 + 63) / 64 + 1;   /* one spare limb to detect a too-wide integer */
+    int nacc = (ta + tb + ceil_log2_i64(K) + 2 + 63) / 64 + 1;
     int nl = (p + 63) / 64;
     int64_t nout = sel_i ? nsel : M * N;
 
@@ -283,28 +303,34 @@ int oz2o_gemm(int64_t M, int64_t N, int64_t K, int p, int t,
     int8_t *cbs = malloc((size_t)(nc * K > 0 ? nc * K : 1));
     uint64_t *ram = malloc(sizeof(uint64_t) * (size_t)(nr * K * na > 0 ? nr * K * na : 1));
     uint64_t *cbm = malloc(sizeof(uint64_t) * (size_t)(nc * K * na > 0 ? nc * K * na : 1));
+    int status = 0;
 
     /* steps 1-2: shared exponents and integer matrices (Eq. 1) */
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for schedule(dynamic, 1) reduction(min : status)
     for (int64_t r = 0; r < nr; r++) {
         int64_t i = rlist[r];
-        er[r] = shared_exponent(&A, i * a_rs, a_cs, K);
-        for (int64_t k = 0; k < K; k++)
-            ras[r * K + k] = (int8_t)integerize_entry(&A, i * a_rs + k * a_cs, p, t, er[r],
-                                                      ram + (r * K + k) * na, na);
+        er[r] = a_efix ? a_efix[i] : shared_exponent(&A, i * a_rs, a_cs, K, a_koff);
+        for (int64_t k = 0; k < K; k++) {
+            uint64_t *m = ram + (r * K + k) * na;
+            ras[r * K + k] = (int8_t)integerize_entry(&A, i * a_rs + k * a_cs, p, ta,
+                                                      a_koff ? a_koff[k] : 0, er[r], m, na);
+            if (bn_bitlen(m, na) > ta + 1) status = -3;
+        }
     }
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for schedule(dynamic, 1) reduction(min : status)
     for (int64_t c = 0; c < nc; c++) {
         int64_t j = clist[c];
-        fc[c] = shared_exponent(&B, j * b_cs, b_rs, K);
-        for (int64_t k = 0; k < K; k++)
-            cbs[c * K + k] = (int8_t)integerize_entry(&B, k * b_rs + j * b_cs, p, t, fc[c],
-                                                      cbm + (c * K + k) * na, na);
+        fc[c] = b_efix ? b_efix[j] : shared_exponent(&B, j * b_cs, b_rs, K, b_koff);
+        for (int64_t k = 0; k < K; k++) {
+            uint64_t *m = cbm + (c * K + k) * na;
+            cbs[c * K + k] = (int8_t)integerize_entry(&B, k * b_rs + j * b_cs, p, tb,
+                                                      b_koff ? b_koff[k] : 0, fc[c], m, na);
+            if (bn_bitlen(m, na) > tb + 1) status = -3;
+        }
     }
     if (e_out) for (int64_t i = 0; i < M; i++) if (rmap[i] >= 0) e_out[i] = er[rmap[i]];
     if (f_out) for (int64_t j = 0; j < N; j++) if (cmap[j] >= 0) f_out[j] = fc[cmap[j]];
 
-    int status = 0;
     /* steps 3-4: exact c^ and the final rounding (Eq. 2) */
 #pragma omp parallel for schedule(dynamic, 16) reduction(min : status)
     for (int64_t s = 0; s < nout; s++) {
@@ -333,12 +359,25 @@ int oz2o_gemm(int64_t M, int64_t N, int64_t K, int p, int t,
             }
         }
         if (c_limbs) {
-            int64_t scale = (int64_t)er[r] + fc[c] - 2 * (int64_t)t;
+            int64_t scale = (int64_t)er[r] + fc[c] - (int64_t)ta - tb;
             if (round_out(sgn, mag, nacc, scale, p, c_sign + s, c_exp + s, c_limbs + s * nl))
-                status = -2;
+                if (status > -2) status = -2;
         }
     }
     free(rmap); free(cmap); free(rlist); free(clist); free(er); free(fc);
     free(ras); free(cbs); free(ram); free(cbm);
     return status;
+}
+
+/* The forward product: both sides at width t, exponents computed (Eqs. 1-3). */
+int oz2o_gemm(int64_t M, int64_t N, int64_t K, int p, int t,
+              const int8_t *As, const int32_t *Ae, const uint64_t *Al, int64_t a_rs, int64_t a_cs,
+              const int8_t *Bs, const int32_t *Be, const uint64_t *Bl, int64_t b_rs, int64_t b_cs,
+              int64_t nsel, const int64_t *sel_i, const int64_t *sel_j,
+              int32_t *e_out, int32_t *f_out,
+              int nlc, uint64_t *chat_mag, int8_t *chat_sign,
+              int8_t *c_sign, int32_t *c_exp, uint64_t *c_limbs) {
+    return oz2o_gemm_scaled(M, N, K, p, t, As, Ae, Al, a_rs, a_cs, NULL, NULL,
+                            t, Bs, Be, Bl, b_rs, b_cs, NULL, NULL, nsel, sel_i, sel_j,
+                            e_out, f_out, nlc, chat_mag, chat_sign, c_sign, c_exp, c_limbs);
 }

@@ -20,6 +20,19 @@ with sign in {-1, 0, +1} (0 is the number zero) and 0 <= mant < 2^p; bits of
 the stored significand at or above p are ignored.  Outputs are normalised:
 2^(p-1) <= mant < 2^p, or (0, 0, 0) for zero.
 
+Backward products (autograd form; the paper has no backward, so this is a
+reading): for C = A B and an upstream gradient W = dL/dC,
+  dA = W B^T  and  dB = A^T W,
+formed either by re-integerizing B^T and A^T as ordinary operands
+(oz2_gemm_ref on the transposes), or by reusing the forward's a^, b^ with the
+exponents folded into W:
+  h_i    = max_j (exp W_ij + f_j),  W'_ij = round(W_ij 2^(t_wA + f_j - h_i))
+  dA_ik  = round_p( (sum_j W'_ij b^_kj) 2^(h_i - t_wA - t) )
+  g_j    = max_i (exp W_ij + e_i),  W''_ij = round(W_ij 2^(t_wB + e_i - g_j))
+  dB_kj  = round_p( (sum_i a^_ik W''_ij) 2^(g_j - t_wB - t) )
+with t_wA = p + g + ceil(log2 N) and t_wB = p + g + ceil(log2 M) (Eq. 3's rule
+for the backward contraction lengths).
+
 Readings of the paper that this file takes (listed with the others in the
 design notes): round() is round-to-nearest-even on the exact dyadic value;
 the final rounding is nearest-even; an all-zero row/column gets exponent 0;
@@ -120,3 +133,36 @@ def oz2_gemm_ref(A, B, guard_bits: int = 16, t_bits: int = 0):
     C = [[round_to_precision(chat[i][j], e[i] + f[j] - 2 * t, p)
           for j in range(len(f))] for i in range(len(e))]
     return {"t": t, "e": e, "f": f, "Ah": Ah, "Bh": Bh, "chat": chat, "C": C}
+
+
+def backward_widths(p: int, M: int, N: int, K: int, guard_bits: int = 16, t_bits: int = 0):
+    """(t, t_wA, t_wB): forward width and the widths of W for dA and dB."""
+    return (internal_width(p, K, guard_bits, t_bits), p + guard_bits + ceil_log2(N),
+            p + guard_bits + ceil_log2(M))
+
+
+def oz2_grad_ref(A, B, W, guard_bits: int = 16, t_bits: int = 0):
+    """Backward products reusing the forward's integer matrices (exponent folding)."""
+    p = A.p
+    M, K = A.sign.shape
+    N = B.sign.shape[1]
+    t, twa, twb = backward_widths(p, M, N, K, guard_bits, t_bits)
+    Ah, Bh, e, f = scaled_matrices(A, B, t)          # the forward's saved integers
+    w = [[W.value_parts(i, j) for j in range(N)] for i in range(M)]
+    # dA: W scaled per row after folding 2^(f_j) into column j
+    h = [shared_exponent([(s, m, x + f[j]) for j, (s, m, x) in enumerate(w[i])]) for i in range(M)]
+    Wa = [[integerize(s, m, x + f[j], h[i], twa, p) for j, (s, m, x) in enumerate(w[i])]
+          for i in range(M)]
+    chat_a = [[sum(Wa[i][j] * Bh[j][k] for j in range(N)) for k in range(K)] for i in range(M)]
+    dA = [[round_to_precision(chat_a[i][k], h[i] - twa - t, p) for k in range(K)]
+          for i in range(M)]
+    # dB: W scaled per column after folding 2^(e_i) into row i
+    g = [shared_exponent([(w[i][j][0], w[i][j][1], w[i][j][2] + e[i]) for i in range(M)])
+         for j in range(N)]
+    Wb = [[integerize(w[i][j][0], w[i][j][1], w[i][j][2] + e[i], g[j], twb, p) for i in range(M)]
+          for j in range(N)]
+    chat_b = [[sum(Ah[i][k] * Wb[j][i] for i in range(M)) for j in range(N)] for k in range(K)]
+    dB = [[round_to_precision(chat_b[k][j], g[j] - twb - t, p) for j in range(N)]
+          for k in range(K)]
+    return {"t": t, "tw": (twa, twb), "e": e, "f": f, "h": h, "g": g,
+            "chat_a": chat_a, "chat_b": chat_b, "dA": dA, "dB": dB}

@@ -5,7 +5,8 @@ format; it holds none of the method's arithmetic.  Both the oracle's tests
 and the GPU path's tests/bench take their inputs from here.
 """
 from .gen import (MPMatrix, splitmix64, mp_random, mp_zeros, operands_for,
-                  limbs_for, CONFIG_SEED_BASE)
+                  mp_unit_uniform, grad_operands_for, limbs_for, CONFIG_SEED_BASE)
 
 __all__ = ["MPMatrix", "splitmix64", "mp_random", "mp_zeros", "operands_for",
+           "mp_unit_uniform", "grad_operands_for",
            "limbs_for", "CONFIG_SEED_BASE"]

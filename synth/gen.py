@@ -117,6 +117,76 @@ def mp_random(seed: int, rows: int, cols: int, p: int, elo: int, ehi: int,
                     limbs.reshape(rows, cols, nl), p)
 
 
+def mp_unit_uniform(seed: int, rows: int, cols: int, p: int, counter: int = 0,
+                    chunk_entries: int = 1 << 20) -> MPMatrix:
+    """Random +-u 2^-p with u uniform on [0, 2^p), stored normalised (|x| < 1).
+
+    Per entry 1 + nl draws: the sign from bit 0 of the first, u from the next nl
+    (masked to p bits).  A zero u gives the number zero.
+    """
+    if p < 2:
+        raise ValueError("p must be >= 2")
+    nl = limbs_for(p)
+    per = 1 + nl
+    total = rows * cols
+    sign = np.empty(total, np.int8)
+    exp = np.empty(total, np.int32)
+    limbs = np.empty((total, nl), np.uint64)
+    top_bits = p - 64 * (nl - 1)
+    top_mask = np.uint64(MASK64 >> (64 - top_bits))
+    for e0 in range(0, total, chunk_entries):
+        ne = min(chunk_entries, total - e0)
+        d = splitmix64(seed, counter + e0 * per, ne * per).reshape(ne, per)
+        u = d[:, 1:].copy()
+        u[:, nl - 1] &= top_mask
+        # bit length of u, from its highest nonzero limb
+        blen = np.zeros(ne, np.int64)
+        for w in range(nl):
+            x = u[:, w]
+            nz = x != 0
+            bl = np.zeros(ne, np.int64)
+            xf = x[nz]
+            b = np.zeros(xf.size, np.int64)
+            for sh in (32, 16, 8, 4, 2, 1):          # integer log2 by halving
+                big = (xf >> np.uint64(sh)) != 0
+                b[big] += sh
+                xf = np.where(big, xf >> np.uint64(sh), xf)
+            bl[nz] = b + 1 + 64 * w
+            blen = np.where(nz, bl, blen)
+        # left-align u to p bits: shift by p - blen (a multi-limb shift)
+        s_all = np.where(blen > 0, p - blen, 0)
+        out = np.zeros_like(u)
+        for w in range(nl):
+            acc = np.zeros(ne, np.uint64)
+            for src in range(nl):
+                off = 64 * (w - src)                  # bit offset of limb src into limb w
+                sh = s_all - off                      # left shift needed for this pair
+                lft = (sh >= 0) & (sh < 64)
+                rgt = (sh < 0) & (sh > -64)
+                acc |= np.where(lft, u[:, src] << np.clip(sh, 0, 63).astype(np.uint64), 0
+                                ).astype(np.uint64)
+                acc |= np.where(rgt, u[:, src] >> np.clip(-sh, 0, 63).astype(np.uint64), 0
+                                ).astype(np.uint64)
+            out[:, w] = acc
+        out[:, nl - 1] &= top_mask
+        zero = blen == 0
+        sign[e0:e0 + ne] = np.where(zero, 0,
+                                    np.where((d[:, 0] & np.uint64(1)) == 1, -1, 1)).astype(np.int8)
+        exp[e0:e0 + ne] = np.where(zero, 0, blen - p).astype(np.int32)
+        limbs[e0:e0 + ne] = out
+    return MPMatrix(sign.reshape(rows, cols), exp.reshape(rows, cols),
+                    limbs.reshape(rows, cols, nl), p)
+
+
+def grad_operands_for(seed: int, M: int, N: int, K: int, p: int, elo: int, ehi: int):
+    """A (M x K), B (K x N) as in operands_for, then the upstream gradient W (M x N)
+    from mp_unit_uniform, all from one counter stream."""
+    per = 2 + limbs_for(p)
+    A, B = operands_for(seed, M, N, K, p, elo, ehi)
+    W = mp_unit_uniform(seed, M, N, p, counter=(M * K + K * N) * per)
+    return A, B, W
+
+
 def operands_for(seed: int, M: int, N: int, K: int, p: int, elo: int, ehi: int):
     """A (M x K) then B (K x N) from one counter stream, in that order."""
     per = 2 + limbs_for(p)
