@@ -108,6 +108,9 @@ typedef struct {
     int32_t nw32;       /* 32-bit words of an integer significand (t+1 bits)         */
     int32_t nd32;       /* 32-bit digits of the CRT accumulator: ceil(log2 P/32) + 2 */
     double log2P;       /* log2 of the moduli product P                              */
+    int32_t tw_a, tw_b; /* plans of oz2h_plan_create_grad: widths of the upstream
+                           gradient for dA and dB (0 otherwise)                      */
+    int64_t grad_M, grad_N; /* and the forward's M and N (0 otherwise)              */
 } oz2h_plan_info;
 
 /* Default options: guard_bits 16, t_bits 0, crt_margin 2, tile AUTO, flags 0. */
@@ -191,6 +194,69 @@ int oz2h_gemm_integers(const oz2h_plan *plan, int64_t M, int64_t N, int64_t K,
                        int8_t *chat_sign, uint64_t *chat_mag, int32_t nlc,
                        int32_t *e, int32_t *f,
                        void *workspace, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------- autograd form: backward products ---------------- */
+
+/*
+ * Plan for a forward product C = A B (op(A) M x K, op(B) K x N) AND its two
+ * backward products for an upstream gradient W = dL/dC (M x N, p bits):
+ *   dA = W B^T (M x K)  and  dB = A^T W (K x N).
+ * The paper defines no backward pass; the backward reuses the forward's
+ * integer matrices (Eq. 1) by folding their scale factors into W:
+ *   dA: h_i = max_j (exp W_ij + f_j), W'_ij = RNE(W_ij 2^(t_wA + f_j - h_i)),
+ *       dA_ik = RNE_p( (sum_j W'_ij b^_kj) 2^(h_i - t_wA - t) );
+ *   dB: g_j = max_i (exp W_ij + e_i), W''_ij = RNE(W_ij 2^(t_wB + e_i - g_j)),
+ *       dB_kj = RNE_p( (sum_i a^_ik W''_ij) 2^(g_j - t_wB - t) ),
+ * where a^, b^, e, f, t are the forward's and t_wA = p + g + ceil(log2 N),
+ * t_wB = p + g + ceil(log2 M) (Eq. 3's rule for the backward contraction
+ * lengths).  The moduli are the prefix of the oz2h_plan_moduli list with
+ *   log2 P > max(2t + ceil(log2 K), t + t_wA + ceil(log2 N), t + t_wB + ceil(log2 M))
+ *            + crt_margin,
+ * so every |c^| < P/2 (Eq. crtcond for each product).  The plan also serves
+ * oz2h_gemm / oz2h_gemm_integers with this K.  M, N <= 133000 (INT32
+ * exactness of the backward GEMMs).
+ */
+int oz2h_plan_create_grad(int32_t p, int64_t M, int64_t N, int64_t K, const oz2h_opts *o,
+                          oz2h_plan **out);
+
+/* Bytes of device workspace oz2h_gemm_backward needs (0 for a plan of another kind). */
+size_t oz2h_gemm_backward_workspace_size(const oz2h_plan *plan);
+
+/*
+ * Backward products from the saved forward.  `saved` is the workspace of a
+ * completed oz2h_gemm or oz2h_gemm_integers call with this plan and these M, N
+ * (earlier on `stream`, or synchronised); its exponents e, f and integer
+ * residue planes are read, not written, so one forward serves any number of
+ * backward calls.  W is M x N, not transposed.  dA (M x K) and dB (K x N) are
+ * outputs; either pointer may be NULL to skip that product.  The residue
+ * planes of the saved forward are re-laid out for the backward contractions
+ * (over j for dA, over i for dB) by a transpose kernel into the workspace.
+ */
+int oz2h_gemm_backward(const oz2h_plan *plan, int64_t M, int64_t N, int64_t K,
+                       const void *saved, size_t saved_bytes, oz2h_cmat W,
+                       const oz2h_mat *dA, const oz2h_mat *dB,
+                       void *workspace, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Float64 carriers of p-bit matrices, for frameworks whose differentiable
+ * tensors must be floating point.  A carrier of a rows x cols matrix is a dense
+ * rows x cols x (2 + 2 nl) array of doubles (nl = ceil(p/64)); element (r, c)
+ * starts at carrier[(r*cols + c)*(2 + 2 nl)]:
+ *   [0]           the value truncated to 53 bits (readable; +-inf or 0 outside
+ *                 the double range), ignored by unpack;
+ *   [1]           4 exp + sign + 1, an exact integer;
+ *   [2+2l, 3+2l]  the low and high 32-bit halves of limb l, exact integers.
+ * Every slot unpack reads is an exactly representable integer, so a carrier
+ * survives any copy, view or device move bit for bit (but not arithmetic).
+ * pack reads X (rows x cols, leading dimension X.ld); unpack writes X.  If
+ * `bad` (a device int32, nullable) is given, unpack stores 1 there when an
+ * element is not a valid encoding of a normalised p-bit number or zero; such
+ * elements are written as zero.  It never clears `bad`.
+ */
+int oz2h_carrier_pack(int64_t rows, int64_t cols, int32_t p, oz2h_cmat X, double *carrier,
+                      hipStream_t stream);
+int oz2h_carrier_unpack(int64_t rows, int64_t cols, int32_t p, const double *carrier,
+                        oz2h_mat X, int32_t *bad, hipStream_t stream);
 
 /* ---------------- stage entry points (parity tests of single kernels) ---------------- */
 

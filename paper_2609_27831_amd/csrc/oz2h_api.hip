@@ -143,18 +143,19 @@ Layout layout_for(const PlanHost &h, int64_t M, int64_t N) {
 }
 
 // shared exponents of a rows x count side (entry (r, k) at r*rs + k*cs)
+// koff (nullable): per-contraction-index exponent offsets added before the max
 int launch_exponents(int64_t rows, int64_t count, const int8_t *sign, const int32_t *exp,
-                     int64_t rs, int64_t cs, int32_t *out, hipStream_t s) {
+                     int64_t rs, int64_t cs, const int32_t *koff, int32_t *out, hipStream_t s) {
     if (rows <= 0) return OZ2H_OK;
     const unsigned nb = (unsigned)((rows + 255) / 256);
     k_fill_i32<<<nb, 256, 0, s>>>(out, rows, INT_MIN);
     if (count > 0) {
         if (cs == 1) {
             dim3 grid((unsigned)((rows + 3) / 4), (unsigned)((count + 4095) / 4096));
-            k_exp_kcontig<<<grid, 256, 0, s>>>(sign, exp, rows, count, rs, out);
+            k_exp_kcontig<<<grid, 256, 0, s>>>(sign, exp, rows, count, rs, koff, out);
         } else {
             dim3 grid(nb, (unsigned)((count + 63) / 64));
-            k_exp_generic<<<grid, 256, 0, s>>>(sign, exp, rows, count, rs, cs, out);
+            k_exp_generic<<<grid, 256, 0, s>>>(sign, exp, rows, count, rs, cs, koff, out);
         }
     }
     k_exp_fix<<<nb, 256, 0, s>>>(out, rows);
@@ -164,15 +165,16 @@ int launch_exponents(int64_t rows, int64_t count, const int8_t *sign, const int3
 int launch_residues(const oz2h_plan *pl, int64_t rows, int64_t count, const uint64_t *limbs,
                     const int32_t *exp, const int8_t *sign, int64_t rs, int64_t cs,
                     const int32_t *erow, int64_t rpad, int64_t kpad, int8_t *planes,
-                    hipStream_t s) {
+                    hipStream_t s, int t = -1, const int32_t *koff = nullptr) {
     const PlanHost &h = pl->h;
+    if (t < 0) t = h.t;
     const int nl = (h.p + 63) / 64;
     const int64_t ps = rpad * kpad;
     int rb = h.nw32 <= 64 ? 4 : (h.nw32 <= 128 ? 2 : 1);   // word columns <= 64 KiB per block
     dim3 grid((unsigned)(kpad / 64), (unsigned)(rpad / rb));
     const size_t lds = (size_t)h.nw32 * 64 * rb * sizeof(uint32_t);
-    const ResArgs a{limbs, exp, sign, rs, cs, rows, count, kpad, ps, erow, h.p, nl, h.t, h.nw32,
-                    pl->d_resid, pl->d_info, h.L, h.lgroups, planes};
+    const ResArgs a{limbs, exp, sign, rs, cs, rows, count, kpad, ps, erow, h.p, nl, t, h.nw32,
+                    pl->d_resid, pl->d_info, h.L, h.lgroups, planes, koff};
     if (rb == 4) k_residues<4><<<grid, 256, lds, s>>>(a);
     else if (rb == 2) k_residues<2><<<grid, 128, lds, s>>>(a);
     else k_residues<1><<<grid, 64, lds, s>>>(a);
@@ -201,8 +203,9 @@ int launch_resgemm(const oz2h_plan *pl, GemmCfg cfg, int64_t mpad, int64_t npad,
 int launch_crt(const oz2h_plan *pl, int64_t M, int64_t N, const int16_t *u, int64_t u_ps,
                int64_t ldu, const int32_t *e, const int32_t *f, bool round, bool weight,
                int8_t *osign, int32_t *oexp, uint64_t *olimbs, int64_t ldc, uint64_t *chat,
-               int nlc, hipStream_t s) {
+               int nlc, hipStream_t s, int tsum = -1) {
     const PlanHost &h = pl->h;
+    if (tsum < 0) tsum = 2 * h.t;
     if (M * N == 0) return OZ2H_OK;
     // two entries per thread; the LDS digit columns (nd32 words per entry) stay <= 64 KiB
     const int ept = h.nd32 <= 64 ? 2 : 1;
@@ -214,7 +217,7 @@ int launch_crt(const oz2h_plan *pl, int64_t M, int64_t N, const int16_t *u, int6
     const size_t lds = cols + (size_t)LB * (h.crt_dc + 1) * sizeof(double);
     const unsigned nb = (unsigned)((M * N + (int64_t)bd * ept - 1) / ((int64_t)bd * ept));
     const CrtArgs ca{u, u_ps, ldu, M, N, pl->d_info, h.L, pl->d_crt, h.crt_ndpad, h.crt_nc, h.nd32,
-                     pl->d_pd, pl->d_phd, e, f, h.t, h.p, osign, oexp, olimbs, ldc, chat, nlc, LB};
+                     pl->d_pd, pl->d_phd, e, f, tsum, h.p, osign, oexp, olimbs, ldc, chat, nlc, LB};
 #define OZ2H_CRT(DC, E, R, W) k_crt<DC, E, R, W><<<nb, bd, lds, s>>>(ca)
 #define OZ2H_CRT_E(DC, R, W)          \
     if (ept == 2) OZ2H_CRT(DC, 2, R, W); \
@@ -346,8 +349,8 @@ int run_pipeline(const oz2h_plan *pl, int64_t M, int64_t N, int64_t K, oz2h_op o
     const int64_t b_rs = opB == OZ2H_OP_N ? 1 : B.ld, b_cs = opB == OZ2H_OP_N ? B.ld : 1;
 
     if (ev) OZ2H_HIP(hipEventRecord(ev[0], s));
-    if ((st = launch_exponents(M, K, A.sign, A.exp, a_rs, a_cs, e, s))) return st;
-    if ((st = launch_exponents(N, K, B.sign, B.exp, b_rs, b_cs, f, s))) return st;
+    if ((st = launch_exponents(M, K, A.sign, A.exp, a_rs, a_cs, nullptr, e, s))) return st;
+    if ((st = launch_exponents(N, K, B.sign, B.exp, b_rs, b_cs, nullptr, f, s))) return st;
     if (ev) OZ2H_HIP(hipEventRecord(ev[1], s));
     if ((st = launch_residues(pl, M, K, A.limbs, A.exp, A.sign, a_rs, a_cs, e, w.mpad, w.kpad, ap, s)))
         return st;
@@ -493,6 +496,10 @@ int oz2h_plan_get_info(const oz2h_plan *plan, oz2h_plan_info *info) {
     info->nw32 = h.nw32;
     info->nd32 = h.nd32;
     info->log2P = h.log2P;
+    info->tw_a = h.grad ? h.tw[0] : 0;
+    info->tw_b = h.grad ? h.tw[1] : 0;
+    info->grad_M = h.grad ? h.gM : 0;
+    info->grad_N = h.grad ? h.gN : 0;
     return ok();
 }
 
@@ -532,6 +539,211 @@ int oz2h_gemm_integers(const oz2h_plan *plan, int64_t M, int64_t N, int64_t K, o
                         e, f, workspace, ws_bytes, stream);
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------- autograd form
+
+namespace {
+
+// Backward workspace: side 0 is dA = W B^T (M x K, contraction N), side 1 is
+// dB = A^T W (K x N, contraction M); the sides run one after the other on the
+// stream and share the same bytes.  Per side: the upstream gradient's shared
+// exponents (h for side 0 per output row, g for side 1 per output column), the
+// left and right INT8 planes of the product, and its weighted residues v.
+struct BwdLayout {
+    GemmCfg cfg[2];
+    int64_t mpad[2], npad[2], kpad[2];
+    size_t off_x[2], off_l[2], off_r[2], off_v[2];
+    size_t total;
+};
+
+BwdLayout bwd_layout(const PlanHost &h) {
+    BwdLayout b{};
+    const int64_t M = h.gM, N = h.gN, K = h.K;
+    const int64_t orows[2] = {M, K}, ocols[2] = {K, N}, contr[2] = {N, M};
+    for (int sd = 0; sd < 2; ++sd) {
+        b.cfg[sd] = choose_gemm(orows[sd], ocols[sd], h.tile);
+        b.mpad[sd] = round_up(orows[sd], b.cfg[sd].bm);
+        b.npad[sd] = round_up(ocols[sd], b.cfg[sd].bn);
+        b.kpad[sd] = round_up(contr[sd], GBK);
+        size_t off = 0;
+        b.off_x[sd] = off;
+        off = align_up(off + sizeof(int32_t) * (sd == 0 ? b.mpad[sd] : b.npad[sd]));
+        b.off_l[sd] = off;
+        off = align_up(off + (size_t)h.G * b.mpad[sd] * b.kpad[sd]);
+        b.off_r[sd] = off;
+        off = align_up(off + (size_t)h.G * b.npad[sd] * b.kpad[sd]);
+        b.off_v[sd] = off;
+        off = align_up(off + sizeof(int16_t) * (size_t)h.L * b.mpad[sd] * b.npad[sd]);
+        b.total = std::max(b.total, off);
+    }
+    return b;
+}
+
+// saved planes [G][R rows][ldi] (rows r < R, columns c < C valid) -> [G][Co][Ro]
+int launch_plane_transpose(const int8_t *in, int64_t R, int64_t C, int64_t ldi, int64_t ips,
+                           int8_t *out, int64_t Ro, int64_t Co, int G, hipStream_t s) {
+    dim3 grid((unsigned)(Co / 64), (unsigned)(Ro / 64), (unsigned)G);
+    k_plane_transpose<<<grid, 256, 0, s>>>(in, R, C, ldi, ips, out, Ro, Co, (int64_t)Co * Ro);
+    return check_launch("plane transpose");
+}
+
+int check_mat_out(const oz2h_mat *X, const char *name, int64_t cols) {
+    if (!X->limbs || !X->exp || !X->sign) return fail(OZ2H_EINVAL, "%s: NULL pointer", name);
+    if (X->ld < std::max<int64_t>(cols, 1)) return fail(OZ2H_EINVAL, "%s: ld < %lld", name, (long long)cols);
+    return OZ2H_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int oz2h_plan_create_grad(int32_t p, int64_t M, int64_t N, int64_t K, const oz2h_opts *o,
+                          oz2h_plan **out) {
+    if (!out) return fail(OZ2H_EINVAL, "out is NULL");
+    *out = nullptr;
+    oz2h_opts d;
+    oz2h_opts_default(&d);
+    if (!o) o = &d;
+    if (o->flags) return fail(OZ2H_EINVAL, "flags must be 0");
+    if (o->tile < OZ2H_TILE_AUTO || o->tile > OZ2H_TILE_128x256) return fail(OZ2H_EINVAL, "bad tile");
+    if (M < 1 || N < 1) return fail(OZ2H_EINVAL, "M and N must be >= 1");
+    if (M > kMaxK || N > kMaxK)
+        return fail(OZ2H_ERANGE, "M and N are backward contraction lengths: at most 133000");
+    std::vector<uint32_t> mods;
+    int t = 0;
+    double lp = 0;
+    std::string err;
+    // forward set first: validates p, K and the options and gives t (Eq. 3)
+    int st = select_moduli(p, K, o->guard_bits, o->t_bits, o->crt_margin, mods, t, lp, err);
+    if (st) return fail(st, "%s", err.c_str());
+    const int twa = p + o->guard_bits + ceil_log2(N), twb = p + o->guard_bits + ceil_log2(M);
+    const double need = std::max({2.0 * t + ceil_log2(K), (double)t + twa + ceil_log2(N),
+                                  (double)t + twb + ceil_log2(M)}) + o->crt_margin;
+    st = select_moduli_bits(need, mods, lp, err);
+    if (st) return fail(st, "%s", err.c_str());
+    oz2h_plan *pl = new oz2h_plan();
+    st = build_plan(p, t, K, mods, pl->h, err, std::max(twa, twb));
+    if (st) {
+        delete pl;
+        return fail(st, "%s", err.c_str());
+    }
+    pl->h.tile = o->tile;
+    pl->h.grad = true;
+    pl->h.gM = M;
+    pl->h.gN = N;
+    pl->h.tw[0] = twa;
+    pl->h.tw[1] = twb;
+    return plan_finish(pl, out);
+}
+
+size_t oz2h_gemm_backward_workspace_size(const oz2h_plan *plan) {
+    if (!plan || !plan->h.grad) return 0;
+    return bwd_layout(plan->h).total;
+}
+
+int oz2h_gemm_backward(const oz2h_plan *plan, int64_t M, int64_t N, int64_t K, const void *saved,
+                       size_t saved_bytes, oz2h_cmat W, const oz2h_mat *dA, const oz2h_mat *dB,
+                       void *workspace, size_t ws_bytes, hipStream_t stream) {
+    int st = check_plan(plan);
+    if (st) return st;
+    const PlanHost &h = plan->h;
+    if (!h.grad) return fail(OZ2H_EINVAL, "plan was not created by oz2h_plan_create_grad");
+    if (M != h.gM || N != h.gN || K != h.K)
+        return fail(OZ2H_EINVAL, "shape %lld x %lld x %lld differs from the plan's %lld x %lld x %lld",
+                    (long long)M, (long long)N, (long long)K, (long long)h.gM, (long long)h.gN,
+                    (long long)h.K);
+    if (!dA && !dB) return ok();
+    if ((st = check_cmat(W, "W", M, N))) return st;
+    if (dA && (st = check_mat_out(dA, "dA", K))) return st;
+    if (dB && (st = check_mat_out(dB, "dB", N))) return st;
+    const Layout f = layout_for(h, M, N);
+    if (!saved) return fail(OZ2H_EINVAL, "saved forward workspace is NULL");
+    if (((uintptr_t)saved) % kAlign) return fail(OZ2H_EINVAL, "saved workspace must be 256-byte aligned");
+    if (saved_bytes < f.total)
+        return fail(OZ2H_EINVAL, "saved workspace too small: %zu < %zu bytes", saved_bytes, f.total);
+    const BwdLayout b = bwd_layout(h);
+    if (!workspace) return fail(OZ2H_EINVAL, "workspace is NULL");
+    if (((uintptr_t)workspace) % kAlign) return fail(OZ2H_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < b.total)
+        return fail(OZ2H_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, b.total);
+    const char *sv = (const char *)saved;
+    const int32_t *e = (const int32_t *)(sv + f.off_e);
+    const int32_t *fc = (const int32_t *)(sv + f.off_f);
+    const int8_t *ah = (const int8_t *)(sv + f.off_a);
+    const int8_t *bh = (const int8_t *)(sv + f.off_b);
+    char *wb = (char *)workspace;
+    const int twsum[2] = {h.t + h.tw[0], h.t + h.tw[1]};
+    if (dA) {   // dA = W B^T: W' rows (exponents folded with f), B^ read transposed
+        int32_t *hx = (int32_t *)(wb + b.off_x[0]);
+        int8_t *lp = (int8_t *)(wb + b.off_l[0]), *rp = (int8_t *)(wb + b.off_r[0]);
+        int16_t *v = (int16_t *)(wb + b.off_v[0]);
+        if ((st = launch_exponents(M, N, W.sign, W.exp, W.ld, 1, fc, hx, stream))) return st;
+        if ((st = launch_residues(plan, M, N, W.limbs, W.exp, W.sign, W.ld, 1, hx, b.mpad[0],
+                                  b.kpad[0], lp, stream, h.tw[0], fc)))
+            return st;
+        if ((st = launch_plane_transpose(bh, N, K, f.kpad, f.npad * f.kpad, rp, b.kpad[0],
+                                         b.npad[0], h.G, stream)))
+            return st;
+        if ((st = launch_resgemm(plan, b.cfg[0], b.mpad[0], b.npad[0], b.kpad[0], lp, rp, v, stream)))
+            return st;
+        if ((st = launch_crt(plan, M, K, v, b.mpad[0] * b.npad[0], b.npad[0], hx, nullptr, true,
+                             false, dA->sign, dA->exp, dA->limbs, dA->ld, nullptr, 0, stream,
+                             twsum[0])))
+            return st;
+    }
+    if (dB) {   // dB = A^T W: A^ read transposed, W'' columns (exponents folded with e)
+        int32_t *gx = (int32_t *)(wb + b.off_x[1]);
+        int8_t *lp = (int8_t *)(wb + b.off_l[1]), *rp = (int8_t *)(wb + b.off_r[1]);
+        int16_t *v = (int16_t *)(wb + b.off_v[1]);
+        if ((st = launch_exponents(N, M, W.sign, W.exp, 1, W.ld, e, gx, stream))) return st;
+        if ((st = launch_residues(plan, N, M, W.limbs, W.exp, W.sign, 1, W.ld, gx, b.npad[1],
+                                  b.kpad[1], rp, stream, h.tw[1], e)))
+            return st;
+        if ((st = launch_plane_transpose(ah, M, K, f.kpad, f.mpad * f.kpad, lp, b.kpad[1],
+                                         b.mpad[1], h.G, stream)))
+            return st;
+        if ((st = launch_resgemm(plan, b.cfg[1], b.mpad[1], b.npad[1], b.kpad[1], lp, rp, v, stream)))
+            return st;
+        if ((st = launch_crt(plan, K, N, v, b.mpad[1] * b.npad[1], b.npad[1], nullptr, gx, true,
+                             false, dB->sign, dB->exp, dB->limbs, dB->ld, nullptr, 0, stream,
+                             twsum[1])))
+            return st;
+    }
+    return ok();
+}
+
+int oz2h_carrier_pack(int64_t rows, int64_t cols, int32_t p, oz2h_cmat X, double *carrier,
+                      hipStream_t stream) {
+    int dev = -1;
+    int st = check_device(&dev);
+    if (st) return st;
+    if (rows < 0 || cols < 0 || p < 2) return fail(OZ2H_EINVAL, "bad shape or p");
+    if (rows * cols == 0) return ok();
+    if (!carrier || (st = check_cmat(X, "X", rows, cols))) return st ? st : fail(OZ2H_EINVAL, "carrier is NULL");
+    const int nl = (p + 63) / 64;
+    k_carrier_pack<<<(unsigned)((rows * cols + 255) / 256), 256, 0, stream>>>(
+        rows, cols, p, nl, X.sign, X.exp, X.limbs, X.ld, carrier);
+    st = check_launch("carrier pack");
+    return st ? st : ok();
+}
+
+int oz2h_carrier_unpack(int64_t rows, int64_t cols, int32_t p, const double *carrier, oz2h_mat X,
+                        int32_t *bad, hipStream_t stream) {
+    int dev = -1;
+    int st = check_device(&dev);
+    if (st) return st;
+    if (rows < 0 || cols < 0 || p < 2) return fail(OZ2H_EINVAL, "bad shape or p");
+    if (rows * cols == 0) return ok();
+    if (!carrier) return fail(OZ2H_EINVAL, "carrier is NULL");
+    if ((st = check_mat_out(&X, "X", cols))) return st;
+    const int nl = (p + 63) / 64;
+    k_carrier_unpack<<<(unsigned)((rows * cols + 255) / 256), 256, 0, stream>>>(
+        rows, cols, p, nl, carrier, X.sign, X.exp, X.limbs, X.ld, bad);
+    st = check_launch("carrier unpack");
+    return st ? st : ok();
+}
+
 int oz2h_exponents(int64_t rows, int64_t count, const int8_t *sign, const int32_t *exp,
                    int64_t rs, int64_t cs, int32_t *out, hipStream_t stream) {
     int dev = -1;
@@ -540,7 +752,7 @@ int oz2h_exponents(int64_t rows, int64_t count, const int8_t *sign, const int32_
     if (rows < 0 || count < 0) return fail(OZ2H_EINVAL, "negative dimension");
     if (rows == 0) return ok();
     if (!out || (count > 0 && (!sign || !exp))) return fail(OZ2H_EINVAL, "NULL pointer");
-    st = launch_exponents(rows, count, sign, exp, rs, cs, out, stream);
+    st = launch_exponents(rows, count, sign, exp, rs, cs, nullptr, out, stream);
     return st ? st : ok();
 }
 

@@ -90,7 +90,7 @@ __device__ __forceinline__ ResArgs res_args(const ProbDev &P, int side, char *ws
     return ResArgs{P.limbs[side], P.exps[side], P.signs[side], P.rs[side], P.cs[side],
                    P.rows[side], P.K, P.kpad, P.rpad[side] * P.kpad,
                    (const int32_t *)(ws + P.erow_off[side]), P.p, P.nl, P.t, P.nw32, P.resid,
-                   P.mi, P.L, P.lgroups, (int8_t *)(ws + P.planes_off[side])};
+                   P.mi, P.L, P.lgroups, (int8_t *)(ws + P.planes_off[side]), nullptr};
 }
 
 // stage 2, grouped: segment (prod, side) is a (kpad/64) x (rpad/RB) grid of blocks
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(256) void k_crt_grouped(const ProbDev *__restrict__
     const CrtArgs a{(const int16_t *)(ws + P.v_off), P.rpad[0] * P.rpad[1], P.rpad[1], P.rows[0],
                     P.rows[1], P.mi, P.L, P.crt, P.crt_ndpad, P.crt_nc, P.nd32, P.pd, P.phd,
                     (const int32_t *)(ws + P.erow_off[0]), (const int32_t *)(ws + P.erow_off[1]),
-                    P.t, P.p, P.csign, P.cexp, P.climbs, P.ldc, nullptr, 0, LB};
+                    2 * P.t, P.p, P.csign, P.cexp, P.climbs, P.ldc, nullptr, 0, LB};
     crt_block<DC, EPT, true, false>(a, (int64_t)blockIdx.x - sg.first, sdig);
 }
 

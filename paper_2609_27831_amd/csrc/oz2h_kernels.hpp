@@ -29,9 +29,12 @@ __global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v) {
 
 // rows whose entries are contiguous along the contraction (cs == 1): one wave
 // per (row, 4096-entry chunk), lanes stride 1, partial maxima combined by atomicMax
+// koff (nullable): a per-contraction-index exponent offset added before the max
+// (the exponent folding of the backward products)
 __global__ __launch_bounds__(256) void k_exp_kcontig(const int8_t *__restrict__ sign,
                                                      const int32_t *__restrict__ exps,
                                                      int64_t rows, int64_t count, int64_t rs,
+                                                     const int32_t *__restrict__ koff,
                                                      int32_t *__restrict__ out) {
     const int lane = threadIdx.x & 63;
     const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -41,7 +44,7 @@ __global__ __launch_bounds__(256) void k_exp_kcontig(const int8_t *__restrict__ 
     int m = INT_MIN;
     for (int64_t k = k0 + lane; k < k1; k += 64) {
         const int64_t idx = r * rs + k;
-        if (sign[idx]) m = max(m, exps[idx]);
+        if (sign[idx]) m = max(m, exps[idx] + (koff ? koff[k] : 0));
     }
     for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off));
     if (lane == 0 && m != INT_MIN) atomicMax(out + r, m);
@@ -51,7 +54,8 @@ __global__ __launch_bounds__(256) void k_exp_kcontig(const int8_t *__restrict__ 
 __global__ __launch_bounds__(256) void k_exp_generic(const int8_t *__restrict__ sign,
                                                      const int32_t *__restrict__ exps,
                                                      int64_t rows, int64_t count, int64_t rs,
-                                                     int64_t cs, int32_t *__restrict__ out) {
+                                                     int64_t cs, const int32_t *__restrict__ koff,
+                                                     int32_t *__restrict__ out) {
     const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (r >= rows) return;
     const int64_t k0 = (int64_t)blockIdx.y * 64;
@@ -59,7 +63,7 @@ __global__ __launch_bounds__(256) void k_exp_generic(const int8_t *__restrict__ 
     int m = INT_MIN;
     for (int64_t k = k0; k < k1; ++k) {
         const int64_t idx = r * rs + k * cs;
-        if (sign[idx]) m = max(m, exps[idx]);
+        if (sign[idx]) m = max(m, exps[idx] + (koff ? koff[k] : 0));
     }
     if (m != INT_MIN) atomicMax(out + r, m);
 }
@@ -72,18 +76,39 @@ __global__ void k_exp_fix(int32_t *__restrict__ p, int64_t n) {
 
 // ---------------------------------------------------------------- stage 2
 
+// global-memory views of pointers (pointers read from a descriptor are generic;
+// the casts let the compiler use global and scalar loads)
+#define OZ2H_G(T) const __attribute__((address_space(1))) T
+typedef __attribute__((address_space(1))) int8_t g_i8;
+
+// a ModInfo record read through a global-memory pointer (field by field: the
+// implicit copy constructor does not bind to an address-space-qualified object)
+__device__ __forceinline__ ModInfo load_info(OZ2H_G(ModInfo) *p) {
+    ModInfo r;
+    r.m = p->m;
+    r.g0 = p->g0;
+    r.nprod = p->nprod;
+    r.minv = p->minv;
+    r.inv_m = p->inv_m;
+    r.kc[0] = p->kc[0];
+    r.kc[1] = p->kc[1];
+    r.kc[2] = p->kc[2];
+    r.pad = 0;
+    return r;
+}
+
 // limb i of a significand (bits at or above p masked off; out of range -> 0),
 // branch-free: the index is clamped and the value selected, so that the
 // compiler can issue the loads of all words back to back
-__device__ __forceinline__ uint64_t glimb(const uint64_t *__restrict__ sl, int nl, uint64_t topmask,
-                                          int64_t i) {
+__device__ __forceinline__ uint64_t glimb(OZ2H_G(uint64_t) *__restrict__ sl, int nl,
+                                          uint64_t topmask, int64_t i) {
     const int ii = (int)min(max(i, (int64_t)0), (int64_t)(nl - 1));
     uint64_t v = sl[ii];
     v &= (ii == nl - 1) ? topmask : ~0ull;
     return (i >= 0 && i < nl) ? v : 0ull;
 }
-__device__ __forceinline__ uint32_t gbits32(const uint64_t *__restrict__ sl, int nl, uint64_t topmask,
-                                            int64_t off) {
+__device__ __forceinline__ uint32_t gbits32(OZ2H_G(uint64_t) *__restrict__ sl, int nl,
+                                            uint64_t topmask, int64_t off) {
     const int64_t q = off >> 6;
     const int r = (int)(off & 63);
     const uint64_t lo = glimb(sl, nl, topmask, q), hi = glimb(sl, nl, topmask, q + 1);
@@ -93,7 +118,7 @@ __device__ __forceinline__ uint32_t gbits32(const uint64_t *__restrict__ sl, int
 // The (t+1)-bit integer a^ = RNE(mant * 2^sh) of one entry as 32-bit words into
 // an LDS column (stride st); returns the sign after rounding (0 if a^ = 0).
 // sh = t - p + exp - e <= t - p (Eq. 1).
-__device__ __forceinline__ int build_words(const uint64_t *__restrict__ sl, int s, int64_t sh,
+__device__ __forceinline__ int build_words(OZ2H_G(uint64_t) *__restrict__ sl, int s, int64_t sh,
                                            int p, int nl, int nw32, uint32_t *col, int st) {
     if (s == 0) return 0;
     const int topbits = p - 64 * (nl - 1);
@@ -149,37 +174,53 @@ struct ResArgs {
     const ModInfo *mi;
     int L, lgroups;
     int8_t *planes;
+    const int32_t *koff;   // nullable per-contraction exponent offsets (exponent folding)
 };
 
+// The pointers are passed as __restrict__ parameters (kept as scoped no-alias
+// information when inlined), so the compiler knows that the plane stores do
+// not clobber the constant tables and reads those with scalar loads.
 template <int RB>
-__device__ __forceinline__ void residue_block(const ResArgs &a, int64_t bx, int64_t by,
-                                              uint32_t *words) {
+__device__ __forceinline__ void residue_block_r(
+    const uint64_t *__restrict__ limbs, const int32_t *__restrict__ exps,
+    const int8_t *__restrict__ signs, const int32_t *__restrict__ erow,
+    const int32_t *__restrict__ koff, const double *__restrict__ tab,
+    const ModInfo *__restrict__ mi, int8_t *__restrict__ planes, int64_t rs, int64_t cs,
+    int64_t rows, int64_t count, int64_t kpad, int64_t plane_stride, int p, int nl, int t,
+    int nw32, int L, int lgroups, int64_t bx, int64_t by, uint32_t *words) {
     constexpr int BD = 64 * RB;
     const int tid = threadIdx.x;
     const int64_t k = bx * 64 + (tid & 63);
     const int64_t r = by * RB + (tid >> 6);
-    const int p = a.p, nl = a.nl, nw32 = a.nw32, L = a.L;
-    const int64_t kpad = a.kpad, plane_stride = a.plane_stride;
-    const ModInfo *__restrict__ mi = a.mi;
 
+    OZ2H_G(int8_t) *gsigns = (OZ2H_G(int8_t) *)signs;
+    OZ2H_G(int32_t) *gexps = (OZ2H_G(int32_t) *)exps;
+    OZ2H_G(int32_t) *gerow = (OZ2H_G(int32_t) *)erow;
+    OZ2H_G(int32_t) *gkoff = (OZ2H_G(int32_t) *)koff;
     uint32_t *col = words + tid;
     int s = 0;
     int64_t sh = 0, idx = 0;
-    if (r < a.rows && k < a.count) {
-        idx = r * a.rs + k * a.cs;
-        s = a.signs[idx];
-        sh = (int64_t)a.t - p + a.exps[idx] - a.erow[r];
+    if (r < rows && k < count) {
+        idx = r * rs + k * cs;
+        s = gsigns[idx];
+        sh = (int64_t)t - p + gexps[idx] + (koff ? gkoff[k] : 0) - gerow[r];
     }
-    s = build_words(a.limbs + idx * nl, s, sh, p, nl, nw32, col, BD);
+    s = build_words((OZ2H_G(uint64_t) *)limbs + idx * nl, s, sh, p, nl, nw32, col, BD);
     if (s == 0)
         for (int w = 0; w < nw32; ++w) col[w * BD] = 0;
 
-    int8_t *out = a.planes + r * kpad + k;
-    for (int grp = 0; grp < a.lgroups; ++grp) {
+    // the tables live in global memory: say so, so that pointers read from a
+    // descriptor (the grouped kernels) still qualify for scalar loads
+    typedef const __attribute__((address_space(1))) double gdouble;
+    typedef const __attribute__((address_space(1))) ModInfo gmodinfo;
+    gdouble *gtab = (gdouble *)tab;
+    gmodinfo *gmi = (gmodinfo *)mi;
+    g_i8 *out = (g_i8 *)planes + r * kpad + k;
+    for (int grp = 0; grp < lgroups; ++grp) {
         double acc[kModGroup];
 #pragma unroll
         for (int g = 0; g < kModGroup; ++g) acc[g] = 0.0;
-        const double *c = a.tab + (size_t)grp * nw32 * kModGroup;   // uniform: scalar loads
+        gdouble *c = gtab + (size_t)grp * nw32 * kModGroup;   // uniform: scalar loads
         for (int w = 0; w < nw32; ++w) {
             const double x = (double)col[w * BD];
 #pragma unroll
@@ -189,12 +230,12 @@ __device__ __forceinline__ void residue_block(const ResArgs &a, int64_t bx, int6
         for (int g = 0; g < kModGroup; ++g) {
             const int l = grp * kModGroup + g;
             if (l >= L) break;
-            const ModInfo info = mi[l];
+            const ModInfo info = load_info(gmi + l);
             const int hi = (int)((info.m - 1) >> 1);
             const double a = s < 0 ? -acc[g] : acc[g];
             int ri = (int)fma(-rint(a * info.inv_m), (double)info.m, a);
             if (ri > hi) ri -= (int)info.m;
-            int8_t *o = out + (int64_t)info.g0 * plane_stride;
+            g_i8 *o = out + (int64_t)info.g0 * plane_stride;
             if (info.nprod == 1) {
                 o[0] = (int8_t)ri;
             } else {
@@ -207,6 +248,14 @@ __device__ __forceinline__ void residue_block(const ResArgs &a, int64_t bx, int6
             }
         }
     }
+}
+
+template <int RB>
+__device__ __forceinline__ void residue_block(const ResArgs &a, int64_t bx, int64_t by,
+                                              uint32_t *words) {
+    residue_block_r<RB>(a.limbs, a.exps, a.signs, a.erow, a.koff, a.tab, a.mi, a.planes, a.rs,
+                        a.cs, a.rows, a.count, a.kpad, a.plane_stride, a.p, a.nl, a.t, a.nw32,
+                        a.L, a.lgroups, bx, by, words);
 }
 
 template <int RB>
@@ -486,8 +535,8 @@ struct CrtArgs {
     const double *dig;
     int ndpad, nc, nd32;
     const uint32_t *Pd, *Phd;
-    const int32_t *erow, *fcol;
-    int t, p;
+    const int32_t *erow, *fcol;   // nullable (0)
+    int tsum, p;                  // value = c^ 2^(erow + fcol - tsum); tsum = 2t in the forward
     int8_t *osign;
     int32_t *oexp;
     uint64_t *olimbs;
@@ -502,14 +551,15 @@ __device__ __forceinline__ void crt_block(const CrtArgs &a, int64_t blk, uint32_
     const int tid = threadIdx.x, bd = blockDim.x, st = bd * EPT;
     const int nd32 = a.nd32, L = a.L, LB = a.LB, ndpad = a.ndpad, p = a.p;
     const int64_t N = a.N, v_ps = a.v_ps;
-    const uint32_t *__restrict__ Pd = a.Pd;
+    // global-memory views (pointers from a descriptor are generic otherwise)
+    OZ2H_G(uint32_t) *Pd = (OZ2H_G(uint32_t) *)a.Pd;
     const uint32_t *__restrict__ Phd = a.Phd;
-    const ModInfo *__restrict__ mi = a.mi;
+    OZ2H_G(ModInfo) *mi = (OZ2H_G(ModInfo) *)a.mi;
     double *stab = (double *)(sdig + (((size_t)nd32 * st + 3) & ~(size_t)3));   // LB x DC digits
     double *sinv = stab + (size_t)LB * DC;                                      // LB x 1/m
     const int64_t MN = a.M * N;
     int64_t idx[EPT];
-    const int16_t *vp[EPT];
+    OZ2H_G(int16_t) *vp[EPT];
     bool live[EPT];
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
@@ -517,7 +567,7 @@ __device__ __forceinline__ void crt_block(const CrtArgs &a, int64_t blk, uint32_
         live[q] = idx[q] < MN;
         // a dead lane reads entry 0 (always valid) and writes nothing: no branch around loads
         const int64_t ii = live[q] ? idx[q] / N : 0, jj = live[q] ? idx[q] - ii * N : 0;
-        vp[q] = a.V + ii * a.ldv + jj;
+        vp[q] = (OZ2H_G(int16_t) *)a.V + ii * a.ldv + jj;
     }
 
     int64_t beta[EPT], carry[EPT];
@@ -536,7 +586,7 @@ __device__ __forceinline__ void crt_block(const CrtArgs &a, int64_t blk, uint32_
 #pragma unroll
             for (int d = 0; d < DC; ++d) acc[q][d] = 0.0;
         }
-        const double *dc = a.dig + c * DC;
+        OZ2H_G(double) *dc = (OZ2H_G(double) *)a.dig + c * DC;
         for (int l0 = 0; l0 < L; l0 += LB) {
             const int nlb = min(LB, L - l0);
             __syncthreads();   // the previous slice has been consumed by every thread
@@ -571,7 +621,7 @@ __device__ __forceinline__ void crt_block(const CrtArgs &a, int64_t blk, uint32_
                 for (int q = 0; q < EPT; ++q) {
                     const int raw = cur[q];
                     if (WEIGHT) {
-                        const ModInfo info = mi[l];
+                        const ModInfo info = load_info(mi + l);
                         vd[q] = (double)centred_mod((double)raw * (double)info.minv, (double)info.m, inv_m);
                     } else {
                         vd[q] = (double)raw;
@@ -622,8 +672,8 @@ __device__ __forceinline__ void crt_block(const CrtArgs &a, int64_t blk, uint32_
             if (neg) dig_neg(sd, st, nd32);
         } else {
             // R in [0, 3P): at most two subtractions of P, then the symmetric lift
-            if (dig_ge(sd, st, Pd, nd32)) dig_sub(sd, st, Pd, nd32);
-            if (dig_ge(sd, st, Pd, nd32)) dig_sub(sd, st, Pd, nd32);
+            if (dig_ge(sd, st, a.Pd, nd32)) dig_sub(sd, st, a.Pd, nd32);
+            if (dig_ge(sd, st, a.Pd, nd32)) dig_sub(sd, st, a.Pd, nd32);
             neg = !dig_ge(sd, st, Phd, nd32) ? false : true;   // x0 >= floor(P/2) ...
             if (neg) {                                         // ... and x0 != floor(P/2)
                 dig_sub(sd, st, Phd, nd32);
@@ -632,14 +682,15 @@ __device__ __forceinline__ void crt_block(const CrtArgs &a, int64_t blk, uint32_
                 dig_add(sd, st, Phd, nd32);
                 neg = !eq;
             }
-            if (neg) dig_rsub(sd, st, Pd, nd32);   // |c^| = P - x0
+            if (neg) dig_rsub(sd, st, a.Pd, nd32);   // |c^| = P - x0
         }
         int top = nd32 - 1;
         while (top >= 0 && sd[top * st] == 0) --top;
         const int64_t i = idx[q] / N, j = idx[q] - i * N;
 
         if (!ROUND) {
-            uint64_t *o = a.chat_mag + idx[q] * a.nlc;
+            __attribute__((address_space(1))) uint64_t *o =
+                (__attribute__((address_space(1))) uint64_t *)a.chat_mag + idx[q] * a.nlc;
             for (int w = 0; w < a.nlc; ++w) {
                 const uint64_t lo = (2 * w < nd32) ? sd[2 * w * st] : 0u;
                 const uint64_t hi = (2 * w + 1 < nd32) ? sd[(2 * w + 1) * st] : 0u;
@@ -649,7 +700,8 @@ __device__ __forceinline__ void crt_block(const CrtArgs &a, int64_t blk, uint32_
             continue;
         }
         const int64_t oi = i * a.ldc + j;
-        uint64_t *o = a.olimbs + oi * nl;
+        __attribute__((address_space(1))) uint64_t *o =
+            (__attribute__((address_space(1))) uint64_t *)a.olimbs + oi * nl;
         if (top < 0) {
             for (int w = 0; w < nl; ++w) o[w] = 0;
             a.osign[oi] = 0;
@@ -698,7 +750,8 @@ __device__ __forceinline__ void crt_block(const CrtArgs &a, int64_t blk, uint32_
             }
         }
         a.osign[oi] = neg ? -1 : 1;
-        a.oexp[oi] = (int32_t)(nb + (int64_t)a.erow[i] + a.fcol[j] - 2 * (int64_t)a.t);
+        a.oexp[oi] = (int32_t)(nb + (int64_t)(a.erow ? a.erow[i] : 0) + (a.fcol ? a.fcol[j] : 0) -
+                               (int64_t)a.tsum);
     }
 }
 
@@ -706,6 +759,28 @@ template <int DC, int EPT, bool ROUND, bool WEIGHT>
 __global__ __launch_bounds__(256) void k_crt(CrtArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint32_t sdig[];
     crt_block<DC, EPT, ROUND, WEIGHT>(a, blockIdx.x, sdig);
+}
+
+// planes [G][R][C] (int8, row stride ldi) -> [G][C'][R'] (row stride ldo = R'), zero
+// where the source is out of range; 64 x 64 tiles through LDS (one byte per lane,
+// coalesced on both sides)
+__global__ __launch_bounds__(256) void k_plane_transpose(const int8_t *__restrict__ in, int64_t R,
+                                                         int64_t C, int64_t ldi, int64_t ips,
+                                                         int8_t *__restrict__ out, int64_t Ro,
+                                                         int64_t Co, int64_t ops) {
+    __shared__ int8_t tile[64][65];
+    const int64_t g = blockIdx.z;
+    const int64_t c0 = (int64_t)blockIdx.x * 64, r0 = (int64_t)blockIdx.y * 64;   // source tile
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int y = ty; y < 64; y += 4) {
+        const int64_t r = r0 + y, c = c0 + tx;
+        tile[y][tx] = (r < R && c < C) ? in[g * ips + r * ldi + c] : 0;
+    }
+    __syncthreads();
+    for (int y = ty; y < 64; y += 4) {   // output row = source column
+        const int64_t orow = c0 + y, ocol = r0 + tx;
+        if (orow < Co && ocol < Ro) out[g * ops + orow * Ro + ocol] = tile[tx][y];
+    }
 }
 
 // zero output for K = 0
@@ -718,6 +793,92 @@ __global__ void k_zero_out(int8_t *__restrict__ s, int32_t *__restrict__ e,
     s[o] = 0;
     e[o] = 0;
     for (int l = 0; l < nl; ++l) limbs[o * nl + l] = 0;
+}
+
+// ---------------------------------------------------------------- float64 carriers
+// Element (r, c) of a carrier is CW = 2 + 2 nl doubles: [0] the value truncated
+// to 53 bits, [1] 4 exp + sign + 1, [2 + 2l], [3 + 2l] the 32-bit halves of limb l.
+// Every slot but [0] is an exactly representable integer, so the encoding
+// survives any copy, view or device move of a floating tensor.
+
+__global__ __launch_bounds__(256) void k_carrier_pack(int64_t rows, int64_t cols, int p, int nl,
+                                                      const int8_t *__restrict__ sign,
+                                                      const int32_t *__restrict__ exps,
+                                                      const uint64_t *__restrict__ limbs,
+                                                      int64_t ld, double *__restrict__ car) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= rows * cols) return;
+    const int64_t r = idx / cols, c = idx - r * cols, src = r * ld + c;
+    const int cw = 2 + 2 * nl;
+    double *o = car + idx * cw;
+    const int s = sign[src];
+    const int e = s ? exps[src] : 0;
+    const int top = p - 64 * (nl - 1);   // bits of the top limb, 1..64
+    uint64_t hi = 0;                     // the 64 (or p, if fewer) leading bits of mant
+    for (int l = 0; l < nl; ++l) {
+        uint64_t x = s ? limbs[src * nl + l] : 0;
+        if (l == nl - 1 && top < 64) x &= (~0ull) >> (64 - top);
+        o[2 + 2 * l] = (double)(uint32_t)x;
+        o[3 + 2 * l] = (double)(uint32_t)(x >> 32);
+        if (l == nl - 1) {
+            if (top == 64 || nl == 1) hi = x;
+            else hi = (x << (64 - top)) | (limbs[src * nl + l - 1] >> top);
+        }
+    }
+    const int hb = p < 64 ? p : 64;      // bits held in `hi`
+    double approx = 0.0;
+    if (s) {
+        const uint64_t m53 = hb > 53 ? hi >> (hb - 53) : hi;
+        const int mb = hb > 53 ? 53 : hb;
+        approx = ldexp((double)m53, e - mb);
+        if (s < 0) approx = -approx;
+    }
+    o[0] = approx;
+    o[1] = 4.0 * (double)e + (double)(s + 1);
+}
+
+// bad (nullable) gets a 1 if any element is not a valid encoding; such an
+// element is written as zero
+__global__ __launch_bounds__(256) void k_carrier_unpack(int64_t rows, int64_t cols, int p, int nl,
+                                                        const double *__restrict__ car,
+                                                        int8_t *__restrict__ sign,
+                                                        int32_t *__restrict__ exps,
+                                                        uint64_t *__restrict__ limbs, int64_t ld,
+                                                        int32_t *bad) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= rows * cols) return;
+    const int64_t r = idx / cols, c = idx - r * cols, dst = r * ld + c;
+    const int cw = 2 + 2 * nl;
+    const double *in = car + idx * cw;
+    const double code = in[1];
+    bool ok = code == rint(code) && fabs(code) < 0x1p33;
+    const double q = floor(code * 0.25);
+    const int s = ok ? (int)(code - 4.0 * q) - 1 : 0;
+    const int64_t e = (int64_t)q;
+    ok = ok && s <= 1 && e >= INT_MIN && e <= INT_MAX;
+    const int top = p - 64 * (nl - 1);
+    for (int l = 0; l < nl; ++l) {
+        const double lo = in[2 + 2 * l], hi = in[3 + 2 * l];
+        ok = ok && lo == rint(lo) && hi == rint(hi) && lo >= 0.0 && hi >= 0.0 &&
+             lo < 0x1p32 && hi < 0x1p32;
+    }
+    uint64_t topl = 0, any = 0;
+    for (int l = 0; l < nl; ++l) {
+        const uint64_t x = ok ? ((uint64_t)(uint32_t)in[2 + 2 * l] |
+                                 ((uint64_t)(uint32_t)in[3 + 2 * l] << 32)) : 0;
+        if (l == nl - 1) topl = x;
+        any |= x;
+        limbs[dst * nl + l] = s && ok ? x : 0;
+    }
+    // a nonzero value must be normalised (bit p - 1 set, nothing above it), a
+    // zero must have zero limbs
+    if (ok) ok = s ? (topl >> (top - 1)) == 1 : any == 0;
+    if (!ok) {
+        for (int l = 0; l < nl; ++l) limbs[dst * nl + l] = 0;
+        if (bad) *bad = 1;
+    }
+    sign[dst] = ok ? (int8_t)s : 0;
+    exps[dst] = ok && s ? (int32_t)e : 0;
 }
 
 }  // namespace oz2h

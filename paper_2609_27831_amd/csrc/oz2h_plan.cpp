@@ -138,7 +138,10 @@ int select_moduli(int p, int64_t K, int guard_bits, int t_bits, int margin,
         err = "internal width t must be >= 1";
         return -1;
     }
-    const double need = 2.0 * t + ceil_log2(K) + margin;   // Eq. crtcond with the safety margin
+    return select_moduli_bits(2.0 * t + ceil_log2(K) + margin, mods, log2P, err);   // Eq. crtcond
+}
+
+int select_moduli_bits(double need, std::vector<uint32_t> &mods, double &log2P, std::string &err) {
     mods.clear();
     log2P = 0;
     for (uint32_t m : global_moduli()) {
@@ -154,7 +157,7 @@ int select_moduli(int p, int64_t K, int guard_bits, int t_bits, int margin,
 }
 
 int build_plan(int p, int t, int64_t K, const std::vector<uint32_t> &mods_in, PlanHost &h,
-               std::string &err) {
+               std::string &err, int wmax) {
     if (mods_in.empty() || (int)mods_in.size() > kMaxModuli) {
         err = "need 1..512 moduli";
         return -1;
@@ -181,7 +184,7 @@ int build_plan(int p, int t, int64_t K, const std::vector<uint32_t> &mods_in, Pl
     h.K = K;
     h.L = (int)mods.size();
     h.moduli = mods;
-    h.nw32 = (t + 1 + 31) / 32;
+    h.nw32 = (std::max(t, wmax) + 1 + 31) / 32;
     if (h.nw32 > kMaxWords) {
         err = "internal width t too large for the residue kernel";
         return -2;

@@ -32,7 +32,11 @@ struct PlanHost {
     int tile = 0;          // oz2h_tile hint of the residue GEMMs (0 = automatic)
     int64_t K = 0;
     int L = 0, L1 = 0, L2 = 0, G = 0;
-    int nw32 = 0;          // 32-bit words of a (t+1)-bit integer significand
+    int nw32 = 0;          // 32-bit words of the widest integer significand (t+1 bits, or
+                           // t_w+1 for the backward's upstream gradient)
+    bool grad = false;     // also covers the backward products of an M x K by K x N product
+    int64_t gM = 0, gN = 0;
+    int tw[2] = {0, 0};    // widths of the upstream gradient W for dA = W B^T and dB = A^T W
     int nd32 = 0;          // 32-bit digits of the CRT accumulator
     int lgroups = 0;       // ceil(L / kModGroup)
     int crt_dc = 0;        // CRT digit chunk (digits accumulated per pass)
@@ -59,8 +63,12 @@ const std::vector<uint32_t> &global_moduli();
 int select_moduli(int p, int64_t K, int guard_bits, int t_bits, int margin,
                   std::vector<uint32_t> &mods, int &t, double &log2P, std::string &err);
 
-// Fill every table for the given moduli (one-limb moduli must come first).
+// Greedy prefix of the global list until log2 P > need.
+int select_moduli_bits(double need, std::vector<uint32_t> &mods, double &log2P, std::string &err);
+
+// Fill every table for the given moduli (one-limb moduli must come first);
+// integer significands are up to max(t, wmax) + 1 bits wide.
 int build_plan(int p, int t, int64_t K, const std::vector<uint32_t> &mods, PlanHost &out,
-               std::string &err);
+               std::string &err, int wmax = 0);
 
 }  // namespace oz2h

@@ -50,7 +50,8 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("t", ctypes.c_int32), ("K", ctypes.c_int64),
                 ("L", ctypes.c_int32), ("L1", ctypes.c_int32), ("L2", ctypes.c_int32),
                 ("G", ctypes.c_int32), ("nw32", ctypes.c_int32), ("nd32", ctypes.c_int32),
-                ("log2P", ctypes.c_double)]
+                ("log2P", ctypes.c_double), ("tw_a", ctypes.c_int32), ("tw_b", ctypes.c_int32),
+                ("grad_M", ctypes.c_int64), ("grad_N", ctypes.c_int64)]
 
 
 class Problem(ctypes.Structure):
@@ -77,6 +78,13 @@ SIGNATURES = {
                                        Mat, _P, _SZ, _P, _P]),
     "oz2h_gemm_integers": (ctypes.c_int, [_P, _I64, _I64, _I64, ctypes.c_int, CMat, ctypes.c_int,
                                           CMat, _P, _P, _I32, _P, _P, _P, _SZ, _P]),
+    "oz2h_plan_create_grad": (ctypes.c_int, [_I32, _I64, _I64, _I64, ctypes.POINTER(Opts),
+                                             ctypes.POINTER(_P)]),
+    "oz2h_gemm_backward_workspace_size": (_SZ, [_P]),
+    "oz2h_gemm_backward": (ctypes.c_int, [_P, _I64, _I64, _I64, _P, _SZ, CMat, ctypes.POINTER(Mat),
+                                          ctypes.POINTER(Mat), _P, _SZ, _P]),
+    "oz2h_carrier_pack": (ctypes.c_int, [_I64, _I64, _I32, CMat, _P, _P]),
+    "oz2h_carrier_unpack": (ctypes.c_int, [_I64, _I64, _I32, _P, Mat, _P, _P]),
     "oz2h_exponents": (ctypes.c_int, [_I64, _I64, _P, _P, _I64, _I64, _P, _P]),
     "oz2h_residues": (ctypes.c_int, [_P, _I64, _I64, _P, _P, _P, _I64, _I64, _P, _I64, _I64, _P, _P]),
     "oz2h_residue_gemm": (ctypes.c_int, [_P, _I64, _I64, _I64, _P, _P, _P, _P]),
@@ -165,6 +173,14 @@ class Plan:
         return cls(h.value)
 
     @classmethod
+    def create_grad(cls, p: int, M: int, N: int, K: int, opts: Optional[Opts] = None) -> "Plan":
+        """Plan of an M x K by K x N product that also serves its backward products."""
+        h = ctypes.c_void_p()
+        o = opts or default_opts()
+        _check(lib().oz2h_plan_create_grad(p, M, N, K, ctypes.byref(o), ctypes.byref(h)))
+        return cls(h.value)
+
+    @classmethod
     def custom(cls, p: int, t: int, K: int, moduli: Sequence[int]) -> "Plan":
         m = np.ascontiguousarray(moduli, dtype=np.uint16)
         h = ctypes.c_void_p()
@@ -179,6 +195,9 @@ class Plan:
 
     def workspace_size(self, M: int, N: int) -> int:
         return int(lib().oz2h_gemm_workspace_size(self.handle, M, N))
+
+    def backward_workspace_size(self) -> int:
+        return int(lib().oz2h_gemm_backward_workspace_size(self.handle))
 
     def destroy(self):
         if self.handle:
@@ -366,6 +385,60 @@ def crt(plan: Plan, u, M: int, N: int, nlc: Optional[int] = None, stream=None):
     _check(lib().oz2h_crt(plan.handle, M, N, u.data_ptr(), ldu, rows * ldu, cs.data_ptr(),
                           cm.data_ptr(), nlc, _stream_ptr(stream)))
     return cs, cm
+
+
+def gemm_backward(plan: Plan, saved, W: DeviceMP, want_a: bool = True, want_b: bool = True,
+                  dA: Optional[DeviceMP] = None, dB: Optional[DeviceMP] = None, ws=None,
+                  stream=None):
+    """dA = W B^T and dB = A^T W from the forward's saved workspace (oz2h_gemm_backward).
+
+    `saved` is the workspace tensor of a completed gemm() with this grad plan."""
+    torch = _torch()
+    M, N = W.shape
+    K = plan.K
+    dev = W.sign.device
+    if want_a and dA is None:
+        dA = empty_mp(M, K, plan.p, device=dev)
+    if want_b and dB is None:
+        dB = empty_mp(K, N, plan.p, device=dev)
+    if ws is None:
+        ws = torch.empty(max(plan.backward_workspace_size(), 256), dtype=torch.uint8, device=dev)
+    ma = ctypes.byref(dA.mat()) if want_a else None
+    mb = ctypes.byref(dB.mat()) if want_b else None
+    _check(lib().oz2h_gemm_backward(plan.handle, M, N, K, saved.data_ptr(), saved.numel(),
+                                    W.cmat(), ma, mb, ws.data_ptr(), ws.numel(),
+                                    _stream_ptr(stream)))
+    return (dA if want_a else None), (dB if want_b else None)
+
+
+def carrier_width(p: int) -> int:
+    """Doubles per element of a float64 carrier: 2 + 2 ceil(p/64)."""
+    return 2 + 2 * ((p + 63) // 64)
+
+
+def carrier_pack(X: DeviceMP, out=None, stream=None):
+    """Float64 carrier [rows, cols, 2 + 2 nl] of a p-bit matrix (oz2h_carrier_pack)."""
+    torch = _torch()
+    r, c = X.shape
+    if out is None:
+        out = torch.empty((r, c, carrier_width(X.p)), dtype=torch.float64, device=X.sign.device)
+    if out.shape != (r, c, carrier_width(X.p)) or not out.is_contiguous():
+        raise ValueError("carrier must be a contiguous [rows, cols, 2 + 2 nl] float64 tensor")
+    _check(lib().oz2h_carrier_pack(r, c, X.p, X.cmat(), out.data_ptr(), _stream_ptr(stream)))
+    return out
+
+
+def carrier_unpack(car, p: int, bad=None, stream=None) -> DeviceMP:
+    """p-bit matrix from a float64 carrier (oz2h_carrier_unpack); `bad` is an optional
+    device int32 tensor that receives 1 if an element is not a valid encoding."""
+    if car.dim() != 3 or car.shape[2] != carrier_width(p) or car.dtype != _torch().float64:
+        raise ValueError(f"not a float64 carrier of {p}-bit numbers: {tuple(car.shape)}")
+    car = car.contiguous()
+    r, c = car.shape[0], car.shape[1]
+    X = empty_mp(r, c, p, device=car.device)
+    _check(lib().oz2h_carrier_unpack(r, c, p, car.data_ptr(), X.mat(),
+                                     None if bad is None else bad.data_ptr(), _stream_ptr(stream)))
+    return X
 
 
 def limbs_to_ints(mag: np.ndarray, sign: np.ndarray):
