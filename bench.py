@@ -204,6 +204,18 @@ def bench_batched(args):
     print(json.dumps(line), flush=True)
 
 
+def copy_calibration():
+    """A plain device copy of known size, for the HBM-counter scale factors."""
+    import torch
+    n = 1 << 30
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": n, "launches": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -212,12 +224,17 @@ def main():
     ap.add_argument("--config", default="cfg2", choices=sorted(CONFIGS) + ["cfg4"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB device to device three times (the reference "
+                         "kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one MI355X only; --gpus N > 1 is not supported "
               "(the multi-GPU sharding is a design, see the design notes)", file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_calibration:
+        return copy_calibration()
     if args.config == "cfg4":
         return bench_batched(args)
 
