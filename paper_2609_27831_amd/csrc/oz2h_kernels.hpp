@@ -12,6 +12,11 @@
 
 #include <climits>
 #include <cstdint>
+#include <type_traits>
+
+#ifndef OZ2H_GEMM_SCHED
+#define OZ2H_GEMM_SCHED 1
+#endif
 
 #include "oz2h_plan.hpp"
 
@@ -341,22 +346,18 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &args, int64_t mt, int6
     const int grow = tid >> 3, gch = tid & 7;
     const int64_t g_off = (int64_t)grow * kpad + gch * 16;
     const int s_off = grow * TBK + ((gch ^ (grow & 7)) << 4);   // (grow + 32 i) & 7 == grow & 7
-    v4i ra[2][AP], rb[2][BP];
-    auto gload = [&](int T, int slot) {
-        const int prod = T / nk, kt = T - prod * nk;
-        const int64_t ko = (int64_t)kt * TBK;
-        const int8_t *Ag = A + (int64_t)(g0 + prod) * a_ps + m0 * kpad + ko + g_off;
-        const int8_t *Bg = B + (int64_t)(g0 + prod) * b_ps + n0 * kpad + ko + g_off;
-#pragma unroll
-        for (int i = 0; i < AP; ++i) ra[slot][i] = *(const v4i *)(Ag + (int64_t)(32 * i) * kpad);
-#pragma unroll
-        for (int i = 0; i < BP; ++i) rb[slot][i] = *(const v4i *)(Bg + (int64_t)(32 * i) * kpad);
+    constexpr int NG = AP + BP;            // 16-byte loads per thread per k-tile
+    constexpr int KS = TBK / 32;           // MFMA k-steps per k-tile
+    constexpr int GQ = (NG + KS - 1) / KS; // loads / LDS stores issued per k-step
+    v4i rg[2][NG];
+    // tile (prod, kt) -> its global address for this thread (A rows first, then B rows)
+    auto gptr = [&](int prod, int kt, int i) -> const v4i * {
+        const int64_t ko = (int64_t)kt * TBK + g_off;
+        return i < AP ? (const v4i *)(A + (int64_t)(g0 + prod) * a_ps + (m0 + 32 * i) * kpad + ko)
+                      : (const v4i *)(B + (int64_t)(g0 + prod) * b_ps + (n0 + 32 * (i - AP)) * kpad + ko);
     };
-    auto sstore = [&](int slot, int8_t *dA, int8_t *dB) {
-#pragma unroll
-        for (int i = 0; i < AP; ++i) *(v4i *)(dA + s_off + 32 * i * TBK) = ra[slot][i];
-#pragma unroll
-        for (int i = 0; i < BP; ++i) *(v4i *)(dB + s_off + 32 * i * TBK) = rb[slot][i];
+    auto sptr = [&](int i, int8_t *dA, int8_t *dB) -> v4i * {
+        return i < AP ? (v4i *)(dA + s_off + 32 * i * TBK) : (v4i *)(dB + s_off + 32 * (i - AP) * TBK);
     };
 
     v16i acc[FM][FN];
@@ -366,23 +367,16 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &args, int64_t mt, int6
         for (int y = 0; y < FN; ++y) acc[x][y] = v16i{};
 
     // fragment reads: row R = (multiple of 32) + lane%32, logical chunk c = 2 s + lane/32;
-    // R & 7 only depends on lane, so each k-step's swizzled offset is a per-lane constant
+    // R & 7 only depends on lane, so each k-step's swizzled offset is a per-lane constant.
+    // Two fragment sets: the reads of k-step s + 1 are in flight while k-step s multiplies.
     const int frow = lane & 31;
-    auto compute = [&](const int8_t *cA, const int8_t *cB) {
+    v4i fa[2][FM], fb[2][FN];
+    auto fload = [&](int set, int ks, const int8_t *cA, const int8_t *cB) {
+        const int fo = frow * TBK + (((2 * ks + (lane >> 5)) ^ (frow & 7)) << 4);
 #pragma unroll
-        for (int ks = 0; ks < TBK / 32; ++ks) {
-            const int fo = frow * TBK + (((2 * ks + (lane >> 5)) ^ (frow & 7)) << 4);
-            v4i fa[FM], fb[FN];
+        for (int x = 0; x < FM; ++x) fa[set][x] = *(const v4i *)(cA + (wr * WM + x * 32) * TBK + fo);
 #pragma unroll
-            for (int x = 0; x < FM; ++x) fa[x] = *(const v4i *)(cA + (wr * WM + x * 32) * TBK + fo);
-#pragma unroll
-            for (int y = 0; y < FN; ++y) fb[y] = *(const v4i *)(cB + (wc * WN + y * 32) * TBK + fo);
-#pragma unroll
-            for (int x = 0; x < FM; ++x)
-#pragma unroll
-                for (int y = 0; y < FN; ++y)
-                    acc[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[x], fb[y], acc[x][y], 0, 0, 0);
-        }
+        for (int y = 0; y < FN; ++y) fb[set][y] = *(const v4i *)(cB + (wc * WN + y * 32) * TBK + fo);
     };
     // end of a product: acc = acc * w mod m, centred (|x| < 2^45 is exact in fp64)
     auto fold = [&](int prod) {
@@ -395,31 +389,92 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &args, int64_t mt, int6
                 for (int e = 0; e < 16; ++e)
                     acc[x][y][e] = centred_mod((double)acc[x][y][e] * w, md, inv_m);
     };
-    // one k-tile: LDS (c) holds tile T, registers `slot ^ 1` hold (or will hold) tile T + 1;
-    // tile T + 2 is fetched into `slot` while T is multiplied, T + 1 goes to LDS (n) after.
-    // Loads and stores are unconditional (indices clamped at the end) so that the
-    // compiler can count the loads in flight and keep two tiles of prefetch.
-    const int last = ntile - 1;
-    auto step = [&](int T, int slot, const int8_t *cA, const int8_t *cB, int8_t *nA, int8_t *nB) {
-        gload(min(T + 2, last), slot);
-        compute(cA, cB);
-        if (!RAW && (T + 1) % nk == 0) fold(T / nk);
-        sstore(slot ^ 1, nA, nB);
-        __builtin_amdgcn_s_waitcnt(lgkmcnt_imm(0));   // own LDS stores done (loads stay in flight)
-        __builtin_amdgcn_s_barrier();
+    // One k-tile.  On entry: LDS (c) holds tile T and fragment set 0 holds its k-step 0;
+    // registers `slot ^ 1` hold tile T + 1 (loads possibly still in flight).  During the
+    // k-steps, tile T + 2 (clamped to the last) is fetched into `slot` and tile T + 1 is
+    // stored from `slot ^ 1` into LDS (n), a share per k-step.  Loads and stores are
+    // unconditional (indices clamped) so the compiler counts the loads in flight.
+    auto step = [&](int slot, int lp, int lk, const int8_t *cA, const int8_t *cB, int8_t *nA,
+                    int8_t *nB) {
+        auto kstep = [&](auto kc_) {
+            constexpr int ks = decltype(kc_)::value;
+#pragma unroll
+            for (int q = 0; q < GQ; ++q) {
+                const int i = ks * GQ + q;
+                if (i < NG) rg[slot][i] = *gptr(lp, lk, i);
+            }
+            if constexpr (ks + 1 < KS) fload((ks + 1) & 1, ks + 1, cA, cB);
+#pragma unroll
+            for (int x = 0; x < FM; ++x)
+#pragma unroll
+                for (int y = 0; y < FN; ++y)
+                    acc[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[ks & 1][x], fb[ks & 1][y],
+                                                                      acc[x][y], 0, 0, 0);
+#pragma unroll
+            for (int q = 0; q < GQ; ++q) {
+                const int i = ks * GQ + q;
+                if (i < NG) *sptr(i, nA, nB) = rg[slot ^ 1][i];
+            }
+#if OZ2H_GEMM_SCHED
+            // issue order: the next k-step's fragment reads and this k-step's global loads
+            // first, then the MFMAs with this k-step's share of LDS stores between them
+            if constexpr (ks + 1 < KS) __builtin_amdgcn_sched_group_barrier(0x100, FM + FN, 0);
+            __builtin_amdgcn_sched_group_barrier(0x020, GQ, 0);
+#pragma unroll
+            for (int i = 0; i < FM * FN; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                if (i < GQ) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+            }
+#endif
+        };
+        kstep(std::integral_constant<int, 0>{});
+        kstep(std::integral_constant<int, 1>{});
+        kstep(std::integral_constant<int, 2>{});
+        kstep(std::integral_constant<int, 3>{});
+        static_assert(KS == 4, "k-tile of 128 bytes = 4 MFMA k-steps");
     };
 
-    gload(0, 0);
-    gload(min(1, last), 1);
-    sstore(0, sA0, sB0);
+#pragma unroll
+    for (int i = 0; i < NG; ++i) rg[0][i] = *gptr(0, 0, i);
+    const int t1 = min(1, ntile - 1);
+#pragma unroll
+    for (int i = 0; i < NG; ++i) rg[1][i] = *gptr(t1 / nk, t1 % nk, i);
+#pragma unroll
+    for (int i = 0; i < NG; ++i) *sptr(i, sA0, sB0) = rg[0][i];
     __builtin_amdgcn_s_waitcnt(lgkmcnt_imm(0));
     __builtin_amdgcn_s_barrier();
+    fload(0, 0, sA0, sB0);
+
+    // (cp, ck): product and k-tile of tile T; (lp, lk): of the tile fetched, min(T + 2, last)
+    int cp = 0, ck = 0;
+    int lp = min(2, ntile - 1) / nk, lk = min(2, ntile - 1) % nk;
+    auto advance = [&](int &pp, int &kk) {
+        if (pp * nk + kk < ntile - 1) {
+            if (++kk == nk) {
+                kk = 0;
+                ++pp;
+            }
+        }
+    };
+    auto finish = [&](int8_t *nA, int8_t *nB) {
+        if (!RAW && ck == nk - 1) fold(cp);
+        advance(cp, ck);
+        advance(lp, lk);
+        __builtin_amdgcn_s_waitcnt(lgkmcnt_imm(0));   // own LDS stores done (loads stay in flight)
+        __builtin_amdgcn_s_barrier();
+        fload(0, 0, nA, nB);
+    };
     int T = 0;
     for (; T + 1 < ntile; T += 2) {
-        step(T, 0, sA0, sB0, sA1, sB1);
-        step(T + 1, 1, sA1, sB1, sA0, sB0);
+        step(0, lp, lk, sA0, sB0, sA1, sB1);
+        finish(sA1, sB1);
+        step(1, lp, lk, sA1, sB1, sA0, sB0);
+        finish(sA0, sB0);
     }
-    if (T < ntile) step(T, 0, sA0, sB0, sA1, sB1);
+    if (T < ntile) {
+        step(0, lp, lk, sA0, sB0, sA1, sB1);
+        finish(sA1, sB1);
+    }
 
     // output element e of block (x, y): row 8*(e/4) + 4*(lane/32) + e%4, column lane%32;
     // the per-element row offsets are uniform, only the lane base is per lane
