@@ -118,8 +118,10 @@ GemmCfg choose_gemm(int64_t M, int64_t N, int tile) {
 struct Layout {
     GemmCfg cfg;
     int64_t mpad, npad, kpad;
-    size_t off_e, off_f, off_a, off_b, off_u, total;
+    size_t off_e, off_f, off_a, off_b, off_u, off_dig, total;
 };
+
+size_t crt_gdig_bytes(const PlanHost &h, int64_t M, int64_t N);
 
 Layout layout_for(const PlanHost &h, int64_t M, int64_t N) {
     Layout w{};
@@ -138,6 +140,15 @@ Layout layout_for(const PlanHost &h, int64_t M, int64_t N) {
     off = align_up(off + (size_t)h.G * w.npad * w.kpad);
     w.off_u = off;
     off = align_up(off + sizeof(int16_t) * (size_t)h.L * w.mpad * w.npad);
+    // digit columns of the CRT (large nd32 only): they reuse the residue planes, which
+    // are dead once the GEMMs are done, unless the planes are too small or must survive
+    // the call (a plan for backward products keeps them as the saved forward state)
+    const size_t dig = crt_gdig_bytes(h, M, N);
+    w.off_dig = w.off_a;
+    if (dig > 0 && (h.grad || dig > w.off_u - w.off_a)) {
+        w.off_dig = off;
+        off = align_up(off + dig);
+    }
     w.total = off;
     return w;
 }
@@ -200,41 +211,82 @@ int launch_resgemm(const oz2h_plan *pl, GemmCfg cfg, int64_t mpad, int64_t npad,
                                      h.L, v, mpad * npad, npad, nullptr, s);
 }
 
+// CRT launch shape.  Up to 32 digits per entry the digit columns live in LDS
+// (two entries per thread, block of 256, columns <= 48 KiB); above that, in a
+// global-memory region (GDIG) so that LDS holds only the constant slices and
+// blocks stay 256 threads wide whatever nd32 is.
+struct CrtCfg {
+    int ept, bd, LB;
+    size_t lds;
+    unsigned nb;
+    bool gdig;
+    int64_t gstride;   // entries per digit row of the global columns
+};
+
+CrtCfg crt_config(const PlanHost &h, int64_t M, int64_t N, bool allow_gdig) {
+    CrtCfg c{};
+    c.gdig = allow_gdig && h.nd32 > 32;
+    c.ept = h.nd32 <= 64 ? 2 : 1;
+    c.bd = 256;
+    size_t cols = 0;
+    if (!c.gdig) {
+        while (c.bd > 64 && (size_t)h.nd32 * c.bd * c.ept * sizeof(uint32_t) > 49152) c.bd /= 2;
+        cols = (((size_t)h.nd32 * c.bd * c.ept + 3) & ~(size_t)3) * sizeof(uint32_t);
+    }
+    // a slice of LB moduli x crt_dc digit constants and LB reciprocals fills LDS up to
+    // 64 KiB (LDS columns) or 32 KiB (global columns, leaving room for more blocks)
+    const size_t cap = c.gdig ? 32768 : 65536;
+    c.LB = std::max(1, std::min(h.L, (int)((cap - cols) / (sizeof(double) * (h.crt_dc + 1)))));
+    c.lds = cols + (size_t)c.LB * (h.crt_dc + 1) * sizeof(double);
+    const int64_t per = (int64_t)c.bd * c.ept;
+    c.nb = (unsigned)((std::max<int64_t>(M * N, 1) + per - 1) / per);
+    c.gstride = (int64_t)c.nb * per;
+    return c;
+}
+
+size_t crt_gdig_bytes(const PlanHost &h, int64_t M, int64_t N) {
+    const CrtCfg c = crt_config(h, M, N, true);
+    return c.gdig ? (size_t)h.nd32 * (size_t)c.gstride * sizeof(uint32_t) : 0;
+}
+
+// gdig: device buffer of crt_gdig_bytes(h, M, N) bytes, or NULL (digit columns in LDS)
 int launch_crt(const oz2h_plan *pl, int64_t M, int64_t N, const int16_t *u, int64_t u_ps,
                int64_t ldu, const int32_t *e, const int32_t *f, bool round, bool weight,
                int8_t *osign, int32_t *oexp, uint64_t *olimbs, int64_t ldc, uint64_t *chat,
-               int nlc, hipStream_t s, int tsum = -1) {
+               int nlc, hipStream_t s, int tsum = -1, uint32_t *gdig = nullptr) {
     const PlanHost &h = pl->h;
     if (tsum < 0) tsum = 2 * h.t;
     if (M * N == 0) return OZ2H_OK;
-    // two entries per thread; the LDS digit columns (nd32 words per entry) stay <= 64 KiB
-    const int ept = h.nd32 <= 64 ? 2 : 1;
-    int bd = 256;
-    while (bd > 64 && (size_t)h.nd32 * bd * ept * sizeof(uint32_t) > 49152) bd /= 2;
-    // digit columns, then a slice of LB moduli x crt_dc digit constants and LB reciprocals
-    const size_t cols = (((size_t)h.nd32 * bd * ept + 3) & ~(size_t)3) * sizeof(uint32_t);
-    const int LB = std::max(1, std::min(h.L, (int)((65536 - cols) / (sizeof(double) * (h.crt_dc + 1)))));
-    const size_t lds = cols + (size_t)LB * (h.crt_dc + 1) * sizeof(double);
-    const unsigned nb = (unsigned)((M * N + (int64_t)bd * ept - 1) / ((int64_t)bd * ept));
+    const CrtCfg c = crt_config(h, M, N, gdig != nullptr && !weight);
+    const unsigned nb = c.nb;
+    const int bd = c.bd, ept = c.ept;
+    const size_t lds = c.lds;
     const CrtArgs ca{u, u_ps, ldu, M, N, pl->d_info, h.L, pl->d_crt, h.crt_ndpad, h.crt_nc, h.nd32,
-                     pl->d_pd, pl->d_phd, e, f, tsum, h.p, osign, oexp, olimbs, ldc, chat, nlc, LB};
-#define OZ2H_CRT(DC, E, R, W) k_crt<DC, E, R, W><<<nb, bd, lds, s>>>(ca)
-#define OZ2H_CRT_E(DC, R, W)          \
-    if (ept == 2) OZ2H_CRT(DC, 2, R, W); \
-    else OZ2H_CRT(DC, 1, R, W);
-#define OZ2H_CRT_DC(R, W)                             \
+                     pl->d_pd, pl->d_phd, e, f, tsum, h.p, osign, oexp, olimbs, ldc, chat, nlc, c.LB,
+                     c.gdig ? gdig : nullptr, c.gstride};
+#define OZ2H_CRT(DC, E, R, W, G) k_crt<DC, E, R, W, G><<<nb, bd, lds, s>>>(ca)
+#define OZ2H_CRT_E(DC, R, W, G)               \
+    if (ept == 2) OZ2H_CRT(DC, 2, R, W, G);    \
+    else OZ2H_CRT(DC, 1, R, W, G);
+#define OZ2H_CRT_DC(R, W, G)                          \
     switch (h.crt_dc) {                               \
-        case 8: OZ2H_CRT_E(8, R, W) break;            \
-        case 16: OZ2H_CRT_E(16, R, W) break;          \
-        case 24: OZ2H_CRT_E(24, R, W) break;          \
-        default: OZ2H_CRT_E(32, R, W) break;          \
+        case 8: OZ2H_CRT_E(8, R, W, G) break;         \
+        case 16: OZ2H_CRT_E(16, R, W, G) break;       \
+        case 24: OZ2H_CRT_E(24, R, W, G) break;       \
+        default: OZ2H_CRT_E(32, R, W, G) break;       \
     }
     if (weight) {
-        OZ2H_CRT_DC(false, true)
+        OZ2H_CRT_DC(false, true, false)
+    } else if (c.gdig) {
+        if (round) {
+            OZ2H_CRT_DC(true, false, true)
+        } else {
+            OZ2H_CRT_DC(false, false, true)
+        }
     } else if (round) {
-        OZ2H_CRT_DC(true, false)
+        OZ2H_CRT_DC(true, false, false)
     } else {
-        OZ2H_CRT_DC(false, false)
+        OZ2H_CRT_DC(false, false, false)
     }
 #undef OZ2H_CRT_DC
 #undef OZ2H_CRT_E
@@ -361,10 +413,10 @@ int run_pipeline(const oz2h_plan *pl, int64_t M, int64_t N, int64_t K, oz2h_op o
     if (ev) OZ2H_HIP(hipEventRecord(ev[3], s));
     if (round) {
         st = launch_crt(pl, M, N, u, w.mpad * w.npad, w.npad, e, f, true, false, C->sign,
-                        C->exp, C->limbs, C->ld, nullptr, 0, s);
+                        C->exp, C->limbs, C->ld, nullptr, 0, s, -1, (uint32_t *)(wb + w.off_dig));
     } else {
         st = launch_crt(pl, M, N, u, w.mpad * w.npad, w.npad, e, f, false, false, chat_sign,
-                        nullptr, nullptr, N, chat_mag, nlc, s);
+                        nullptr, nullptr, N, chat_mag, nlc, s, -1, (uint32_t *)(wb + w.off_dig));
         if (!st) {
             OZ2H_HIP(hipMemcpyAsync(e_out, e, sizeof(int32_t) * M, hipMemcpyDeviceToDevice, s));
             OZ2H_HIP(hipMemcpyAsync(f_out, f, sizeof(int32_t) * N, hipMemcpyDeviceToDevice, s));
@@ -553,7 +605,7 @@ namespace {
 struct BwdLayout {
     GemmCfg cfg[2];
     int64_t mpad[2], npad[2], kpad[2];
-    size_t off_x[2], off_l[2], off_r[2], off_v[2];
+    size_t off_x[2], off_l[2], off_r[2], off_v[2], off_dig[2];
     size_t total;
 };
 
@@ -575,6 +627,13 @@ BwdLayout bwd_layout(const PlanHost &h) {
         off = align_up(off + (size_t)h.G * b.npad[sd] * b.kpad[sd]);
         b.off_v[sd] = off;
         off = align_up(off + sizeof(int16_t) * (size_t)h.L * b.mpad[sd] * b.npad[sd]);
+        // CRT digit columns: over this side's planes (dead after its GEMMs) if they fit
+        const size_t dig = crt_gdig_bytes(h, orows[sd], ocols[sd]);
+        b.off_dig[sd] = b.off_l[sd];
+        if (dig > b.off_v[sd] - b.off_l[sd]) {
+            b.off_dig[sd] = off;
+            off = align_up(off + dig);
+        }
         b.total = std::max(b.total, off);
     }
     return b;
@@ -689,7 +748,7 @@ int oz2h_gemm_backward(const oz2h_plan *plan, int64_t M, int64_t N, int64_t K, c
             return st;
         if ((st = launch_crt(plan, M, K, v, b.mpad[0] * b.npad[0], b.npad[0], hx, nullptr, true,
                              false, dA->sign, dA->exp, dA->limbs, dA->ld, nullptr, 0, stream,
-                             twsum[0])))
+                             twsum[0], (uint32_t *)(wb + b.off_dig[0]))))
             return st;
     }
     if (dB) {   // dB = A^T W: A^ read transposed, W'' columns (exponents folded with e)
@@ -707,7 +766,7 @@ int oz2h_gemm_backward(const oz2h_plan *plan, int64_t M, int64_t N, int64_t K, c
             return st;
         if ((st = launch_crt(plan, K, N, v, b.mpad[1] * b.npad[1], b.npad[1], nullptr, gx, true,
                              false, dB->sign, dB->exp, dB->limbs, dB->ld, nullptr, 0, stream,
-                             twsum[1])))
+                             twsum[1], (uint32_t *)(wb + b.off_dig[1]))))
             return st;
     }
     return ok();

@@ -510,24 +510,14 @@ __global__ __launch_bounds__(256) void k_resgemm(GemmArgs args, int L) {
 
 // ---------------------------------------------------------------- stage 4 + 5
 
-// bits [pos, pos + 32) of a digit column in LDS (bits outside [0, 32 nd) read as 0)
-__device__ __forceinline__ uint32_t dig_bits32(const uint32_t *__restrict__ sd, int bd, int nd,
-                                               int64_t pos) {
-    const int64_t q = pos >> 5;
-    const int r = (int)(pos & 31);
-    const uint64_t lo = (q >= 0 && q < nd) ? sd[q * bd] : 0u;
-    const uint64_t hi = (q + 1 >= 0 && q + 1 < nd) ? sd[(q + 1) * bd] : 0u;
-    return (uint32_t)(((hi << 32) | lo) >> r);
-}
-
 // multi-digit helpers on an LDS digit column (stride `st` words between digits)
-__device__ __forceinline__ bool dig_ge(const uint32_t *sd, int st, const uint32_t *__restrict__ Q,
+__device__ __forceinline__ bool dig_ge(const uint32_t *sd, int64_t st, const uint32_t *__restrict__ Q,
                                        int nd) {   // column >= Q ?
     int64_t br = 0;
     for (int k = 0; k < nd; ++k) br = ((int64_t)sd[k * st] - (int64_t)Q[k] - br) < 0;
     return br == 0;
 }
-__device__ __forceinline__ void dig_sub(uint32_t *sd, int st, const uint32_t *__restrict__ Q,
+__device__ __forceinline__ void dig_sub(uint32_t *sd, int64_t st, const uint32_t *__restrict__ Q,
                                         int nd) {   // column -= Q
     int64_t br = 0;
     for (int k = 0; k < nd; ++k) {
@@ -536,7 +526,7 @@ __device__ __forceinline__ void dig_sub(uint32_t *sd, int st, const uint32_t *__
         br = d < 0;
     }
 }
-__device__ __forceinline__ void dig_rsub(uint32_t *sd, int st, const uint32_t *__restrict__ Q,
+__device__ __forceinline__ void dig_rsub(uint32_t *sd, int64_t st, const uint32_t *__restrict__ Q,
                                          int nd) {   // column = Q - column
     int64_t br = 0;
     for (int k = 0; k < nd; ++k) {
@@ -545,7 +535,7 @@ __device__ __forceinline__ void dig_rsub(uint32_t *sd, int st, const uint32_t *_
         br = d < 0;
     }
 }
-__device__ __forceinline__ void dig_add(uint32_t *sd, int st, const uint32_t *__restrict__ Q,
+__device__ __forceinline__ void dig_add(uint32_t *sd, int64_t st, const uint32_t *__restrict__ Q,
                                         int nd) {   // column += Q (mod 2^(32 nd))
     uint64_t cy = 0;
     for (int k = 0; k < nd; ++k) {
@@ -554,14 +544,39 @@ __device__ __forceinline__ void dig_add(uint32_t *sd, int st, const uint32_t *__
         cy = d >> 32;
     }
 }
-__device__ __forceinline__ void dig_neg(uint32_t *sd, int st, int nd) {   // two's complement
-    uint64_t cy = 1;
-    for (int k = 0; k < nd; ++k) {
-        const uint64_t d = (uint64_t)(uint32_t)~sd[k * st] + cy;
-        sd[k * st] = (uint32_t)d;
-        cy = d >> 32;
+// The magnitude digits of c^ read from its digit column.  On the fast path the
+// column holds c^ in two's complement; for c^ < 0, |c^| = ~X + 1, so with z the
+// lowest nonzero digit of X: digit k of |c^| is ~X_k above z, -X_z at z and 0
+// below (no negation pass over the column).  Digits outside [0, nd) read as 0.
+struct MagView {
+    const uint32_t *sd;
+    int64_t st;
+    int nd, z;
+    bool inv;
+    __device__ __forceinline__ uint32_t operator()(int64_t k) const {
+        if (k < 0 || k >= nd) return 0u;
+        const uint32_t x = sd[k * st];
+        if (!inv) return x;
+        return k > z ? ~x : (k == z ? 0u - x : 0u);
     }
-}
+    // bits [pos, pos + 32)
+    __device__ __forceinline__ uint32_t bits32(int64_t pos) const {
+        const int64_t q = pos >> 5;
+        const int r = (int)(pos & 31);
+        const uint64_t lo = (*this)(q), hi = (*this)(q + 1);
+        return (uint32_t)(((hi << 32) | lo) >> r);
+    }
+    // any nonzero bit below position pos
+    __device__ __forceinline__ bool any_below(int64_t pos) const {
+        const int64_t full = pos >> 5;
+        const int rr = (int)(pos & 31);
+        if (rr && ((*this)(full) & ((1u << rr) - 1)) != 0) return true;
+        if (inv) return z < full;   // digit z is nonzero, everything below it is zero
+        for (int64_t k = min(full, (int64_t)nd) - 1; k >= 0; --k)
+            if (sd[k * st] != 0) return true;
+        return false;
+    }
+};
 
 // Direct CRT (subsection "Direct CRT without multiple-precision division").
 // Each thread reconstructs EPT output entries (entries tid + q*blockDim of the
@@ -598,19 +613,25 @@ struct CrtArgs {
     int64_t ldc;
     uint64_t *chat_mag;
     int nlc, LB;
+    uint32_t *gdig;    // GDIG: digit columns in global memory, digit k of entry e at
+    int64_t gstride;   // gdig[k * gstride + e] (gstride >= all entries the grid covers)
 };
 
 // LDS of a CRT block: bd * EPT digit columns of nd32 words, then LB x (DC + 1) doubles
-template <int DC, int EPT, bool ROUND, bool WEIGHT>
+// GDIG = false: each entry's digit column sits in LDS (stride blockDim * EPT words);
+// GDIG = true: in global memory (large nd32), and LDS holds only the constant slices.
+template <int DC, int EPT, bool ROUND, bool WEIGHT, bool GDIG = false>
 __device__ __forceinline__ void crt_block(const CrtArgs &a, int64_t blk, uint32_t *sdig) {
     const int tid = threadIdx.x, bd = blockDim.x, st = bd * EPT;
+    const int64_t cst = GDIG ? a.gstride : (int64_t)st;   // digit stride of a column
     const int nd32 = a.nd32, L = a.L, LB = a.LB, ndpad = a.ndpad, p = a.p;
     const int64_t N = a.N, v_ps = a.v_ps;
     // global-memory views (pointers from a descriptor are generic otherwise)
     OZ2H_G(uint32_t) *Pd = (OZ2H_G(uint32_t) *)a.Pd;
     const uint32_t *__restrict__ Phd = a.Phd;
     OZ2H_G(ModInfo) *mi = (OZ2H_G(ModInfo) *)a.mi;
-    double *stab = (double *)(sdig + (((size_t)nd32 * st + 3) & ~(size_t)3));   // LB x DC digits
+    double *stab = GDIG ? (double *)sdig                                            // LB x DC digits
+                        : (double *)(sdig + (((size_t)nd32 * st + 3) & ~(size_t)3));
     double *sinv = stab + (size_t)LB * DC;                                      // LB x 1/m
     const int64_t MN = a.M * N;
     int64_t idx[EPT];
@@ -624,6 +645,7 @@ __device__ __forceinline__ void crt_block(const CrtArgs &a, int64_t blk, uint32_
         const int64_t ii = live[q] ? idx[q] / N : 0, jj = live[q] ? idx[q] - ii * N : 0;
         vp[q] = (OZ2H_G(int16_t) *)a.V + ii * a.ldv + jj;
     }
+    auto col = [&](int q) -> uint32_t * { return GDIG ? a.gdig + idx[q] : sdig + q * bd + tid; };
 
     int64_t beta[EPT], carry[EPT];
     bool slow[EPT];
@@ -703,13 +725,13 @@ __device__ __forceinline__ void crt_block(const CrtArgs &a, int64_t blk, uint32_
                 slow[q] = fabs(asum[q] - r) > 0.5 - 0x1p-30;
                 beta[q] = slow[q] ? (int64_t)floor(asum[q]) - 1 : (int64_t)r;   // alpha - 1 when slow
             }
-            uint32_t *sd = sdig + q * bd + tid;
+            uint32_t *sd = col(q);
 #pragma unroll
             for (int d = 0; d < DC; ++d) {
                 const int k = c * DC + d;
                 if (k < nd32) {
                     const int64_t x = (int64_t)acc[q][d] - beta[q] * (int64_t)Pd[k] + carry[q];
-                    sd[k * st] = (uint32_t)x;
+                    sd[k * cst] = (uint32_t)x;
                     carry[q] = x >> 32;
                 }
             }
@@ -720,37 +742,40 @@ __device__ __forceinline__ void crt_block(const CrtArgs &a, int64_t blk, uint32_
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
         if (!live[q]) continue;
-        uint32_t *sd = sdig + q * bd + tid;
+        uint32_t *sd = col(q);
         bool neg;
+        MagView mag{sd, cst, nd32, 0, false};
         if (!slow[q]) {
             neg = carry[q] < 0;   // two's complement c^ over nd32 digits
-            if (neg) dig_neg(sd, st, nd32);
+            if (neg) {
+                int z = 0;
+                while (z < nd32 - 1 && sd[z * cst] == 0) ++z;
+                mag.z = z;
+                mag.inv = true;
+            }
         } else {
             // R in [0, 3P): at most two subtractions of P, then the symmetric lift
-            if (dig_ge(sd, st, a.Pd, nd32)) dig_sub(sd, st, a.Pd, nd32);
-            if (dig_ge(sd, st, a.Pd, nd32)) dig_sub(sd, st, a.Pd, nd32);
-            neg = !dig_ge(sd, st, Phd, nd32) ? false : true;   // x0 >= floor(P/2) ...
-            if (neg) {                                         // ... and x0 != floor(P/2)
-                dig_sub(sd, st, Phd, nd32);
+            if (dig_ge(sd, cst, a.Pd, nd32)) dig_sub(sd, cst, a.Pd, nd32);
+            if (dig_ge(sd, cst, a.Pd, nd32)) dig_sub(sd, cst, a.Pd, nd32);
+            neg = !dig_ge(sd, cst, Phd, nd32) ? false : true;   // x0 >= floor(P/2) ...
+            if (neg) {                                          // ... and x0 != floor(P/2)
+                dig_sub(sd, cst, Phd, nd32);
                 bool eq = true;
-                for (int k = 0; k < nd32 && eq; ++k) eq = sd[k * st] == 0;
-                dig_add(sd, st, Phd, nd32);
+                for (int k = 0; k < nd32 && eq; ++k) eq = sd[k * cst] == 0;
+                dig_add(sd, cst, Phd, nd32);
                 neg = !eq;
             }
-            if (neg) dig_rsub(sd, st, a.Pd, nd32);   // |c^| = P - x0
+            if (neg) dig_rsub(sd, cst, a.Pd, nd32);   // |c^| = P - x0
         }
         int top = nd32 - 1;
-        while (top >= 0 && sd[top * st] == 0) --top;
+        while (top >= 0 && mag(top) == 0) --top;
         const int64_t i = idx[q] / N, j = idx[q] - i * N;
 
         if (!ROUND) {
             __attribute__((address_space(1))) uint64_t *o =
                 (__attribute__((address_space(1))) uint64_t *)a.chat_mag + idx[q] * a.nlc;
-            for (int w = 0; w < a.nlc; ++w) {
-                const uint64_t lo = (2 * w < nd32) ? sd[2 * w * st] : 0u;
-                const uint64_t hi = (2 * w + 1 < nd32) ? sd[(2 * w + 1) * st] : 0u;
-                o[w] = lo | (hi << 32);
-            }
+            for (int w = 0; w < a.nlc; ++w)
+                o[w] = (uint64_t)mag(2 * w) | ((uint64_t)mag(2 * w + 1) << 32);
             a.osign[idx[q]] = top < 0 ? 0 : (neg ? -1 : 1);
             continue;
         }
@@ -763,26 +788,19 @@ __device__ __forceinline__ void crt_block(const CrtArgs &a, int64_t blk, uint32_
             a.oexp[oi] = 0;
             continue;
         }
-        int64_t nb = 32 * (int64_t)top + (32 - __builtin_clz(sd[top * st]));
+        int64_t nb = 32 * (int64_t)top + (32 - __builtin_clz(mag(top)));
         const int64_t sh = nb - p;   // mant = RNE(mag / 2^sh)
         bool inc = false;
         if (sh > 0) {
             const int64_t rpos = sh - 1;
-            const int rbit = (int)((sd[(rpos >> 5) * st] >> (rpos & 31)) & 1u);
-            if (rbit) {
-                bool sticky = false;
-                const int64_t full = rpos >> 5;
-                for (int64_t k = 0; k < full && !sticky; ++k) sticky = sd[k * st] != 0;
-                const int rr = (int)(rpos & 31);
-                if (!sticky && rr) sticky = (sd[full * st] & ((1u << rr) - 1)) != 0;
-                inc = sticky || (dig_bits32(sd, st, nd32, sh) & 1u);
-            }
+            if ((mag.bits32(rpos) & 1u) != 0)   // round bit set: up unless an exact tie to even
+                inc = mag.any_below(rpos) || (mag.bits32(sh) & 1u);
         }
         bool allones = inc;
         if (inc) {   // mant = 2^p - 1 rounds up to 2^p: renormalise
             for (int w = 0; w < nl && allones; ++w) {
-                const uint64_t v = (uint64_t)dig_bits32(sd, st, nd32, 64 * (int64_t)w + sh) |
-                                   ((uint64_t)dig_bits32(sd, st, nd32, 64 * (int64_t)w + 32 + sh) << 32);
+                const uint64_t v = (uint64_t)mag.bits32(64 * (int64_t)w + sh) |
+                                   ((uint64_t)mag.bits32(64 * (int64_t)w + 32 + sh) << 32);
                 const int bits = (w == nl - 1) ? p - 64 * (nl - 1) : 64;
                 const uint64_t mask = bits >= 64 ? ~0ull : ((1ull << bits) - 1);
                 allones = v == mask;
@@ -795,8 +813,8 @@ __device__ __forceinline__ void crt_block(const CrtArgs &a, int64_t blk, uint32_
         } else {
             bool cy = inc;
             for (int w = 0; w < nl; ++w) {
-                uint64_t v = (uint64_t)dig_bits32(sd, st, nd32, 64 * (int64_t)w + sh) |
-                             ((uint64_t)dig_bits32(sd, st, nd32, 64 * (int64_t)w + 32 + sh) << 32);
+                uint64_t v = (uint64_t)mag.bits32(64 * (int64_t)w + sh) |
+                             ((uint64_t)mag.bits32(64 * (int64_t)w + 32 + sh) << 32);
                 if (cy) {
                     v += 1;
                     cy = v == 0;
@@ -810,10 +828,10 @@ __device__ __forceinline__ void crt_block(const CrtArgs &a, int64_t blk, uint32_
     }
 }
 
-template <int DC, int EPT, bool ROUND, bool WEIGHT>
+template <int DC, int EPT, bool ROUND, bool WEIGHT, bool GDIG>
 __global__ __launch_bounds__(256) void k_crt(CrtArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint32_t sdig[];
-    crt_block<DC, EPT, ROUND, WEIGHT>(a, blockIdx.x, sdig);
+    crt_block<DC, EPT, ROUND, WEIGHT, GDIG>(a, blockIdx.x, sdig);
 }
 
 // planes [G][R][C] (int8, row stride ldi) -> [G][C'][R'] (row stride ldo = R'), zero
