@@ -29,6 +29,7 @@ struct oz2h_plan {
     void *dbuf = nullptr;
     ModInfo *d_info = nullptr;
     double *d_resid = nullptr;
+    ResGroup *d_rgrp = nullptr;
     double *d_crt = nullptr;
     uint32_t *d_pd = nullptr;
     uint32_t *d_phd = nullptr;
@@ -185,7 +186,7 @@ int launch_residues(const oz2h_plan *pl, int64_t rows, int64_t count, const uint
     dim3 grid((unsigned)(kpad / 64), (unsigned)(rpad / rb));
     const size_t lds = (size_t)h.nw32 * 64 * rb * sizeof(uint32_t);
     const ResArgs a{limbs, exp, sign, rs, cs, rows, count, kpad, ps, erow, h.p, nl, t, h.nw32,
-                    pl->d_resid, pl->d_info, h.L, h.lgroups, planes, koff};
+                    pl->d_resid, pl->d_rgrp, h.L, h.lgroups, planes, koff};
     if (rb == 4) k_residues<4><<<grid, 256, lds, s>>>(a);
     else if (rb == 2) k_residues<2><<<grid, 128, lds, s>>>(a);
     else k_residues<1><<<grid, 64, lds, s>>>(a);
@@ -305,6 +306,9 @@ int upload_plan(oz2h_plan *pl) {
     off = align_up(off + n_info);
     const size_t o_res = off;
     off = align_up(off + n_res);
+    const size_t n_rg = sizeof(ResGroup) * h.resgrp.size();
+    const size_t o_rg = off;
+    off = align_up(off + n_rg);
     const size_t o_crt = off;
     off = align_up(off + n_crt);
     const size_t o_pd = off;
@@ -317,11 +321,13 @@ int upload_plan(oz2h_plan *pl) {
     char *b = (char *)buf;
     pl->d_info = (ModInfo *)(b + o_info);
     pl->d_resid = (double *)(b + o_res);
+    pl->d_rgrp = (ResGroup *)(b + o_rg);
     pl->d_crt = (double *)(b + o_crt);
     pl->d_pd = (uint32_t *)(b + o_pd);
     pl->d_phd = (uint32_t *)(b + o_phd);
     OZ2H_HIP(hipMemcpy(pl->d_info, h.info.data(), n_info, hipMemcpyHostToDevice));
     OZ2H_HIP(hipMemcpy(pl->d_resid, h.resid_tab.data(), n_res, hipMemcpyHostToDevice));
+    OZ2H_HIP(hipMemcpy(pl->d_rgrp, h.resgrp.data(), n_rg, hipMemcpyHostToDevice));
     OZ2H_HIP(hipMemcpy(pl->d_crt, h.crt_digits.data(), n_crt, hipMemcpyHostToDevice));
     OZ2H_HIP(hipMemcpy(pl->d_pd, h.p_digits.data(), n_pd, hipMemcpyHostToDevice));
     OZ2H_HIP(hipMemcpy(pl->d_phd, h.ph_digits.data(), n_pd, hipMemcpyHostToDevice));
@@ -1134,13 +1140,16 @@ int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2
 
     // device table layout
     size_t off = 0;
-    std::vector<size_t> o_info(count), o_res(count), o_crt(count), o_pd(count), o_phd(count);
+    std::vector<size_t> o_info(count), o_res(count), o_rg(count), o_crt(count), o_pd(count),
+        o_phd(count);
     for (int b = 0; b < count; ++b) {
         const PlanHost &h = bp->hosts[b];
         o_info[b] = off;
         off = align_up(off + sizeof(ModInfo) * h.L);
         o_res[b] = off;
         off = align_up(off + sizeof(double) * h.resid_tab.size());
+        o_rg[b] = off;
+        off = align_up(off + sizeof(ResGroup) * h.resgrp.size());
         o_crt[b] = off;
         off = align_up(off + sizeof(double) * h.crt_digits.size());
         o_pd[b] = off;
@@ -1267,11 +1276,13 @@ int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2
         ProbDev &P = bp->pd[b];
         P.mi = (const ModInfo *)(db + o_info[b]);
         P.resid = (const double *)(db + o_res[b]);
+        P.rgrp = (const ResGroup *)(db + o_rg[b]);
         P.crt = (const double *)(db + o_crt[b]);
         P.pd = (const uint32_t *)(db + o_pd[b]);
         P.phd = (const uint32_t *)(db + o_phd[b]);
         OZ2H_HIP(hipMemcpy(db + o_info[b], h.info.data(), sizeof(ModInfo) * h.L, hipMemcpyHostToDevice));
         OZ2H_HIP(hipMemcpy(db + o_res[b], h.resid_tab.data(), sizeof(double) * h.resid_tab.size(), hipMemcpyHostToDevice));
+        OZ2H_HIP(hipMemcpy(db + o_rg[b], h.resgrp.data(), sizeof(ResGroup) * h.resgrp.size(), hipMemcpyHostToDevice));
         OZ2H_HIP(hipMemcpy(db + o_crt[b], h.crt_digits.data(), sizeof(double) * h.crt_digits.size(), hipMemcpyHostToDevice));
         OZ2H_HIP(hipMemcpy(db + o_pd[b], h.p_digits.data(), sizeof(uint32_t) * h.nd32, hipMemcpyHostToDevice));
         OZ2H_HIP(hipMemcpy(db + o_phd[b], h.ph_digits.data(), sizeof(uint32_t) * h.nd32, hipMemcpyHostToDevice));

@@ -24,6 +24,7 @@ struct ProbDev {
     int32_t nd32, crt_dc, crt_nc, crt_ndpad;
     const ModInfo *mi;
     const double *resid, *crt;
+    const ResGroup *rgrp;
     const uint32_t *pd, *phd;
     uint64_t *climbs;
     int32_t *cexp;
@@ -90,7 +91,7 @@ __device__ __forceinline__ ResArgs res_args(const ProbDev &P, int side, char *ws
     return ResArgs{P.limbs[side], P.exps[side], P.signs[side], P.rs[side], P.cs[side],
                    P.rows[side], P.K, P.kpad, P.rpad[side] * P.kpad,
                    (const int32_t *)(ws + P.erow_off[side]), P.p, P.nl, P.t, P.nw32, P.resid,
-                   P.mi, P.L, P.lgroups, (int8_t *)(ws + P.planes_off[side]), nullptr};
+                   P.rgrp, P.L, P.lgroups, (int8_t *)(ws + P.planes_off[side]), nullptr};
 }
 
 // stage 2, grouped: segment (prod, side) is a (kpad/64) x (rpad/RB) grid of blocks

@@ -165,9 +165,13 @@ __device__ __forceinline__ int build_words(OZ2H_G(uint64_t) *__restrict__ sl, in
 // an LDS column of 32-bit words; the moduli are then swept in groups of 8 with
 // fp64 FMAs against centred 2^(32 w) mod m weights (every partial sum is an
 // exact integer below 2^53), read with wave-uniform scalar loads.  Reduction:
-// r = a - rint(a/m) m (the rint quotient is off by at most one, so one
-// correction step gives the canonical centred residue in [-floor(m/2), (m-1)/2]),
-// and for two-limb moduli the balanced base-128 split r = r0 + 128 r1.
+// r = a - rint(a/m) m.  The quotient is exact for the odd one-limb moduli (a is
+// below 2^51, so a/m stays 1/(2m) away from a half-integer, farther than the
+// rounding error) and at worst off by one for a two-limb modulus, so |r| <= 127
+// for every one-limb modulus (|r| <= 64 for m = 128, ties included) and
+// |r| <= (m + 3)/2 for a two-limb one, whose balanced base-128 split
+// r = r0 + 128 r1 then has |r0|, |r1|, |r0 + r1| <= 127.  Any representative
+// of a^ mod m within these bounds gives the same exact GEMM result mod m.
 struct ResArgs {
     const uint64_t *limbs;
     const int32_t *exps;
@@ -176,7 +180,7 @@ struct ResArgs {
     const int32_t *erow;
     int p, nl, t, nw32;
     const double *tab;
-    const ModInfo *mi;
+    const ResGroup *rgrp;
     int L, lgroups;
     int8_t *planes;
     const int32_t *koff;   // nullable per-contraction exponent offsets (exponent folding)
@@ -190,7 +194,7 @@ __device__ __forceinline__ void residue_block_r(
     const uint64_t *__restrict__ limbs, const int32_t *__restrict__ exps,
     const int8_t *__restrict__ signs, const int32_t *__restrict__ erow,
     const int32_t *__restrict__ koff, const double *__restrict__ tab,
-    const ModInfo *__restrict__ mi, int8_t *__restrict__ planes, int64_t rs, int64_t cs,
+    const ResGroup *__restrict__ rgrp, int8_t *__restrict__ planes, int64_t rs, int64_t cs,
     int64_t rows, int64_t count, int64_t kpad, int64_t plane_stride, int p, int nl, int t,
     int nw32, int L, int lgroups, int64_t bx, int64_t by, uint32_t *words) {
     constexpr int BD = 64 * RB;
@@ -217,10 +221,12 @@ __device__ __forceinline__ void residue_block_r(
     // the tables live in global memory: say so, so that pointers read from a
     // descriptor (the grouped kernels) still qualify for scalar loads
     typedef const __attribute__((address_space(1))) double gdouble;
-    typedef const __attribute__((address_space(1))) ModInfo gmodinfo;
     gdouble *gtab = (gdouble *)tab;
-    gmodinfo *gmi = (gmodinfo *)mi;
-    g_i8 *out = (g_i8 *)planes + r * kpad + k;
+    OZ2H_G(ResGroup) *grec = (OZ2H_G(ResGroup) *)rgrp;
+    // per-plane base (uniform) + a 32-bit lane offset: scalar-base stores, no
+    // per-lane 64-bit address arithmetic
+    const uint32_t loff = (uint32_t)(r * kpad + k);
+    const double sgn = s < 0 ? -1.0 : 1.0;
     for (int grp = 0; grp < lgroups; ++grp) {
         double acc[kModGroup];
 #pragma unroll
@@ -231,25 +237,22 @@ __device__ __forceinline__ void residue_block_r(
 #pragma unroll
             for (int g = 0; g < kModGroup; ++g) acc[g] = fma(x, c[w * kModGroup + g], acc[g]);
         }
+        OZ2H_G(ResGroup) *R = grec + grp;
+        const uint32_t two = R->two;
 #pragma unroll
         for (int g = 0; g < kModGroup; ++g) {
-            const int l = grp * kModGroup + g;
-            if (l >= L) break;
-            const ModInfo info = load_info(gmi + l);
-            const int hi = (int)((info.m - 1) >> 1);
-            const double a = s < 0 ? -acc[g] : acc[g];
-            int ri = (int)fma(-rint(a * info.inv_m), (double)info.m, a);
-            if (ri > hi) ri -= (int)info.m;
-            g_i8 *o = out + (int64_t)info.g0 * plane_stride;
-            if (info.nprod == 1) {
-                o[0] = (int8_t)ri;
+            if (grp * kModGroup + g >= L) break;
+            const double a = acc[g] * sgn;
+            const int ri = (int)fma(-rint(a * R->inv_m[g]), R->md[g], a);
+            g_i8 *pb = (g_i8 *)planes + (int64_t)R->g0[g] * plane_stride;
+            if (!((two >> g) & 1u)) {
+                pb[loff] = (int8_t)ri;
             } else {
-                if (ri < -hi) ri += (int)info.m;
                 const int r0 = ((ri + 64) & 127) - 64;   // balanced base-128 split
                 const int r1 = (ri - r0) >> 7;
-                o[0] = (int8_t)r0;
-                o[plane_stride] = (int8_t)r1;
-                o[2 * plane_stride] = (int8_t)(r0 + r1);
+                pb[loff] = (int8_t)r0;
+                pb[plane_stride + loff] = (int8_t)r1;
+                pb[2 * plane_stride + loff] = (int8_t)(r0 + r1);
             }
         }
     }
@@ -258,7 +261,7 @@ __device__ __forceinline__ void residue_block_r(
 template <int RB>
 __device__ __forceinline__ void residue_block(const ResArgs &a, int64_t bx, int64_t by,
                                               uint32_t *words) {
-    residue_block_r<RB>(a.limbs, a.exps, a.signs, a.erow, a.koff, a.tab, a.mi, a.planes, a.rs,
+    residue_block_r<RB>(a.limbs, a.exps, a.signs, a.erow, a.koff, a.tab, a.rgrp, a.planes, a.rs,
                         a.cs, a.rows, a.count, a.kpad, a.plane_stride, a.p, a.nl, a.t, a.nw32,
                         a.L, a.lgroups, bx, by, words);
 }

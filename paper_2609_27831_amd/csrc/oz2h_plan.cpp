@@ -278,6 +278,15 @@ int build_plan(int p, int t, int64_t K, const std::vector<uint32_t> &mods_in, Pl
 
     // residue weights: centred 2^(32 w) mod m, grouped by kModGroup moduli
     h.lgroups = (h.L + kModGroup - 1) / kModGroup;
+    h.resgrp.assign(h.lgroups, ResGroup{});
+    for (int l = 0; l < h.L; ++l) {
+        ResGroup &R = h.resgrp[l / kModGroup];
+        const int g = l % kModGroup;
+        R.inv_m[g] = h.info[l].inv_m;
+        R.md[g] = (double)h.info[l].m;
+        R.g0[g] = h.info[l].g0;
+        if (h.info[l].nprod == 3) R.two |= 1u << g;
+    }
     h.resid_tab.assign((size_t)h.lgroups * h.nw32 * kModGroup, 0.0);
     for (int l = 0; l < h.L; ++l) {
         const uint64_t m = mods[l];

@@ -27,6 +27,17 @@ struct ModInfo {
     int32_t pad;
 };
 
+// One group of kModGroup moduli as the residue kernel reads it (wave-uniform
+// scalar loads, 192 bytes).
+struct ResGroup {
+    double inv_m[kModGroup];   // fl(1/m)
+    double md[kModGroup];      // m as a double
+    uint32_t g0[kModGroup];    // first INT8 plane of the modulus
+    uint32_t two;              // bit g: modulus g is two-limb (three planes)
+    uint32_t pad[7];
+};
+static_assert(sizeof(ResGroup) == 192, "ResGroup layout");
+
 struct PlanHost {
     int p = 0, t = 0;
     int tile = 0;          // oz2h_tile hint of the residue GEMMs (0 = automatic)
@@ -47,6 +58,7 @@ struct PlanHost {
     std::vector<uint32_t> moduli;    // L, one-limb first
     std::vector<ModInfo> info;       // L
     std::vector<double> resid_tab;   // [lgroups][nw32][kModGroup]: centred 2^(32w) mod m
+    std::vector<ResGroup> resgrp;    // [lgroups]
     std::vector<double> crt_digits;  // [L][crt_ndpad]: balanced base-2^32 digits of P/m
     std::vector<uint32_t> p_digits;  // [nd32] digits of P
     std::vector<uint32_t> ph_digits; // [nd32] digits of floor(P/2)

@@ -93,17 +93,23 @@ def test_residue_planes(oz, c_oracle, p, lo, hi, side):
     # padding is zero
     assert not planes[:, rows:, :].any() and not planes[:, :, K:].any()
     ahat = np.array(oz.limbs_to_ints(mag, sg), dtype=object).reshape(rows, K)
+    # any representative of a^ mod m is a valid residue for the exact GEMM, as long
+    # as it fits the INT8 operands: |r| <= 127 for a one-limb modulus (<= 64 for 128),
+    # and for a two-limb one |r| <= (m + 3)/2 with the balanced base-128 split
     for li, m in enumerate(plan.moduli.tolist()):
         res = np.vectorize(lambda v: py_centered_residue(v, m), otypes=[np.int64])(ahat)
         g0 = li if li < plan.L1 else plan.L1 + 3 * (li - plan.L1)
         if m <= 255:
             got = planes[g0, :rows, :K].astype(np.int64)
-            assert np.array_equal(got, res), f"modulus {m}"
+            assert np.array_equal(np.mod(got - res, m), np.zeros_like(res)), f"modulus {m}"
+            assert np.abs(got).max() <= min(127, m // 2 + (m % 2 == 0)), f"modulus {m}"
         else:
             r0 = planes[g0, :rows, :K].astype(np.int64)
             r1 = planes[g0 + 1, :rows, :K].astype(np.int64)
             rs = planes[g0 + 2, :rows, :K].astype(np.int64)
-            assert np.array_equal(r0 + 128 * r1, res), f"modulus {m}"
+            r = r0 + 128 * r1
+            assert np.array_equal(np.mod(r - res, m), np.zeros_like(res)), f"modulus {m}"
+            assert np.abs(r).max() <= (m + 3) // 2
             assert np.array_equal(rs, r0 + r1)
             assert r0.min() >= -64 and r0.max() <= 63 and np.abs(r1).max() <= 63
 
