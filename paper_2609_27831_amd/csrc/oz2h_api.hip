@@ -13,6 +13,7 @@
 #include <cstdlib>
 #include <fstream>
 #include <map>
+#include <tuple>
 #include <memory>
 #include <sstream>
 
@@ -907,6 +908,7 @@ struct oz2h_batched_plan {
     size_t res_lds = 0;
     struct CrtClass {
         int dc, ept, bd, LB;
+        bool gdig;
         size_t lds;
         Seg *d_segs;
         int nseg;
@@ -1048,22 +1050,27 @@ int launch_batched_crt(oz2h_batched_plan *bp, char *ws, hipStream_t s) {
     for (auto &c : bp->crt) {
         if (!c.blocks) continue;
         const unsigned nb = (unsigned)c.blocks;
-#define OZ2H_GCRT(DC, E) k_crt_grouped<DC, E><<<nb, c.bd, c.lds, s>>>(bp->d_probs, c.d_segs, c.nseg, ws, c.LB)
-        if (c.ept == 2) {
-            switch (c.dc) {
-                case 8: OZ2H_GCRT(8, 2); break;
-                case 16: OZ2H_GCRT(16, 2); break;
-                case 24: OZ2H_GCRT(24, 2); break;
-                default: OZ2H_GCRT(32, 2); break;
+#define OZ2H_GCRT(DC, E, G) \
+    k_crt_grouped<DC, E, G><<<nb, c.bd, c.lds, s>>>(bp->d_probs, c.d_segs, c.nseg, ws, c.LB)
+#define OZ2H_GCRT_DC(E, G)                     \
+    switch (c.dc) {                            \
+        case 8: OZ2H_GCRT(8, E, G); break;     \
+        case 16: OZ2H_GCRT(16, E, G); break;   \
+        case 24: OZ2H_GCRT(24, E, G); break;   \
+        default: OZ2H_GCRT(32, E, G); break;   \
+    }
+        if (c.gdig) {
+            if (c.ept == 2) {
+                OZ2H_GCRT_DC(2, true)
+            } else {
+                OZ2H_GCRT_DC(1, true)
             }
+        } else if (c.ept == 2) {
+            OZ2H_GCRT_DC(2, false)
         } else {
-            switch (c.dc) {
-                case 8: OZ2H_GCRT(8, 1); break;
-                case 16: OZ2H_GCRT(16, 1); break;
-                case 24: OZ2H_GCRT(24, 1); break;
-                default: OZ2H_GCRT(32, 1); break;
-            }
+            OZ2H_GCRT_DC(1, false)
         }
+#undef OZ2H_GCRT_DC
 #undef OZ2H_GCRT
         int st = check_launch("grouped CRT");
         if (st) return st;
@@ -1210,7 +1217,6 @@ int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2
         P.v_off = w;
         w = align_up(w + sizeof(int16_t) * (size_t)h.L * P.rpad[0] * P.rpad[1]);
     }
-    bp->ws_bytes = w;
 
     // segment tables
     std::vector<Seg> exp_segs, res_segs;
@@ -1228,23 +1234,32 @@ int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2
             res_segs.push_back(Seg{bp->res_blocks, b, sd, nbx});
             bp->res_blocks += nbx * nby;
         }
-    // CRT classes by digit chunk; two entries per thread while the LDS columns allow it
-    std::map<std::pair<int, int>, std::vector<int>> classes;
-    for (int b = 0; b < count; ++b)
-        classes[{bp->hosts[b].crt_dc, bp->hosts[b].nd32 <= 64 ? 2 : 1}].push_back(b);
+    // CRT classes: (digit chunk, entries per thread, digit columns in LDS or global
+    // memory), the same shapes a plain call would take (crt_config)
+    std::map<std::tuple<int, int, int>, std::vector<int>> classes;
+    for (int b = 0; b < count; ++b) {
+        const CrtCfg cc = crt_config(bp->hosts[b], probs[b].M, probs[b].N, true);
+        classes[std::make_tuple(bp->hosts[b].crt_dc, cc.ept, (int)cc.gdig)].push_back(b);
+    }
     std::vector<std::vector<Seg>> crt_segs;
     for (auto &kv : classes) {
         oz2h_batched_plan::CrtClass c{};
-        c.dc = kv.first.first;
-        c.ept = kv.first.second;
-        int maxnd = 1;
-        for (int b : kv.second) maxnd = std::max(maxnd, bp->hosts[b].nd32);
+        c.dc = std::get<0>(kv.first);
+        c.ept = std::get<1>(kv.first);
+        c.gdig = std::get<2>(kv.first) != 0;
+        int maxnd = 1, maxL = 1;
+        for (int b : kv.second) {
+            maxnd = std::max(maxnd, bp->hosts[b].nd32);
+            maxL = std::max(maxL, bp->hosts[b].L);
+        }
         c.bd = 256;
-        while (c.bd > 64 && (size_t)maxnd * c.bd * c.ept * 4 > 49152) c.bd /= 2;
-        const size_t cols = (((size_t)maxnd * c.bd * c.ept + 3) & ~(size_t)3) * 4;
-        int maxL = 1;
-        for (int b : kv.second) maxL = std::max(maxL, bp->hosts[b].L);
-        c.LB = std::max(1, std::min(maxL, (int)((65536 - cols) / (sizeof(double) * (c.dc + 1)))));
+        size_t cols = 0;
+        if (!c.gdig) {
+            while (c.bd > 64 && (size_t)maxnd * c.bd * c.ept * 4 > 49152) c.bd /= 2;
+            cols = (((size_t)maxnd * c.bd * c.ept + 3) & ~(size_t)3) * 4;
+        }
+        const size_t cap = c.gdig ? 32768 : 65536;
+        c.LB = std::max(1, std::min(maxL, (int)((cap - cols) / (sizeof(double) * (c.dc + 1)))));
         c.lds = cols + (size_t)c.LB * (c.dc + 1) * sizeof(double);
         std::vector<Seg> segs;
         for (int b : kv.second) {
@@ -1252,11 +1267,25 @@ int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2
             const int64_t nb = (probs[b].M * probs[b].N + per - 1) / per;
             segs.push_back(Seg{c.blocks, b, 0, nb});
             c.blocks += nb;
+            ProbDev &P = bp->pd[b];
+            P.dig_off = 0;
+            P.dig_stride = nb * per;
+            if (c.gdig) {   // over the product's residue planes (dead after the GEMMs) if they fit
+                const size_t dig = (size_t)bp->hosts[b].nd32 * (size_t)P.dig_stride * sizeof(uint32_t);
+                const size_t planes = P.v_off - P.planes_off[0];
+                if (dig <= planes) {
+                    P.dig_off = P.planes_off[0];
+                } else {
+                    P.dig_off = w;
+                    w = align_up(w + dig);
+                }
+            }
         }
         c.nseg = (int)segs.size();
         bp->crt.push_back(c);
         crt_segs.push_back(segs);
     }
+    bp->ws_bytes = w;
     const size_t o_exp = off;
     off = align_up(off + sizeof(Seg) * exp_segs.size());
     const size_t o_rs = off;

@@ -19,6 +19,8 @@ struct ProbDev {
     const int8_t *signs[2];
     int64_t rs[2], cs[2], rows[2], rpad[2];
     uint64_t erow_off[2], planes_off[2], v_off;
+    uint64_t dig_off;     // CRT digit columns in global memory (classes with large nd32)
+    int64_t dig_stride;   // entries per digit row there
     int64_t K, kpad;
     int32_t p, nl, t, nw32, L, lgroups, G;
     int32_t nd32, crt_dc, crt_nc, crt_ndpad;
@@ -131,7 +133,7 @@ __global__ __launch_bounds__(256) void k_resgemm_grouped(const ProbDev *__restri
 }
 
 // stages 4-5, grouped: segment prod is a 1-D grid of CRT blocks
-template <int DC, int EPT>
+template <int DC, int EPT, bool GDIG>
 __global__ __launch_bounds__(256) void k_crt_grouped(const ProbDev *__restrict__ probs,
                                                      const Seg *__restrict__ segs, int nseg,
                                                      char *ws, int LB) {
@@ -142,8 +144,9 @@ __global__ __launch_bounds__(256) void k_crt_grouped(const ProbDev *__restrict__
     const CrtArgs a{(const int16_t *)(ws + P.v_off), P.rpad[0] * P.rpad[1], P.rpad[1], P.rows[0],
                     P.rows[1], P.mi, P.L, P.crt, P.crt_ndpad, P.crt_nc, P.nd32, P.pd, P.phd,
                     (const int32_t *)(ws + P.erow_off[0]), (const int32_t *)(ws + P.erow_off[1]),
-                    2 * P.t, P.p, P.csign, P.cexp, P.climbs, P.ldc, nullptr, 0, LB};
-    crt_block<DC, EPT, true, false>(a, (int64_t)blockIdx.x - sg.first, sdig);
+                    2 * P.t, P.p, P.csign, P.cexp, P.climbs, P.ldc, nullptr, 0, LB,
+                    GDIG ? (uint32_t *)(ws + P.dig_off) : nullptr, P.dig_stride};
+    crt_block<DC, EPT, true, false, GDIG>(a, (int64_t)blockIdx.x - sg.first, sdig);
 }
 
 }  // namespace oz2h
