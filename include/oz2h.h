@@ -352,7 +352,7 @@ size_t oz2h_batched_workspace_size(const oz2h_batched_plan *plan);
 /*
  * Autotuner: runs stages 1-2 once, then times the grouped GEMM for every
  * block tile (128x128, 256x128, 128x256) and every persistent schedule (1, 2
- * or 4 resident blocks per compute unit), keeps the fastest and records it in
+ * or 4 resident blocks per compute unit, or one block per work item), keeps the fastest and records it in
  * an in-process cache keyed by the batch's shapes (and, if the environment
  * variable OZ2H_TUNE_CACHE names a file, appends it there; plans created later
  * with OZ2H_TILE_AUTO pick it up).  Synchronizes `stream`; the outputs C are
@@ -371,10 +371,11 @@ int oz2h_batched_run(oz2h_batched_plan *plan, void *workspace, size_t ws_bytes,
 /* The same launches issued directly on `stream` (no graph). */
 int oz2h_batched_run_eager(oz2h_batched_plan *plan, void *workspace, size_t ws_bytes,
                            hipStream_t stream);
-/* Current block tile (oz2h_tile), resident blocks per compute unit, GEMM work items. */
+/* Current block tile (oz2h_tile), resident blocks per compute unit (0: one block per
+   work item instead of a persistent grid), GEMM work items. */
 int oz2h_batched_get_config(const oz2h_batched_plan *plan, int32_t *tile, int32_t *blocks_per_cu,
                             int64_t *gemm_items);
-/* Sets the tile (1..3) and blocks per compute unit (1..16) by hand. */
+/* Sets the tile (1..3) and blocks per compute unit (0..16) by hand. */
 int oz2h_batched_set_config(oz2h_batched_plan *plan, int32_t tile, int32_t blocks_per_cu);
 void oz2h_batched_plan_destroy(oz2h_batched_plan *plan);
 

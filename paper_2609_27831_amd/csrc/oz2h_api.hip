@@ -1013,7 +1013,9 @@ void drop_graph(oz2h_batched_plan *bp) {
 
 int launch_batched_gemm(oz2h_batched_plan *bp, char *ws, hipStream_t s) {
     if (!bp->nitems) return OZ2H_OK;
-    const int grid = (int)std::min<int64_t>(bp->nitems, (int64_t)bp->ncu * bp->bpc);
+    // bpc > 0: a persistent grid of bpc blocks per compute unit; bpc = 0: one block per item
+    const int grid = bp->bpc > 0 ? (int)std::min<int64_t>(bp->nitems, (int64_t)bp->ncu * bp->bpc)
+                                 : bp->nitems;
     switch (bp->tile) {
         case OZ2H_TILE_256x128:
             k_resgemm_grouped<128, 64><<<grid, 256, 0, s>>>(bp->d_probs, bp->d_items, bp->nitems, ws);
@@ -1367,7 +1369,7 @@ int oz2h_batched_get_config(const oz2h_batched_plan *plan, int32_t *tile, int32_
 
 int oz2h_batched_set_config(oz2h_batched_plan *plan, int32_t tile, int32_t blocks_per_cu) {
     if (!plan) return fail(OZ2H_EINVAL, "plan is NULL");
-    if (tile < OZ2H_TILE_128x128 || tile > OZ2H_TILE_128x256 || blocks_per_cu < 1 || blocks_per_cu > 16)
+    if (tile < OZ2H_TILE_128x128 || tile > OZ2H_TILE_128x256 || blocks_per_cu < 0 || blocks_per_cu > 16)
         return fail(OZ2H_EINVAL, "bad tile or blocks_per_cu");
     if (tile != plan->tile || blocks_per_cu != plan->bpc) {
         plan->tile = tile;
@@ -1419,7 +1421,7 @@ int oz2h_batched_tune(oz2h_batched_plan *plan, void *ws, size_t ws_bytes, hipStr
     float best = 1e30f;
     int bt = plan->tile, bb = plan->bpc;
     const int tiles[3] = {OZ2H_TILE_128x128, OZ2H_TILE_256x128, OZ2H_TILE_128x256};
-    const int bpcs[3] = {1, 2, 4};
+    const int bpcs[4] = {1, 2, 4, 0};
     for (int ti : tiles)
         for (int bc : bpcs) {
             plan->tile = ti;
