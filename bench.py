@@ -204,6 +204,66 @@ def bench_batched(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_autograd(args):
+    """Autograd form: forward C = A B plus both backward products (dA = W B^T, dB = A^T W)
+    at 4096^2, p = 256, through torch.autograd (float64 carriers), reuse vs recompute."""
+    import torch
+
+    import synth
+    from paper_2609_27831_amd import autograd as ag
+    from paper_2609_27831_amd import oz2h
+    torch.cuda.set_device(0)
+    M = N = K = 4096
+    p = 256
+    A, B, W = synth.grad_operands_for(synth.CONFIG_SEED_BASE + 5, M, N, K, p, -4, 4)
+    a0, b0, w = ag.to_carrier(A), ag.to_carrier(B), ag.to_carrier(W)
+    flops = 3 * 2.0 * M * N * K
+    out = {}
+    for mode in ("reuse", "recompute"):
+        def step():
+            a = a0.detach().requires_grad_()
+            b = b0.detach().requires_grad_()
+            c = ag.oz_matmul(a, b, p, mode=mode)
+            c.backward(w)
+            return a.grad, b.grad
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ga, gb = step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        out[mode] = ms
+    # the backward entry point alone, from a saved forward (no carrier conversions)
+    plan = oz2h.Plan.create_grad(p, M, N, K)
+    Ad, Bd, Wd = oz2h.to_device(A), oz2h.to_device(B), oz2h.to_device(W)
+    ws = oz2h.workspace(plan, M, N)
+    bws = torch.empty(plan.backward_workspace_size(), dtype=torch.uint8, device="cuda")
+    dA, dB = oz2h.empty_mp(M, K, p), oz2h.empty_mp(K, N, p)
+    oz2h.gemm(plan, Ad, Bd, ws=ws)
+    for _ in range(args.warmup):
+        oz2h.gemm_backward(plan, ws, Wd, dA=dA, dB=dB, ws=bws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        oz2h.gemm_backward(plan, ws, Wd, dA=dA, dB=dB, ws=bws)
+    torch.cuda.synchronize()
+    ms_bwd = (time.perf_counter() - t0) * 1e3 / args.steps
+    line = {
+        "metric": "autograd effective p-bit GFlop/s (forward + both backward products, 3 x 2MNK / s)",
+        "unit": "GFlop/s", "value": round(flops / (out["reuse"] * 1e-3) / 1e9, 3), "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(out["reuse"], 4),
+        "higher_is_better": True, "dtype": "i8", "data": "synthetic",
+        "config": {"workload": "C = A B and its backward, M=N=K=4096, p=256, A and B exponents "
+                               "U[-4,4], upstream gradient +-u 2^-p", "mode": "reuse"},
+        "recompute_ms_per_step": round(out["recompute"], 4),
+        "backward_entry_point_ms": round(ms_bwd, 4),
+        "backward_effective_gflops": round(2 * 2.0 * M * N * K / (ms_bwd * 1e-3) / 1e9, 3),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def copy_calibration():
     """A plain device copy of known size, for the HBM-counter scale factors."""
     import torch
@@ -221,7 +281,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="cfg2", choices=sorted(CONFIGS) + ["cfg4"])
+    ap.add_argument("--config", default="cfg2", choices=sorted(CONFIGS) + ["cfg4", "cfg5"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -237,6 +297,8 @@ def main():
         return copy_calibration()
     if args.config == "cfg4":
         return bench_batched(args)
+    if args.config == "cfg5":
+        return bench_autograd(args)
 
     import numpy as np
     import torch

@@ -837,25 +837,39 @@ __global__ __launch_bounds__(256) void k_crt(CrtArgs a) {
     crt_block<DC, EPT, ROUND, WEIGHT, GDIG>(a, blockIdx.x, sdig);
 }
 
-// planes [G][R][C] (int8, row stride ldi) -> [G][C'][R'] (row stride ldo = R'), zero
-// where the source is out of range; 64 x 64 tiles through LDS (one byte per lane,
-// coalesced on both sides)
+// planes [G][R][C] (int8, row stride ldi) -> [G][Co][Ro] (row stride Ro), zero where
+// the source is out of range.  A block moves a 64 x 64 byte tile: 16-byte global
+// loads of source rows into LDS, then each thread gathers 16 bytes of a source column
+// (one output row) and writes them with one 16-byte store.  Requires ldi, C, Ro and
+// Co to be multiples of 16 (the residue planes are padded to 128).
 __global__ __launch_bounds__(256) void k_plane_transpose(const int8_t *__restrict__ in, int64_t R,
                                                          int64_t C, int64_t ldi, int64_t ips,
                                                          int8_t *__restrict__ out, int64_t Ro,
                                                          int64_t Co, int64_t ops) {
-    __shared__ int8_t tile[64][65];
+    __shared__ uint8_t tile[64][64 + 4];
     const int64_t g = blockIdx.z;
     const int64_t c0 = (int64_t)blockIdx.x * 64, r0 = (int64_t)blockIdx.y * 64;   // source tile
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    for (int y = ty; y < 64; y += 4) {
-        const int64_t r = r0 + y, c = c0 + tx;
-        tile[y][tx] = (r < R && c < C) ? in[g * ips + r * ldi + c] : 0;
+    const int t = threadIdx.x, tr = t >> 2, tq = (t & 3) * 16;
+    {   // source row r0 + tr, columns c0 + tq .. + 15
+        const int64_t r = r0 + tr, c = c0 + tq;
+        v4i x = v4i{0, 0, 0, 0};
+        if (r < R && c < C) x = *(const v4i *)(in + g * ips + r * ldi + c);
+        uint32_t *dst = (uint32_t *)&tile[tr][tq];
+        dst[0] = (uint32_t)x[0];
+        dst[1] = (uint32_t)x[1];
+        dst[2] = (uint32_t)x[2];
+        dst[3] = (uint32_t)x[3];
     }
     __syncthreads();
-    for (int y = ty; y < 64; y += 4) {   // output row = source column
-        const int64_t orow = c0 + y, ocol = r0 + tx;
-        if (orow < Co && ocol < Ro) out[g * ops + orow * Ro + ocol] = tile[tx][y];
+    {   // output row c0 + tr (= source column), output columns r0 + tq .. + 15 (= source rows)
+        const int64_t orow = c0 + tr, ocol = r0 + tq;
+        uint32_t w[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            w[j] = (uint32_t)tile[tq + 4 * j][tr] | ((uint32_t)tile[tq + 4 * j + 1][tr] << 8) |
+                   ((uint32_t)tile[tq + 4 * j + 2][tr] << 16) | ((uint32_t)tile[tq + 4 * j + 3][tr] << 24);
+        if (orow < Co && ocol < Ro)
+            *(v4i *)(out + g * ops + orow * Ro + ocol) = v4i{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
     }
 }
 
