@@ -272,9 +272,13 @@ int launch_crt(const oz2h_plan *pl, int64_t M, int64_t N, const int16_t *u, int6
     else OZ2H_CRT(DC, 1, R, W, G);
 #define OZ2H_CRT_DC(R, W, G)                          \
     switch (h.crt_dc) {                               \
+        case 4: OZ2H_CRT_E(4, R, W, G) break;         \
         case 8: OZ2H_CRT_E(8, R, W, G) break;         \
+        case 12: OZ2H_CRT_E(12, R, W, G) break;       \
         case 16: OZ2H_CRT_E(16, R, W, G) break;       \
+        case 20: OZ2H_CRT_E(20, R, W, G) break;       \
         case 24: OZ2H_CRT_E(24, R, W, G) break;       \
+        case 28: OZ2H_CRT_E(28, R, W, G) break;       \
         default: OZ2H_CRT_E(32, R, W, G) break;       \
     }
     if (weight) {
@@ -1056,9 +1060,13 @@ int launch_batched_crt(oz2h_batched_plan *bp, char *ws, hipStream_t s) {
     k_crt_grouped<DC, E, G><<<nb, c.bd, c.lds, s>>>(bp->d_probs, c.d_segs, c.nseg, ws, c.LB)
 #define OZ2H_GCRT_DC(E, G)                     \
     switch (c.dc) {                            \
+        case 4: OZ2H_GCRT(4, E, G); break;     \
         case 8: OZ2H_GCRT(8, E, G); break;     \
+        case 12: OZ2H_GCRT(12, E, G); break;   \
         case 16: OZ2H_GCRT(16, E, G); break;   \
+        case 20: OZ2H_GCRT(20, E, G); break;   \
         case 24: OZ2H_GCRT(24, E, G); break;   \
+        case 28: OZ2H_GCRT(28, E, G); break;   \
         default: OZ2H_GCRT(32, E, G); break;   \
     }
         if (c.gdig) {

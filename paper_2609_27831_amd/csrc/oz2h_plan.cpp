@@ -214,7 +214,7 @@ int build_plan(int p, int t, int64_t K, const std::vector<uint32_t> &mods_in, Pl
     // direct-CRT weights: M_l = P / m_l, minv = M_l^-1 mod m_l
     h.crt_nc = (h.nd32 + 31) / 32;
     int per = (h.nd32 + h.crt_nc - 1) / h.crt_nc;
-    h.crt_dc = ((per + 7) / 8) * 8;
+    h.crt_dc = ((per + 3) / 4) * 4;   // a multiple of 4 (two digits per LDS read, little padding)
     h.crt_ndpad = h.crt_dc * h.crt_nc;
     h.crt_digits.assign((size_t)h.L * h.crt_ndpad, 0.0);
     for (int l = 0; l < h.L; ++l) {
