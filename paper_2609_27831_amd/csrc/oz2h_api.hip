@@ -188,9 +188,15 @@ int launch_residues(const oz2h_plan *pl, int64_t rows, int64_t count, const uint
     const size_t lds = (size_t)h.nw32 * 64 * rb * sizeof(uint32_t);
     const ResArgs a{limbs, exp, sign, rs, cs, rows, count, kpad, ps, erow, h.p, nl, t, h.nw32,
                     pl->d_resid, pl->d_rgrp, h.L, h.lgroups, planes, koff};
-    if (rb == 4) k_residues<4><<<grid, 256, lds, s>>>(a);
-    else if (rb == 2) k_residues<2><<<grid, 128, lds, s>>>(a);
-    else k_residues<1><<<grid, 64, lds, s>>>(a);
+    if (h.kg == kModGroupWide) {
+        if (rb == 4) k_residues<4, kModGroupWide><<<grid, 256, lds, s>>>(a);
+        else if (rb == 2) k_residues<2, kModGroupWide><<<grid, 128, lds, s>>>(a);
+        else k_residues<1, kModGroupWide><<<grid, 64, lds, s>>>(a);
+    } else {
+        if (rb == 4) k_residues<4, kModGroup><<<grid, 256, lds, s>>>(a);
+        else if (rb == 2) k_residues<2, kModGroup><<<grid, 128, lds, s>>>(a);
+        else k_residues<1, kModGroup><<<grid, 64, lds, s>>>(a);
+    }
     return check_launch("residues");
 }
 
@@ -1151,7 +1157,7 @@ int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2
         std::string err;
         st = select_moduli(q.p, q.K, o->guard_bits, o->t_bits, o->crt_margin, mods, t, lp, err);
         if (st) return fail(st, "problem %d: %s", b, err.c_str());
-        st = build_plan(q.p, t, q.K, mods, bp->hosts[b], err);
+        st = build_plan(q.p, t, q.K, mods, bp->hosts[b], err, 0, false);
         if (st) return fail(st, "problem %d: %s", b, err.c_str());
     }
 

@@ -106,7 +106,7 @@ __global__ __launch_bounds__(64 * RB) void k_residues_grouped(const ProbDev *__r
     const Seg sg = segs[si];
     const int64_t lb = (int64_t)blockIdx.x - sg.first;
     const ResArgs a = res_args(probs[sg.prod], sg.side, ws);
-    residue_block<RB>(a, lb % sg.nbx, lb / sg.nbx, words);
+    residue_block<RB, kModGroup>(a, lb % sg.nbx, lb / sg.nbx, words);
 }
 
 // one work item of the grouped GEMM: output tile (mt, nt) of modulus l of product prod

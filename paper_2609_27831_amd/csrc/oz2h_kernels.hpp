@@ -189,7 +189,7 @@ struct ResArgs {
 // The pointers are passed as __restrict__ parameters (kept as scoped no-alias
 // information when inlined), so the compiler knows that the plane stores do
 // not clobber the constant tables and reads those with scalar loads.
-template <int RB>
+template <int RB, int KG>
 __device__ __forceinline__ void residue_block_r(
     const uint64_t *__restrict__ limbs, const int32_t *__restrict__ exps,
     const int8_t *__restrict__ signs, const int32_t *__restrict__ erow,
@@ -228,20 +228,20 @@ __device__ __forceinline__ void residue_block_r(
     const uint32_t loff = (uint32_t)(r * kpad + k);
     const double sgn = s < 0 ? -1.0 : 1.0;
     for (int grp = 0; grp < lgroups; ++grp) {
-        double acc[kModGroup];
+        double acc[KG];
 #pragma unroll
-        for (int g = 0; g < kModGroup; ++g) acc[g] = 0.0;
-        gdouble *c = gtab + (size_t)grp * nw32 * kModGroup;   // uniform: scalar loads
+        for (int g = 0; g < KG; ++g) acc[g] = 0.0;
+        gdouble *c = gtab + (size_t)grp * nw32 * KG;   // uniform: scalar loads
         for (int w = 0; w < nw32; ++w) {
             const double x = (double)col[w * BD];
 #pragma unroll
-            for (int g = 0; g < kModGroup; ++g) acc[g] = fma(x, c[w * kModGroup + g], acc[g]);
+            for (int g = 0; g < KG; ++g) acc[g] = fma(x, c[w * KG + g], acc[g]);
         }
         OZ2H_G(ResGroup) *R = grec + grp;
         const uint32_t two = R->two;
 #pragma unroll
-        for (int g = 0; g < kModGroup; ++g) {
-            if (grp * kModGroup + g >= L) break;
+        for (int g = 0; g < KG; ++g) {
+            if (grp * KG + g >= L) break;
             const double a = acc[g] * sgn;
             const int ri = (int)fma(-rint(a * R->inv_m[g]), R->md[g], a);
             g_i8 *pb = (g_i8 *)planes + (int64_t)R->g0[g] * plane_stride;
@@ -258,18 +258,18 @@ __device__ __forceinline__ void residue_block_r(
     }
 }
 
-template <int RB>
+template <int RB, int KG>
 __device__ __forceinline__ void residue_block(const ResArgs &a, int64_t bx, int64_t by,
                                               uint32_t *words) {
-    residue_block_r<RB>(a.limbs, a.exps, a.signs, a.erow, a.koff, a.tab, a.rgrp, a.planes, a.rs,
+    residue_block_r<RB, KG>(a.limbs, a.exps, a.signs, a.erow, a.koff, a.tab, a.rgrp, a.planes, a.rs,
                         a.cs, a.rows, a.count, a.kpad, a.plane_stride, a.p, a.nl, a.t, a.nw32,
                         a.L, a.lgroups, bx, by, words);
 }
 
-template <int RB>
+template <int RB, int KG>
 __global__ __launch_bounds__(64 * RB) void k_residues(ResArgs a) {
     extern __shared__ uint32_t words[];
-    residue_block<RB>(a, blockIdx.x, blockIdx.y, words);
+    residue_block<RB, KG>(a, blockIdx.x, blockIdx.y, words);
 }
 
 // ---------------------------------------------------------------- stage 3

@@ -157,7 +157,7 @@ int select_moduli_bits(double need, std::vector<uint32_t> &mods, double &log2P, 
 }
 
 int build_plan(int p, int t, int64_t K, const std::vector<uint32_t> &mods_in, PlanHost &h,
-               std::string &err, int wmax) {
+               std::string &err, int wmax, bool allow_wide) {
     if (mods_in.empty() || (int)mods_in.size() > kMaxModuli) {
         err = "need 1..512 moduli";
         return -1;
@@ -276,25 +276,28 @@ int build_plan(int p, int t, int64_t K, const std::vector<uint32_t> &mods_in, Pl
         h.ph_digits[k] = lo | hi;
     }
 
-    // residue weights: centred 2^(32 w) mod m, grouped by kModGroup moduli
-    h.lgroups = (h.L + kModGroup - 1) / kModGroup;
+    // residue weights: centred 2^(32 w) mod m, grouped by kg moduli (16 for wide sets:
+    // each word read then feeds twice the FMAs)
+    h.kg = allow_wide && h.L >= kWideL ? kModGroupWide : kModGroup;
+    const int kg = h.kg;
+    h.lgroups = (h.L + kg - 1) / kg;
     h.resgrp.assign(h.lgroups, ResGroup{});
     for (int l = 0; l < h.L; ++l) {
-        ResGroup &R = h.resgrp[l / kModGroup];
-        const int g = l % kModGroup;
+        ResGroup &R = h.resgrp[l / kg];
+        const int g = l % kg;
         R.inv_m[g] = h.info[l].inv_m;
         R.md[g] = (double)h.info[l].m;
         R.g0[g] = h.info[l].g0;
         if (h.info[l].nprod == 3) R.two |= 1u << g;
     }
-    h.resid_tab.assign((size_t)h.lgroups * h.nw32 * kModGroup, 0.0);
+    h.resid_tab.assign((size_t)h.lgroups * h.nw32 * kg, 0.0);
     for (int l = 0; l < h.L; ++l) {
         const uint64_t m = mods[l];
         uint64_t x = 1 % m;
         for (int w = 0; w < h.nw32; ++w) {
             int64_t c = (int64_t)x;
             if (c > (int64_t)((m - 1) / 2)) c -= (int64_t)m;
-            h.resid_tab[((size_t)(l / kModGroup) * h.nw32 + w) * kModGroup + (l % kModGroup)] =
+            h.resid_tab[((size_t)(l / kg) * h.nw32 + w) * kg + (l % kg)] =
                 (double)c;
             x = ((x << 32) % m);
         }

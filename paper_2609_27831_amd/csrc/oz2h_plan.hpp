@@ -8,7 +8,9 @@
 
 namespace oz2h {
 
-constexpr int kModGroup = 8;          // moduli per group in the residue kernel
+constexpr int kModGroup = 8;          // moduli per group in the residue kernel (small L)
+constexpr int kModGroupWide = 16;     // ... and for wide moduli sets (L >= kWideL)
+constexpr int kWideL = 96;
 constexpr int kMaxModuli = 512;       // fp64-exact CRT digit sums need L * 2^44 < 2^53
 constexpr int kMaxWords = 256;        // fp64-exact residue sums need nw32 * 2^45 < 2^53
 constexpr int64_t kMaxK = 133000;     // K * 127^2 < 2^31, the cap the paper's implementation uses
@@ -27,16 +29,16 @@ struct ModInfo {
     int32_t pad;
 };
 
-// One group of kModGroup moduli as the residue kernel reads it (wave-uniform
-// scalar loads, 192 bytes).
+// One group of up to kModGroupWide moduli as the residue kernel reads it
+// (wave-uniform scalar loads, 384 bytes).
 struct ResGroup {
-    double inv_m[kModGroup];   // fl(1/m)
-    double md[kModGroup];      // m as a double
-    uint32_t g0[kModGroup];    // first INT8 plane of the modulus
-    uint32_t two;              // bit g: modulus g is two-limb (three planes)
-    uint32_t pad[7];
+    double inv_m[kModGroupWide];   // fl(1/m)
+    double md[kModGroupWide];      // m as a double
+    uint32_t g0[kModGroupWide];    // first INT8 plane of the modulus
+    uint32_t two;                  // bit g: modulus g is two-limb (three planes)
+    uint32_t pad[15];
 };
-static_assert(sizeof(ResGroup) == 192, "ResGroup layout");
+static_assert(sizeof(ResGroup) == 384, "ResGroup layout");
 
 struct PlanHost {
     int p = 0, t = 0;
@@ -49,7 +51,8 @@ struct PlanHost {
     int64_t gM = 0, gN = 0;
     int tw[2] = {0, 0};    // widths of the upstream gradient W for dA = W B^T and dB = A^T W
     int nd32 = 0;          // 32-bit digits of the CRT accumulator
-    int lgroups = 0;       // ceil(L / kModGroup)
+    int kg = kModGroup;    // moduli per residue group: kModGroup, or kModGroupWide for L >= kWideL
+    int lgroups = 0;       // ceil(L / kg)
     int crt_dc = 0;        // CRT digit chunk (digits accumulated per pass)
     int crt_nc = 0;        // CRT passes
     int crt_ndpad = 0;     // crt_dc * crt_nc
@@ -57,7 +60,7 @@ struct PlanHost {
     int pbits = 0;         // bit length of P
     std::vector<uint32_t> moduli;    // L, one-limb first
     std::vector<ModInfo> info;       // L
-    std::vector<double> resid_tab;   // [lgroups][nw32][kModGroup]: centred 2^(32w) mod m
+    std::vector<double> resid_tab;   // [lgroups][nw32][kg]: centred 2^(32w) mod m
     std::vector<ResGroup> resgrp;    // [lgroups]
     std::vector<double> crt_digits;  // [L][crt_ndpad]: balanced base-2^32 digits of P/m
     std::vector<uint32_t> p_digits;  // [nd32] digits of P
@@ -81,6 +84,6 @@ int select_moduli_bits(double need, std::vector<uint32_t> &mods, double &log2P, 
 // Fill every table for the given moduli (one-limb moduli must come first);
 // integer significands are up to max(t, wmax) + 1 bits wide.
 int build_plan(int p, int t, int64_t K, const std::vector<uint32_t> &mods, PlanHost &out,
-               std::string &err, int wmax = 0);
+               std::string &err, int wmax = 0, bool allow_wide = true);
 
 }  // namespace oz2h
