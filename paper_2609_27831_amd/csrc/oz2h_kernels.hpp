@@ -282,6 +282,10 @@ __device__ __forceinline__ int32_t centred_mod(double x, double md, double inv_m
     return (int32_t)fma(-rint(x * inv_m), md, x);
 }
 
+// chunk swizzle of LDS tile row r: distinct over the rows of equal parity among any 16
+// aligned rows, and over any 8 aligned rows
+__device__ __forceinline__ int lds_swz(int r) { return (r & 7) ^ ((r >> 3) & 1); }
+
 // s_waitcnt immediate: wait until at most `lgkm` LDS/scalar ops are outstanding,
 // leaving vector-memory loads in flight (gfx9 encoding, vmcnt and expcnt at max)
 constexpr int lgkmcnt_imm(int lgkm) { return 0xF | (3 << 14) | (0x7 << 4) | ((lgkm & 0xF) << 8); }
@@ -290,8 +294,9 @@ constexpr int lgkmcnt_imm(int lgkm) { return 0xF | (3 << 14) | (0x7 << 4) | ((lg
 // each a WM x WN sub-tile of v_mfma_i32_32x32x32_i8 blocks (exact int32 sums,
 // K * 127^2 < 2^31).  k-tiles of 128 bytes are prefetched two tiles ahead into
 // registers and stored to a double-buffered LDS ring; a tile row is 128 bytes
-// = eight 16-byte chunks, chunk c of row r stored at c ^ (r & 7), so the MFMA
-// fragment reads of 8 consecutive rows hit 8 different bank groups.
+// = eight 16-byte chunks, chunk c of row r stored at c ^ lds_swz(r): the 16 rows a
+// ds_read_b128 serves per LDS cycle (64 banks of 4 bytes, two 128-byte rows per bank
+// period) then hit 16 different 16-byte bank groups, and so do any 8 consecutive rows.
 // The output is v_l = c_l (P/m_l)^-1 mod m_l as a centred int16: the reduction
 // mod m_l and the first step of the direct CRT are fused here.
 // A two-limb modulus runs its three Karatsuba products (planes r0, r1, r0 + r1:
@@ -348,7 +353,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &args, int64_t mt, int6
     // global -> register -> LDS: thread t moves row t/8 (+32 per pass), chunk t%8
     const int grow = tid >> 3, gch = tid & 7;
     const int64_t g_off = (int64_t)grow * kpad + gch * 16;
-    const int s_off = grow * TBK + ((gch ^ (grow & 7)) << 4);   // (grow + 32 i) & 7 == grow & 7
+    const int s_off = grow * TBK + ((gch ^ lds_swz(grow)) << 4);   // lds_swz(grow + 32 i) == lds_swz(grow)
     constexpr int NG = AP + BP;            // 16-byte loads per thread per k-tile
     constexpr int KS = TBK / 32;           // MFMA k-steps per k-tile
     constexpr int GQ = (NG + KS - 1) / KS; // loads / LDS stores issued per k-step
@@ -370,12 +375,12 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &args, int64_t mt, int6
         for (int y = 0; y < FN; ++y) acc[x][y] = v16i{};
 
     // fragment reads: row R = (multiple of 32) + lane%32, logical chunk c = 2 s + lane/32;
-    // R & 7 only depends on lane, so each k-step's swizzled offset is a per-lane constant.
+    // lds_swz(R) only depends on lane, so each k-step's swizzled offset is a per-lane constant.
     // Two fragment sets: the reads of k-step s + 1 are in flight while k-step s multiplies.
     const int frow = lane & 31;
     v4i fa[2][FM], fb[2][FN];
     auto fload = [&](int set, int ks, const int8_t *cA, const int8_t *cB) {
-        const int fo = frow * TBK + (((2 * ks + (lane >> 5)) ^ (frow & 7)) << 4);
+        const int fo = frow * TBK + (((2 * ks + (lane >> 5)) ^ lds_swz(frow)) << 4);
 #pragma unroll
         for (int x = 0; x < FM; ++x) fa[set][x] = *(const v4i *)(cA + (wr * WM + x * 32) * TBK + fo);
 #pragma unroll
