@@ -120,7 +120,6 @@ template <int WM, int WN>
 __global__ __launch_bounds__(256) void k_resgemm_grouped(const ProbDev *__restrict__ probs,
                                                          const GemmItem *__restrict__ items,
                                                          int nitems, char *ws) {
-    __shared__ __attribute__((aligned(1024))) int8_t lds[gemm_lds_bytes<WM, WN>()];
     for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
         const GemmItem it = items[i];
         const ProbDev &P = probs[it.prod];
@@ -128,7 +127,7 @@ __global__ __launch_bounds__(256) void k_resgemm_grouped(const ProbDev *__restri
                          P.kpad, P.rpad[0] * P.kpad, P.rpad[1] * P.kpad, P.mi,
                          (int16_t *)(ws + P.v_off), P.rpad[0] * P.rpad[1], P.rpad[1], nullptr};
         __syncthreads();   // the previous item's LDS tiles are no longer read
-        gemm_tile<WM, WN, false>(g, it.mt, it.nt, it.l, lds);
+        gemm_tile<WM, WN, false>(g, it.mt, it.nt, it.l);
     }
 }
 

@@ -286,17 +286,18 @@ __device__ __forceinline__ int32_t centred_mod(double x, double md, double inv_m
 // aligned rows, and over any 8 aligned rows
 __device__ __forceinline__ int lds_swz(int r) { return (r & 7) ^ ((r >> 3) & 1); }
 
-// s_waitcnt immediate: wait until at most `lgkm` LDS/scalar ops are outstanding,
-// leaving vector-memory loads in flight (gfx9 encoding, vmcnt and expcnt at max)
-constexpr int lgkmcnt_imm(int lgkm) { return 0xF | (3 << 14) | (0x7 << 4) | ((lgkm & 0xF) << 8); }
-
 // One (2 WM) x (2 WN) output tile of one modulus per block; four waves in 2x2,
 // each a WM x WN sub-tile of v_mfma_i32_32x32x32_i8 blocks (exact int32 sums,
-// K * 127^2 < 2^31).  k-tiles of 128 bytes are prefetched two tiles ahead into
-// registers and stored to a double-buffered LDS ring; a tile row is 128 bytes
+// K * 127^2 < 2^31).  k-tiles of 128 bytes move global -> LDS by direct loads
+// (global_load_lds_dwordx4: no register staging, no LDS store instructions) into a
+// three-stage LDS ring, two tiles ahead of the multiplies.  A tile row is 128 bytes
 // = eight 16-byte chunks, chunk c of row r stored at c ^ lds_swz(r): the 16 rows a
 // ds_read_b128 serves per LDS cycle (64 banks of 4 bytes, two 128-byte rows per bank
 // period) then hit 16 different 16-byte bank groups, and so do any 8 consecutive rows.
+// The lane order of a direct load fixes the LDS side (16 bytes per lane, consecutive),
+// so the swizzle is applied to the global addresses: load i of wave w fills LDS rows
+// 32 i + 8 w .. + 7, lane -> row 32 i + 8 w + lane / 8, physical chunk lane % 8, which
+// holds logical chunk (lane % 8) ^ lds_swz(row).
 // The output is v_l = c_l (P/m_l)^-1 mod m_l as a centred int16: the reduction
 // mod m_l and the first step of the direct CRT are fused here.
 // A two-limb modulus runs its three Karatsuba products (planes r0, r1, r0 + r1:
@@ -317,20 +318,29 @@ struct GemmArgs {
     int32_t *Craw;
 };
 
-template <int WM, int WN>
-constexpr int gemm_lds_bytes() { return 2 * (2 * WM + 2 * WN) * TBK; }
+// LDS stage S of the direct-load GEMM: one object per stage, so that the compiler can
+// tell a read of one stage from a load still filling another
+template <int WM, int WN, int S>
+__device__ __forceinline__ int8_t *gemm_stage() {
+    __shared__ __attribute__((aligned(1024))) int8_t st[(2 * WM + 2 * WN) * TBK];
+    return st;
+}
 
-// one output tile (mt, nt) of modulus l; `lds` holds gemm_lds_bytes<WM, WN>() bytes
-template <int WM, int WN, bool RAW>
-__device__ __forceinline__ void gemm_tile(const GemmArgs &args, int64_t mt, int64_t nt, int l,
-                                          int8_t *lds) {
+// s_waitcnt immediate: wait until at most `vm` vector-memory loads are outstanding
+// (LDS/scalar and export counters left at their maximum)
+constexpr int vmcnt_imm(int vm) { return (vm & 0xF) | (((vm >> 4) & 3) << 14) | (0x7 << 4) | (0xF << 8); }
+
+// one output tile (mt, nt) of modulus l with an NS-stage LDS ring, NS - 1 tiles ahead
+template <int WM, int WN, bool RAW, int NS = 3>
+__device__ __forceinline__ void gemm_tile(const GemmArgs &args, int64_t mt, int64_t nt, int l) {
+    static_assert(NS == 2 || NS == 3, "two or three LDS stages");
     constexpr int BM = 2 * WM, BN = 2 * WN, FM = WM / 32, FN = WN / 32;
-    constexpr int AP = BM / 32, BP = BN / 32;   // 32 rows x 128 bytes per pass of 256 lanes
-    int8_t *sA0 = lds, *sA1 = lds + BM * TBK, *sB0 = lds + 2 * BM * TBK, *sB1 = sB0 + BN * TBK;
+    constexpr int NLA = BM / 32, NL = (BM + BN) / 32;   // direct loads per wave per k-tile
     const int8_t *__restrict__ A = args.A;
     const int8_t *__restrict__ B = args.B;
     const int64_t kpad = args.kpad, a_ps = args.a_ps, b_ps = args.b_ps, ldv = args.ldv;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wr = wave >> 1, wc = wave & 1;
     const int64_t m0 = mt * BM, n0 = nt * BN;
 
@@ -350,22 +360,24 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &args, int64_t mt, int6
     const int nk = (int)(kpad / TBK);   // kpad is a multiple of 128
     const int ntile = (int)nprod * nk;
 
-    // global -> register -> LDS: thread t moves row t/8 (+32 per pass), chunk t%8
-    const int grow = tid >> 3, gch = tid & 7;
-    const int64_t g_off = (int64_t)grow * kpad + gch * 16;
-    const int s_off = grow * TBK + ((gch ^ lds_swz(grow)) << 4);   // lds_swz(grow + 32 i) == lds_swz(grow)
-    constexpr int NG = AP + BP;            // 16-byte loads per thread per k-tile
-    constexpr int KS = TBK / 32;           // MFMA k-steps per k-tile
-    constexpr int GQ = (NG + KS - 1) / KS; // loads / LDS stores issued per k-step
-    v4i rg[2][NG];
-    // tile (prod, kt) -> its global address for this thread (A rows first, then B rows)
-    auto gptr = [&](int prod, int kt, int i) -> const v4i * {
-        const int64_t ko = (int64_t)kt * TBK + g_off;
-        return i < AP ? (const v4i *)(A + (int64_t)(g0 + prod) * a_ps + (m0 + 32 * i) * kpad + ko)
-                      : (const v4i *)(B + (int64_t)(g0 + prod) * b_ps + (n0 + 32 * (i - AP)) * kpad + ko);
-    };
-    auto sptr = [&](int i, int8_t *dA, int8_t *dB) -> v4i * {
-        return i < AP ? (v4i *)(dA + s_off + 32 * i * TBK) : (v4i *)(dB + s_off + 32 * (i - AP) * TBK);
+    uint32_t goff[NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        const int R = 32 * i + 8 * wave + (lane >> 3);
+        const int rl = i < NLA ? R : R - BM;
+        goff[i] = (uint32_t)(rl * kpad) + ((((lane & 7) ^ lds_swz(R))) << 4);
+    }
+    const int8_t *Ab = A + m0 * kpad, *Bb = B + n0 * kpad;
+    auto issue = [&](auto s_, int prod, int kt) {
+        int8_t *dst = gemm_stage<WM, WN, decltype(s_)::value>();
+        const int64_t ko = (int64_t)kt * TBK;
+        const int8_t *a = Ab + (int64_t)(g0 + prod) * a_ps + ko;
+        const int8_t *b = Bb + (int64_t)(g0 + prod) * b_ps + ko;
+#pragma unroll
+        for (int i = 0; i < NL; ++i)
+            __builtin_amdgcn_global_load_lds((const void *)((i < NLA ? a : b) + goff[i]),
+                                             (__attribute__((address_space(3))) void *)(dst + (4 * i + wave) * 1024),
+                                             16, 0, 0);
     };
 
     v16i acc[FM][FN];
@@ -374,9 +386,6 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &args, int64_t mt, int6
 #pragma unroll
         for (int y = 0; y < FN; ++y) acc[x][y] = v16i{};
 
-    // fragment reads: row R = (multiple of 32) + lane%32, logical chunk c = 2 s + lane/32;
-    // lds_swz(R) only depends on lane, so each k-step's swizzled offset is a per-lane constant.
-    // Two fragment sets: the reads of k-step s + 1 are in flight while k-step s multiplies.
     const int frow = lane & 31;
     v4i fa[2][FM], fb[2][FN];
     auto fload = [&](int set, int ks, const int8_t *cA, const int8_t *cB) {
@@ -386,9 +395,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &args, int64_t mt, int6
 #pragma unroll
         for (int y = 0; y < FN; ++y) fb[set][y] = *(const v4i *)(cB + (wc * WN + y * 32) * TBK + fo);
     };
-    // end of a product: acc = acc * w mod m, centred (|x| < 2^45 is exact in fp64)
     auto fold = [&](int prod) {
-        const double w = (double)kc[prod];
+        const double w = (double)(prod == 0 ? kc[0] : prod == 1 ? kc[1] : kc[2]);
 #pragma unroll
         for (int x = 0; x < FM; ++x)
 #pragma unroll
@@ -397,95 +405,73 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &args, int64_t mt, int6
                 for (int e = 0; e < 16; ++e)
                     acc[x][y][e] = centred_mod((double)acc[x][y][e] * w, md, inv_m);
     };
-    // One k-tile.  On entry: LDS (c) holds tile T and fragment set 0 holds its k-step 0;
-    // registers `slot ^ 1` hold tile T + 1 (loads possibly still in flight).  During the
-    // k-steps, tile T + 2 (clamped to the last) is fetched into `slot` and tile T + 1 is
-    // stored from `slot ^ 1` into LDS (n), a share per k-step.  Loads and stores are
-    // unconditional (indices clamped) so the compiler counts the loads in flight.
-    auto step = [&](int slot, int lp, int lk, const int8_t *cA, const int8_t *cB, int8_t *nA,
-                    int8_t *nB) {
+
+    // (cp, ck): product and k-tile of tile T; (lp, lk): of the tile loaded next, clamped to
+    // the last one.  Every k-tile issues one tile (the last one again near the end), so the
+    // number of loads in flight behind a tile does not depend on the path taken.
+    int cp = 0, ck = 0, lp = 0, lk = 0;
+    auto advance = [&](int &pp, int &kk) {
+        if (++kk == nk) {
+            kk = 0;
+            ++pp;
+        }
+    };
+    auto advance_clamped = [&](int &pp, int &kk) {   // branch-free: selects only
+        const bool more = pp * nk + kk < ntile - 1, wrap = kk + 1 == nk;
+        pp = more && wrap ? pp + 1 : pp;
+        kk = more ? (wrap ? 0 : kk + 1) : kk;
+    };
+    auto mfma = [&](int set) {
+#pragma unroll
+        for (int x = 0; x < FM; ++x)
+#pragma unroll
+            for (int y = 0; y < FN; ++y)
+                acc[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[set][x], fb[set][y], acc[x][y], 0, 0, 0);
+    };
+    issue(std::integral_constant<int, 0>{}, lp, lk);
+    advance_clamped(lp, lk);
+    if constexpr (NS == 3) {
+        issue(std::integral_constant<int, 1>{}, lp, lk);
+        advance_clamped(lp, lk);
+    }
+    // one k-tile from stage S; the tile NS - 1 ahead goes into stage (S + NS - 1) % NS,
+    // which every wave finished reading before the barrier
+    auto body = [&](auto s_) {
+        constexpr int S = decltype(s_)::value, SN = (S + NS - 1) % NS;
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm((NS - 2) * NL));   // own loads of tile T landed
+        __builtin_amdgcn_s_barrier();                            // everyone's did
+        issue(std::integral_constant<int, SN>{}, lp, lk);
+        advance_clamped(lp, lk);
+        const int8_t *cA = gemm_stage<WM, WN, S>(), *cB = cA + BM * TBK;
+        fload(0, 0, cA, cB);
         auto kstep = [&](auto kc_) {
             constexpr int ks = decltype(kc_)::value;
-#pragma unroll
-            for (int q = 0; q < GQ; ++q) {
-                const int i = ks * GQ + q;
-                if (i < NG) rg[slot][i] = *gptr(lp, lk, i);
-            }
-            if constexpr (ks + 1 < KS) fload((ks + 1) & 1, ks + 1, cA, cB);
-#pragma unroll
-            for (int x = 0; x < FM; ++x)
-#pragma unroll
-                for (int y = 0; y < FN; ++y)
-                    acc[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[ks & 1][x], fb[ks & 1][y],
-                                                                      acc[x][y], 0, 0, 0);
-#pragma unroll
-            for (int q = 0; q < GQ; ++q) {
-                const int i = ks * GQ + q;
-                if (i < NG) *sptr(i, nA, nB) = rg[slot ^ 1][i];
-            }
+            if constexpr (ks + 1 < 4) fload((ks + 1) & 1, ks + 1, cA, cB);
+            mfma(ks & 1);
 #if OZ2H_GEMM_SCHED
-            // issue order: the next k-step's fragment reads and this k-step's global loads
-            // first, then the MFMAs with this k-step's share of LDS stores between them
-            if constexpr (ks + 1 < KS) __builtin_amdgcn_sched_group_barrier(0x100, FM + FN, 0);
-            __builtin_amdgcn_sched_group_barrier(0x020, GQ, 0);
-#pragma unroll
-            for (int i = 0; i < FM * FN; ++i) {
-                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                if (i < GQ) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
-            }
+            if constexpr (ks + 1 < 4) __builtin_amdgcn_sched_group_barrier(0x100, FM + FN, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, FM * FN, 0);
 #endif
         };
         kstep(std::integral_constant<int, 0>{});
         kstep(std::integral_constant<int, 1>{});
         kstep(std::integral_constant<int, 2>{});
         kstep(std::integral_constant<int, 3>{});
-        static_assert(KS == 4, "k-tile of 128 bytes = 4 MFMA k-steps");
-    };
-
-#pragma unroll
-    for (int i = 0; i < NG; ++i) rg[0][i] = *gptr(0, 0, i);
-    const int t1 = min(1, ntile - 1);
-#pragma unroll
-    for (int i = 0; i < NG; ++i) rg[1][i] = *gptr(t1 / nk, t1 % nk, i);
-#pragma unroll
-    for (int i = 0; i < NG; ++i) *sptr(i, sA0, sB0) = rg[0][i];
-    __builtin_amdgcn_s_waitcnt(lgkmcnt_imm(0));
-    __builtin_amdgcn_s_barrier();
-    fload(0, 0, sA0, sB0);
-
-    // (cp, ck): product and k-tile of tile T; (lp, lk): of the tile fetched, min(T + 2, last)
-    int cp = 0, ck = 0;
-    int lp = min(2, ntile - 1) / nk, lk = min(2, ntile - 1) % nk;
-    auto advance = [&](int &pp, int &kk) {
-        if (pp * nk + kk < ntile - 1) {
-            if (++kk == nk) {
-                kk = 0;
-                ++pp;
-            }
-        }
-    };
-    auto finish = [&](int8_t *nA, int8_t *nB) {
         if (!RAW && ck == nk - 1) fold(cp);
         advance(cp, ck);
-        advance(lp, lk);
-        __builtin_amdgcn_s_waitcnt(lgkmcnt_imm(0));   // own LDS stores done (loads stay in flight)
-        __builtin_amdgcn_s_barrier();
-        fload(0, 0, nA, nB);
     };
-    int T = 0;
-    for (; T + 1 < ntile; T += 2) {
-        step(0, lp, lk, sA0, sB0, sA1, sB1);
-        finish(sA1, sB1);
-        step(1, lp, lk, sA1, sB1, sA0, sB0);
-        finish(sA0, sB0);
+    int t0 = 0;
+    for (; t0 + NS <= ntile; t0 += NS) {
+        body(std::integral_constant<int, 0>{});
+        body(std::integral_constant<int, 1>{});
+        if constexpr (NS == 3) body(std::integral_constant<int, 2>{});
     }
-    if (T < ntile) {
-        step(0, lp, lk, sA0, sB0, sA1, sB1);
-        finish(sA1, sB1);
+    if (t0 < ntile) {
+        body(std::integral_constant<int, 0>{});
+        if (NS == 3 && t0 + 1 < ntile) body(std::integral_constant<int, 1>{});
     }
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));   // no load still writing LDS past the block's end
 
-    // output element e of block (x, y): row 8*(e/4) + 4*(lane/32) + e%4, column lane%32;
-    // the per-element row offsets are uniform, only the lane base is per lane
     const int64_t lane_off = (m0 + wr * WM + 4 * (lane >> 5)) * ldv + n0 + wc * WN + (lane & 31);
     if (RAW) {
         int32_t *base = args.Craw + lane_off;
@@ -511,9 +497,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &args, int64_t mt, int6
 // plain launch: grid (N tiles, M tiles, moduli), two-limb moduli (listed last) first
 template <int WM, int WN, bool RAW>
 __global__ __launch_bounds__(256) void k_resgemm(GemmArgs args, int L) {
-    __shared__ __attribute__((aligned(1024))) int8_t lds[gemm_lds_bytes<WM, WN>()];
     const int l = RAW ? 0 : L - 1 - (int)blockIdx.z;
-    gemm_tile<WM, WN, RAW>(args, blockIdx.y, blockIdx.x, l, lds);
+    gemm_tile<WM, WN, RAW>(args, blockIdx.y, blockIdx.x, l);
 }
 
 // ---------------------------------------------------------------- stage 4 + 5
