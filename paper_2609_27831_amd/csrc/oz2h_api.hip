@@ -31,6 +31,8 @@ struct oz2h_plan {
     ModInfo *d_info = nullptr;
     double *d_resid = nullptr;
     ResGroup *d_rgrp = nullptr;
+    int8_t *d_rmma_w = nullptr;
+    ResRowBlock *d_rmma_rb = nullptr;
     double *d_crt = nullptr;
     uint32_t *d_pd = nullptr;
     uint32_t *d_phd = nullptr;
@@ -183,6 +185,19 @@ int launch_residues(const oz2h_plan *pl, int64_t rows, int64_t count, const uint
     if (t < 0) t = h.t;
     const int nl = (h.p + 63) / 64;
     const int64_t ps = rpad * kpad;
+    if (h.nw32 >= kResMmaMinWords) {
+        // matrix-core residues: waves of 64 entries, as many per block as fit 64 KiB
+        const size_t wl = (size_t)res_mma_wave_lds(h.rnq);
+        const int rbm = 4 * wl <= 65536 ? 4 : (2 * wl <= 65536 ? 2 : 1);
+        dim3 grid((unsigned)(kpad / 64), (unsigned)(rpad / rbm));
+        const ResMmaArgs a{limbs, exp, sign, rs, cs, rows, count, kpad, ps, erow, koff,
+                           h.p, nl, t, h.nw32, h.rnq, h.rnrb, res_mma_es(h.rnq),
+                           pl->d_rmma_w, pl->d_rmma_rb, planes};
+        if (rbm == 4) k_residues_mma<4><<<grid, 256, 4 * wl, s>>>(a);
+        else if (rbm == 2) k_residues_mma<2><<<grid, 128, 2 * wl, s>>>(a);
+        else k_residues_mma<1><<<grid, 64, wl, s>>>(a);
+        return check_launch("residues");
+    }
     int rb = h.nw32 <= 64 ? 4 : (h.nw32 <= 128 ? 2 : 1);   // word columns <= 64 KiB per block
     dim3 grid((unsigned)(kpad / 64), (unsigned)(rpad / rb));
     const size_t lds = (size_t)h.nw32 * 64 * rb * sizeof(uint32_t);
@@ -320,6 +335,11 @@ int upload_plan(oz2h_plan *pl) {
     const size_t n_rg = sizeof(ResGroup) * h.resgrp.size();
     const size_t o_rg = off;
     off = align_up(off + n_rg);
+    const size_t n_rw = h.rmma_w.size(), n_rrb = sizeof(ResRowBlock) * h.rmma_rb.size();
+    const size_t o_rw = off;
+    off = align_up(off + n_rw);
+    const size_t o_rrb = off;
+    off = align_up(off + n_rrb);
     const size_t o_crt = off;
     off = align_up(off + n_crt);
     const size_t o_pd = off;
@@ -333,12 +353,16 @@ int upload_plan(oz2h_plan *pl) {
     pl->d_info = (ModInfo *)(b + o_info);
     pl->d_resid = (double *)(b + o_res);
     pl->d_rgrp = (ResGroup *)(b + o_rg);
+    pl->d_rmma_w = (int8_t *)(b + o_rw);
+    pl->d_rmma_rb = (ResRowBlock *)(b + o_rrb);
     pl->d_crt = (double *)(b + o_crt);
     pl->d_pd = (uint32_t *)(b + o_pd);
     pl->d_phd = (uint32_t *)(b + o_phd);
     OZ2H_HIP(hipMemcpy(pl->d_info, h.info.data(), n_info, hipMemcpyHostToDevice));
     OZ2H_HIP(hipMemcpy(pl->d_resid, h.resid_tab.data(), n_res, hipMemcpyHostToDevice));
     OZ2H_HIP(hipMemcpy(pl->d_rgrp, h.resgrp.data(), n_rg, hipMemcpyHostToDevice));
+    OZ2H_HIP(hipMemcpy(pl->d_rmma_w, h.rmma_w.data(), n_rw, hipMemcpyHostToDevice));
+    OZ2H_HIP(hipMemcpy(pl->d_rmma_rb, h.rmma_rb.data(), n_rrb, hipMemcpyHostToDevice));
     OZ2H_HIP(hipMemcpy(pl->d_crt, h.crt_digits.data(), n_crt, hipMemcpyHostToDevice));
     OZ2H_HIP(hipMemcpy(pl->d_pd, h.p_digits.data(), n_pd, hipMemcpyHostToDevice));
     OZ2H_HIP(hipMemcpy(pl->d_phd, h.ph_digits.data(), n_pd, hipMemcpyHostToDevice));

@@ -102,59 +102,54 @@ __device__ __forceinline__ ModInfo load_info(OZ2H_G(ModInfo) *p) {
     return r;
 }
 
-// limb i of a significand (bits at or above p masked off; out of range -> 0),
-// branch-free: the index is clamped and the value selected, so that the
-// compiler can issue the loads of all words back to back
-__device__ __forceinline__ uint64_t glimb(OZ2H_G(uint64_t) *__restrict__ sl, int nl,
-                                          uint64_t topmask, int64_t i) {
-    const int ii = (int)min(max(i, (int64_t)0), (int64_t)(nl - 1));
-    uint64_t v = sl[ii];
-    v &= (ii == nl - 1) ? topmask : ~0ull;
-    return (i >= 0 && i < nl) ? v : 0ull;
-}
-__device__ __forceinline__ uint32_t gbits32(OZ2H_G(uint64_t) *__restrict__ sl, int nl,
-                                            uint64_t topmask, int64_t off) {
-    const int64_t q = off >> 6;
-    const int r = (int)(off & 63);
-    const uint64_t lo = glimb(sl, nl, topmask, q), hi = glimb(sl, nl, topmask, q + 1);
-    return (uint32_t)(r ? ((lo >> r) | (hi << (64 - r))) : lo);
-}
-
-// The (t+1)-bit integer a^ = RNE(mant * 2^sh) of one entry as 32-bit words into
-// an LDS column (stride st); returns the sign after rounding (0 if a^ = 0).
-// sh = t - p + exp - e <= t - p (Eq. 1).
+// The (t+1)-bit integer a^ = RNE(mant * 2^sh) of one entry as nw 32-bit words
+// col[w * st] (zero above the value); returns the sign after rounding (0 if a^ = 0).
+// sh = t - p + exp - e <= t - p (Eq. 1); mant is p bits in 64-bit limbs (bits at or
+// above p ignored).  One pass over the significand's 32-bit words: with sh = 32 q + r,
+// r in [1, 32], word j lands in output word q + j as the funnel shift
+// alignbit(m_j, m_{j-1}, 32 - r); for sh < 0 the same pass collects the round bit
+// (position -sh - 1) and the sticky bits below it, and a round-up carries through the
+// words.  A shift below -(32 nd + 2) drops every bit, the round bit included (a^ = 0).
 __device__ __forceinline__ int build_words(OZ2H_G(uint64_t) *__restrict__ sl, int s, int64_t sh,
-                                           int p, int nl, int nw32, uint32_t *col, int st) {
+                                           int p, int nw, uint32_t *col, int st) {
+    for (int w = 0; w < nw; ++w) col[w * st] = 0u;
     if (s == 0) return 0;
-    const int topbits = p - 64 * (nl - 1);
-    const uint64_t topmask = topbits >= 64 ? ~0ull : ((1ull << topbits) - 1);
-    if (sh >= 0) {
-        for (int w = 0; w < nw32; ++w) col[w * st] = gbits32(sl, nl, topmask, 32 * (int64_t)w - sh);
-        return s;
-    }
-    const int64_t rsh = -sh;   // round to nearest even on the dropped bits
-    uint32_t nz = 0;
-    for (int w = 0; w < nw32; ++w) {
-        const uint32_t v = gbits32(sl, nl, topmask, 32 * (int64_t)w + rsh);
-        col[w * st] = v;
-        nz |= v;
-    }
-    const int64_t rpos = rsh - 1;   // round bit position, sticky = any bit below it
-    const int rbit = (int)((glimb(sl, nl, topmask, rpos >> 6) >> (rpos & 63)) & 1u);
-    if (rbit) {
-        bool sticky = false;
-        const int64_t full = rpos >> 6;
-        for (int64_t i = 0; i < full && i < nl; ++i) sticky |= glimb(sl, nl, topmask, i) != 0;
-        const int rr = (int)(rpos & 63);
-        if (rr && full < nl) sticky |= (glimb(sl, nl, topmask, full) & ((1ull << rr) - 1)) != 0;
-        if (sticky || (col[0] & 1u)) {
-            for (int w = 0; w < nw32; ++w) {
-                const uint32_t v = col[w * st] + 1u;
-                col[w * st] = v;
-                if (v) break;
-            }
-            nz = 1;
+    OZ2H_G(uint32_t) *m = (OZ2H_G(uint32_t) *)sl;
+    const int nd = (p + 31) >> 5;
+    const uint32_t topm = (p & 31) ? (1u << (p & 31)) - 1u : ~0u;
+    const int shc = (int)max(sh, (int64_t)-(32 * nd + 2));
+    const int q = (shc - 1) >> 5;        // floor((sh - 1) / 32)
+    const int sa = 32 * (q + 1) - shc;   // 32 - r, in [0, 31]
+    const int rp = -shc - 1;             // round bit position (sh < 0)
+    uint32_t prev = 0u, nz = 0u;
+    bool rbit = false, sticky = false;
+    for (int j = 0; j <= nd; ++j) {
+        uint32_t cur = 0u;
+        if (j < nd) cur = j == nd - 1 ? (m[j] & topm) : m[j];
+        const int w = q + j;
+        if (w >= 0 && w < nw) {
+            const uint32_t v = __builtin_amdgcn_alignbit(cur, prev, sa);
+            col[w * st] = v;
+            nz |= v;
         }
+        if (shc < 0 && j < nd) {
+            const int b = rp - 32 * j;   // the round bit's position within word j
+            if (b >= 32) {
+                sticky |= cur != 0u;
+            } else if (b >= 0) {
+                rbit = (cur >> b) & 1u;
+                sticky |= (cur & ((1u << b) - 1u)) != 0u;
+            }
+        }
+        prev = cur;
+    }
+    if (rbit && (sticky || (col[0] & 1u))) {   // round half to even: add one
+        for (int w = 0; w < nw; ++w) {
+            const uint32_t v = col[w * st] + 1u;
+            col[w * st] = v;
+            if (v) break;
+        }
+        nz = 1u;
     }
     return nz ? s : 0;
 }
@@ -214,9 +209,7 @@ __device__ __forceinline__ void residue_block_r(
         s = gsigns[idx];
         sh = (int64_t)t - p + gexps[idx] + (koff ? gkoff[k] : 0) - gerow[r];
     }
-    s = build_words((OZ2H_G(uint64_t) *)limbs + idx * nl, s, sh, p, nl, nw32, col, BD);
-    if (s == 0)
-        for (int w = 0; w < nw32; ++w) col[w * BD] = 0;
+    s = build_words((OZ2H_G(uint64_t) *)limbs + idx * nl, s, sh, p, nw32, col, BD);
 
     // the tables live in global memory: say so, so that pointers read from a
     // descriptor (the grouped kernels) still qualify for scalar loads
@@ -270,6 +263,157 @@ template <int RB, int KG>
 __global__ __launch_bounds__(64 * RB) void k_residues(ResArgs a) {
     extern __shared__ uint32_t words[];
     residue_block<RB, KG>(a, blockIdx.x, blockIdx.y, words);
+}
+
+// Residues of a^ on the matrix cores (stage 2).  For every modulus the residue of an
+// entry is a dot product of its magnitude's bytes with the weights 256^j mod m, so a
+// wave computes a (weight rows) x (64 entries) int8 product with
+// v_mfma_i32_32x32x32_i8 and then reduces each exact int32 sum x to the centred
+// x - rint(x/m) m (exact in fp64, |x| < 2^31): no per-modulus pass over the words.
+// The weight rows, the correction bytes that carry the sign, and the row layout are
+// described with build_residue_mma_tables.  One wave per (row r, 64 consecutive k):
+//   phase 0: lane k writes its entry's bytes to LDS (entry-major, stride es words),
+//            complemented if negative, already offset by -128 (xor 0x80);
+//   phase 1: per block of 32 weight rows, rnq k-steps of two MFMAs (entries 0-31 and
+//            32-63) with A = weight fragments (global), B = entry bytes (LDS);
+//   phase 2: the 32 x 64 sums go through an LDS scratch (entry-major, 144-byte rows) so
+//            that lane k reduces its own entry for every modulus of the block with
+//            wave-uniform modulus data, and stores 64 contiguous bytes per plane.
+// Bank layout: es = 4 (2 i + 1) words and the 144-byte scratch rows put the 16 lanes a
+// 16-byte LDS access serves per cycle on 16 different bank groups.
+struct ResMmaArgs {
+    const uint64_t *limbs;
+    const int32_t *exps;
+    const int8_t *signs;
+    int64_t rs, cs, rows, count, kpad, plane_stride;
+    const int32_t *erow;
+    const int32_t *koff;
+    int p, nl, t, nw32, nq, nrb, es;
+    const int8_t *wfrag;
+    const ResRowBlock *rblk;
+    int8_t *planes;
+};
+
+constexpr int kResScratchRow = 144;   // bytes per entry in the sums scratch (32 rows + 16)
+
+__host__ __device__ constexpr int res_mma_es(int nq) { return 8 * nq + 4; }
+__host__ __device__ constexpr int res_mma_wave_lds(int nq) {
+    return 64 * res_mma_es(nq) * 4 + 64 * kResScratchRow;
+}
+
+// lanes of one wave hand data over through LDS: keep the compiler from moving LDS
+// accesses across this point (LDS itself serves a wave's instructions in order)
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// a wave-uniform plane pointer held in scalar registers, so that a store through it with a
+// 32-bit lane offset takes the scalar-base form
+__device__ __forceinline__ g_i8 *uniform_ptr(g_i8 *p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (g_i8 *)(((uint64_t)hi << 32) | lo);
+}
+
+template <int RB>
+__device__ __forceinline__ void residue_block_mma_r(
+    const uint64_t *__restrict__ limbs, const int32_t *__restrict__ exps,
+    const int8_t *__restrict__ signs, const int32_t *__restrict__ erow,
+    const int32_t *__restrict__ koff, const int8_t *__restrict__ wfrag,
+    const ResRowBlock *__restrict__ rblk, int8_t *__restrict__ planes, int64_t rs, int64_t cs,
+    int64_t rows, int64_t count, int64_t kpad, int64_t plane_stride, int p, int nl, int t,
+    int nw32, int nq, int nrb, int64_t bx, int64_t by, uint32_t *smem) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int es = res_mma_es(nq);
+    uint32_t *ent = smem + (size_t)wv * (res_mma_wave_lds(nq) / 4);
+    uint8_t *scr = (uint8_t *)(ent + 64 * es);
+    const int64_t k = bx * 64 + lane;
+    const int64_t r = by * RB + wv;
+
+    // phase 0: this lane's entry, bytes offset by -128
+    OZ2H_G(int8_t) *gsigns = (OZ2H_G(int8_t) *)signs;
+    OZ2H_G(int32_t) *gexps = (OZ2H_G(int32_t) *)exps;
+    OZ2H_G(int32_t) *gerow = (OZ2H_G(int32_t) *)erow;
+    OZ2H_G(int32_t) *gkoff = (OZ2H_G(int32_t) *)koff;
+    int s = 0;
+    int64_t sh = 0, idx = 0;
+    if (r < rows && k < count) {
+        idx = r * rs + k * cs;
+        s = gsigns[idx];
+        sh = (int64_t)t - p + gexps[idx] + (koff ? gkoff[k] : 0) - gerow[r];
+    }
+    uint32_t *ew = ent + lane * es;
+    s = build_words((OZ2H_G(uint64_t) *)limbs + idx * nl, s, sh, p, nw32, ew, 1);
+    const uint32_t cmask = s < 0 ? 0xFFFFFFFFu : 0u;
+    for (int w = 0; w < nw32; ++w) ew[w] = (s == 0 ? 0u : ew[w] ^ cmask) ^ 0x80808080u;
+    ew[nw32] = (s < 0 ? 0x100u : 0u) ^ 0x80808080u;   // correction bytes nb, nb + 1
+    for (int w = nw32 + 1; w < 8 * nq; ++w) ew[w] = 0x80808080u;
+
+    typedef const __attribute__((address_space(1))) v4i gv4i;
+    gv4i *wf = (gv4i *)wfrag;
+    // read-only for the whole launch: the constant address space keeps these wave-uniform
+    // reads on the scalar unit across the LDS hand-over fences
+    typedef const __attribute__((address_space(4))) ResRowBlock crb_t;
+    crb_t *grb = (crb_t *)rblk;
+    const int h = lane >> 5, c = lane & 31;
+    const v4i *b0p = (const v4i *)(ent + c * es + 4 * h);          // entries 0-31
+    const v4i *b1p = (const v4i *)(ent + (32 + c) * es + 4 * h);   // entries 32-63
+    const uint32_t loff = (uint32_t)(r * kpad + k);
+    const uint32_t *xrow = (const uint32_t *)(scr + lane * kResScratchRow);
+    for (int rb = 0; rb < nrb; ++rb) {
+        wave_lds_sync();   // entry bytes written; the previous block's sums read
+        v16i acc0 = v16i{}, acc1 = v16i{};
+        gv4i *wq = wf + (size_t)rb * nq * 64 + lane;
+        for (int q = 0; q < nq; ++q) {
+            const v4i a = wq[q * 64];
+            acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b0p[2 * q], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b1p[2 * q], acc1, 0, 0, 0);
+        }
+        // sums element e: row 8 (e / 4) + 4 h + e % 4, entry c (acc0) or 32 + c (acc1)
+#pragma unroll
+        for (int a4 = 0; a4 < 4; ++a4) {
+            const int ro = (8 * a4 + 4 * h) * 4;
+            *(v4i *)(scr + c * kResScratchRow + ro) =
+                v4i{acc0[4 * a4], acc0[4 * a4 + 1], acc0[4 * a4 + 2], acc0[4 * a4 + 3]};
+            *(v4i *)(scr + (32 + c) * kResScratchRow + ro) =
+                v4i{acc1[4 * a4], acc1[4 * a4 + 1], acc1[4 * a4 + 2], acc1[4 * a4 + 3]};
+        }
+        wave_lds_sync();   // sums written
+        crb_t *B = grb + rb;
+        const int n1 = (int)B->n1, p0 = (int)B->p0, n2 = (int)B->n2;
+#pragma unroll 4
+        for (int i = 0; i < n1; ++i) {
+            const double x = (double)(int32_t)xrow[i];
+            const int ri = (int)fma(-rint(x * B->inv_m[i]), B->md[i], x);
+            g_i8 *pb = uniform_ptr((g_i8 *)planes + (int64_t)B->g0[i] * plane_stride);
+            pb[loff] = (int8_t)ri;
+        }
+#pragma unroll 4
+        for (int j = 0; j < n2; ++j) {
+            const int i = p0 + 2 * j;
+            const uint2 xv = *(const uint2 *)(xrow + i);
+            const double x = (double)((int32_t)xv.x + 128 * (int32_t)xv.y);
+            const int ri = (int)fma(-rint(x * B->inv_m[i]), B->md[i], x);
+            const int r0 = ((ri + 64) & 127) - 64;   // balanced base-128 split
+            const int r1 = (ri - r0) >> 7;
+            g_i8 *pb = uniform_ptr((g_i8 *)planes + (int64_t)B->g0[i] * plane_stride);
+            g_i8 *pb1 = uniform_ptr(pb + plane_stride), *pb2 = uniform_ptr(pb + 2 * plane_stride);
+            pb[loff] = (int8_t)r0;
+            pb1[loff] = (int8_t)r1;
+            pb2[loff] = (int8_t)(r0 + r1);
+        }
+    }
+}
+
+template <int RB>
+__global__ __launch_bounds__(64 * RB) void k_residues_mma(ResMmaArgs a) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t smem_res[];
+    residue_block_mma_r<RB>(a.limbs, a.exps, a.signs, a.erow, a.koff, a.wfrag, a.rblk, a.planes,
+                            a.rs, a.cs, a.rows, a.count, a.kpad, a.plane_stride, a.p, a.nl, a.t,
+                            a.nw32, a.nq, a.nrb, blockIdx.x, blockIdx.y, smem_res);
 }
 
 // ---------------------------------------------------------------- stage 3

@@ -156,6 +156,73 @@ int select_moduli_bits(double need, std::vector<uint32_t> &mods, double &log2P, 
     return 0;
 }
 
+// Tables of the MFMA residue kernel.  The residue of a magnitude |a| = sum_j b_j 256^j
+// (bytes b_j, j < nb) is sum_j b_j w_j mod m with w_j the centred 256^j mod m: an int8
+// product of the byte string and a weight row (two rows of balanced base-128 halves for
+// a two-limb modulus).  The kernel feeds the bytes as b_j - 128 (int8 range) and a
+// negative entry as its complement 255 - b_j; two correction bytes at nb (always 0) and
+// nb + 1 (1 for a negative entry) with weights C1 = 254 S and C2 = -255 S, S = sum_j w_j,
+// make the product congruent to the signed entry:
+//   positive: sum (b_j - 128) w_j - 128 C1 - 128 C2 = |a| + (-128 - 128*254 + 128*255) S = |a|
+//   negative: sum (127 - b_j) w_j - 128 C1 - 127 C2 = -|a| + (127 - 128*254 + 127*255) S = -|a|
+// (mod m).  Every weight row has |w| <= 127, so |product| <= 128 * 127 * (nb + 2) < 2^31.
+void build_residue_mma_tables(PlanHost &h, const std::vector<uint32_t> &mods) {
+    h.rnb = 4 * h.nw32;
+    const int nbk = (h.rnb + 2 + 31) / 32 * 32;
+    h.rnq = nbk / 32;
+    const int r0 = h.L1 + (h.L1 & 1);   // two-limb pairs start on an even row
+    const int ml = r0 + 2 * (h.L - h.L1);
+    h.rnrb = (ml + 31) / 32;
+    std::vector<int8_t> W((size_t)h.rnrb * 32 * nbk, 0);
+    for (int l = 0; l < h.L; ++l) {
+        const int64_t m = mods[l];
+        auto centred = [m](int64_t x) { return x > (m - 1) / 2 ? x - m : x; };
+        std::vector<int64_t> v(nbk, 0);
+        int64_t x = 1 % m, S = 0;
+        for (int j = 0; j < h.rnb; ++j) {
+            v[j] = centred(x);
+            S = (S + x) % m;
+            x = x * 256 % m;
+        }
+        v[h.rnb] = centred(254 * S % m);
+        v[h.rnb + 1] = centred((m - 255 * S % m) % m);
+        if (l < h.L1) {
+            for (int j = 0; j < nbk; ++j) W[(size_t)l * nbk + j] = (int8_t)v[j];
+        } else {
+            const size_t R = (size_t)(r0 + 2 * (l - h.L1));
+            for (int j = 0; j < nbk; ++j) {
+                const int64_t lo = ((v[j] + 64) & 127) - 64;
+                W[R * nbk + j] = (int8_t)lo;
+                W[(R + 1) * nbk + j] = (int8_t)((v[j] - lo) / 128);
+            }
+        }
+    }
+    // MFMA A fragments: lane l of k-step q holds row l % 32, bytes 32 q + 16 (l / 32) ..
+    h.rmma_w.assign((size_t)h.rnrb * h.rnq * 64 * 16, 0);
+    for (int rb = 0; rb < h.rnrb; ++rb)
+        for (int q = 0; q < h.rnq; ++q)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int e = 0; e < 16; ++e)
+                    h.rmma_w[(((size_t)rb * h.rnq + q) * 64 + lane) * 16 + e] =
+                        W[(size_t)(rb * 32 + lane % 32) * nbk + 32 * q + 16 * (lane / 32) + e];
+    h.rmma_rb.assign(h.rnrb, ResRowBlock{});
+    for (int rb = 0; rb < h.rnrb; ++rb) {
+        ResRowBlock &B = h.rmma_rb[rb];
+        const int lo = rb * 32, hi = lo + 32;
+        B.n1 = (uint32_t)std::max(0, std::min(32, h.L1 - lo));
+        const int pa = std::max(r0, lo), pb = std::min(ml, hi);
+        B.p0 = (uint32_t)(pa - lo);
+        B.n2 = pb > pa ? (uint32_t)((pb - pa) / 2) : 0u;
+        for (int l = 0; l < h.L; ++l) {
+            const int R = l < h.L1 ? l : r0 + 2 * (l - h.L1);
+            if (R < lo || R >= hi) continue;
+            B.inv_m[R - lo] = h.info[l].inv_m;
+            B.md[R - lo] = (double)h.info[l].m;
+            B.g0[R - lo] = h.info[l].g0;
+        }
+    }
+}
+
 int build_plan(int p, int t, int64_t K, const std::vector<uint32_t> &mods_in, PlanHost &h,
                std::string &err, int wmax, bool allow_wide) {
     if (mods_in.empty() || (int)mods_in.size() > kMaxModuli) {
@@ -302,6 +369,7 @@ int build_plan(int p, int t, int64_t K, const std::vector<uint32_t> &mods_in, Pl
             x = ((x << 32) % m);
         }
     }
+    build_residue_mma_tables(h, mods);
     return 0;
 }
 

@@ -11,6 +11,8 @@ namespace oz2h {
 constexpr int kModGroup = 8;          // moduli per group in the residue kernel (small L)
 constexpr int kModGroupWide = 16;     // ... and for wide moduli sets (L >= kWideL)
 constexpr int kWideL = 96;
+constexpr int kResMmaMinWords = 30;   // integers of >= this many 32-bit words (p >~ 900) take
+                                      // the matrix-core residue kernel, narrower ones the fp64 one
 constexpr int kMaxModuli = 512;       // fp64-exact CRT digit sums need L * 2^44 < 2^53
 constexpr int kMaxWords = 256;        // fp64-exact residue sums need nw32 * 2^45 < 2^53
 constexpr int64_t kMaxK = 133000;     // K * 127^2 < 2^31, the cap the paper's implementation uses
@@ -40,6 +42,19 @@ struct ResGroup {
 };
 static_assert(sizeof(ResGroup) == 384, "ResGroup layout");
 
+// One block of 32 weight rows of the MFMA residue kernel as it reads it (wave-uniform
+// scalar loads, 768 bytes).  Rows [0, n1) are one-limb moduli; rows p0 + 2 j and
+// p0 + 2 j + 1 (j < n2) hold the low and high balanced base-128 halves of a two-limb
+// modulus's weights.  A modulus's data sit at its first row.
+struct ResRowBlock {
+    double inv_m[32];   // fl(1/m)
+    double md[32];      // m as a double
+    uint32_t g0[32];    // first INT8 plane of the modulus
+    uint32_t n1, p0, n2;
+    uint32_t pad[29];
+};
+static_assert(sizeof(ResRowBlock) == 768, "ResRowBlock layout");
+
 struct PlanHost {
     int p = 0, t = 0;
     int tile = 0;          // oz2h_tile hint of the residue GEMMs (0 = automatic)
@@ -62,6 +77,11 @@ struct PlanHost {
     std::vector<ModInfo> info;       // L
     std::vector<double> resid_tab;   // [lgroups][nw32][kg]: centred 2^(32w) mod m
     std::vector<ResGroup> resgrp;    // [lgroups]
+    int rnb = 0;           // MFMA residues: magnitude bytes (4 nw32), then two correction bytes
+    int rnq = 0;           // ... 32-byte k-steps covering rnb + 2 bytes
+    int rnrb = 0;          // ... blocks of 32 weight rows
+    std::vector<int8_t> rmma_w;          // [rnrb][rnq][64 lanes][16]: MFMA A fragments
+    std::vector<ResRowBlock> rmma_rb;    // [rnrb]
     std::vector<double> crt_digits;  // [L][crt_ndpad]: balanced base-2^32 digits of P/m
     std::vector<uint32_t> p_digits;  // [nd32] digits of P
     std::vector<uint32_t> ph_digits; // [nd32] digits of floor(P/2)

@@ -72,7 +72,7 @@ def rng_idx(r, c, frac, seed=0):
 
 @pytest.mark.parametrize("p,lo,hi,side", [(128, -4, 4, "A"), (256, -32, 32, "B"),
                                           (2048, -16, 16, "A"), (53, -300, 300, "B"),
-                                          (113, -64, 64, "A")])
+                                          (113, -64, 64, "A"), (1024, -300, 300, "B")])
 def test_residue_planes(oz, c_oracle, p, lo, hi, side):
     """Stage 2 vs Python-int centred residues of the oracle's integers a^."""
     import torch
