@@ -236,8 +236,9 @@ int launch_resgemm(const oz2h_plan *pl, GemmCfg cfg, int64_t mpad, int64_t npad,
 
 // CRT launch shape.  Up to 32 digits per entry the digit columns live in LDS
 // (two entries per thread, block of 256, columns <= 48 KiB); above that, in a
-// global-memory region (GDIG) so that LDS holds only the constant slices and
-// blocks stay 256 threads wide whatever nd32 is.
+// global-memory region (GDIG), so that blocks stay 256 threads wide whatever nd32
+// is and LDS holds only slices of the digit constants (read with scalar loads when
+// the columns are in LDS).
 struct CrtCfg {
     int ept, bd, LB;
     size_t lds;
@@ -256,11 +257,10 @@ CrtCfg crt_config(const PlanHost &h, int64_t M, int64_t N, bool allow_gdig) {
         while (c.bd > 64 && (size_t)h.nd32 * c.bd * c.ept * sizeof(uint32_t) > 49152) c.bd /= 2;
         cols = (((size_t)h.nd32 * c.bd * c.ept + 3) & ~(size_t)3) * sizeof(uint32_t);
     }
-    // a slice of LB moduli x crt_dc digit constants and LB reciprocals fills LDS up to
-    // 64 KiB (LDS columns) or 32 KiB (global columns, leaving room for more blocks)
-    const size_t cap = c.gdig ? 32768 : 65536;
-    c.LB = std::max(1, std::min(h.L, (int)((cap - cols) / (sizeof(double) * (h.crt_dc + 1)))));
-    c.lds = cols + (size_t)c.LB * (h.crt_dc + 1) * sizeof(double);
+    // LDS columns: scalar constants, one pass over the moduli per digit chunk; global
+    // columns: a slice of LB moduli x crt_dc constants and LB reciprocals in 32 KiB
+    c.LB = c.gdig ? std::max(1, std::min(h.L, (int)(32768 / (sizeof(double) * (h.crt_dc + 1))))) : h.L;
+    c.lds = c.gdig ? (size_t)c.LB * (h.crt_dc + 1) * sizeof(double) : cols;
     const int64_t per = (int64_t)c.bd * c.ept;
     c.nb = (unsigned)((std::max<int64_t>(M * N, 1) + per - 1) / per);
     c.gstride = (int64_t)c.nb * per;
@@ -1298,9 +1298,8 @@ int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2
             while (c.bd > 64 && (size_t)maxnd * c.bd * c.ept * 4 > 49152) c.bd /= 2;
             cols = (((size_t)maxnd * c.bd * c.ept + 3) & ~(size_t)3) * 4;
         }
-        const size_t cap = c.gdig ? 32768 : 65536;
-        c.LB = std::max(1, std::min(maxL, (int)((cap - cols) / (sizeof(double) * (c.dc + 1)))));
-        c.lds = cols + (size_t)c.LB * (c.dc + 1) * sizeof(double);
+        c.LB = c.gdig ? std::max(1, std::min(maxL, (int)(32768 / (sizeof(double) * (c.dc + 1))))) : maxL;
+        c.lds = c.gdig ? (size_t)c.LB * (c.dc + 1) * sizeof(double) : cols;
         std::vector<Seg> segs;
         for (int b : kv.second) {
             const int64_t per = (int64_t)c.bd * c.ept;

@@ -732,8 +732,8 @@ struct MagView {
 // nearest-even, to p bits with the scale 2^(e_i + f_j - 2t).
 // The planes hold v_l = u_l (P/m_l)^-1 mod m_l as centred int16 (the residue
 // GEMM applies the weight); WEIGHT = true takes plain residues u_l instead.
-// The digit constants of a block of LB moduli (and their 1/m_l) are staged in
-// LDS and read with wave-uniform addresses (broadcast), two per ds_read_b128.
+// The digit constants (and 1/m_l) are wave-uniform: scalar loads (SGPR operands of the
+// FMAs) with LDS digit columns, LDS-staged slices of LB moduli with global ones.
 struct CrtArgs {
     const int16_t *V;
     int64_t v_ps, ldv, M, N;
@@ -754,9 +754,9 @@ struct CrtArgs {
     int64_t gstride;   // gdig[k * gstride + e] (gstride >= all entries the grid covers)
 };
 
-// LDS of a CRT block: bd * EPT digit columns of nd32 words, then LB x (DC + 1) doubles
-// GDIG = false: each entry's digit column sits in LDS (stride blockDim * EPT words);
-// GDIG = true: in global memory (large nd32), and LDS holds only the constant slices.
+// LDS of a CRT block: bd * EPT digit columns of nd32 words (GDIG = false), or the
+// LB x (DC + 1) doubles of a constant slice (GDIG = true: the digit columns of large
+// nd32 sit in global memory).
 template <int DC, int EPT, bool ROUND, bool WEIGHT, bool GDIG = false>
 __device__ __forceinline__ void crt_block(const CrtArgs &a, int64_t blk, uint32_t *sdig) {
     const int tid = threadIdx.x, bd = blockDim.x, st = bd * EPT;
@@ -767,9 +767,16 @@ __device__ __forceinline__ void crt_block(const CrtArgs &a, int64_t blk, uint32_
     OZ2H_G(uint32_t) *Pd = (OZ2H_G(uint32_t) *)a.Pd;
     const uint32_t *__restrict__ Phd = a.Phd;
     OZ2H_G(ModInfo) *mi = (OZ2H_G(ModInfo) *)a.mi;
-    double *stab = GDIG ? (double *)sdig                                            // LB x DC digits
-                        : (double *)(sdig + (((size_t)nd32 * st + 3) & ~(size_t)3));
-    double *sinv = stab + (size_t)LB * DC;                                      // LB x 1/m
+    // digit constants and 1/m: read-only for the launch and wave-uniform.  With LDS digit
+    // columns (two entries per thread) the constant address space puts them on the scalar
+    // unit (SGPR operands of the FMAs); with global columns (GDIG) a slice of LB moduli is
+    // staged in LDS and read as broadcasts, two constants per ds_read_b128.
+    typedef const __attribute__((address_space(4))) double cdouble;
+    typedef const __attribute__((address_space(4))) ModInfo cmodinfo;
+    cdouble *cdig = (cdouble *)a.dig;
+    cmodinfo *cmi = (cmodinfo *)a.mi;
+    double *stab = (double *)sdig;               // GDIG: LB x DC digits
+    double *sinv = stab + (size_t)LB * DC;       // GDIG: LB x 1/m
     const int64_t MN = a.M * N;
     int64_t idx[EPT];
     OZ2H_G(int16_t) *vp[EPT];
@@ -800,16 +807,18 @@ __device__ __forceinline__ void crt_block(const CrtArgs &a, int64_t blk, uint32_
 #pragma unroll
             for (int d = 0; d < DC; ++d) acc[q][d] = 0.0;
         }
-        OZ2H_G(double) *dc = (OZ2H_G(double) *)a.dig + c * DC;
         for (int l0 = 0; l0 < L; l0 += LB) {
             const int nlb = min(LB, L - l0);
-            __syncthreads();   // the previous slice has been consumed by every thread
-            for (int e = tid; e < nlb * DC; e += bd) {
-                const int ll = e / DC, d = e - ll * DC;
-                stab[e] = dc[(size_t)(l0 + ll) * ndpad + d];
+            if constexpr (GDIG) {
+                OZ2H_G(double) *dc = (OZ2H_G(double) *)a.dig + c * DC;
+                __syncthreads();   // the previous slice has been consumed by every thread
+                for (int e = tid; e < nlb * DC; e += bd) {
+                    const int ll = e / DC, d = e - ll * DC;
+                    stab[e] = dc[(size_t)(l0 + ll) * ndpad + d];
+                }
+                for (int e = tid; e < nlb; e += bd) sinv[e] = mi[l0 + e].inv_m;
+                __syncthreads();
             }
-            for (int e = tid; e < nlb; e += bd) sinv[e] = mi[l0 + e].inv_m;
-            __syncthreads();
             // v_l of the next PF moduli are loaded ahead (unconditional, clamped at the end)
             constexpr int PF = 4;
             int ring[PF][EPT];
@@ -823,7 +832,7 @@ __device__ __forceinline__ void crt_block(const CrtArgs &a, int64_t blk, uint32_
                 const int ll = lb + f;
                 if (ll >= nlb) break;
                 const int l = l0 + ll;
-                const double inv_m = sinv[ll];
+                const double inv_m = GDIG ? sinv[ll] : cmi[l].inv_m;
                 int cur[EPT];
 #pragma unroll
                 for (int q = 0; q < EPT; ++q) {
@@ -842,14 +851,24 @@ __device__ __forceinline__ void crt_block(const CrtArgs &a, int64_t blk, uint32_
                     }
                     if (c == 0) asum[q] = fma(vd[q], inv_m, asum[q]);
                 }
-                const double *dl = stab + (size_t)ll * DC;
+                if constexpr (GDIG) {
+                    const double *dl = stab + (size_t)ll * DC;
 #pragma unroll
-                for (int d = 0; d < DC; d += 2) {
-                    const double2 w = *(const double2 *)(dl + d);
+                    for (int d = 0; d < DC; d += 2) {
+                        const double2 w = *(const double2 *)(dl + d);
 #pragma unroll
-                    for (int q = 0; q < EPT; ++q) {
-                        acc[q][d] = fma(vd[q], w.x, acc[q][d]);
-                        acc[q][d + 1] = fma(vd[q], w.y, acc[q][d + 1]);
+                        for (int q = 0; q < EPT; ++q) {
+                            acc[q][d] = fma(vd[q], w.x, acc[q][d]);
+                            acc[q][d + 1] = fma(vd[q], w.y, acc[q][d + 1]);
+                        }
+                    }
+                } else {
+                    cdouble *dl = cdig + (size_t)l * ndpad + c * DC;
+#pragma unroll
+                    for (int d = 0; d < DC; ++d) {
+                        const double w = dl[d];
+#pragma unroll
+                        for (int q = 0; q < EPT; ++q) acc[q][d] = fma(vd[q], w, acc[q][d]);
                     }
                 }
             }
