@@ -193,9 +193,19 @@ int launch_residues(const oz2h_plan *pl, int64_t rows, int64_t count, const uint
         const ResMmaArgs a{limbs, exp, sign, rs, cs, rows, count, kpad, ps, erow, koff,
                            h.p, nl, t, h.nw32, h.rnq, h.rnrb, res_mma_es(h.rnq),
                            pl->d_rmma_w, pl->d_rmma_rb, planes};
-        if (rbm == 4) k_residues_mma<4><<<grid, 256, 4 * wl, s>>>(a);
-        else if (rbm == 2) k_residues_mma<2><<<grid, 128, 2 * wl, s>>>(a);
-        else k_residues_mma<1><<<grid, 64, wl, s>>>(a);
+#define OZ2H_RES_MMA(NQ)                                                             \
+    do {                                                                             \
+        if (rbm == 4) k_residues_mma<4, NQ><<<grid, 256, 4 * wl, s>>>(a);            \
+        else if (rbm == 2) k_residues_mma<2, NQ><<<grid, 128, 2 * wl, s>>>(a);       \
+        else k_residues_mma<1, NQ><<<grid, 64, wl, s>>>(a);                          \
+    } while (0)
+        if (h.rnq <= 2) OZ2H_RES_MMA(2);
+        else if (h.rnq <= 4) OZ2H_RES_MMA(4);
+        else if (h.rnq <= 8) OZ2H_RES_MMA(8);
+        else if (h.rnq <= 12) OZ2H_RES_MMA(12);
+        else if (h.rnq <= kResMmaMaxQ) OZ2H_RES_MMA(kResMmaMaxQ);
+        else return fail(OZ2H_ERANGE, "residues: integers of %d words exceed the kernel's k-steps", h.nw32);
+#undef OZ2H_RES_MMA
         return check_launch("residues");
     }
     int rb = h.nw32 <= 64 ? 4 : (h.nw32 <= 128 ? 2 : 1);   // word columns <= 64 KiB per block

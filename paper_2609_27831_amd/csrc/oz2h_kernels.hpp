@@ -275,7 +275,8 @@ __global__ __launch_bounds__(64 * RB) void k_residues(ResArgs a) {
 //   phase 0: lane k writes its entry's bytes to LDS (entry-major, stride es words),
 //            complemented if negative, already offset by -128 (xor 0x80);
 //   phase 1: per block of 32 weight rows, rnq k-steps of two MFMAs (entries 0-31 and
-//            32-63) with A = weight fragments (global), B = entry bytes (LDS);
+//            32-63) with A = weight fragments (global), B = entry bytes (read from LDS
+//            into registers once);
 //   phase 2: the 32 x 64 sums go through an LDS scratch (entry-major, 144-byte rows) so
 //            that lane k reduces its own entry for every modulus of the block with
 //            wave-uniform modulus data, and stores 64 contiguous bytes per plane.
@@ -295,10 +296,13 @@ struct ResMmaArgs {
 };
 
 constexpr int kResScratchRow = 144;   // bytes per entry in the sums scratch (32 rows + 16)
+constexpr int kResMmaMaxQ = 16;       // k-steps of the widest integer (t < 3400 bits: 14)
+constexpr int kResMmaPfQ = 8;         // up to this many k-steps the next weights are prefetched
 
 __host__ __device__ constexpr int res_mma_es(int nq) { return 8 * nq + 4; }
+// LDS per wave: the entry bytes, later reused by the sums scratch
 __host__ __device__ constexpr int res_mma_wave_lds(int nq) {
-    return 64 * res_mma_es(nq) * 4 + 64 * kResScratchRow;
+    return 64 * res_mma_es(nq) * 4 > 64 * kResScratchRow ? 64 * res_mma_es(nq) * 4 : 64 * kResScratchRow;
 }
 
 // lanes of one wave hand data over through LDS: keep the compiler from moving LDS
@@ -318,7 +322,10 @@ __device__ __forceinline__ g_i8 *uniform_ptr(g_i8 *p) {
     return (g_i8 *)(((uint64_t)hi << 32) | lo);
 }
 
-template <int RB>
+// At most NQ k-steps: entry and weight fragments live in registers (up to kResMmaPfQ
+// k-steps the weights of the next block of rows are prefetched while one block is
+// reduced), and the sums scratch reuses the entry bytes' LDS.
+template <int RB, int NQ>
 __device__ __forceinline__ void residue_block_mma_r(
     const uint64_t *__restrict__ limbs, const int32_t *__restrict__ exps,
     const int8_t *__restrict__ signs, const int32_t *__restrict__ erow,
@@ -326,12 +333,21 @@ __device__ __forceinline__ void residue_block_mma_r(
     const ResRowBlock *__restrict__ rblk, int8_t *__restrict__ planes, int64_t rs, int64_t cs,
     int64_t rows, int64_t count, int64_t kpad, int64_t plane_stride, int p, int nl, int t,
     int nw32, int nq, int nrb, int64_t bx, int64_t by, uint32_t *smem) {
+    static_assert(NQ >= 1 && NQ <= kResMmaMaxQ, "k-steps");
+    constexpr bool PF = NQ <= kResMmaPfQ;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int es = res_mma_es(nq);
     uint32_t *ent = smem + (size_t)wv * (res_mma_wave_lds(nq) / 4);
-    uint8_t *scr = (uint8_t *)(ent + 64 * es);
+    uint8_t *scr = (uint8_t *)ent;
     const int64_t k = bx * 64 + lane;
     const int64_t r = by * RB + wv;
+
+    typedef const __attribute__((address_space(1))) v4i gv4i;
+    gv4i *wf = (gv4i *)wfrag + lane;
+    v4i wa[NQ], wn[PF ? NQ : 1];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)   // the first block's weights load while the entry is built
+        if (q < nq) wa[q] = wf[q * 64];
 
     // phase 0: this lane's entry, bytes offset by -128
     OZ2H_G(int8_t) *gsigns = (OZ2H_G(int8_t) *)signs;
@@ -352,8 +368,6 @@ __device__ __forceinline__ void residue_block_mma_r(
     ew[nw32] = (s < 0 ? 0x100u : 0u) ^ 0x80808080u;   // correction bytes nb, nb + 1
     for (int w = nw32 + 1; w < 8 * nq; ++w) ew[w] = 0x80808080u;
 
-    typedef const __attribute__((address_space(1))) v4i gv4i;
-    gv4i *wf = (gv4i *)wfrag;
     // read-only for the whole launch: the constant address space keeps these wave-uniform
     // reads on the scalar unit across the LDS hand-over fences
     typedef const __attribute__((address_space(4))) ResRowBlock crb_t;
@@ -361,17 +375,36 @@ __device__ __forceinline__ void residue_block_mma_r(
     const int h = lane >> 5, c = lane & 31;
     const v4i *b0p = (const v4i *)(ent + c * es + 4 * h);          // entries 0-31
     const v4i *b1p = (const v4i *)(ent + (32 + c) * es + 4 * h);   // entries 32-63
+    v4i bf0[NQ], bf1[NQ];
+    wave_lds_sync();   // entry bytes written
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+        if (q < nq) {
+            bf0[q] = b0p[2 * q];
+            bf1[q] = b1p[2 * q];
+        }
     const uint32_t loff = (uint32_t)(r * kpad + k);
     const uint32_t *xrow = (const uint32_t *)(scr + lane * kResScratchRow);
     for (int rb = 0; rb < nrb; ++rb) {
-        wave_lds_sync();   // entry bytes written; the previous block's sums read
+        wave_lds_sync();   // entry bytes read; the previous block's sums read
         v16i acc0 = v16i{}, acc1 = v16i{};
-        gv4i *wq = wf + (size_t)rb * nq * 64 + lane;
-        for (int q = 0; q < nq; ++q) {
-            const v4i a = wq[q * 64];
-            acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b0p[2 * q], acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b1p[2 * q], acc1, 0, 0, 0);
+        if constexpr (PF) {
+            if (rb + 1 < nrb) {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)
+                    if (q < nq) wn[q] = wf[((size_t)(rb + 1) * nq + q) * 64];
+            }
+        } else if (rb > 0) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+                if (q < nq) wa[q] = wf[((size_t)rb * nq + q) * 64];
         }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (q < nq) {
+                acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(wa[q], bf0[q], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(wa[q], bf1[q], acc1, 0, 0, 0);
+            }
         // sums element e: row 8 (e / 4) + 4 h + e % 4, entry c (acc0) or 32 + c (acc1)
 #pragma unroll
         for (int a4 = 0; a4 < 4; ++a4) {
@@ -382,36 +415,53 @@ __device__ __forceinline__ void residue_block_mma_r(
                 v4i{acc1[4 * a4], acc1[4 * a4 + 1], acc1[4 * a4 + 2], acc1[4 * a4 + 3]};
         }
         wave_lds_sync();   // sums written
+        // lane k reduces its own entry: four rows per 16-byte read (two-limb pairs start
+        // on a multiple of 4)
         crb_t *B = grb + rb;
         const int n1 = (int)B->n1, p0 = (int)B->p0, n2 = (int)B->n2;
-#pragma unroll 4
-        for (int i = 0; i < n1; ++i) {
-            const double x = (double)(int32_t)xrow[i];
-            const int ri = (int)fma(-rint(x * B->inv_m[i]), B->md[i], x);
-            g_i8 *pb = uniform_ptr((g_i8 *)planes + (int64_t)B->g0[i] * plane_stride);
-            pb[loff] = (int8_t)ri;
+        for (int i4 = 0; i4 < n1; i4 += 4) {
+            const v4i x4 = *(const v4i *)(xrow + i4);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int i = i4 + e;
+                if (i < n1) {
+                    const double x = (double)x4[e];
+                    const int ri = (int)fma(-rint(x * B->inv_m[i]), B->md[i], x);
+                    g_i8 *pb = uniform_ptr((g_i8 *)planes + (int64_t)B->g0[i] * plane_stride);
+                    pb[loff] = (int8_t)ri;
+                }
+            }
         }
-#pragma unroll 4
-        for (int j = 0; j < n2; ++j) {
-            const int i = p0 + 2 * j;
-            const uint2 xv = *(const uint2 *)(xrow + i);
-            const double x = (double)((int32_t)xv.x + 128 * (int32_t)xv.y);
-            const int ri = (int)fma(-rint(x * B->inv_m[i]), B->md[i], x);
-            const int r0 = ((ri + 64) & 127) - 64;   // balanced base-128 split
-            const int r1 = (ri - r0) >> 7;
-            g_i8 *pb = uniform_ptr((g_i8 *)planes + (int64_t)B->g0[i] * plane_stride);
-            g_i8 *pb1 = uniform_ptr(pb + plane_stride), *pb2 = uniform_ptr(pb + 2 * plane_stride);
-            pb[loff] = (int8_t)r0;
-            pb1[loff] = (int8_t)r1;
-            pb2[loff] = (int8_t)(r0 + r1);
+        for (int j2 = 0; j2 < n2; j2 += 2) {
+            const v4i x4 = *(const v4i *)(xrow + p0 + 2 * j2);
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int j = j2 + e;
+                if (j < n2) {
+                    const int i = p0 + 2 * j;
+                    const double x = (double)(x4[2 * e] + 128 * x4[2 * e + 1]);
+                    const int ri = (int)fma(-rint(x * B->inv_m[i]), B->md[i], x);
+                    const int r0 = ((ri + 64) & 127) - 64;   // balanced base-128 split
+                    const int r1 = (ri - r0) >> 7;
+                    g_i8 *pb = uniform_ptr((g_i8 *)planes + (int64_t)B->g0[i] * plane_stride);
+                    g_i8 *pb1 = uniform_ptr(pb + plane_stride), *pb2 = uniform_ptr(pb + 2 * plane_stride);
+                    pb[loff] = (int8_t)r0;
+                    pb1[loff] = (int8_t)r1;
+                    pb2[loff] = (int8_t)(r0 + r1);
+                }
+            }
+        }
+        if constexpr (PF) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) wa[q] = wn[q];
         }
     }
 }
 
-template <int RB>
+template <int RB, int NQ>
 __global__ __launch_bounds__(64 * RB) void k_residues_mma(ResMmaArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint32_t smem_res[];
-    residue_block_mma_r<RB>(a.limbs, a.exps, a.signs, a.erow, a.koff, a.wfrag, a.rblk, a.planes,
+    residue_block_mma_r<RB, NQ>(a.limbs, a.exps, a.signs, a.erow, a.koff, a.wfrag, a.rblk, a.planes,
                             a.rs, a.cs, a.rows, a.count, a.kpad, a.plane_stride, a.p, a.nl, a.t,
                             a.nw32, a.nq, a.nrb, blockIdx.x, blockIdx.y, smem_res);
 }

@@ -170,7 +170,7 @@ void build_residue_mma_tables(PlanHost &h, const std::vector<uint32_t> &mods) {
     h.rnb = 4 * h.nw32;
     const int nbk = (h.rnb + 2 + 31) / 32 * 32;
     h.rnq = nbk / 32;
-    const int r0 = h.L1 + (h.L1 & 1);   // two-limb pairs start on an even row
+    const int r0 = (h.L1 + 3) / 4 * 4;   // two-limb pairs start on a multiple of 4
     const int ml = r0 + 2 * (h.L - h.L1);
     h.rnrb = (ml + 31) / 32;
     std::vector<int8_t> W((size_t)h.rnrb * 32 * nbk, 0);

@@ -11,7 +11,7 @@ namespace oz2h {
 constexpr int kModGroup = 8;          // moduli per group in the residue kernel (small L)
 constexpr int kModGroupWide = 16;     // ... and for wide moduli sets (L >= kWideL)
 constexpr int kWideL = 96;
-constexpr int kResMmaMinWords = 30;   // integers of >= this many 32-bit words (p >~ 900) take
+constexpr int kResMmaMinWords = 8;    // integers of >= this many 32-bit words (p >~ 200) take
                                       // the matrix-core residue kernel, narrower ones the fp64 one
 constexpr int kMaxModuli = 512;       // fp64-exact CRT digit sums need L * 2^44 < 2^53
 constexpr int kMaxWords = 256;        // fp64-exact residue sums need nw32 * 2^45 < 2^53

@@ -66,6 +66,7 @@ CASES = [
     ("tiny_p2", 106, 5, 3, 4, 2, -20, 20, 0.0, 0, 0),
     ("p1024_two_limb", 107, 64, 70, 33, 1024, -40, 40, 0.0, 0, 0),
     ("p2048_small", 108, 20, 30, 17, 2048, -16, 16, 0.0, 0, 0),
+    ("p3250_widest", 113, 9, 12, 7, 3250, -8, 8, 0.0, 0, 1),
     ("p113_K_odd", 109, 140, 129, 1001, 113, -16, 16, 0.01, 0, 0),
     ("tile256x128_p256", 110, 300, 200, 150, 256, -32, 32, 0.02, 0, 0, 2),
     ("tile128x256_p512", 111, 130, 260, 70, 512, -32, 32, 0.0, 0, 1, 3),
