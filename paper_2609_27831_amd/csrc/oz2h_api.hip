@@ -230,9 +230,24 @@ int launch_gemm_kernel(GemmCfg cfg, dim3 grid, const int8_t *a, const int8_t *b,
                        int64_t a_ps, int64_t b_ps, const ModInfo *mi, int L, int16_t *v,
                        int64_t v_ps, int64_t ldv, int32_t *craw, hipStream_t s) {
     const GemmArgs g{a, b, kpad, a_ps, b_ps, mi, v, v_ps, ldv, craw};
-    if (cfg.bm == 256 && cfg.bn == 128) k_resgemm<128, 64, RAW><<<grid, 256, 0, s>>>(g, L);
-    else if (cfg.bm == 128 && cfg.bn == 256) k_resgemm<64, 128, RAW><<<grid, 256, 0, s>>>(g, L);
-    else k_resgemm<64, 64, RAW><<<grid, 256, 0, s>>>(g, L);
+    // XCD map: split each modulus's ny x nx tiles into 8 rectangles (ry x rx of them) with
+    // the smallest A + B footprint per XCD; keep the 3-D grid when no split divides evenly
+    XcdMap xm{0, 1, 1, 1};
+    size_t best = SIZE_MAX;
+    for (uint32_t ry = 1; ry <= 8; ry *= 2) {
+        const uint32_t rx = 8 / ry;
+        if (grid.y % ry || grid.x % rx) continue;
+        const uint32_t h = grid.y / ry, w = grid.x / rx;
+        const size_t foot = (size_t)h * cfg.bm + (size_t)w * cfg.bn;
+        if (foot < best) {
+            best = foot;
+            xm = XcdMap{1, rx, h, w};
+        }
+    }
+    if (xm.on) grid = dim3(grid.x * grid.y * grid.z, 1, 1);
+    if (cfg.bm == 256 && cfg.bn == 128) k_resgemm<128, 64, RAW><<<grid, 256, 0, s>>>(g, L, xm);
+    else if (cfg.bm == 128 && cfg.bn == 256) k_resgemm<64, 128, RAW><<<grid, 256, 0, s>>>(g, L, xm);
+    else k_resgemm<64, 64, RAW><<<grid, 256, 0, s>>>(g, L, xm);
     return check_launch("residue GEMM");
 }
 

@@ -688,11 +688,29 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &args, int64_t mt, int6
                 base[(int64_t)(x * 32 + 8 * (e >> 2) + (e & 3)) * ldv + y * 32] = (int16_t)acc[x][y][e];
 }
 
-// plain launch: grid (N tiles, M tiles, moduli), two-limb moduli (listed last) first
+// XCD-aware block order of the plain launch.  Blocks are dealt to the 8 XCDs round-robin
+// (block b runs on XCD b % 8, as its (b / 8)-th block there), and each XCD has its own L2.
+// With `on`, XCD x covers one rectangle of h x w tiles (rectangle row x / rx, column x % rx)
+// of every modulus, moduli in launch order: all XCDs still share each modulus's work
+// evenly, but an XCD reads h tile rows of A and w tile columns of B instead of all of A.
+struct XcdMap {
+    uint32_t on, rx, h, w;   // h * w tiles per XCD and modulus
+};
+
+// plain launch: two-limb moduli (listed last) first; grid (N tiles, M tiles, moduli), or
+// with an XCD map a 1-D grid of the same blocks
 template <int WM, int WN, bool RAW>
-__global__ __launch_bounds__(256) void k_resgemm(GemmArgs args, int L) {
-    const int l = RAW ? 0 : L - 1 - (int)blockIdx.z;
-    gemm_tile<WM, WN, RAW>(args, blockIdx.y, blockIdx.x, l);
+__global__ __launch_bounds__(256) void k_resgemm(GemmArgs args, int L, XcdMap xm) {
+    uint32_t mt = blockIdx.y, nt = blockIdx.x, zi = blockIdx.z;
+    if (xm.on) {
+        const uint32_t b = blockIdx.x, x = b & 7u, s = b >> 3, t8 = xm.h * xm.w;
+        zi = s / t8;
+        const uint32_t u = s - zi * t8;
+        mt = (x / xm.rx) * xm.h + u / xm.w;
+        nt = (x % xm.rx) * xm.w + u % xm.w;
+    }
+    const int l = RAW ? 0 : L - 1 - (int)zi;
+    gemm_tile<WM, WN, RAW>(args, mt, nt, l);
 }
 
 // ---------------------------------------------------------------- stage 4 + 5
