@@ -416,40 +416,48 @@ __device__ __forceinline__ void residue_block_mma_r(
         }
         wave_lds_sync();   // sums written
         // lane k reduces its own entry: four rows per 16-byte read (two-limb pairs start
-        // on a multiple of 4)
+        // on a multiple of 4), the modulus data of four rows per scalar load, every row of
+        // the four computed (rows past the moduli hold zeros) and only the stores guarded
         crb_t *B = grb + rb;
         const int n1 = (int)B->n1, p0 = (int)B->p0, n2 = (int)B->n2;
+        typedef double d4 __attribute__((ext_vector_type(4)));
+        typedef const __attribute__((address_space(4))) d4 cd4;
         for (int i4 = 0; i4 < n1; i4 += 4) {
             const v4i x4 = *(const v4i *)(xrow + i4);
+            const d4 im = *(cd4 *)(B->inv_m + i4), mm = *(cd4 *)(B->md + i4);
+            // one-limb moduli of consecutive rows own consecutive planes
+            g_i8 *pb = (g_i8 *)planes + (int64_t)B->g0[i4] * plane_stride;
+            int ri[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int i = i4 + e;
-                if (i < n1) {
-                    const double x = (double)x4[e];
-                    const int ri = (int)fma(-rint(x * B->inv_m[i]), B->md[i], x);
-                    g_i8 *pb = uniform_ptr((g_i8 *)planes + (int64_t)B->g0[i] * plane_stride);
-                    pb[loff] = (int8_t)ri;
-                }
+                const double x = (double)x4[e];
+                ri[e] = (int)fma(-rint(x * im[e]), mm[e], x);
             }
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (i4 + e < n1) uniform_ptr(pb + e * plane_stride)[loff] = (int8_t)ri[e];
         }
         for (int j2 = 0; j2 < n2; j2 += 2) {
-            const v4i x4 = *(const v4i *)(xrow + p0 + 2 * j2);
+            const int i4 = p0 + 2 * j2;
+            const v4i x4 = *(const v4i *)(xrow + i4);
+            const d4 im = *(cd4 *)(B->inv_m + i4), mm = *(cd4 *)(B->md + i4);
+            // consecutive two-limb moduli own consecutive triples of planes
+            g_i8 *pb = (g_i8 *)planes + (int64_t)B->g0[i4] * plane_stride;
+            int r0[2], r1[2];
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
-                const int j = j2 + e;
-                if (j < n2) {
-                    const int i = p0 + 2 * j;
-                    const double x = (double)(x4[2 * e] + 128 * x4[2 * e + 1]);
-                    const int ri = (int)fma(-rint(x * B->inv_m[i]), B->md[i], x);
-                    const int r0 = ((ri + 64) & 127) - 64;   // balanced base-128 split
-                    const int r1 = (ri - r0) >> 7;
-                    g_i8 *pb = uniform_ptr((g_i8 *)planes + (int64_t)B->g0[i] * plane_stride);
-                    g_i8 *pb1 = uniform_ptr(pb + plane_stride), *pb2 = uniform_ptr(pb + 2 * plane_stride);
-                    pb[loff] = (int8_t)r0;
-                    pb1[loff] = (int8_t)r1;
-                    pb2[loff] = (int8_t)(r0 + r1);
-                }
+                const double x = (double)(x4[2 * e] + 128 * x4[2 * e + 1]);
+                const int ri = (int)fma(-rint(x * im[2 * e]), mm[2 * e], x);
+                r0[e] = ((ri + 64) & 127) - 64;   // balanced base-128 split
+                r1[e] = (ri - r0[e]) >> 7;
             }
+#pragma unroll
+            for (int e = 0; e < 2; ++e)
+                if (j2 + e < n2) {
+                    uniform_ptr(pb + (3 * e) * plane_stride)[loff] = (int8_t)r0[e];
+                    uniform_ptr(pb + (3 * e + 1) * plane_stride)[loff] = (int8_t)r1[e];
+                    uniform_ptr(pb + (3 * e + 2) * plane_stride)[loff] = (int8_t)(r0[e] + r1[e]);
+                }
         }
         if constexpr (PF) {
 #pragma unroll

@@ -45,7 +45,9 @@ static_assert(sizeof(ResGroup) == 384, "ResGroup layout");
 // One block of 32 weight rows of the MFMA residue kernel as it reads it (wave-uniform
 // scalar loads, 768 bytes).  Rows [0, n1) are one-limb moduli; rows p0 + 2 j and
 // p0 + 2 j + 1 (j < n2) hold the low and high balanced base-128 halves of a two-limb
-// modulus's weights.  A modulus's data sit at its first row.
+// modulus's weights.  A modulus's data sit at its first row.  Planes follow the moduli
+// order (one plane per one-limb modulus, three per two-limb one), so consecutive one-limb
+// rows own consecutive planes and consecutive pairs consecutive triples.
 struct ResRowBlock {
     double inv_m[32];   // fl(1/m)
     double md[32];      // m as a double
