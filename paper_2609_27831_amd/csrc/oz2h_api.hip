@@ -33,6 +33,7 @@ struct oz2h_plan {
     ResGroup *d_rgrp = nullptr;
     int8_t *d_rmma_w = nullptr;
     ResRowBlock *d_rmma_rb = nullptr;
+    int8_t *d_crt_afr = nullptr;
     double *d_crt = nullptr;
     uint32_t *d_pd = nullptr;
     uint32_t *d_phd = nullptr;
@@ -311,7 +312,16 @@ int launch_crt(const oz2h_plan *pl, int64_t M, int64_t N, const int16_t *u, int6
     const size_t lds = c.lds;
     const CrtArgs ca{u, u_ps, ldu, M, N, pl->d_info, h.L, pl->d_crt, h.crt_ndpad, h.crt_nc, h.nd32,
                      pl->d_pd, pl->d_phd, e, f, tsum, h.p, osign, oexp, olimbs, ldc, chat, nlc, c.LB,
-                     c.gdig ? gdig : nullptr, c.gstride};
+                     c.gdig ? gdig : nullptr, c.gstride, pl->d_crt_afr, h.crt_nbk, h.crt_kq,
+                     h.crt_nt, h.crt_inv_ptop};
+    if (!weight && !c.gdig && h.crt_mma && h.crt_kq <= kCrtMmaMaxQ && h.nd32 >= kCrtMmaMinDigits) {
+        // matrix-core digit sums: 256 entries per block, one LDS digit column each
+        const unsigned nbm = (unsigned)((M * N + 255) / 256);
+        const size_t ldsm = (size_t)256 * h.nd32 * sizeof(uint32_t);
+        if (round) k_crt_mma<kCrtMmaMaxQ, true><<<nbm, 256, ldsm, s>>>(ca);
+        else k_crt_mma<kCrtMmaMaxQ, false><<<nbm, 256, ldsm, s>>>(ca);
+        return check_launch("CRT");
+    }
 #define OZ2H_CRT(DC, E, R, W, G) k_crt<DC, E, R, W, G><<<nb, bd, lds, s>>>(ca)
 #define OZ2H_CRT_E(DC, R, W, G)               \
     if (ept == 2) OZ2H_CRT(DC, 2, R, W, G);    \
@@ -365,6 +375,9 @@ int upload_plan(oz2h_plan *pl) {
     off = align_up(off + n_rw);
     const size_t o_rrb = off;
     off = align_up(off + n_rrb);
+    const size_t n_cafr = h.crt_afr.size();
+    const size_t o_cafr = off;
+    off = align_up(off + n_cafr);
     const size_t o_crt = off;
     off = align_up(off + n_crt);
     const size_t o_pd = off;
@@ -380,6 +393,7 @@ int upload_plan(oz2h_plan *pl) {
     pl->d_rgrp = (ResGroup *)(b + o_rg);
     pl->d_rmma_w = (int8_t *)(b + o_rw);
     pl->d_rmma_rb = (ResRowBlock *)(b + o_rrb);
+    pl->d_crt_afr = (int8_t *)(b + o_cafr);
     pl->d_crt = (double *)(b + o_crt);
     pl->d_pd = (uint32_t *)(b + o_pd);
     pl->d_phd = (uint32_t *)(b + o_phd);
@@ -388,6 +402,7 @@ int upload_plan(oz2h_plan *pl) {
     OZ2H_HIP(hipMemcpy(pl->d_rgrp, h.resgrp.data(), n_rg, hipMemcpyHostToDevice));
     OZ2H_HIP(hipMemcpy(pl->d_rmma_w, h.rmma_w.data(), n_rw, hipMemcpyHostToDevice));
     OZ2H_HIP(hipMemcpy(pl->d_rmma_rb, h.rmma_rb.data(), n_rrb, hipMemcpyHostToDevice));
+    if (n_cafr) OZ2H_HIP(hipMemcpy(pl->d_crt_afr, h.crt_afr.data(), n_cafr, hipMemcpyHostToDevice));
     OZ2H_HIP(hipMemcpy(pl->d_crt, h.crt_digits.data(), n_crt, hipMemcpyHostToDevice));
     OZ2H_HIP(hipMemcpy(pl->d_pd, h.p_digits.data(), n_pd, hipMemcpyHostToDevice));
     OZ2H_HIP(hipMemcpy(pl->d_phd, h.ph_digits.data(), n_pd, hipMemcpyHostToDevice));

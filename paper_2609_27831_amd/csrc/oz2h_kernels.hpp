@@ -828,7 +828,105 @@ struct CrtArgs {
     int nlc, LB;
     uint32_t *gdig;    // GDIG: digit columns in global memory, digit k of entry e at
     int64_t gstride;   // gdig[k * gstride + e] (gstride >= all entries the grid covers)
+    // matrix-core CRT (k_crt_mma): A fragments, row blocks, contraction steps, top digits
+    const int8_t *afr;
+    int nbk, kq, nt;
+    double inv_ptop;
 };
+
+// Lift and (ROUND) rounding of one output entry e from its digit column sd (stride
+// cst): on the fast path the column holds c^ in two's complement over nd32 digits
+// (sign = carry < 0); on the slow path it holds R = S - (alpha - 1) P in [0, 3P).
+template <bool ROUND>
+__device__ __forceinline__ void crt_finish(const CrtArgs &a, int64_t e, uint32_t *sd, int64_t cst,
+                                           bool slow, int64_t carry) {
+    const int nd32 = a.nd32, p = a.p;
+    const int64_t N = a.N;
+    const uint32_t *__restrict__ Phd = a.Phd;
+    const int nl = (p + 63) / 64;
+    bool neg;
+    MagView mag{sd, cst, nd32, 0, false};
+    if (!slow) {
+        neg = carry < 0;   // two's complement c^ over nd32 digits
+        if (neg) {
+            int z = 0;
+            while (z < nd32 - 1 && sd[z * cst] == 0) ++z;
+            mag.z = z;
+            mag.inv = true;
+        }
+    } else {
+        // R in [0, 3P): at most two subtractions of P, then the symmetric lift
+        if (dig_ge(sd, cst, a.Pd, nd32)) dig_sub(sd, cst, a.Pd, nd32);
+        if (dig_ge(sd, cst, a.Pd, nd32)) dig_sub(sd, cst, a.Pd, nd32);
+        neg = !dig_ge(sd, cst, Phd, nd32) ? false : true;   // x0 >= floor(P/2) ...
+        if (neg) {                                          // ... and x0 != floor(P/2)
+            dig_sub(sd, cst, Phd, nd32);
+            bool eq = true;
+            for (int k = 0; k < nd32 && eq; ++k) eq = sd[k * cst] == 0;
+            dig_add(sd, cst, Phd, nd32);
+            neg = !eq;
+        }
+        if (neg) dig_rsub(sd, cst, a.Pd, nd32);   // |c^| = P - x0
+    }
+    int top = nd32 - 1;
+    while (top >= 0 && mag(top) == 0) --top;
+    const int64_t i = e / N, j = e - i * N;
+
+    if (!ROUND) {
+        __attribute__((address_space(1))) uint64_t *o =
+            (__attribute__((address_space(1))) uint64_t *)a.chat_mag + e * a.nlc;
+        for (int w = 0; w < a.nlc; ++w)
+            o[w] = (uint64_t)mag(2 * w) | ((uint64_t)mag(2 * w + 1) << 32);
+        a.osign[e] = top < 0 ? 0 : (neg ? -1 : 1);
+        return;
+    }
+    const int64_t oi = i * a.ldc + j;
+    __attribute__((address_space(1))) uint64_t *o =
+        (__attribute__((address_space(1))) uint64_t *)a.olimbs + oi * nl;
+    if (top < 0) {
+        for (int w = 0; w < nl; ++w) o[w] = 0;
+        a.osign[oi] = 0;
+        a.oexp[oi] = 0;
+        return;
+    }
+    int64_t nb = 32 * (int64_t)top + (32 - __builtin_clz(mag(top)));
+    const int64_t sh = nb - p;   // mant = RNE(mag / 2^sh)
+    bool inc = false;
+    if (sh > 0) {
+        const int64_t rpos = sh - 1;
+        if ((mag.bits32(rpos) & 1u) != 0)   // round bit set: up unless an exact tie to even
+            inc = mag.any_below(rpos) || (mag.bits32(sh) & 1u);
+    }
+    bool allones = inc;
+    if (inc) {   // mant = 2^p - 1 rounds up to 2^p: renormalise
+        for (int w = 0; w < nl && allones; ++w) {
+            const uint64_t v = (uint64_t)mag.bits32(64 * (int64_t)w + sh) |
+                               ((uint64_t)mag.bits32(64 * (int64_t)w + 32 + sh) << 32);
+            const int bits = (w == nl - 1) ? p - 64 * (nl - 1) : 64;
+            const uint64_t mask = bits >= 64 ? ~0ull : ((1ull << bits) - 1);
+            allones = v == mask;
+        }
+    }
+    if (allones) {
+        for (int w = 0; w < nl; ++w) o[w] = 0;
+        o[(p - 1) >> 6] = 1ull << ((p - 1) & 63);
+        nb += 1;
+    } else {
+        bool cy = inc;
+        for (int w = 0; w < nl; ++w) {
+            uint64_t v = (uint64_t)mag.bits32(64 * (int64_t)w + sh) |
+                         ((uint64_t)mag.bits32(64 * (int64_t)w + 32 + sh) << 32);
+            if (cy) {
+                v += 1;
+                cy = v == 0;
+            }
+            o[w] = v;
+        }
+    }
+    a.osign[oi] = neg ? -1 : 1;
+    a.oexp[oi] = (int32_t)(nb + (int64_t)(a.erow ? a.erow[i] : 0) + (a.fcol ? a.fcol[j] : 0) -
+                           (int64_t)a.tsum);
+}
 
 // LDS of a CRT block: bd * EPT digit columns of nd32 words (GDIG = false), or the
 // LB x (DC + 1) doubles of a constant slice (GDIG = true: the digit columns of large
@@ -1001,100 +1099,143 @@ __device__ __forceinline__ void crt_block(const CrtArgs &a, int64_t blk, uint32_
         }
     }
 
-    const int nl = (p + 63) / 64;
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-        if (!live[q]) continue;
-        uint32_t *sd = col(q);
-        bool neg;
-        MagView mag{sd, cst, nd32, 0, false};
-        if (!slow[q]) {
-            neg = carry[q] < 0;   // two's complement c^ over nd32 digits
-            if (neg) {
-                int z = 0;
-                while (z < nd32 - 1 && sd[z * cst] == 0) ++z;
-                mag.z = z;
-                mag.inv = true;
-            }
-        } else {
-            // R in [0, 3P): at most two subtractions of P, then the symmetric lift
-            if (dig_ge(sd, cst, a.Pd, nd32)) dig_sub(sd, cst, a.Pd, nd32);
-            if (dig_ge(sd, cst, a.Pd, nd32)) dig_sub(sd, cst, a.Pd, nd32);
-            neg = !dig_ge(sd, cst, Phd, nd32) ? false : true;   // x0 >= floor(P/2) ...
-            if (neg) {                                          // ... and x0 != floor(P/2)
-                dig_sub(sd, cst, Phd, nd32);
-                bool eq = true;
-                for (int k = 0; k < nd32 && eq; ++k) eq = sd[k * cst] == 0;
-                dig_add(sd, cst, Phd, nd32);
-                neg = !eq;
-            }
-            if (neg) dig_rsub(sd, cst, a.Pd, nd32);   // |c^| = P - x0
-        }
-        int top = nd32 - 1;
-        while (top >= 0 && mag(top) == 0) --top;
-        const int64_t i = idx[q] / N, j = idx[q] - i * N;
-
-        if (!ROUND) {
-            __attribute__((address_space(1))) uint64_t *o =
-                (__attribute__((address_space(1))) uint64_t *)a.chat_mag + idx[q] * a.nlc;
-            for (int w = 0; w < a.nlc; ++w)
-                o[w] = (uint64_t)mag(2 * w) | ((uint64_t)mag(2 * w + 1) << 32);
-            a.osign[idx[q]] = top < 0 ? 0 : (neg ? -1 : 1);
-            continue;
-        }
-        const int64_t oi = i * a.ldc + j;
-        __attribute__((address_space(1))) uint64_t *o =
-            (__attribute__((address_space(1))) uint64_t *)a.olimbs + oi * nl;
-        if (top < 0) {
-            for (int w = 0; w < nl; ++w) o[w] = 0;
-            a.osign[oi] = 0;
-            a.oexp[oi] = 0;
-            continue;
-        }
-        int64_t nb = 32 * (int64_t)top + (32 - __builtin_clz(mag(top)));
-        const int64_t sh = nb - p;   // mant = RNE(mag / 2^sh)
-        bool inc = false;
-        if (sh > 0) {
-            const int64_t rpos = sh - 1;
-            if ((mag.bits32(rpos) & 1u) != 0)   // round bit set: up unless an exact tie to even
-                inc = mag.any_below(rpos) || (mag.bits32(sh) & 1u);
-        }
-        bool allones = inc;
-        if (inc) {   // mant = 2^p - 1 rounds up to 2^p: renormalise
-            for (int w = 0; w < nl && allones; ++w) {
-                const uint64_t v = (uint64_t)mag.bits32(64 * (int64_t)w + sh) |
-                                   ((uint64_t)mag.bits32(64 * (int64_t)w + 32 + sh) << 32);
-                const int bits = (w == nl - 1) ? p - 64 * (nl - 1) : 64;
-                const uint64_t mask = bits >= 64 ? ~0ull : ((1ull << bits) - 1);
-                allones = v == mask;
-            }
-        }
-        if (allones) {
-            for (int w = 0; w < nl; ++w) o[w] = 0;
-            o[(p - 1) >> 6] = 1ull << ((p - 1) & 63);
-            nb += 1;
-        } else {
-            bool cy = inc;
-            for (int w = 0; w < nl; ++w) {
-                uint64_t v = (uint64_t)mag.bits32(64 * (int64_t)w + sh) |
-                             ((uint64_t)mag.bits32(64 * (int64_t)w + 32 + sh) << 32);
-                if (cy) {
-                    v += 1;
-                    cy = v == 0;
-                }
-                o[w] = v;
-            }
-        }
-        a.osign[oi] = neg ? -1 : 1;
-        a.oexp[oi] = (int32_t)(nb + (int64_t)(a.erow ? a.erow[i] : 0) + (a.fcol ? a.fcol[j] : 0) -
-                               (int64_t)a.tsum);
-    }
+    for (int q = 0; q < EPT; ++q)
+        if (live[q]) crt_finish<ROUND>(a, idx[q], col(q), cst, slow[q], carry[q]);
 }
 
 template <int DC, int EPT, bool ROUND, bool WEIGHT, bool GDIG>
 __global__ __launch_bounds__(256) void k_crt(CrtArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint32_t sdig[];
     crt_block<DC, EPT, ROUND, WEIGHT, GDIG>(a, blockIdx.x, sdig);
+}
+
+// Direct CRT on the matrix cores (digit columns in LDS: nd32 <= 32, L <= 127).  The
+// digit sums S = sum_l v_l M_l are formed as the int8 product (byte rows of S) x
+// (entries) of the tables of build_crt_mma_tables with each v_l's two bytes; one wave
+// covers 64 consecutive entries as two 32-entry column blocks.
+//   B fragments: lane (h, c) holds, per 32-byte step q, the words of moduli
+//     16 q + 8 h .. + 7 of entries c and 32 + c, each xor 0x0080 (low byte - 128).
+//   Output element 4 a + i of a 32 x 32 block is byte row 8 a + 4 h + i, i.e. byte i of
+//     digit 2 a + h: a lane assembles four digit partials per block; one ds_bpermute
+//     hand-over then gives lane (0, c) all digits of entry c and lane (1, c) all digits of
+//     entry 32 + c, which it carries into its LDS column.
+//   S / P is estimated from the top nt digits (error below 2^-40); the nearest integer
+//   beta is exact unless the estimate lies within 2^-30 of a half-integer, else the
+//   paper's alpha - 1 (at most two subtractions of P follow in crt_finish).  Then the
+//   column receives S - beta P and crt_finish lifts and rounds as in k_crt.
+constexpr int kCrtMmaMaxQ = 8;   // contraction steps of the matrix-core CRT (2 L + 1 <= 256)
+// below this many digits (p <~ 180) the fp64 CRT is faster: the matrix-core kernel's
+// per-entry carry and subtraction passes outweigh its L x nd32 multiply-adds
+constexpr int kCrtMmaMinDigits = 16;
+
+template <int KQ, bool ROUND>
+__global__ __launch_bounds__(256) void k_crt_mma(CrtArgs a) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t sdig[];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int h = lane >> 5, c = lane & 31;
+    const int nd32 = a.nd32, L = a.L, kq = a.kq, nbk = a.nbk;
+    const int64_t N = a.N, MN = a.M * N, v_ps = a.v_ps;
+    const int64_t e0 = (int64_t)blockIdx.x * 256 + wv * 64;
+    typedef const __attribute__((address_space(1))) uint16_t gu16;
+    typedef const __attribute__((address_space(1))) v4i gv4i;
+    typedef const __attribute__((address_space(4))) uint32_t cu32;
+
+    // B fragments (a dead entry reads entry 0, always valid, and writes nothing).  Steps
+    // with all 16 moduli present load unguarded (a lane base plus a wave-uniform offset);
+    // the last step clamps the modulus and feeds 0 past L.
+    v4i bf0[KQ], bf1[KQ];
+    {
+        gu16 *vb[2];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int64_t e = e0 + 32 * b + c, ee = e < MN ? e : 0;
+            const int64_t i = ee / N, j = ee - i * N;
+            vb[b] = (gu16 *)a.V + i * a.ldv + j + (int64_t)(8 * h) * v_ps;
+        }
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) {
+            if (q < kq) {
+                const bool full = 16 * q + 16 <= L;   // wave-uniform
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    uint32_t w[8];
+                    if (full) {
+#pragma unroll
+                        for (int t = 0; t < 8; ++t) w[t] = vb[b][(int64_t)(16 * q + t) * v_ps];
+                    } else {
+#pragma unroll
+                        for (int t = 0; t < 8; ++t) {
+                            const int l = 16 * q + 8 * h + t;
+                            const int lc = min(l, L - 1) - 8 * h;   // relative to the lane base
+                            const uint32_t x = vb[b][(int64_t)lc * v_ps];
+                            w[t] = l < L ? x : 0u;
+                        }
+                    }
+                    const v4i f = v4i{(int)((w[0] | (w[1] << 16)) ^ 0x00800080u),
+                                      (int)((w[2] | (w[3] << 16)) ^ 0x00800080u),
+                                      (int)((w[4] | (w[5] << 16)) ^ 0x00800080u),
+                                      (int)((w[6] | (w[7] << 16)) ^ 0x00800080u)};
+                    if (b == 0) bf0[q] = f;
+                    else bf1[q] = f;
+                }
+            }
+        }
+    }
+
+    // S: eight digits per block of 32 byte rows, carried into this lane's LDS column
+    gv4i *af = (gv4i *)a.afr + lane;
+    uint32_t *col = sdig + tid;   // digit k at col[256 k]
+    int64_t carry = 0;
+    for (int nb = 0; nb < nbk; ++nb) {
+        v16i acc0 = v16i{}, acc1 = v16i{};
+#pragma unroll
+        for (int q = 0; q < KQ; ++q)
+            if (q < kq) {
+                const v4i f = af[((size_t)nb * kq + q) * 64];
+                acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(f, bf0[q], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(f, bf1[q], acc1, 0, 0, 0);
+            }
+        int64_t mine[4], got[4];
+#pragma unroll
+        for (int a4 = 0; a4 < 4; ++a4) {
+            const int64_t d0 = (int64_t)acc0[4 * a4] + (int64_t)acc0[4 * a4 + 1] * 256 +
+                               (int64_t)acc0[4 * a4 + 2] * 65536 + (int64_t)acc0[4 * a4 + 3] * 16777216;
+            const int64_t d1 = (int64_t)acc1[4 * a4] + (int64_t)acc1[4 * a4 + 1] * 256 +
+                               (int64_t)acc1[4 * a4 + 2] * 65536 + (int64_t)acc1[4 * a4 + 3] * 16777216;
+            const int64_t send = h ? d0 : d1;   // the partner's entry
+            mine[a4] = h ? d1 : d0;
+            const int plo = __builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, (int)(uint32_t)send);
+            const int phi = __builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, (int)(send >> 32));
+            got[a4] = (int64_t)(((uint64_t)(uint32_t)phi << 32) | (uint32_t)plo);
+        }
+#pragma unroll
+        for (int dk = 0; dk < 8; ++dk) {
+            const int k = 8 * nb + dk;
+            const int64_t D = (dk & 1) == h ? mine[dk >> 1] : got[dk >> 1];
+            if (k < nd32) {
+                const int64_t x = D + carry;
+                col[256 * k] = (uint32_t)x;
+                carry = x >> 32;
+            }
+        }
+    }
+
+    // beta from S / P, then S - beta P into the column
+    double val = (double)(int32_t)col[256 * (nd32 - 1)];
+    for (int k = nd32 - 2; k >= nd32 - a.nt; --k) val = val * 4294967296.0 + (double)col[256 * k];
+    const double est = val * a.inv_ptop, r = rint(est);
+    const bool slow = fabs(est - r) > 0.5 - 0x1p-30;
+    const int64_t beta = slow ? (int64_t)floor(est) - 1 : (int64_t)r;
+    cu32 *Pd = (cu32 *)a.Pd;
+    int64_t cy = 0;
+    for (int k = 0; k < nd32; ++k) {
+        const int64_t x = (int64_t)col[256 * k] - beta * (int64_t)Pd[k] + cy;
+        col[256 * k] = (uint32_t)x;
+        cy = x >> 32;
+    }
+    const int64_t e = e0 + lane;
+    if (e < MN) crt_finish<ROUND>(a, e, col, 256, slow, cy + carry);
 }
 
 // planes [G][R][C] (int8, row stride ldi) -> [G][Co][Ro] (row stride Ro), zero where

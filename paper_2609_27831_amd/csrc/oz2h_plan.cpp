@@ -50,6 +50,49 @@ uint32_t nat_mod_small(const Nat &a, uint32_t m) {
     return (uint32_t)rem;
 }
 
+void nat_add(Nat &a, const Nat &b) {   // a += b
+    if (a.size() < b.size()) a.resize(b.size(), 0u);
+    uint64_t carry = 0;
+    for (size_t i = 0; i < a.size(); ++i) {
+        const uint64_t x = (uint64_t)a[i] + (i < b.size() ? b[i] : 0u) + carry;
+        a[i] = (uint32_t)x;
+        carry = x >> 32;
+    }
+    if (carry) a.push_back((uint32_t)carry);
+}
+
+bool nat_ge(const Nat &a, const Nat &b) {
+    const size_t n = std::max(a.size(), b.size());
+    for (size_t i = n; i-- > 0;) {
+        const uint32_t x = i < a.size() ? a[i] : 0u, y = i < b.size() ? b[i] : 0u;
+        if (x != y) return x > y;
+    }
+    return true;
+}
+
+void nat_sub(Nat &a, const Nat &b) {   // a -= b, a >= b
+    int64_t borrow = 0;
+    for (size_t i = 0; i < a.size(); ++i) {
+        const int64_t x = (int64_t)a[i] - (i < b.size() ? b[i] : 0u) - borrow;
+        a[i] = (uint32_t)x;
+        borrow = x < 0;
+    }
+    nat_trim(a);
+}
+
+// balanced base-256 digits of a (each in [-128, 127]) at n positions
+std::vector<int> nat_balanced_bytes(const Nat &a, int n) {
+    std::vector<int> d(n, 0);
+    int carry = 0;
+    for (int j = 0; j < n; ++j) {
+        const size_t w = (size_t)j / 4;
+        int x = (w < a.size() ? (int)((a[w] >> (8 * (j % 4))) & 255u) : 0) + carry;
+        carry = x >= 128;
+        d[j] = carry ? x - 256 : x;
+    }
+    return d;
+}
+
 int nat_bitlen(const Nat &a) {
     for (size_t i = a.size(); i-- > 0;)
         if (a[i]) return (int)(32 * i + (32 - __builtin_clz(a[i])));
@@ -154,6 +197,56 @@ int select_moduli_bits(double need, std::vector<uint32_t> &mods, double &log2P, 
         return -2;
     }
     return 0;
+}
+
+// Tables of the matrix-core CRT (digit columns in LDS, nd32 <= 32, L <= 127).  The digit
+// sums S = sum_l v_l M_l (M_l = P/m_l) are an int8 product: v_l = Lo + 256 Hi with Lo its
+// low byte (fed as Lo - 128) and Hi its signed high byte, so with b_{l,j} the balanced
+// base-256 digits of M_l the byte column j of S is
+//   sum_l (Lo_l - 128) b_{l,j} + Hi_l b_{l,j-1},
+// contraction index 2 l (the Lo byte) and 2 l + 1 (the Hi byte).  Contraction index 2 L
+// is fed the byte -128 against the digits of (-sum_l M_l mod P), which adds back
+// 128 sum_l M_l modulo P.  Column sums stay below 128 * 128 * (2 L + 1) < 2^23.
+void build_crt_mma_tables(PlanHost &h, const std::vector<uint32_t> &mods, const Nat &P) {
+    h.crt_mma = false;
+    h.crt_afr.clear();
+    if (h.nd32 > 32 || h.L > 127) return;
+    const int nb = 4 * h.nd32;                // byte rows of S
+    h.crt_nbk = (nb + 31) / 32;               // blocks of 32 byte rows (8 digits)
+    h.crt_kq = (2 * h.L + 1 + 31) / 32;       // 32-byte contraction steps
+    const int rows = 32 * h.crt_nbk, kk = 32 * h.crt_kq;
+    std::vector<int8_t> T((size_t)rows * kk, 0);
+    Nat sum;
+    for (int l = 0; l < h.L; ++l) {
+        const Nat Ml = nat_divexact_small(P, mods[l]);
+        nat_add(sum, Ml);
+        const std::vector<int> b = nat_balanced_bytes(Ml, rows);
+        for (int j = 0; j < rows; ++j) {
+            T[(size_t)j * kk + 2 * l] = (int8_t)b[j];
+            T[(size_t)j * kk + 2 * l + 1] = (int8_t)(j ? b[j - 1] : 0);
+        }
+    }
+    while (nat_ge(sum, P) && !sum.empty()) nat_sub(sum, P);   // sum_l M_l mod P
+    Nat corr = P;
+    if (sum.empty()) corr.clear();
+    else nat_sub(corr, sum);                                     // -sum_l M_l mod P
+    const std::vector<int> bc = nat_balanced_bytes(corr, rows);
+    for (int j = 0; j < rows; ++j) T[(size_t)j * kk + 2 * h.L] = (int8_t)bc[j];
+    // MFMA A fragments: lane l of step q of row block r holds row 32 r + l % 32,
+    // contraction bytes 32 q + 16 (l / 32) ..
+    h.crt_afr.assign((size_t)h.crt_nbk * h.crt_kq * 64 * 16, 0);
+    for (int r = 0; r < h.crt_nbk; ++r)
+        for (int q = 0; q < h.crt_kq; ++q)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int e = 0; e < 16; ++e)
+                    h.crt_afr[(((size_t)r * h.crt_kq + q) * 64 + lane) * 16 + e] =
+                        T[(size_t)(32 * r + lane % 32) * kk + 32 * q + 16 * (lane / 32) + e];
+    // S/P from the top crt_nt digits of S: S_top 2^(32 (nd32 - nt)) / P
+    h.crt_nt = std::min(h.nd32, 5);
+    double pd = 0.0;
+    for (size_t i = P.size(); i-- > 0;) pd = pd * 4294967296.0 + (double)P[i];
+    h.crt_inv_ptop = std::ldexp(1.0, 32 * (h.nd32 - h.crt_nt)) / pd;
+    h.crt_mma = true;
 }
 
 // Tables of the MFMA residue kernel.  The residue of a magnitude |a| = sum_j b_j 256^j
@@ -334,6 +427,7 @@ int build_plan(int p, int t, int64_t K, const std::vector<uint32_t> &mods_in, Pl
             return -1;
         }
     }
+    build_crt_mma_tables(h, mods, P);
     h.p_digits.assign(h.nd32, 0);
     h.ph_digits.assign(h.nd32, 0);
     for (int k = 0; k < h.nd32 && k < (int)P.size(); ++k) h.p_digits[k] = P[k];

@@ -85,6 +85,12 @@ struct PlanHost {
     std::vector<int8_t> rmma_w;          // [rnrb][rnq][64 lanes][16]: MFMA A fragments
     std::vector<ResRowBlock> rmma_rb;    // [rnrb]
     std::vector<double> crt_digits;  // [L][crt_ndpad]: balanced base-2^32 digits of P/m
+    bool crt_mma = false;  // matrix-core CRT tables built (nd32 <= 32, L <= 127)
+    int crt_nbk = 0;       // ... blocks of 32 byte rows of S
+    int crt_kq = 0;        // ... 32-byte contraction steps (2 L + 1 bytes)
+    int crt_nt = 0;        // ... top digits of S that estimate S / P
+    double crt_inv_ptop = 0;           // ... 2^(32 (nd32 - crt_nt)) / P
+    std::vector<int8_t> crt_afr;       // [crt_nbk][crt_kq][64 lanes][16]: MFMA A fragments
     std::vector<uint32_t> p_digits;  // [nd32] digits of P
     std::vector<uint32_t> ph_digits; // [nd32] digits of floor(P/2)
 };
