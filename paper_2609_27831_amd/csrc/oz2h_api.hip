@@ -293,6 +293,11 @@ CrtCfg crt_config(const PlanHost &h, int64_t M, int64_t N, bool allow_gdig) {
     return c;
 }
 
+// the matrix-core CRT: digit columns in LDS, tables built, enough digits to pay off
+bool crt_mma_eligible(const PlanHost &h, const CrtCfg &c) {
+    return !c.gdig && h.crt_mma && h.crt_kq <= kCrtMmaMaxQ && h.nd32 >= kCrtMmaMinDigits;
+}
+
 size_t crt_gdig_bytes(const PlanHost &h, int64_t M, int64_t N) {
     const CrtCfg c = crt_config(h, M, N, true);
     return c.gdig ? (size_t)h.nd32 * (size_t)c.gstride * sizeof(uint32_t) : 0;
@@ -314,7 +319,7 @@ int launch_crt(const oz2h_plan *pl, int64_t M, int64_t N, const int16_t *u, int6
                      pl->d_pd, pl->d_phd, e, f, tsum, h.p, osign, oexp, olimbs, ldc, chat, nlc, c.LB,
                      c.gdig ? gdig : nullptr, c.gstride, pl->d_crt_afr, h.crt_nbk, h.crt_kq,
                      h.crt_nt, h.crt_inv_ptop};
-    if (!weight && !c.gdig && h.crt_mma && h.crt_kq <= kCrtMmaMaxQ && h.nd32 >= kCrtMmaMinDigits) {
+    if (!weight && crt_mma_eligible(h, c)) {
         // matrix-core digit sums: 256 entries per block, one LDS digit column each
         const unsigned nbm = (unsigned)((M * N + 255) / 256);
         const size_t ldsm = (size_t)256 * h.nd32 * sizeof(uint32_t);
@@ -982,7 +987,7 @@ struct oz2h_batched_plan {
     size_t res_lds = 0;
     struct CrtClass {
         int dc, ept, bd, LB;
-        bool gdig;
+        bool gdig, mma;
         size_t lds;
         Seg *d_segs;
         int nseg;
@@ -1139,7 +1144,9 @@ int launch_batched_crt(oz2h_batched_plan *bp, char *ws, hipStream_t s) {
         case 28: OZ2H_GCRT(28, E, G); break;   \
         default: OZ2H_GCRT(32, E, G); break;   \
     }
-        if (c.gdig) {
+        if (c.mma) {
+            k_crt_mma_grouped<kCrtMmaMaxQ><<<nb, 256, c.lds, s>>>(bp->d_probs, c.d_segs, c.nseg, ws);
+        } else if (c.gdig) {
             if (c.ept == 2) {
                 OZ2H_GCRT_DC(2, true)
             } else {
@@ -1228,7 +1235,7 @@ int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2
     // device table layout
     size_t off = 0;
     std::vector<size_t> o_info(count), o_res(count), o_rg(count), o_crt(count), o_pd(count),
-        o_phd(count);
+        o_phd(count), o_cafr(count);
     for (int b = 0; b < count; ++b) {
         const PlanHost &h = bp->hosts[b];
         o_info[b] = off;
@@ -1243,6 +1250,8 @@ int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2
         off = align_up(off + sizeof(uint32_t) * h.nd32);
         o_phd[b] = off;
         off = align_up(off + sizeof(uint32_t) * h.nd32);
+        o_cafr[b] = off;
+        off = align_up(off + h.crt_afr.size());
     }
     const size_t o_probs = off;
     off = align_up(off + sizeof(ProbDev) * count);
@@ -1316,10 +1325,13 @@ int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2
         }
     // CRT classes: (digit chunk, entries per thread, digit columns in LDS or global
     // memory), the same shapes a plain call would take (crt_config)
+    // (digit chunk -1: the matrix-core CRT, under the rule a plain call applies)
     std::map<std::tuple<int, int, int>, std::vector<int>> classes;
     for (int b = 0; b < count; ++b) {
-        const CrtCfg cc = crt_config(bp->hosts[b], probs[b].M, probs[b].N, true);
-        classes[std::make_tuple(bp->hosts[b].crt_dc, cc.ept, (int)cc.gdig)].push_back(b);
+        const PlanHost &h = bp->hosts[b];
+        const CrtCfg cc = crt_config(h, probs[b].M, probs[b].N, true);
+        if (crt_mma_eligible(h, cc)) classes[std::make_tuple(-1, 1, 0)].push_back(b);
+        else classes[std::make_tuple(h.crt_dc, cc.ept, (int)cc.gdig)].push_back(b);
     }
     std::vector<std::vector<Seg>> crt_segs;
     for (auto &kv : classes) {
@@ -1332,9 +1344,12 @@ int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2
             maxnd = std::max(maxnd, bp->hosts[b].nd32);
             maxL = std::max(maxL, bp->hosts[b].L);
         }
+        c.mma = c.dc < 0;
         c.bd = 256;
         size_t cols = 0;
-        if (!c.gdig) {
+        if (c.mma) {
+            cols = (size_t)256 * maxnd * 4;   // 256 entries per block, one column each
+        } else if (!c.gdig) {
             while (c.bd > 64 && (size_t)maxnd * c.bd * c.ept * 4 > 49152) c.bd /= 2;
             cols = (((size_t)maxnd * c.bd * c.ept + 3) & ~(size_t)3) * 4;
         }
@@ -1388,6 +1403,13 @@ int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2
         P.crt = (const double *)(db + o_crt[b]);
         P.pd = (const uint32_t *)(db + o_pd[b]);
         P.phd = (const uint32_t *)(db + o_phd[b]);
+        P.crt_afr = (const int8_t *)(db + o_cafr[b]);
+        P.crt_nbk = h.crt_nbk;
+        P.crt_kq = h.crt_kq;
+        P.crt_nt = h.crt_nt;
+        P.crt_inv_ptop = h.crt_inv_ptop;
+        if (!h.crt_afr.empty())
+            OZ2H_HIP(hipMemcpy(db + o_cafr[b], h.crt_afr.data(), h.crt_afr.size(), hipMemcpyHostToDevice));
         OZ2H_HIP(hipMemcpy(db + o_info[b], h.info.data(), sizeof(ModInfo) * h.L, hipMemcpyHostToDevice));
         OZ2H_HIP(hipMemcpy(db + o_res[b], h.resid_tab.data(), sizeof(double) * h.resid_tab.size(), hipMemcpyHostToDevice));
         OZ2H_HIP(hipMemcpy(db + o_rg[b], h.resgrp.data(), sizeof(ResGroup) * h.resgrp.size(), hipMemcpyHostToDevice));

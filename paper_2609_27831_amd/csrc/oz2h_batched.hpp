@@ -32,6 +32,9 @@ struct ProbDev {
     int32_t *cexp;
     int8_t *csign;
     int64_t ldc;
+    const int8_t *crt_afr;   // matrix-core CRT tables (plan fields of the same names)
+    int32_t crt_nbk, crt_kq, crt_nt;
+    double crt_inv_ptop;
 };
 
 struct Seg {
@@ -146,6 +149,23 @@ __global__ __launch_bounds__(256) void k_crt_grouped(const ProbDev *__restrict__
                     2 * P.t, P.p, P.csign, P.cexp, P.climbs, P.ldc, nullptr, 0, LB,
                     GDIG ? (uint32_t *)(ws + P.dig_off) : nullptr, P.dig_stride};
     crt_block<DC, EPT, true, false, GDIG>(a, (int64_t)blockIdx.x - sg.first, sdig);
+}
+
+// stages 4-5, grouped, on the matrix cores (products whose plan has the tables)
+template <int KQ>
+__global__ __launch_bounds__(256) void k_crt_mma_grouped(const ProbDev *__restrict__ probs,
+                                                         const Seg *__restrict__ segs, int nseg,
+                                                         char *ws) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t sdig[];
+    const int si = find_seg(segs, nseg, blockIdx.x);
+    const Seg sg = segs[si];
+    const ProbDev &P = probs[sg.prod];
+    const CrtArgs a{(const int16_t *)(ws + P.v_off), P.rpad[0] * P.rpad[1], P.rpad[1], P.rows[0],
+                    P.rows[1], P.mi, P.L, P.crt, P.crt_ndpad, P.crt_nc, P.nd32, P.pd, P.phd,
+                    (const int32_t *)(ws + P.erow_off[0]), (const int32_t *)(ws + P.erow_off[1]),
+                    2 * P.t, P.p, P.csign, P.cexp, P.climbs, P.ldc, nullptr, 0, 0, nullptr, 0,
+                    P.crt_afr, P.crt_nbk, P.crt_kq, P.crt_nt, P.crt_inv_ptop};
+    crt_mma_block<KQ, true>(a, (int64_t)blockIdx.x - sg.first, sdig);
 }
 
 }  // namespace oz2h

@@ -1130,13 +1130,12 @@ constexpr int kCrtMmaMaxQ = 8;   // contraction steps of the matrix-core CRT (2 
 constexpr int kCrtMmaMinDigits = 16;
 
 template <int KQ, bool ROUND>
-__global__ __launch_bounds__(256) void k_crt_mma(CrtArgs a) {
-    extern __shared__ __attribute__((aligned(16))) uint32_t sdig[];
+__device__ __forceinline__ void crt_mma_block(const CrtArgs &a, int64_t blk, uint32_t *sdig) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int h = lane >> 5, c = lane & 31;
     const int nd32 = a.nd32, L = a.L, kq = a.kq, nbk = a.nbk;
     const int64_t N = a.N, MN = a.M * N, v_ps = a.v_ps;
-    const int64_t e0 = (int64_t)blockIdx.x * 256 + wv * 64;
+    const int64_t e0 = blk * 256 + wv * 64;
     typedef const __attribute__((address_space(1))) uint16_t gu16;
     typedef const __attribute__((address_space(1))) v4i gv4i;
     typedef const __attribute__((address_space(4))) uint32_t cu32;
@@ -1236,6 +1235,12 @@ __global__ __launch_bounds__(256) void k_crt_mma(CrtArgs a) {
     }
     const int64_t e = e0 + lane;
     if (e < MN) crt_finish<ROUND>(a, e, col, 256, slow, cy + carry);
+}
+
+template <int KQ, bool ROUND>
+__global__ __launch_bounds__(256) void k_crt_mma(CrtArgs a) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t sdig[];
+    crt_mma_block<KQ, ROUND>(a, blockIdx.x, sdig);
 }
 
 // planes [G][R][C] (int8, row stride ldi) -> [G][Co][Ro] (row stride Ro), zero where
