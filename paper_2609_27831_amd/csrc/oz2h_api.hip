@@ -167,10 +167,10 @@ int launch_exponents(int64_t rows, int64_t count, const int8_t *sign, const int3
     k_fill_i32<<<nb, 256, 0, s>>>(out, rows, INT_MIN);
     if (count > 0) {
         if (cs == 1) {
-            dim3 grid((unsigned)((rows + 3) / 4), (unsigned)((count + 4095) / 4096));
+            dim3 grid((unsigned)((rows + 3) / 4), (unsigned)((count + kExpChunk - 1) / kExpChunk));
             k_exp_kcontig<<<grid, 256, 0, s>>>(sign, exp, rows, count, rs, koff, out);
         } else {
-            dim3 grid(nb, (unsigned)((count + 63) / 64));
+            dim3 grid(nb, (unsigned)((count + kExpRowsK - 1) / kExpRowsK));
             k_exp_generic<<<grid, 256, 0, s>>>(sign, exp, rows, count, rs, cs, koff, out);
         }
     }

@@ -27,13 +27,16 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 
 // ---------------------------------------------------------------- stage 1
 
+constexpr int kExpChunk = 1024;   // contraction entries per wave (contiguous rows)
+constexpr int kExpRowsK = 16;     // contraction entries per thread (other layouts)
+
 __global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
 }
 
 // rows whose entries are contiguous along the contraction (cs == 1): one wave
-// per (row, 4096-entry chunk), lanes stride 1, partial maxima combined by atomicMax
+// per (row, kExpChunk-entry chunk), lanes stride 1, partial maxima combined by atomicMax
 // koff (nullable): a per-contraction-index exponent offset added before the max
 // (the exponent folding of the backward products)
 __global__ __launch_bounds__(256) void k_exp_kcontig(const int8_t *__restrict__ sign,
@@ -44,8 +47,8 @@ __global__ __launch_bounds__(256) void k_exp_kcontig(const int8_t *__restrict__ 
     const int lane = threadIdx.x & 63;
     const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (r >= rows) return;
-    const int64_t k0 = (int64_t)blockIdx.y * 4096;
-    const int64_t k1 = min(count, k0 + 4096);
+    const int64_t k0 = (int64_t)blockIdx.y * kExpChunk;
+    const int64_t k1 = min(count, k0 + kExpChunk);
     int m = INT_MIN;
     for (int64_t k = k0 + lane; k < k1; k += 64) {
         const int64_t idx = r * rs + k;
@@ -55,7 +58,8 @@ __global__ __launch_bounds__(256) void k_exp_kcontig(const int8_t *__restrict__ 
     if (lane == 0 && m != INT_MIN) atomicMax(out + r, m);
 }
 
-// any other layout: one thread per row, 64 entries of the contraction per block row
+// any other layout: one thread per row, kExpRowsK entries of the contraction per block
+// row (loads unrolled, so that they are all in flight at once)
 __global__ __launch_bounds__(256) void k_exp_generic(const int8_t *__restrict__ sign,
                                                      const int32_t *__restrict__ exps,
                                                      int64_t rows, int64_t count, int64_t rs,
@@ -63,12 +67,15 @@ __global__ __launch_bounds__(256) void k_exp_generic(const int8_t *__restrict__ 
                                                      int32_t *__restrict__ out) {
     const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (r >= rows) return;
-    const int64_t k0 = (int64_t)blockIdx.y * 64;
-    const int64_t k1 = min(count, k0 + 64);
+    const int64_t k0 = (int64_t)blockIdx.y * kExpRowsK;
     int m = INT_MIN;
-    for (int64_t k = k0; k < k1; ++k) {
-        const int64_t idx = r * rs + k * cs;
-        if (sign[idx]) m = max(m, exps[idx] + (koff ? koff[k] : 0));
+#pragma unroll
+    for (int u = 0; u < kExpRowsK; ++u) {
+        const int64_t k = k0 + u;
+        if (k < count) {
+            const int64_t idx = r * rs + k * cs;
+            if (sign[idx]) m = max(m, exps[idx] + (koff ? koff[k] : 0));
+        }
     }
     if (m != INT_MIN) atomicMax(out + r, m);
 }
