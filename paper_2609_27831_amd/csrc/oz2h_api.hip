@@ -190,7 +190,8 @@ int launch_residues(const oz2h_plan *pl, int64_t rows, int64_t count, const uint
         // matrix-core residues: waves of 64 entries, as many per block as fit 64 KiB
         const size_t wl = (size_t)res_mma_wave_lds(h.rnq);
         const int rbm = 4 * wl <= 65536 ? 4 : (2 * wl <= 65536 ? 2 : 1);
-        dim3 grid((unsigned)(kpad / 64), (unsigned)(rpad / rbm));
+        const int kw = res_waves_k(rbm);
+        dim3 grid((unsigned)(kpad / (64 * kw)), (unsigned)(rpad / (rbm / kw)));
         const ResMmaArgs a{limbs, exp, sign, rs, cs, rows, count, kpad, ps, erow, koff,
                            h.p, nl, t, h.nw32, h.rnq, h.rnrb, res_mma_es(h.rnq),
                            pl->d_rmma_w, pl->d_rmma_rb, planes};
@@ -210,7 +211,8 @@ int launch_residues(const oz2h_plan *pl, int64_t rows, int64_t count, const uint
         return check_launch("residues");
     }
     int rb = h.nw32 <= 64 ? 4 : (h.nw32 <= 128 ? 2 : 1);   // word columns <= 64 KiB per block
-    dim3 grid((unsigned)(kpad / 64), (unsigned)(rpad / rb));
+    const int kw = res_waves_k(rb);
+    dim3 grid((unsigned)(kpad / (64 * kw)), (unsigned)(rpad / (rb / kw)));
     const size_t lds = (size_t)h.nw32 * 64 * rb * sizeof(uint32_t);
     const ResArgs a{limbs, exp, sign, rs, cs, rows, count, kpad, ps, erow, h.p, nl, t, h.nw32,
                     pl->d_resid, pl->d_rgrp, h.L, h.lgroups, planes, koff};
@@ -1319,7 +1321,8 @@ int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2
             const int64_t nbe = P.cs[sd] == 1 ? (P.rows[sd] + 3) / 4 : (P.rows[sd] + 255) / 256;
             exp_segs.push_back(Seg{bp->exp_blocks, b, sd, nbe});
             bp->exp_blocks += nbe;
-            const int64_t nbx = P.kpad / 64, nby = P.rpad[sd] / bp->res_rb;
+            const int kw = res_waves_k(bp->res_rb);
+            const int64_t nbx = P.kpad / (64 * kw), nby = P.rpad[sd] / (bp->res_rb / kw);
             res_segs.push_back(Seg{bp->res_blocks, b, sd, nbx});
             bp->res_blocks += nbx * nby;
         }

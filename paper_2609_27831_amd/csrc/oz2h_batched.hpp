@@ -99,7 +99,8 @@ __device__ __forceinline__ ResArgs res_args(const ProbDev &P, int side, char *ws
                    P.rgrp, P.L, P.lgroups, (int8_t *)(ws + P.planes_off[side]), nullptr};
 }
 
-// stage 2, grouped: segment (prod, side) is a (kpad/64) x (rpad/RB) grid of blocks
+// stage 2, grouped: segment (prod, side) is a (kpad / (64 KW)) x (rpad / (RB / KW)) grid of
+// blocks, KW = res_waves_k(RB)
 template <int RB>
 __global__ __launch_bounds__(64 * RB) void k_residues_grouped(const ProbDev *__restrict__ probs,
                                                               const Seg *__restrict__ segs,

@@ -92,6 +92,7 @@ __global__ void k_exp_fix(int32_t *__restrict__ p, int64_t n) {
 // the casts let the compiler use global and scalar loads)
 #define OZ2H_G(T) const __attribute__((address_space(1))) T
 typedef __attribute__((address_space(1))) int8_t g_i8;
+typedef __attribute__((address_space(1))) uint32_t g_u32;
 
 // a ModInfo record read through a global-memory pointer (field by field: the
 // implicit copy constructor does not bind to an address-space-qualified object)
@@ -188,6 +189,47 @@ struct ResArgs {
     const int32_t *koff;   // nullable per-contraction exponent offsets (exponent folding)
 };
 
+// a wave-uniform plane pointer held in scalar registers, so that a store through it with a
+// 32-bit lane offset takes the scalar-base form
+__device__ __forceinline__ g_i8 *uniform_ptr(g_i8 *p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (g_i8 *)(((uint64_t)hi << 32) | lo);
+}
+
+// Low bytes of four ints in one dword, byte i from b[i].
+__device__ __forceinline__ uint32_t pack_bytes(int b0, int b1, int b2, int b3) {
+    const uint32_t lo = __builtin_amdgcn_perm((uint32_t)b1, (uint32_t)b0, 0x0c0c0400u);
+    const uint32_t hi = __builtin_amdgcn_perm((uint32_t)b3, (uint32_t)b2, 0x0c0c0400u);
+    return __builtin_amdgcn_perm(hi, lo, 0x05040100u);
+}
+
+// 4 x 4 byte transpose within each quad of lanes: lane 4 a + q enters holding byte i of
+// row q and leaves holding byte q of rows 0..3 (byte j from row j).  Two exchanges (with
+// lane ^ 2, then lane ^ 1) of DPP quad permutes, each followed by a byte select whose
+// selector depends on the lane's place in the quad (v_perm_b32: selector values 0-3 take
+// the bytes of the second operand, 4-7 those of the first).
+struct QuadSel {
+    uint32_t a, b;
+};
+__device__ __forceinline__ QuadSel quad_sel(int lane) {
+    const int q = lane & 3;
+    return QuadSel{q < 2 ? 0x05040100u : 0x03020706u, (q & 1) ? 0x03070105u : 0x06020400u};
+}
+__device__ __forceinline__ uint32_t quad_transpose_bytes(uint32_t w, QuadSel sel) {
+    const uint32_t p2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)w, 0x4E, 0xF, 0xF, false);
+    w = __builtin_amdgcn_perm(p2, w, sel.a);
+    const uint32_t p1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)w, 0xB1, 0xF, 0xF, false);
+    return __builtin_amdgcn_perm(p1, w, sel.b);
+}
+
+// Waves of a residue block along k: two when the block has at least two, so that a block
+// covers 128 consecutive entries of RB / 2 rows.  Blocks are dealt to the XCDs round-robin,
+// so with one wave per row the two 64-byte halves of a plane line would be written from two
+// different L2s.  Grids: (kpad / (64 KW)) x (rpad / (RB / KW)) blocks.
+__host__ __device__ constexpr int res_waves_k(int rb) { return rb >= 2 ? 2 : 1; }
+
 // The pointers are passed as __restrict__ parameters (kept as scoped no-alias
 // information when inlined), so the compiler knows that the plane stores do
 // not clobber the constant tables and reads those with scalar loads.
@@ -201,8 +243,11 @@ __device__ __forceinline__ void residue_block_r(
     int nw32, int L, int lgroups, int64_t bx, int64_t by, uint32_t *words) {
     constexpr int BD = 64 * RB;
     const int tid = threadIdx.x;
-    const int64_t k = bx * 64 + (tid & 63);
-    const int64_t r = by * RB + (tid >> 6);
+    // KW waves of a block side by side along k (res_waves_k): the block writes whole
+    // 128-byte lines of each plane row, so both halves of a line meet in one L2
+    constexpr int KW = res_waves_k(RB);
+    const int64_t k = (bx * KW + (tid >> 6) % KW) * 64 + (tid & 63);
+    const int64_t r = by * (RB / KW) + (tid >> 6) / KW;
 
     OZ2H_G(int8_t) *gsigns = (OZ2H_G(int8_t) *)signs;
     OZ2H_G(int32_t) *gexps = (OZ2H_G(int32_t) *)exps;
@@ -226,6 +271,10 @@ __device__ __forceinline__ void residue_block_r(
     // per-plane base (uniform) + a 32-bit lane offset: scalar-base stores, no
     // per-lane 64-bit address arithmetic
     const uint32_t loff = (uint32_t)(r * kpad + k);
+    // packed stores: lane 4 a + q writes entries 4 a .. 4 a + 3 of plane q of four
+    const int lane = tid & 63;
+    const QuadSel qsel = quad_sel(lane);
+    const int64_t qoff = (int64_t)(lane & 3) * plane_stride + (int64_t)(loff & ~3u);
     const double sgn = s < 0 ? -1.0 : 1.0;
     for (int grp = 0; grp < lgroups; ++grp) {
         double acc[KG];
@@ -239,6 +288,38 @@ __device__ __forceinline__ void residue_block_r(
         }
         OZ2H_G(ResGroup) *R = grec + grp;
         const uint32_t two = R->two;
+        // a full group of one kind owns consecutive planes from that of its first modulus:
+        // dword stores after a quad byte transpose, four planes per store
+        if ((grp + 1) * KG <= L && (two == 0u || two == (1u << KG) - 1u)) {
+            const uint32_t gb = R->g0[0];
+            int ri[KG];
+#pragma unroll
+            for (int g = 0; g < KG; ++g) {
+                const double a = acc[g] * sgn;
+                ri[g] = (int)fma(-rint(a * R->inv_m[g]), R->md[g], a);
+            }
+            auto store4 = [&](uint32_t gp, int b0, int b1, int b2, int b3) {
+                g_i8 *pb = uniform_ptr((g_i8 *)planes + (int64_t)gp * plane_stride);
+                *(g_u32 *)(pb + qoff) = quad_transpose_bytes(pack_bytes(b0, b1, b2, b3), qsel);
+            };
+            if (two == 0u) {
+#pragma unroll
+                for (int g = 0; g < KG; g += 4) store4(gb + g, ri[g], ri[g + 1], ri[g + 2], ri[g + 3]);
+            } else {
+                int pl[3 * KG];   // (r0, r1, r0 + r1) of each modulus, in plane order
+#pragma unroll
+                for (int g = 0; g < KG; ++g) {
+                    const int r0 = ((ri[g] + 64) & 127) - 64;   // balanced base-128 split
+                    const int r1 = (ri[g] - r0) >> 7;
+                    pl[3 * g] = r0;
+                    pl[3 * g + 1] = r1;
+                    pl[3 * g + 2] = r0 + r1;
+                }
+#pragma unroll
+                for (int j = 0; j < 3 * KG; j += 4) store4(gb + j, pl[j], pl[j + 1], pl[j + 2], pl[j + 3]);
+            }
+            continue;
+        }
 #pragma unroll
         for (int g = 0; g < KG; ++g) {
             if (grp * KG + g >= L) break;
@@ -302,6 +383,10 @@ struct ResMmaArgs {
     int8_t *planes;
 };
 
+static_assert(offsetof(ResRowBlock, md) == 256 && offsetof(ResRowBlock, g0) == 512 &&
+                  offsetof(ResRowBlock, n1) == 640 && offsetof(ResRowBlock, p0) == 644 &&
+                  offsetof(ResRowBlock, n2) == 648,
+              "byte offsets the MFMA residue kernel reads the row block record at");
 constexpr int kResScratchRow = 144;   // bytes per entry in the sums scratch (32 rows + 16)
 constexpr int kResMmaMaxQ = 16;       // k-steps of the widest integer (t < 3400 bits: 14)
 constexpr int kResMmaPfQ = 8;         // up to this many k-steps the next weights are prefetched
@@ -318,15 +403,6 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// a wave-uniform plane pointer held in scalar registers, so that a store through it with a
-// 32-bit lane offset takes the scalar-base form
-__device__ __forceinline__ g_i8 *uniform_ptr(g_i8 *p) {
-    const uint64_t v = (uint64_t)p;
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return (g_i8 *)(((uint64_t)hi << 32) | lo);
 }
 
 // At most NQ k-steps: entry and weight fragments live in registers (up to kResMmaPfQ
@@ -346,8 +422,9 @@ __device__ __forceinline__ void residue_block_mma_r(
     const int es = res_mma_es(nq);
     uint32_t *ent = smem + (size_t)wv * (res_mma_wave_lds(nq) / 4);
     uint8_t *scr = (uint8_t *)ent;
-    const int64_t k = bx * 64 + lane;
-    const int64_t r = by * RB + wv;
+    constexpr int KW = res_waves_k(RB);   // waves side by side along k, as in residue_block_r
+    const int64_t k = (bx * KW + wv % KW) * 64 + lane;
+    const int64_t r = by * (RB / KW) + wv / KW;
 
     typedef const __attribute__((address_space(1))) v4i gv4i;
     gv4i *wf = (gv4i *)wfrag + lane;
@@ -391,6 +468,10 @@ __device__ __forceinline__ void residue_block_mma_r(
             bf1[q] = b1p[2 * q];
         }
     const uint32_t loff = (uint32_t)(r * kpad + k);
+    // stores: after a quad byte transpose, lane 4 a + q writes entries 4 a .. 4 a + 3 of
+    // plane q of a group of four (a dword at the quad's first entry)
+    const QuadSel qsel = quad_sel(lane);
+    const int64_t qoff = (int64_t)(lane & 3) * plane_stride + (int64_t)(loff & ~3u);
     const uint32_t *xrow = (const uint32_t *)(scr + lane * kResScratchRow);
     for (int rb = 0; rb < nrb; ++rb) {
         wave_lds_sync();   // entry bytes read; the previous block's sums read
@@ -424,47 +505,97 @@ __device__ __forceinline__ void residue_block_mma_r(
         wave_lds_sync();   // sums written
         // lane k reduces its own entry: four rows per 16-byte read (two-limb pairs start
         // on a multiple of 4), the modulus data of four rows per scalar load, every row of
-        // the four computed (rows past the moduli hold zeros) and only the stores guarded
-        crb_t *B = grb + rb;
-        const int n1 = (int)B->n1, p0 = (int)B->p0, n2 = (int)B->n2;
+        // the four computed (rows past the moduli hold zeros).  The sums and modulus data of
+        // the next four rows load while four rows are reduced (scheduling fences keep those
+        // loads behind the first use of the current ones, whose wait covers every scalar and
+        // LDS load in flight); reads up to row 35 stay inside the block record and the
+        // scratch row.  Only the last group of a kind guards its stores.
         typedef double d4 __attribute__((ext_vector_type(4)));
         typedef const __attribute__((address_space(4))) d4 cd4;
-        for (int i4 = 0; i4 < n1; i4 += 4) {
-            const v4i x4 = *(const v4i *)(xrow + i4);
-            const d4 im = *(cd4 *)(B->inv_m + i4), mm = *(cd4 *)(B->md + i4);
-            // one-limb moduli of consecutive rows own consecutive planes
-            g_i8 *pb = (g_i8 *)planes + (int64_t)B->g0[i4] * plane_stride;
-            int ri[4];
+        typedef const __attribute__((address_space(4))) char cch;
+        typedef const __attribute__((address_space(4))) uint32_t cu32;
+        cch *B = (cch *)(grb + rb);
+        const int n1 = (int)((cu32 *)(B + 640))[0], p0 = (int)((cu32 *)(B + 640))[1],
+                  n2 = (int)((cu32 *)(B + 640))[2];
+        // row data of rows i .. i + 3: fl(1/m) at byte 8 i, m at 256 + 8 i
+        v4i xn;
+        d4 imn, mmn;
+        auto fetch = [&](uint32_t i) {
+            xn = *(const v4i *)(xrow + i);
+            imn = *(cd4 *)(B + 8u * i);
+            mmn = *(cd4 *)(B + (256u + 8u * i));
+        };
+        // first planes (byte 512 + 4 i): the one-limb rows of a block own consecutive planes
+        // from that of row 0, and its two-limb pairs consecutive triples from that of row p0
+        const uint32_t g1 = *(cu32 *)(B + 512);
+        int i4 = 0;
+        fetch(0);
+        auto group1 = [&](auto full_) {   // one-limb rows i4 .. i4 + 3
+            constexpr bool FULL = decltype(full_)::value;
+            const d4 mm = mmn;
+            double x[4], q[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const double x = (double)x4[e];
-                ri[e] = (int)fma(-rint(x * im[e]), mm[e], x);
+                x[e] = (double)xn[e];
+                q[e] = rint(x[e] * imn[e]);
             }
+            __builtin_amdgcn_sched_barrier(0);
+            fetch(i4 + 4);
+            __builtin_amdgcn_sched_barrier(0);
+            g_i8 *pb = uniform_ptr((g_i8 *)planes + (int64_t)(g1 + i4) * plane_stride);
+            int ri[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                if (i4 + e < n1) uniform_ptr(pb + e * plane_stride)[loff] = (int8_t)ri[e];
-        }
-        for (int j2 = 0; j2 < n2; j2 += 2) {
-            const int i4 = p0 + 2 * j2;
-            const v4i x4 = *(const v4i *)(xrow + i4);
-            const d4 im = *(cd4 *)(B->inv_m + i4), mm = *(cd4 *)(B->md + i4);
-            // consecutive two-limb moduli own consecutive triples of planes
-            g_i8 *pb = (g_i8 *)planes + (int64_t)B->g0[i4] * plane_stride;
-            int r0[2], r1[2];
+            for (int e = 0; e < 4; ++e) ri[e] = (int)fma(-q[e], mm[e], x[e]);
+            const uint32_t w = quad_transpose_bytes(pack_bytes(ri[0], ri[1], ri[2], ri[3]), qsel);
+            if (FULL || (lane & 3) < n1 - i4) *(g_u32 *)(pb + qoff) = w;
+        };
+        for (; i4 + 4 <= n1; i4 += 4) group1(std::true_type{});
+        if (i4 < n1) group1(std::false_type{});
+        if (n2 > 0) {
+            const uint32_t g2 = *(cu32 *)(B + (512u + 4u * (uint32_t)p0));
+            // only the first row of a pair holds modulus data: load those two of four rows
+            // (loading all four would leave half of the destination registers dead, free for
+            // reuse while the load is still in flight)
+            typedef const __attribute__((address_space(4))) double cdbl;
+            double im0, im2, mm0, mm2;
+            auto fetch2 = [&](uint32_t i) {
+                xn = *(const v4i *)(xrow + i);
+                im0 = *(cdbl *)(B + 8u * i);
+                im2 = *(cdbl *)(B + (16u + 8u * i));
+                mm0 = *(cdbl *)(B + (256u + 8u * i));
+                mm2 = *(cdbl *)(B + (272u + 8u * i));
+            };
+            int j2 = 0;
+            fetch2((uint32_t)p0);
+            auto group2 = [&](auto full_) {   // two-limb pairs j2, j2 + 1 (rows p0 + 2 j2 ..)
+                constexpr bool FULL = decltype(full_)::value;
+                const uint32_t i4 = (uint32_t)(p0 + 2 * j2);
+                const double mm[2] = {mm0, mm2};
+                double x[2], q[2];
 #pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                const double x = (double)(x4[2 * e] + 128 * x4[2 * e + 1]);
-                const int ri = (int)fma(-rint(x * im[2 * e]), mm[2 * e], x);
-                r0[e] = ((ri + 64) & 127) - 64;   // balanced base-128 split
-                r1[e] = (ri - r0[e]) >> 7;
-            }
+                for (int e = 0; e < 2; ++e) x[e] = (double)(xn[2 * e] + 128 * xn[2 * e + 1]);
+                q[0] = rint(x[0] * im0);
+                q[1] = rint(x[1] * im2);
+                __builtin_amdgcn_sched_barrier(0);
+                fetch2(i4 + 4);
+                __builtin_amdgcn_sched_barrier(0);
+                g_i8 *pb = uniform_ptr((g_i8 *)planes + (int64_t)(g2 + 3u * (uint32_t)j2) * plane_stride);
+                int r0[2], r1[2];
 #pragma unroll
-            for (int e = 0; e < 2; ++e)
-                if (j2 + e < n2) {
-                    uniform_ptr(pb + (3 * e) * plane_stride)[loff] = (int8_t)r0[e];
-                    uniform_ptr(pb + (3 * e + 1) * plane_stride)[loff] = (int8_t)r1[e];
-                    uniform_ptr(pb + (3 * e + 2) * plane_stride)[loff] = (int8_t)(r0[e] + r1[e]);
+                for (int e = 0; e < 2; ++e) {
+                    const int ri = (int)fma(-q[e], mm[e], x[e]);
+                    r0[e] = ((ri + 64) & 127) - 64;   // balanced base-128 split
+                    r1[e] = (ri - r0[e]) >> 7;
                 }
+                // planes 0-5 of the two pairs: (r0, r1, r0 + r1) of the first, then the second
+                const uint32_t wa = quad_transpose_bytes(pack_bytes(r0[0], r1[0], r0[0] + r1[0], r0[1]), qsel);
+                const uint32_t wb = quad_transpose_bytes(pack_bytes(r1[1], r0[1] + r1[1], 0, 0), qsel);
+                const int nv = FULL ? 6 : 3 * (n2 - j2);   // planes to write
+                if ((lane & 3) < nv) *(g_u32 *)(pb + qoff) = wa;
+                if ((lane & 3) + 4 < nv) *(g_u32 *)(pb + 4 * plane_stride + qoff) = wb;
+            };
+            for (; j2 + 2 <= n2; j2 += 2) group2(std::true_type{});
+            if (j2 < n2) group2(std::false_type{});
         }
         if constexpr (PF) {
 #pragma unroll
