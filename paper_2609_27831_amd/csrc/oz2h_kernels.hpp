@@ -1139,9 +1139,9 @@ __device__ __forceinline__ void crt_block(const CrtArgs &a, int64_t blk, uint32_
 #pragma unroll
                 for (int q = 0; q < EPT; ++q) ring[f][q] = vp[q][(int64_t)(l0 + min(f, nlb - 1)) * v_ps];
             // one modulus: its v values (one per entry of the thread) into the digit sums
-            auto modulus = [&](int ll, const int *cur) {
+            auto inv_of = [&](int ll) { return GDIG ? sinv[ll] : cmi[l0 + ll].inv_m; };
+            auto modulus = [&](int ll, const int *cur, double inv_m) {
                 const int l = l0 + ll;
-                const double inv_m = GDIG ? sinv[ll] : cmi[l].inv_m;
                 double vd[EPT];
 #pragma unroll
                 for (int q = 0; q < EPT; ++q) {
@@ -1175,11 +1175,13 @@ __device__ __forceinline__ void crt_block(const CrtArgs &a, int64_t blk, uint32_
                     }
                 }
             };
-            // full groups of PF moduli: straight-line code, so that the loads of a modulus
-            // can be issued while the previous one multiplies (measured faster from 16
-            // digits per pass on; narrower passes keep one guarded loop); the v ring runs
-            // PF moduli ahead
-            const int nfull = DC >= 16 ? nlb - nlb % PF : 0;
+            // full groups of PF moduli: straight-line code, so that the scalar constants of a
+            // modulus can load while the previous one multiplies (measured faster from 16
+            // digits per pass on with LDS columns; narrower passes and global columns, whose
+            // constants come from the LDS slice, keep one guarded loop, which measured 2x
+            // faster there at 4096^3 and p = 2048); the v ring runs PF moduli ahead
+            constexpr bool SL = DC >= 16 && !GDIG;
+            const int nfull = SL ? nlb - nlb % PF : 0;
             for (int lb = 0; lb < nfull; lb += PF) {
 #pragma unroll
                 for (int f = 0; f < PF; ++f) {
@@ -1190,15 +1192,15 @@ __device__ __forceinline__ void crt_block(const CrtArgs &a, int64_t blk, uint32_
                         cur[q] = ring[f][q];
                         ring[f][q] = vp[q][(int64_t)(l0 + min(ll + PF, nlb - 1)) * v_ps];
                     }
-                    modulus(ll, cur);
+                    modulus(ll, cur, inv_of(ll));
                 }
             }
-            if constexpr (DC >= 16) {
+            if constexpr (SL) {
                 for (int ll = nfull; ll < nlb; ++ll) {   // the last nlb % PF moduli
                     int cur[EPT];
 #pragma unroll
                     for (int q = 0; q < EPT; ++q) cur[q] = vp[q][(int64_t)(l0 + ll) * v_ps];
-                    modulus(ll, cur);
+                    modulus(ll, cur, inv_of(ll));
                 }
             } else {
                 for (int lb = 0; lb < nlb; lb += PF) {
@@ -1206,13 +1208,16 @@ __device__ __forceinline__ void crt_block(const CrtArgs &a, int64_t blk, uint32_
                     for (int f = 0; f < PF; ++f) {
                         const int ll = lb + f;
                         if (ll >= nlb) break;
+                        // 1/m is read before the next v load is issued: with global columns
+                        // (1/m from LDS) the other order measured 1.4x slower at p = 2048
+                        const double inv_m = inv_of(ll);
                         int cur[EPT];
 #pragma unroll
                         for (int q = 0; q < EPT; ++q) {
                             cur[q] = ring[f][q];
                             ring[f][q] = vp[q][(int64_t)(l0 + min(ll + PF, nlb - 1)) * v_ps];
                         }
-                        modulus(ll, cur);
+                        modulus(ll, cur, inv_m);
                     }
                 }
             }
