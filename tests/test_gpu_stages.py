@@ -157,6 +157,40 @@ def test_residue_gemm_mod_m(oz, mpad, npad, kpad, tile):
         assert np.array_equal(np.mod(v[li], m), np.mod(np.mod(prod, m) * minv, m)), f"modulus {m}"
 
 
+def test_residue_gemm_high_address(oz):
+    """Stage 3 writing v at a device address whose low 32-bit word has bit 31 set (a base
+    address composed from two 32-bit halves must not sign-extend the low one): same v as a
+    plain allocation, and correct mod m."""
+    import torch
+    plan = oz.Plan.create(256, 320)
+    G, L = plan.G, plan.L
+    mpad = npad = kpad = 128
+    rng = np.random.default_rng(11)
+    A = rng.integers(-60, 61, (G, mpad, kpad)).astype(np.int8)
+    B = rng.integers(-60, 61, (G, npad, kpad)).astype(np.int8)
+    Ad, Bd = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    ref = oz.residue_gemm(plan, Ad, Bd).cpu().numpy()
+    nbytes = L * mpad * npad * 2
+    buf = torch.empty(2 ** 31 + nbytes + 512, dtype=torch.uint8, device="cuda")
+    base = buf.data_ptr()
+    x = base if base & 0x80000000 else (base & ~0xFFFFFFFF) + 0x80000000
+    x = (x + 255) & ~255
+    assert x & 0x80000000 and base <= x and x + nbytes <= base + buf.numel()
+    print("residue gemm at high address", hex(x), flush=True)
+    oz._check(oz.lib().oz2h_residue_gemm(plan.handle, mpad, npad, kpad, Ad.data_ptr(),
+                                         Bd.data_ptr(), x, oz._stream_ptr(None)))
+    got = buf[x - base:x - base + nbytes].cpu().numpy().view(np.int16).reshape(L, mpad, npad)
+    assert np.array_equal(got, ref)
+    P = 1
+    for m in plan.moduli.tolist():
+        P *= m
+    m = int(plan.moduli[0])   # a one-limb modulus: plane 0
+    prod = A[0].astype(np.int64) @ B[0].astype(np.int64).T
+    minv = pow((P // m) % m, -1, m)
+    assert np.array_equal(np.mod(got[0].astype(np.int64), m), np.mod(np.mod(prod, m) * minv, m))
+    del buf
+
+
 def test_crt_worked_example(oz):
     """The tutorial's worked example: moduli 5, 7, 9 and residues (0, 3, 1) give 10."""
     import torch
