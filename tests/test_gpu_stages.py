@@ -75,19 +75,36 @@ def rng_idx(r, c, frac, seed=0):
                                           (113, -64, 64, "A"), (1024, -300, 300, "B")])
 def test_residue_planes(oz, c_oracle, p, lo, hi, side):
     """Stage 2 vs Python-int centred residues of the oracle's integers a^."""
-    import torch
     R, C = (70, 150) if side == "A" else (150, 70)
     X = synth.mp_random(11 + p, R, C, p, lo, hi)
     X.sign[rng_idx(R, C, 0.05, p)] = 0
     K = C if side == "A" else R
-    plan = oz.Plan.create(p, K)
+    check_residue_planes(oz, c_oracle, oz.Plan.create(p, K), X, side, K, f"p={p} side={side}")
+
+
+def test_residue_planes_wide_set_narrow_integers(oz, c_oracle):
+    """The fp64 residue kernel with groups of 16 moduli: integers below 8 words (p = 113)
+    against a 100-modulus prefix of the global list (54 one-limb, 46 two-limb), so that
+    full one-limb groups, a mixed group, full two-limb groups and a partial group occur."""
+    p, side, R, C = 113, "A", 70, 150
+    mods = oz.Plan.create(1024, C).moduli.tolist()[:100]
+    base = oz.Plan.create(p, C)
+    plan = oz.Plan.custom(p, base.t, C, mods)
+    assert plan.L == 100 and plan.L1 == 54 and plan.nw32 < 8   # the fp64 kernel, 16 per group
+    X = synth.mp_random(23, R, C, p, -20, 20)
+    X.sign[rng_idx(R, C, 0.05, 23)] = 0
+    check_residue_planes(oz, c_oracle, plan, X, side, C, "wide set, p=113")
+
+
+def check_residue_planes(oz, c_oracle, plan, X, side, K, label):
+    import torch
     t = plan.t
     e, sg, mag = c_oracle.integerize(X, t, side)
     rows = e.size
     Xd = dev_mp(X)
     erow = torch.from_numpy(e).cuda()
     rpad, kpad = 128, 256
-    print(f"residues p={p} side={side}", flush=True)
+    print(f"residues {label}", flush=True)
     planes = oz.residues(plan, Xd, erow, side, rpad, kpad).cpu().numpy()
     assert planes.shape == (plan.G, rpad, kpad)
     # padding is zero
