@@ -3,11 +3,21 @@
 
 One step = one full pass of the hot path (shared exponents, residues, INT8
 MFMA residue GEMMs with the fused reduction, direct CRT + lift + rounding)
-over one synthetic input already resident in HBM.  The default workload is
-the plain square product M = N = K = 2048 at p = 256 bits with exponents
-uniform in [-32, 32].  Prints ONE JSON line (rank 0, N = 1 GPU).
+over one synthetic input already resident in HBM.
 
-  python bench.py [--steps K] [--warmup W] [--config cfg2] [--cpu-seconds S]
+The default line headlines the high-precision workload, M = N = K = 4096 at
+p = 2048 bits (exponents uniform in [-16, 16]), and carries as extra keys:
+  - the large-GEMM workload, M = N = K = 8192 at p = 113 bits;
+  - the matrix-core variants of stages 2 and 4 timed beside the default
+    MFMA-free kernels (same inputs, bit-identical outputs);
+  - the batched form (64 uneven products, one graph) against the loop of plain
+    calls ("speedup_vs_loop"), and the autograd form's residue reuse against
+    recomputation ("reuse_vs_recompute");
+  - the oracle on the host cores over a bounded block of outputs, which also
+    checks the timed GPU output on that block bit for bit.
+
+  python bench.py [--steps K] [--warmup W] [--config cfg3|cfg1|cfg2|cfg3a|cfg3b|cfg4|cfg5]
+                  [--cpu-seconds S] [--no-cpu-baseline] [--no-extras]
 
 Per-stage times come from HIP events that the library records on the launch
 stream between stages (oz2h_gemm_timed); the end-to-end time is wall clock
@@ -20,6 +30,7 @@ import ctypes
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -43,6 +54,7 @@ PEAK_HBM_GBS = 8000.0        # HBM3E, GB/s
 PEAK_FP64_TFLOPS = 78.6      # FP64 vector, TFLOP/s (FMA = 2 flops)
 
 CSRC = os.path.join(ROOT, "paper_2609_27831_amd", "csrc")
+PHASES = ["exponents", "residues", "gemm", "crt"]
 
 
 class Hip:
@@ -85,7 +97,8 @@ def source_digest() -> str:
 
 
 def measured_traffic(kernel: str, config: str):
-    """HBM bytes per launch from a committed rocprofv3 PMC summary, if it matches these sources."""
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel of known
+    size) from a committed rocprofv3 PMC summary, if it was taken from these sources."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{config}.json")
     if not os.path.exists(path):
         return None
@@ -96,34 +109,169 @@ def measured_traffic(kernel: str, config: str):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(A, B, seconds: float):
-    """The oracle on the host cores over a bounded sample: the first r rows of C."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def device_operands(cfg, seed):
+    """The workload's A and B drawn straight into device memory (same counters and
+    values as synth.operands_for)."""
+    import torch
+
+    from paper_2609_27831_amd import oz2h
+    from synth.gen_torch import operands_for_torch
+    _, M, N, K, p, elo, ehi, _ = cfg
+    (sa, ea, la), (sb, eb, lb) = operands_for_torch(seed, M, N, K, p, elo, ehi, device="cuda")
+    torch.cuda.synchronize()
+    return oz2h.DeviceMP(sa, ea, la, p), oz2h.DeviceMP(sb, eb, lb, p)
+
+
+def kernel_names(plan, flags):
+    """The stage-2 / stage-4 kernels a plain call of this plan launches."""
+    from paper_2609_27831_amd import oz2h
+    res = "k_residues_mma" if (flags & oz2h.FLAG_RESIDUES_MMA) and plan.nw32 >= 8 else "k_residues"
+    crt_mma = (flags & oz2h.FLAG_CRT_MMA) and 16 <= plan.nd32 <= 32 and plan.L <= 127
+    return res, "k_crt_mma" if crt_mma else "k_crt"
+
+
+def time_plain(name, Ad, Bd, steps, warmup, flags=0):
+    """Time `steps` plain products; per-stage event times and derived rates."""
+    import numpy as np
+    import torch
+
+    from paper_2609_27831_amd import oz2h
+    workload, M, N, K, p, elo, ehi, _ = CONFIGS[name]
+    plan = oz2h.Plan.create(p, K, oz2h.default_opts(flags=flags))
+    ws = oz2h.workspace(plan, M, N)
+    out = oz2h.empty_mp(M, N, p)
+    hip = Hip()
+    stream = torch.cuda.current_stream()
+    evs = [hip.events(5) for _ in range(steps)]
+    wev = hip.events(5)
+    for _ in range(warmup):
+        oz2h.gemm_timed(plan, Ad, Bd, out, ws, wev, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        oz2h.gemm_timed(plan, Ad, Bd, out, ws, evs[s], stream=stream)
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / steps
+    phase_ms = {n: float(np.mean([hip.elapsed_ms(e[k], e[k + 1]) for e in evs]))
+                for k, n in enumerate(PHASES)}
+    for e in evs + [wev]:
+        hip.destroy(e)
+    del ws
+
+    flops = 2.0 * M * N * K
+    nl = (p + 63) // 64
+    L, G, nd32, nw32 = plan.L, plan.G, plan.nd32, plan.nw32
+    res_k, crt_k = kernel_names(plan, flags)
+    # algorithmic work per stage (per launch = per step)
+    res_bytes = (M * K + K * N) * (8 * nl + 5) + (M * K + K * N) * G
+    res_fma = (M * K + K * N) * L * nw32          # word x weight multiply-adds
+    gemm_ops = G * 2.0 * M * N * K
+    gemm_bytes = G * (M * K + K * N) + L * M * N * 2
+    crt_bytes = L * M * N * 2 + M * N * (8 * nl + 5)
+    crt_fma = M * N * L * nd32                     # weight x digit multiply-adds
+    phases = {n: {"ms": round(phase_ms[n], 4),
+                  "effective_gflops": round(flops / (phase_ms[n] * 1e-3) / 1e9, 2)}
+              for n in PHASES}
+    sec = {n: phase_ms[n] * 1e-3 for n in PHASES}
+    gemm_tops = gemm_ops / sec["gemm"] / 1e12
+    phases["residues"].update({
+        "kernel": res_k, "hbm_gbs": round(res_bytes / sec["residues"] / 1e9, 1),
+        "fp64_tflops": round(2.0 * res_fma / sec["residues"] / 1e12, 2) if res_k == "k_residues" else None,
+        "counter_hbm_gbs": None})
+    phases["gemm"].update({"kernel": "k_resgemm", "int8_tops": round(gemm_tops, 1),
+                           "int8_mfma_pct_of_peak": round(100.0 * gemm_tops / PEAK_INT8_TOPS, 2)})
+    phases["crt"].update({
+        "kernel": crt_k, "hbm_gbs": round(crt_bytes / sec["crt"] / 1e9, 1),
+        "fp64_tflops": round(2.0 * crt_fma / sec["crt"] / 1e12, 2) if crt_k == "k_crt" else None,
+        "counter_hbm_gbs": None})
+    for ph, kern in (("residues", res_k), ("crt", crt_k)):
+        tb = measured_traffic(kern, name)
+        if tb:
+            phases[ph]["counter_hbm_gbs"] = round(tb / sec[ph] / 1e9, 1)
+
+    def roof(ph):
+        if ph == "gemm":
+            r = {"kernel": "k_resgemm", "bound": "mfma", "achieved": round(gemm_tops, 2),
+                 "peak": PEAK_INT8_TOPS, "unit": "TOP/s", "frac": round(gemm_tops / PEAK_INT8_TOPS, 4),
+                 "algorithmic_bytes": gemm_bytes}
+            kern = "k_resgemm"
+        else:
+            kern = phases[ph]["kernel"]
+            fma = res_fma if ph == "residues" else crt_fma
+            a = 2.0 * fma / sec[ph] / 1e12
+            r = {"kernel": kern, "bound": "alu", "achieved": round(a, 3), "peak": PEAK_FP64_TFLOPS,
+                 "unit": "TFLOP/s", "frac": round(a / PEAK_FP64_TFLOPS, 4),
+                 "algorithmic_bytes": res_bytes if ph == "residues" else crt_bytes}
+            if kern.endswith("_mma"):   # a matrix-core variant: no fp64 work to rate
+                r = {"kernel": kern, "bound": "alu", "achieved": None, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": None}
+        r["traffic"] = measured_traffic(kern, name)
+        return r
+
+    dominant = max(("residues", "gemm", "crt"), key=lambda n: phase_ms[n])
+    res = {
+        "workload": workload, "M": M, "N": N, "K": K, "p": p, "t": plan.t, "moduli": L,
+        "int8_gemms": G, "exponent_range": [elo, ehi], "flags": flags,
+        "ms_per_step": round(ms_per_step, 4),
+        "value": round(flops / (ms_per_step * 1e-3) / 1e9, 3),
+        "int8_mfma_pct_of_peak": round(100.0 * gemm_tops / PEAK_INT8_TOPS, 2),
+        "phases": phases, "roofline": roof(dominant),
+        "rooflines": {ph: roof(ph) for ph in ("residues", "gemm", "crt")},
+    }
+    return res, out
+
+
+def cpu_baseline_and_check(name, out, seconds: float):
+    """The oracle on the host cores over a bounded block of C (rows 0..r-1, columns
+    0..c-1, drawn from the generator's counters) and a bit-for-bit check of the GPU's
+    timed output on that block."""
     import numpy as np
 
+    import synth
     from oracle import c_oracle
-    M, K = A.sign.shape
-    N = B.sign.shape[1]
+    _, M, N, K, p, elo, ehi, soff = CONFIGS[name]
+    seed = synth.CONFIG_SEED_BASE + soff
 
-    def run(r):
-        si = np.repeat(np.arange(r, dtype=np.int64), N)
-        sj = np.tile(np.arange(N, dtype=np.int64), r)
+    def run(r, c):
+        A, B = synth.operand_blocks_for(seed, M, N, K, p, elo, ehi, range(0, r), range(0, c))
         t0 = time.perf_counter()
-        c_oracle.gemm(A, B, sel=(si, sj), want_chat=False)
-        return time.perf_counter() - t0
+        ref = c_oracle.gemm(A, B, want_chat=False)
+        return time.perf_counter() - t0, ref
 
-    r = 1
-    t = run(r)
-    while t < seconds / 8 and r < M:
-        r = min(M, r * 4)
-        t = run(r)
-    if t < seconds / 2 and r < M:
-        r = min(M, max(r + 1, int(r * seconds / max(t, 1e-3))))
-        t = run(r)
-    return {"value": round(2.0 * r * N * K / t / 1e9, 4), "unit": "GFlop/s",
+    r = c = 1
+    t, ref = run(r, c)
+    while t < seconds / 8 and (r < M or c < N):
+        r, c = min(M, r * 2), min(N, c * 2)
+        t, ref = run(r, c)
+    if t < seconds / 2:
+        f = (seconds / max(t, 1e-3)) ** 0.5
+        r, c = min(M, max(r + 1, int(r * f))), min(N, max(c + 1, int(c * f)))
+        t, ref = run(r, c)
+    gs = out.sign[:r, :c].cpu().numpy()
+    ge = out.exp[:r, :c].cpu().numpy()
+    gl = out.limbs[:r, :c].cpu().numpy().view(np.uint64)
+    same = (np.array_equal(gs, ref["c_sign"]) and np.array_equal(ge, ref["c_exp"])
+            and np.array_equal(gl, ref["c_limbs"]))
+    ent = r * c
+    base = {"value": round(2.0 * ent * K / t / 1e9, 4), "unit": "GFlop/s",
             "cores": c_oracle.num_threads(), "kind": "oracle",
-            "sample": f"rows 0..{r - 1} of C ({r}x{N} entries, K={K}); exact bignum c^ plus "
-                      f"nearest-even rounding, including the integerization of those rows "
-                      f"and of every column of B; {t:.1f} s"}
+            "sample": f"block C[0:{r}, 0:{c}] ({ent} entries, K={K}): exact bignum c^ of the "
+                      f"shared-exponent integers plus one nearest-even rounding, including the "
+                      f"integerization of those rows of A and columns of B; {t:.1f} s; the rate "
+                      f"extrapolates to the whole product (full-matrix time = {t * M * N / ent:.0f} s)",
+            "extrapolated": True, "host_cpu": cpu_model(), "nproc": os.cpu_count()}
+    return base, {"entries": ent, "bit_identical": bool(same)}
 
 
 def batched_problems(seed: int, count: int = 64, lo: int = 128, hi: int = 4096,
@@ -142,27 +290,25 @@ def batched_problems(seed: int, count: int = 64, lo: int = 128, hi: int = 4096,
     return out
 
 
-def bench_batched(args):
+def measure_batched(steps, warmup):
     """Batched form: 64 products in one graph vs the same products as a loop of plain calls."""
-    import numpy as np
     import torch
 
     import synth
     from paper_2609_27831_amd import oz2h
-    torch.cuda.set_device(0)
+    from synth.gen_torch import operands_for_torch
     spec = batched_problems(synth.CONFIG_SEED_BASE + 4)
     probs, plans = [], []
     flops = 0.0
     for (M, N, K, p, sd) in spec:
-        A, B = synth.operands_for(sd, M, N, K, p, -4, 4)
-        probs.append((oz2h.to_device(A), oz2h.to_device(B), oz2h.empty_mp(M, N, p), 0, 0))
+        (sa, ea, la), (sb, eb, lb) = operands_for_torch(sd, M, N, K, p, -4, 4, device="cuda")
+        probs.append((oz2h.DeviceMP(sa, ea, la, p), oz2h.DeviceMP(sb, eb, lb, p),
+                      oz2h.empty_mp(M, N, p), 0, 0))
         flops += 2.0 * M * N * K
-    hip = Hip()
     stream = torch.cuda.current_stream()
-    ev = hip.events(2)
 
     def timed(fn, reps):
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -171,7 +317,6 @@ def bench_batched(args):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / reps
 
-    # loop of plain per-product calls (one plan per product, one shared workspace)
     for (Ad, Bd, C, _, _) in probs:
         plans.append(oz2h.Plan.create(Ad.p, Ad.shape[1]))
     wsz = max(pl.workspace_size(Ad.shape[0], Bd.shape[1]) for pl, (Ad, Bd, _, _, _) in zip(plans, probs))
@@ -180,31 +325,26 @@ def bench_batched(args):
     def loop():
         for pl, (Ad, Bd, C, _, _) in zip(plans, probs):
             oz2h.gemm(pl, Ad, Bd, out=C, ws=ws1, stream=stream)
-    ms_loop = timed(loop, args.steps)
+    ms_loop = timed(loop, steps)
     ref = [tuple(x.clone() for x in (C.sign, C.exp, C.limbs)) for (_, _, C, _, _) in probs]
     del ws1
-
     bp = oz2h.BatchedPlan(probs)
     ws = bp.workspace()
     cfg = bp.tune(ws)
-    ms_eager = timed(lambda: bp.run_eager(ws, stream=stream), args.steps)
-    ms_graph = timed(lambda: bp.run(ws, stream=stream), args.steps)
+    ms_eager = timed(lambda: bp.run_eager(ws, stream=stream), steps)
+    ms_graph = timed(lambda: bp.run(ws, stream=stream), steps)
     same = all(torch.equal(a, C.sign) and torch.equal(b, C.exp) and torch.equal(c, C.limbs)
                for (a, b, c), (_, _, C, _, _) in zip(ref, probs))
-    line = {
-        "metric": "batched effective p-bit GFlop/s (sum 2MNK / s)", "unit": "GFlop/s",
-        "value": round(flops / (ms_graph * 1e-3) / 1e9, 3), "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_graph, 4), "higher_is_better": True,
-        "dtype": "i8", "data": "synthetic",
-        "config": {"workload": "64 products, M, N, K log-uniform in [128, 4096], p in {53, 113, 256, 512}, exponents U[-4,4]",
-                   "products": len(spec), "sum_2MNK": flops, "tuned": cfg},
-        "graph_ms": round(ms_graph, 4), "eager_ms": round(ms_eager, 4), "loop_of_plain_calls_ms": round(ms_loop, 4),
-        "speedup_vs_loop": round(ms_loop / ms_graph, 3), "bit_identical_to_loop": bool(same),
-    }
-    print(json.dumps(line), flush=True)
+    bp.destroy()
+    return {"workload": "64 products, M, N, K log-uniform in [128, 4096], p in {53, 113, 256, 512}, "
+                        "exponents U[-4,4]",
+            "sum_2MNK": flops, "tuned": cfg, "graph_ms": round(ms_graph, 4),
+            "eager_ms": round(ms_eager, 4), "loop_of_plain_calls_ms": round(ms_loop, 4),
+            "value": round(flops / (ms_graph * 1e-3) / 1e9, 3),
+            "speedup_vs_loop": round(ms_loop / ms_graph, 3), "bit_identical_to_loop": bool(same)}
 
 
-def bench_autograd(args):
+def measure_autograd(steps, warmup):
     """Autograd form: forward C = A B plus both backward products (dA = W B^T, dB = A^T W)
     at 4096^2, p = 256, through torch.autograd (float64 carriers), reuse vs recompute."""
     import torch
@@ -212,7 +352,6 @@ def bench_autograd(args):
     import synth
     from paper_2609_27831_amd import autograd as ag
     from paper_2609_27831_amd import oz2h
-    torch.cuda.set_device(0)
     M = N = K = 4096
     p = 256
     A, B, W = synth.grad_operands_for(synth.CONFIG_SEED_BASE + 5, M, N, K, p, -4, 4)
@@ -226,42 +365,35 @@ def bench_autograd(args):
             c = ag.oz_matmul(a, b, p, mode=mode)
             c.backward(w)
             return a.grad, b.grad
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             step()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
-            ga, gb = step()
+        for _ in range(steps):
+            step()
         torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / args.steps
-        out[mode] = ms
-    # the backward entry point alone, from a saved forward (no carrier conversions)
+        out[mode] = (time.perf_counter() - t0) * 1e3 / steps
     plan = oz2h.Plan.create_grad(p, M, N, K)
     Ad, Bd, Wd = oz2h.to_device(A), oz2h.to_device(B), oz2h.to_device(W)
     ws = oz2h.workspace(plan, M, N)
     bws = torch.empty(plan.backward_workspace_size(), dtype=torch.uint8, device="cuda")
     dA, dB = oz2h.empty_mp(M, K, p), oz2h.empty_mp(K, N, p)
     oz2h.gemm(plan, Ad, Bd, ws=ws)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         oz2h.gemm_backward(plan, ws, Wd, dA=dA, dB=dB, ws=bws)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         oz2h.gemm_backward(plan, ws, Wd, dA=dA, dB=dB, ws=bws)
     torch.cuda.synchronize()
-    ms_bwd = (time.perf_counter() - t0) * 1e3 / args.steps
-    line = {
-        "metric": "autograd effective p-bit GFlop/s (forward + both backward products, 3 x 2MNK / s)",
-        "unit": "GFlop/s", "value": round(flops / (out["reuse"] * 1e-3) / 1e9, 3), "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(out["reuse"], 4),
-        "higher_is_better": True, "dtype": "i8", "data": "synthetic",
-        "config": {"workload": "C = A B and its backward, M=N=K=4096, p=256, A and B exponents "
-                               "U[-4,4], upstream gradient +-u 2^-p", "mode": "reuse"},
-        "recompute_ms_per_step": round(out["recompute"], 4),
-        "backward_entry_point_ms": round(ms_bwd, 4),
-        "backward_effective_gflops": round(2 * 2.0 * M * N * K / (ms_bwd * 1e-3) / 1e9, 3),
-    }
-    print(json.dumps(line), flush=True)
+    ms_bwd = (time.perf_counter() - t0) * 1e3 / steps
+    return {"workload": "C = A B and its backward, M=N=K=4096, p=256, A and B exponents U[-4,4], "
+                        "upstream gradient +-u 2^-p",
+            "reuse_ms_per_step": round(out["reuse"], 4),
+            "recompute_ms_per_step": round(out["recompute"], 4),
+            "reuse_vs_recompute": round(out["recompute"] / out["reuse"], 3),
+            "value": round(flops / (out["reuse"] * 1e-3) / 1e9, 3),
+            "backward_entry_point_ms": round(ms_bwd, 4)}
 
 
 def copy_calibration():
@@ -276,121 +408,98 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_per_launch": n, "launches": 3}), flush=True)
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="cfg2", choices=sorted(CONFIGS) + ["cfg4", "cfg5"])
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="cfg3",
+                    choices=sorted(CONFIGS) + ["cfg3", "cfg4", "cfg5"])
+    ap.add_argument("--flags", type=int, default=0,
+                    help="OZ2H_FLAG_* bits of the timed plain products (default 0: MFMA-free "
+                         "stages 2 and 4)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline workload (no variant, batched or autograd keys)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device to device three times (the reference "
                          "kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one MI355X only; --gpus N > 1 is not supported "
-              "(the multi-GPU sharding is a design, see the design notes)", file=sys.stderr)
+              "(the multi-GPU sharding is a design only)", file=sys.stderr)
         sys.exit(2)
-
     if args.copy_calibration:
         return copy_calibration()
-    if args.config == "cfg4":
-        return bench_batched(args)
-    if args.config == "cfg5":
-        return bench_autograd(args)
 
-    import numpy as np
     import torch
 
     import synth
-    from paper_2609_27831_amd import oz2h
-
-    workload, M, N, K, p, elo, ehi, soff = CONFIGS[args.config]
     torch.cuda.set_device(0)
-    A, B = synth.operands_for(synth.CONFIG_SEED_BASE + soff, M, N, K, p, elo, ehi)
-    Ad, Bd = oz2h.to_device(A), oz2h.to_device(B)
-    plan = oz2h.Plan.create(p, K)
-    ws = oz2h.workspace(plan, M, N)
-    out = oz2h.empty_mp(M, N, p)
-    hip = Hip()
-    stream = torch.cuda.current_stream()
-    evs = [hip.events(5) for _ in range(args.steps)]
-    wev = hip.events(5)
+    base = {"metric": METRIC, "unit": "GFlop/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "i8", "data": "synthetic"}
 
-    for _ in range(args.warmup):
-        oz2h.gemm_timed(plan, Ad, Bd, out, ws, wev, stream=stream)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        oz2h.gemm_timed(plan, Ad, Bd, out, ws, evs[s], stream=stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    if args.config in ("cfg4", "cfg5"):
+        log(f"{args.config}")
+        r = (measure_batched if args.config == "cfg4" else measure_autograd)(args.steps, args.warmup)
+        line = dict(base, value=r.pop("value"),
+                    ms_per_step=r.get("graph_ms", r.get("reuse_ms_per_step")),
+                    config={"workload": r.pop("workload")}, **r)
+        print(json.dumps(line), flush=True)
+        return
 
-    names = ["exponents", "residues", "gemm", "crt"]
-    phase_ms = {n: float(np.mean([hip.elapsed_ms(e[k], e[k + 1]) for e in evs]))
-                for k, n in enumerate(names)}
-    for e in evs + [wev]:
-        hip.destroy(e)
-
-    flops = 2.0 * M * N * K
-    nl = (p + 63) // 64
-    L, G, nd32 = plan.L, plan.G, plan.nd32
-    gemm_ops = G * 2.0 * M * N * K
-    gemm_tops = gemm_ops / (phase_ms["gemm"] * 1e-3) / 1e12
-    res_bytes = (M * K + K * N) * (8 * nl + 5 + 4) + (M * K + K * N) * G
-    crt_bytes = L * M * N * 2 + M * N * (8 * nl + 5)
-    crt_flops = 2.0 * M * N * L * (nd32 + 1)
-    res_flops = 2.0 * (M * K + K * N) * L * plan.nw32
-    phases = {
-        n: {"ms": round(phase_ms[n], 4),
-            "effective_gflops": round(flops / (phase_ms[n] * 1e-3) / 1e9, 2)} for n in names}
-    # residues and CRT: the rate of the fp64 multiply-adds of the plain formulation (nw32
-    # words x L moduli per operand element; L x (nd32 + 1) digits per output entry), which
-    # the matrix-core kernels replace where they apply: an equivalent rate, not fp64 work done
-    phases["residues"]["hbm_gbs"] = round(res_bytes / (phase_ms["residues"] * 1e-3) / 1e9, 1)
-    phases["residues"]["fp64_equiv_tflops"] = round(res_flops / (phase_ms["residues"] * 1e-3) / 1e12, 2)
-    phases["gemm"]["int8_tops"] = round(gemm_tops, 1)
-    phases["crt"]["hbm_gbs"] = round(crt_bytes / (phase_ms["crt"] * 1e-3) / 1e9, 1)
-    phases["crt"]["fp64_equiv_tflops"] = round(crt_flops / (phase_ms["crt"] * 1e-3) / 1e12, 2)
-
-    dominant = max(("residues", "gemm", "crt"), key=lambda n: phase_ms[n])
-    if dominant == "gemm":
-        roof = {"kernel": "k_resgemm", "bound": "mfma", "achieved": round(gemm_tops, 2),
-                "peak": PEAK_INT8_TOPS, "unit": "TFLOP/s",
-                "frac": round(gemm_tops / PEAK_INT8_TOPS, 4)}
-    elif dominant == "crt":
-        a = crt_flops / (phase_ms["crt"] * 1e-3) / 1e12
-        roof = {"kernel": "k_crt", "bound": "alu", "achieved": round(a, 3),
-                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(a / PEAK_FP64_TFLOPS, 4)}
-    else:
-        a = res_flops / (phase_ms["residues"] * 1e-3) / 1e12
-        roof = {"kernel": "k_residues", "bound": "alu", "achieved": round(a, 3),
-                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(a / PEAK_FP64_TFLOPS, 4)}
-    roof["traffic"] = measured_traffic(roof["kernel"], args.config)
-
-    line = {
-        "metric": METRIC,
-        "value": round(flops / (ms_per_step * 1e-3) / 1e9, 3),
-        "unit": "GFlop/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "i8",
-        "data": "synthetic",
-        "config": {"workload": workload, "M": M, "N": N, "K": K, "p": p, "t": plan.t,
-                   "moduli": L, "int8_gemms": G, "exponent_range": [elo, ehi]},
-        "int8_mfma_pct_of_peak": round(100.0 * gemm_tops / PEAK_INT8_TOPS, 2),
-        "phases": phases,
-        "roofline": roof,
-    }
+    head = "cfg3a" if args.config == "cfg3" else args.config
+    cfg = CONFIGS[head]
+    log(f"{head}: drawing inputs on the GPU")
+    Ad, Bd = device_operands(cfg, synth.CONFIG_SEED_BASE + cfg[7])
+    log(f"{head}: timing")
+    r, out = time_plain(head, Ad, Bd, args.steps, args.warmup, args.flags)
+    line = dict(base, value=r["value"], ms_per_step=r["ms_per_step"],
+                config={"workload": r["workload"], "M": r["M"], "N": r["N"], "K": r["K"],
+                        "p": r["p"], "t": r["t"], "moduli": r["moduli"], "int8_gemms": r["int8_gemms"],
+                        "exponent_range": r["exponent_range"], "flags": r["flags"]},
+                int8_mfma_pct_of_peak=r["int8_mfma_pct_of_peak"], phases=r["phases"],
+                roofline=r["roofline"], rooflines=r["rooflines"])
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(A, B, args.cpu_seconds)
+        log(f"{head}: oracle on the host cores")
+        cb, chk = cpu_baseline_and_check(head, out, args.cpu_seconds)
+        line["cpu_baseline"] = cb
+        line["output_check_vs_oracle"] = chk
+    del out
+    if not args.no_extras:
+        variants = {}
+        log(f"{head}: matrix-core variants of stages 2 and 4")
+        rv, _ = time_plain(head, Ad, Bd, max(2, args.steps // 2), 1, args.flags ^ 3)
+        variants[head] = {"flags": rv["flags"], "ms_per_step": rv["ms_per_step"],
+                          "residues": {k: rv["phases"]["residues"][k] for k in ("ms", "kernel")},
+                          "crt": {k: rv["phases"]["crt"][k] for k in ("ms", "kernel")}}
+        del Ad, Bd
+        torch.cuda.empty_cache()
+        if args.config == "cfg3":
+            log("cfg3b: drawing inputs on the GPU")
+            c3b = CONFIGS["cfg3b"]
+            Ad, Bd = device_operands(c3b, synth.CONFIG_SEED_BASE + c3b[7])
+            log("cfg3b: timing")
+            rb, outb = time_plain("cfg3b", Ad, Bd, args.steps, args.warmup, args.flags)
+            del outb
+            rb.pop("rooflines")
+            line["cfg3b"] = rb
+            del Ad, Bd
+            torch.cuda.empty_cache()
+        line["stage_variants"] = variants
+        log("cfg4: batched form vs loop of plain calls")
+        line["batched"] = measure_batched(max(2, args.steps // 2), 1)
+        line["speedup_vs_loop"] = line["batched"]["speedup_vs_loop"]
+        torch.cuda.empty_cache()
+        log("cfg5: autograd reuse vs recompute")
+        line["autograd"] = measure_autograd(max(2, args.steps // 2), 1)
+        line["reuse_vs_recompute"] = line["autograd"]["reuse_vs_recompute"]
     print(json.dumps(line), flush=True)
 
 

@@ -76,8 +76,27 @@ typedef struct {
     int32_t crt_margin;  /* moduli satisfy log2 P > 2t + ceil(log2 K) + margin; the
                             paper's implementation uses 2 (after Eq. crtcond)        */
     int32_t tile;        /* oz2h_tile of the residue GEMMs; default OZ2H_TILE_AUTO    */
-    uint32_t flags;      /* reserved, must be 0                                      */
+    uint32_t flags;      /* OZ2H_FLAG_* bits below; default 0                        */
 } oz2h_opts;
+
+/*
+ * Option flags.  By default stage 2 (residues) and stage 4 (direct CRT) run as
+ * MFMA-free multi-limb integer kernels on the vector ALUs: exact fp64
+ * multiply-adds of 32-bit words against 2^(32 w) mod m (residues), and of the
+ * moduli weights v_l against balanced base-2^32 digits of P/m_l (CRT); only the
+ * residue GEMMs use the INT8 matrix cores.  The two flags select, per plan, the
+ * compared variants that cast these stages as INT8 contractions on the matrix
+ * cores as well (the paper's "Faster residue conversion" direction):
+ *   OZ2H_FLAG_RESIDUES_MMA  residues as (bytes of a^) x (256^j mod m) INT8
+ *                           products; taken for integers of 8 or more 32-bit
+ *                           words (t >= 224), the VALU kernel below that;
+ *   OZ2H_FLAG_CRT_MMA       CRT digit sums as (bytes of v_l) x (bytes of P/m_l)
+ *                           INT8 products; taken when the CRT has 16..32 digits
+ *                           and L <= 127, the VALU kernel otherwise.
+ * Both variants give bit-identical results.  Any other bit is rejected.
+ */
+#define OZ2H_FLAG_RESIDUES_MMA 0x1u
+#define OZ2H_FLAG_CRT_MMA 0x2u
 
 /* Input matrix (device pointers). */
 typedef struct {
@@ -113,7 +132,8 @@ typedef struct {
     int64_t grad_M, grad_N; /* and the forward's M and N (0 otherwise)              */
 } oz2h_plan_info;
 
-/* Default options: guard_bits 16, t_bits 0, crt_margin 2, tile AUTO, flags 0. */
+/* Default options: guard_bits 16, t_bits 0, crt_margin 2, tile AUTO, flags 0
+   (MFMA-free residue and CRT stages). */
 void oz2h_opts_default(oz2h_opts *o);
 
 /* Message for the last failed call on this thread ("" if none). */
@@ -145,11 +165,20 @@ int oz2h_plan_create(int32_t p, int64_t K, const oz2h_opts *o, oz2h_plan **out);
  * pairwise-coprime moduli 2 <= m <= 16191 (e.g. the worked example's 5, 7, 9).
  * Moduli <= 255 are one-limb, larger ones two-limb; they are reordered so that
  * the one-limb moduli come first (oz2h_plan_get_moduli returns that order).
- * K is the contraction length the plan accepts.  No CRT-bound check is made:
- * the caller guarantees |c^| < P/2.
+ * K is the contraction length the plan accepts.  The moduli must satisfy
+ * Eq. crtcond with the least margin, P > 2^(2t + ceil(log2 K) + 1), so that
+ * every |c^| <= K 2^(2t) is below P/2; otherwise OZ2H_ERANGE.  Options are the
+ * defaults (flags 0); see oz2h_plan_set_flags.
  */
 int oz2h_plan_create_custom(int32_t p, int32_t t, int64_t K, int32_t L, const uint16_t *moduli,
                             oz2h_plan **out);
+
+/*
+ * Replace the OZ2H_FLAG_* bits of a plan (the stage-2 / stage-4 kernel variants;
+ * results are identical).  Host only; must not race with calls that launch with
+ * the plan.  OZ2H_EINVAL for unknown bits.
+ */
+int oz2h_plan_set_flags(oz2h_plan *plan, uint32_t flags);
 
 void oz2h_plan_destroy(oz2h_plan *plan);
 int oz2h_plan_get_info(const oz2h_plan *plan, oz2h_plan_info *info);
@@ -309,10 +338,14 @@ int oz2h_i8gemm(int64_t M, int64_t N, int64_t K, const int8_t *A, const int8_t *
                 int32_t tile, hipStream_t stream);
 
 /*
- * Stage 4, direct CRT + symmetric lift from plain residues: from
- * u_l = c^ mod m_l (int16, any representative with |u_l| < m_l, plane l at
- * u[l*plane_stride + i*ldu + j]) reconstructs c^ with |c^| < P/2 as
- * chat_sign[i*N + j] and nlc magnitude limbs chat_mag[(i*N + j)*nlc + l].
+ * Stage 4, direct CRT + symmetric lift from plain residues ("Direct CRT without
+ * multiple-precision division"): from u_l = c^ mod m_l (int16, any
+ * representative with |u_l| < m_l, plane l at u[l*plane_stride + i*ldu + j])
+ * reconstructs c^ with |c^| < P/2 as chat_sign[i*N + j] and nlc magnitude limbs
+ * chat_mag[(i*N + j)*nlc + l].  The kernel is the plan's stage-4 variant (the
+ * matrix-core one under OZ2H_FLAG_CRT_MMA where it applies).  Every c^ in
+ * (-P/2, P/2) is reconstructed, those next to +-P/2 through the paper's
+ * alpha - 1 sequence; for even P the class of P/2 comes back as +P/2.
  */
 int oz2h_crt(const oz2h_plan *plan, int64_t M, int64_t N, const int16_t *u, int64_t ldu,
              int64_t plane_stride, int8_t *chat_sign, uint64_t *chat_mag, int32_t nlc,

@@ -91,6 +91,13 @@ int check_device(int *dev_out) {
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+constexpr uint32_t kAllFlags = OZ2H_FLAG_RESIDUES_MMA | OZ2H_FLAG_CRT_MMA;
+
+int check_flags(uint32_t flags) {
+    if (flags & ~kAllFlags) return fail(OZ2H_EINVAL, "unknown option flags 0x%x", flags & ~kAllFlags);
+    return OZ2H_OK;
+}
+
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -186,12 +193,14 @@ int launch_residues(const oz2h_plan *pl, int64_t rows, int64_t count, const uint
     if (t < 0) t = h.t;
     const int nl = (h.p + 63) / 64;
     const int64_t ps = rpad * kpad;
-    if (h.nw32 >= kResMmaMinWords) {
+    if ((h.flags & OZ2H_FLAG_RESIDUES_MMA) && h.nw32 >= kResMmaMinWords) {
         // matrix-core residues: waves of 64 entries, as many per block as fit 64 KiB
         const size_t wl = (size_t)res_mma_wave_lds(h.rnq);
         const int rbm = 4 * wl <= 65536 ? 4 : (2 * wl <= 65536 ? 2 : 1);
         const int kw = res_waves_k(rbm);
-        dim3 grid((unsigned)(kpad / (64 * kw)), (unsigned)(rpad / (rbm / kw)));
+        const int64_t nblk = (kpad / (64 * kw)) * (rpad / (rbm / kw));
+        if (nblk > INT32_MAX) return fail(OZ2H_ERANGE, "residues: operand too large for one launch");
+        const dim3 grid((unsigned)nblk);
         const ResMmaArgs a{limbs, exp, sign, rs, cs, rows, count, kpad, ps, erow, koff,
                            h.p, nl, t, h.nw32, h.rnq, h.rnrb, res_mma_es(h.rnq),
                            pl->d_rmma_w, pl->d_rmma_rb, planes};
@@ -212,7 +221,9 @@ int launch_residues(const oz2h_plan *pl, int64_t rows, int64_t count, const uint
     }
     int rb = h.nw32 <= 64 ? 4 : (h.nw32 <= 128 ? 2 : 1);   // word columns <= 64 KiB per block
     const int kw = res_waves_k(rb);
-    dim3 grid((unsigned)(kpad / (64 * kw)), (unsigned)(rpad / (rb / kw)));
+    const int64_t nblk = (kpad / (64 * kw)) * (rpad / (rb / kw));
+    if (nblk > INT32_MAX) return fail(OZ2H_ERANGE, "residues: operand too large for one launch");
+    const dim3 grid((unsigned)nblk);
     const size_t lds = (size_t)h.nw32 * 64 * rb * sizeof(uint32_t);
     const ResArgs a{limbs, exp, sign, rs, cs, rows, count, kpad, ps, erow, h.p, nl, t, h.nw32,
                     pl->d_resid, pl->d_rgrp, h.L, h.lgroups, planes, koff};
@@ -295,9 +306,11 @@ CrtCfg crt_config(const PlanHost &h, int64_t M, int64_t N, bool allow_gdig) {
     return c;
 }
 
-// the matrix-core CRT: digit columns in LDS, tables built, enough digits to pay off
+// the matrix-core CRT (compared variant): selected by the plan's flags, digit columns in
+// LDS, tables built, enough digits to pay off
 bool crt_mma_eligible(const PlanHost &h, const CrtCfg &c) {
-    return !c.gdig && h.crt_mma && h.crt_kq <= kCrtMmaMaxQ && h.nd32 >= kCrtMmaMinDigits;
+    return (h.flags & OZ2H_FLAG_CRT_MMA) && !c.gdig && h.crt_mma && h.crt_kq <= kCrtMmaMaxQ &&
+           h.nd32 >= kCrtMmaMinDigits;
 }
 
 size_t crt_gdig_bytes(const PlanHost &h, int64_t M, int64_t N) {
@@ -321,12 +334,13 @@ int launch_crt(const oz2h_plan *pl, int64_t M, int64_t N, const int16_t *u, int6
                      pl->d_pd, pl->d_phd, e, f, tsum, h.p, osign, oexp, olimbs, ldc, chat, nlc, c.LB,
                      c.gdig ? gdig : nullptr, c.gstride, pl->d_crt_afr, h.crt_nbk, h.crt_kq,
                      h.crt_nt, h.crt_inv_ptop};
-    if (!weight && crt_mma_eligible(h, c)) {
+    if (crt_mma_eligible(h, c)) {
         // matrix-core digit sums: 256 entries per block, one LDS digit column each
         const unsigned nbm = (unsigned)((M * N + 255) / 256);
         const size_t ldsm = (size_t)256 * h.nd32 * sizeof(uint32_t);
-        if (round) k_crt_mma<kCrtMmaMaxQ, true><<<nbm, 256, ldsm, s>>>(ca);
-        else k_crt_mma<kCrtMmaMaxQ, false><<<nbm, 256, ldsm, s>>>(ca);
+        if (weight) k_crt_mma<kCrtMmaMaxQ, false, true><<<nbm, 256, ldsm, s>>>(ca);
+        else if (round) k_crt_mma<kCrtMmaMaxQ, true, false><<<nbm, 256, ldsm, s>>>(ca);
+        else k_crt_mma<kCrtMmaMaxQ, false, false><<<nbm, 256, ldsm, s>>>(ca);
         return check_launch("CRT");
     }
 #define OZ2H_CRT(DC, E, R, W, G) k_crt<DC, E, R, W, G><<<nb, bd, lds, s>>>(ca)
@@ -361,6 +375,14 @@ int launch_crt(const oz2h_plan *pl, int64_t M, int64_t N, const int16_t *u, int6
 #undef OZ2H_CRT_E
 #undef OZ2H_CRT
     return check_launch("CRT");
+}
+
+// P > 2^n, from the plan's digits of P
+bool p_exceeds_pow2(const PlanHost &h, int64_t n) {
+    if (h.pbits != n + 1) return h.pbits > n + 1;
+    int bits = 0;
+    for (uint32_t d : h.p_digits) bits += __builtin_popcount(d);
+    return bits > 1;   // bit n is set: P > 2^n unless P is exactly 2^n
 }
 
 int upload_plan(oz2h_plan *pl) {
@@ -535,7 +557,7 @@ int oz2h_plan_moduli(int32_t p, int64_t K, const oz2h_opts *o, int32_t *L, int32
     oz2h_opts d;
     oz2h_opts_default(&d);
     if (!o) o = &d;
-    if (o->flags) return fail(OZ2H_EINVAL, "flags must be 0");
+    if (check_flags(o->flags)) return OZ2H_EINVAL;
     std::vector<uint32_t> mods;
     int tt = 0;
     double lp = 0;
@@ -581,7 +603,7 @@ int oz2h_plan_create(int32_t p, int64_t K, const oz2h_opts *o, oz2h_plan **out) 
     oz2h_opts d;
     oz2h_opts_default(&d);
     if (!o) o = &d;
-    if (o->flags) return fail(OZ2H_EINVAL, "flags must be 0");
+    if (check_flags(o->flags)) return OZ2H_EINVAL;
     std::vector<uint32_t> mods;
     int t = 0;
     double lp = 0;
@@ -596,6 +618,7 @@ int oz2h_plan_create(int32_t p, int64_t K, const oz2h_opts *o, oz2h_plan **out) 
         return fail(st, "%s", err.c_str());
     }
     pl->h.tile = o->tile;
+    pl->h.flags = o->flags;
     return plan_finish(pl, out);
 }
 
@@ -614,7 +637,21 @@ int oz2h_plan_create_custom(int32_t p, int32_t t, int64_t K, int32_t L, const ui
         delete pl;
         return fail(st, "%s", err.c_str());
     }
+    // Eq. crtcond with the least margin: |c^| <= K 2^(2t) < P/2 needs P > 2^(2t + ceil(log2 K) + 1)
+    const int64_t need = 2 * (int64_t)t + ceil_log2(K) + 1;
+    if (!p_exceeds_pow2(pl->h, need)) {
+        delete pl;
+        return fail(OZ2H_ERANGE, "moduli product P = 2^%.3f does not exceed 2^(2t + ceil(log2 K) + 1) "
+                                 "= 2^%lld, so |c^| < P/2 is not guaranteed", pl->h.log2P, (long long)need);
+    }
     return plan_finish(pl, out);
+}
+
+int oz2h_plan_set_flags(oz2h_plan *plan, uint32_t flags) {
+    if (!plan) return fail(OZ2H_EINVAL, "plan is NULL");
+    if (check_flags(flags)) return OZ2H_EINVAL;
+    plan->h.flags = flags;
+    return ok();
 }
 
 void oz2h_plan_destroy(oz2h_plan *plan) {
@@ -752,7 +789,7 @@ int oz2h_plan_create_grad(int32_t p, int64_t M, int64_t N, int64_t K, const oz2h
     oz2h_opts d;
     oz2h_opts_default(&d);
     if (!o) o = &d;
-    if (o->flags) return fail(OZ2H_EINVAL, "flags must be 0");
+    if (check_flags(o->flags)) return OZ2H_EINVAL;
     if (o->tile < OZ2H_TILE_AUTO || o->tile > OZ2H_TILE_128x256) return fail(OZ2H_EINVAL, "bad tile");
     if (M < 1 || N < 1) return fail(OZ2H_EINVAL, "M and N must be >= 1");
     if (M > kMaxK || N > kMaxK)
@@ -776,6 +813,7 @@ int oz2h_plan_create_grad(int32_t p, int64_t M, int64_t N, int64_t K, const oz2h
         return fail(st, "%s", err.c_str());
     }
     pl->h.tile = o->tile;
+    pl->h.flags = o->flags;
     pl->h.grad = true;
     pl->h.gM = M;
     pl->h.gN = N;
@@ -1198,7 +1236,7 @@ int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2
     oz2h_opts d;
     oz2h_opts_default(&d);
     if (!o) o = &d;
-    if (o->flags) return fail(OZ2H_EINVAL, "flags must be 0");
+    if (check_flags(o->flags)) return OZ2H_EINVAL;
     int dev = -1;
     int st = check_device(&dev);
     if (st) return st;
@@ -1232,6 +1270,7 @@ int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2
         if (st) return fail(st, "problem %d: %s", b, err.c_str());
         st = build_plan(q.p, t, q.K, mods, bp->hosts[b], err, 0, false);
         if (st) return fail(st, "problem %d: %s", b, err.c_str());
+        bp->hosts[b].flags = o->flags;
     }
 
     // device table layout

@@ -227,7 +227,8 @@ __device__ __forceinline__ uint32_t quad_transpose_bytes(uint32_t w, QuadSel sel
 // Waves of a residue block along k: two when the block has at least two, so that a block
 // covers 128 consecutive entries of RB / 2 rows.  Blocks are dealt to the XCDs round-robin,
 // so with one wave per row the two 64-byte halves of a plane line would be written from two
-// different L2s.  Grids: (kpad / (64 KW)) x (rpad / (RB / KW)) blocks.
+// different L2s.  Grids: (kpad / (64 KW)) x (rpad / (RB / KW)) blocks, launched as a 1-D grid
+// with the k blocks fastest (no 65535 limit on the rows).
 __host__ __device__ constexpr int res_waves_k(int rb) { return rb >= 2 ? 2 : 1; }
 
 // The pointers are passed as __restrict__ parameters (kept as scoped no-alias
@@ -268,9 +269,12 @@ __device__ __forceinline__ void residue_block_r(
     typedef const __attribute__((address_space(1))) double gdouble;
     gdouble *gtab = (gdouble *)tab;
     OZ2H_G(ResGroup) *grec = (OZ2H_G(ResGroup) *)rgrp;
-    // per-plane base (uniform) + a 32-bit lane offset: scalar-base stores, no
+    // per-plane base of this block's region (uniform, 64-bit) + a 32-bit lane offset within
+    // it (below (RB / KW) kpad + 128 < 2^32 whatever the plane size): scalar-base stores, no
     // per-lane 64-bit address arithmetic
-    const uint32_t loff = (uint32_t)(r * kpad + k);
+    const int64_t r0b = by * (RB / KW), k0b = bx * KW * 64;
+    planes += r0b * kpad + k0b;
+    const uint32_t loff = (uint32_t)((r - r0b) * kpad + (k - k0b));
     // packed stores: lane 4 a + q writes entries 4 a .. 4 a + 3 of plane q of four
     const int lane = tid & 63;
     const QuadSel qsel = quad_sel(lane);
@@ -350,7 +354,8 @@ __device__ __forceinline__ void residue_block(const ResArgs &a, int64_t bx, int6
 template <int RB, int KG>
 __global__ __launch_bounds__(64 * RB) void k_residues(ResArgs a) {
     extern __shared__ uint32_t words[];
-    residue_block<RB, KG>(a, blockIdx.x, blockIdx.y, words);
+    const int64_t nbx = a.kpad / (64 * res_waves_k(RB));
+    residue_block<RB, KG>(a, (int64_t)blockIdx.x % nbx, (int64_t)blockIdx.x / nbx, words);
 }
 
 // Residues of a^ on the matrix cores (stage 2).  For every modulus the residue of an
@@ -467,7 +472,10 @@ __device__ __forceinline__ void residue_block_mma_r(
             bf0[q] = b0p[2 * q];
             bf1[q] = b1p[2 * q];
         }
-    const uint32_t loff = (uint32_t)(r * kpad + k);
+    // the block's region of every plane (uniform 64-bit base) and a 32-bit lane offset in it
+    const int64_t r0b = by * (RB / KW), k0b = bx * KW * 64;
+    planes += r0b * kpad + k0b;
+    const uint32_t loff = (uint32_t)((r - r0b) * kpad + (k - k0b));
     // stores: after a quad byte transpose, lane 4 a + q writes entries 4 a .. 4 a + 3 of
     // plane q of a group of four (a dword at the quad's first entry)
     const QuadSel qsel = quad_sel(lane);
@@ -607,9 +615,11 @@ __device__ __forceinline__ void residue_block_mma_r(
 template <int RB, int NQ>
 __global__ __launch_bounds__(64 * RB) void k_residues_mma(ResMmaArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint32_t smem_res[];
+    const int64_t nbx = a.kpad / (64 * res_waves_k(RB));
     residue_block_mma_r<RB, NQ>(a.limbs, a.exps, a.signs, a.erow, a.koff, a.wfrag, a.rblk, a.planes,
                             a.rs, a.cs, a.rows, a.count, a.kpad, a.plane_stride, a.p, a.nl, a.t,
-                            a.nw32, a.nq, a.nrb, blockIdx.x, blockIdx.y, smem_res);
+                            a.nw32, a.nq, a.nrb, (int64_t)blockIdx.x % nbx, (int64_t)blockIdx.x / nbx,
+                            smem_res);
 }
 
 // ---------------------------------------------------------------- stage 3
@@ -1272,7 +1282,9 @@ constexpr int kCrtMmaMaxQ = 8;   // contraction steps of the matrix-core CRT (2 
 // per-entry carry and subtraction passes outweigh its L x nd32 multiply-adds
 constexpr int kCrtMmaMinDigits = 16;
 
-template <int KQ, bool ROUND>
+// WEIGHT = true: the planes hold plain residues u_l (any representative, |u_l| < m_l),
+// weighted here to v_l = u_l (P/m_l)^-1 mod m_l (the stage-4 parity entry point).
+template <int KQ, bool ROUND, bool WEIGHT = false>
 __device__ __forceinline__ void crt_mma_block(const CrtArgs &a, int64_t blk, uint32_t *sdig) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int h = lane >> 5, c = lane & 31;
@@ -1312,6 +1324,18 @@ __device__ __forceinline__ void crt_mma_block(const CrtArgs &a, int64_t blk, uin
                             const int lc = min(l, L - 1) - 8 * h;   // relative to the lane base
                             const uint32_t x = vb[b][(int64_t)lc * v_ps];
                             w[t] = l < L ? x : 0u;
+                        }
+                    }
+                    if constexpr (WEIGHT) {
+#pragma unroll
+                        for (int t = 0; t < 8; ++t) {
+                            const int l = 16 * q + 8 * h + t;
+                            if (l < L) {
+                                const ModInfo info = load_info((OZ2H_G(ModInfo) *)a.mi + l);
+                                const int32_t v = centred_mod((double)(int16_t)w[t] * (double)info.minv,
+                                                              (double)info.m, info.inv_m);
+                                w[t] = (uint32_t)(uint16_t)(int16_t)v;
+                            }
                         }
                     }
                     const v4i f = v4i{(int)((w[0] | (w[1] << 16)) ^ 0x00800080u),
@@ -1380,10 +1404,10 @@ __device__ __forceinline__ void crt_mma_block(const CrtArgs &a, int64_t blk, uin
     if (e < MN) crt_finish<ROUND>(a, e, col, 256, slow, cy + carry);
 }
 
-template <int KQ, bool ROUND>
+template <int KQ, bool ROUND, bool WEIGHT>
 __global__ __launch_bounds__(256) void k_crt_mma(CrtArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint32_t sdig[];
-    crt_mma_block<KQ, ROUND>(a, blockIdx.x, sdig);
+    crt_mma_block<KQ, ROUND, WEIGHT>(a, blockIdx.x, sdig);
 }
 
 // planes [G][R][C] (int8, row stride ldi) -> [G][Co][Ro] (row stride Ro), zero where

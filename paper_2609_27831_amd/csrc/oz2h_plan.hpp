@@ -11,8 +11,9 @@ namespace oz2h {
 constexpr int kModGroup = 8;          // moduli per group in the residue kernel (small L)
 constexpr int kModGroupWide = 16;     // ... and for wide moduli sets (L >= kWideL)
 constexpr int kWideL = 96;
-constexpr int kResMmaMinWords = 8;    // integers of >= this many 32-bit words (p >~ 200) take
-                                      // the matrix-core residue kernel, narrower ones the fp64 one
+constexpr int kResMmaMinWords = 8;    // with the matrix-core residue variant selected, integers
+                                      // of >= this many 32-bit words (t >= 224) take it, narrower
+                                      // ones the fp64 kernel
 constexpr int kMaxModuli = 512;       // fp64-exact CRT digit sums need L * 2^44 < 2^53
 constexpr int kMaxWords = 256;        // fp64-exact residue sums need nw32 * 2^45 < 2^53
 constexpr int64_t kMaxK = 133000;     // K * 127^2 < 2^31, the cap the paper's implementation uses
@@ -60,6 +61,7 @@ static_assert(sizeof(ResRowBlock) == 768, "ResRowBlock layout");
 struct PlanHost {
     int p = 0, t = 0;
     int tile = 0;          // oz2h_tile hint of the residue GEMMs (0 = automatic)
+    uint32_t flags = 0;    // OZ2H_FLAG_* bits: matrix-core variants of stages 2 and 4
     int64_t K = 0;
     int L = 0, L1 = 0, L2 = 0, G = 0;
     int nw32 = 0;          // 32-bit words of the widest integer significand (t+1 bits, or

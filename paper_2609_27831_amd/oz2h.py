@@ -27,6 +27,8 @@ class Oz2hError(RuntimeError):
 
 
 TILE_AUTO, TILE_128x128, TILE_256x128, TILE_128x256 = 0, 1, 2, 3
+# option flags: the matrix-core variants of stage 2 (residues) and stage 4 (CRT)
+FLAG_RESIDUES_MMA, FLAG_CRT_MMA = 0x1, 0x2
 TILE_SHAPES = {TILE_128x128: (128, 128), TILE_256x128: (256, 128), TILE_128x256: (128, 256)}
 
 
@@ -68,6 +70,7 @@ SIGNATURES = {
     "oz2h_plan_moduli": (ctypes.c_int, [_I32, _I64, ctypes.POINTER(Opts), _P, _P, _P, _P, _P, _P]),
     "oz2h_plan_create": (ctypes.c_int, [_I32, _I64, ctypes.POINTER(Opts), ctypes.POINTER(_P)]),
     "oz2h_plan_create_custom": (ctypes.c_int, [_I32, _I32, _I64, _I32, _P, ctypes.POINTER(_P)]),
+    "oz2h_plan_set_flags": (ctypes.c_int, [_P, ctypes.c_uint32]),
     "oz2h_plan_destroy": (None, [_P]),
     "oz2h_plan_get_info": (ctypes.c_int, [_P, ctypes.POINTER(PlanInfo)]),
     "oz2h_plan_get_moduli": (ctypes.c_int, [_P, _P]),
@@ -125,9 +128,12 @@ def _check(code: int):
 
 
 def default_opts(guard_bits: Optional[int] = None, t_bits: Optional[int] = None,
-                 crt_margin: Optional[int] = None, tile: Optional[int] = None) -> Opts:
+                 crt_margin: Optional[int] = None, tile: Optional[int] = None,
+                 flags: Optional[int] = None) -> Opts:
     o = Opts()
     lib().oz2h_opts_default(ctypes.byref(o))
+    if flags is not None:
+        o.flags = flags
     if tile is not None:
         o.tile = tile
     if guard_bits is not None:
@@ -192,6 +198,11 @@ class Plan:
         if info is not None and k in info:
             return info[k]
         raise AttributeError(k)
+
+    def set_flags(self, flags: int) -> "Plan":
+        """Select the stage-2 / stage-4 kernel variants (FLAG_* bits)."""
+        _check(lib().oz2h_plan_set_flags(self.handle, flags))
+        return self
 
     def workspace_size(self, M: int, N: int) -> int:
         return int(lib().oz2h_gemm_workspace_size(self.handle, M, N))
@@ -271,6 +282,20 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _keep_for(stream, *tensors):
+    """Tensors this module allocated on the current stream but handed to a launch on
+    another stream: tell the caching allocator, so that their memory is not reused
+    before that stream's work is done."""
+    if stream is None:
+        return
+    torch = _torch()
+    if stream == torch.cuda.current_stream(stream.device):
+        return
+    for t in tensors:
+        if t is not None:
+            t.record_stream(stream)
+
+
 def workspace(plan: Plan, M: int, N: int, device="cuda"):
     torch = _torch()
     n = plan.workspace_size(M, N)
@@ -289,12 +314,17 @@ def gemm(plan: Plan, A: DeviceMP, B: DeviceMP, opA: int = OP_N, opB: int = OP_N,
          out: Optional[DeviceMP] = None, ws=None, stream=None) -> DeviceMP:
     """C = op(A) op(B) at the plan's precision (oz2h_gemm)."""
     M, N, K = _dims(A, B, opA, opB)
+    new_out, new_ws = out is None, ws is None
     if out is None:
         out = empty_mp(M, N, plan.p, device=A.sign.device)
     if ws is None:
         ws = workspace(plan, M, N, device=A.sign.device)
     _check(lib().oz2h_gemm(plan.handle, M, N, K, opA, A.cmat(), opB, B.cmat(), out.mat(),
                            ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
+    if new_out:
+        _keep_for(stream, out.sign, out.exp, out.limbs)
+    if new_ws:
+        _keep_for(stream, ws)
     return out
 
 
@@ -320,11 +350,13 @@ def gemm_integers(plan: Plan, A: DeviceMP, B: DeviceMP, opA: int = OP_N, opB: in
     cm = torch.empty((M, N, nlc), dtype=torch.int64, device=dev)
     e = torch.empty(M, dtype=torch.int32, device=dev)
     f = torch.empty(N, dtype=torch.int32, device=dev)
+    new_ws = ws is None
     if ws is None:
         ws = workspace(plan, M, N, device=dev)
     _check(lib().oz2h_gemm_integers(plan.handle, M, N, K, opA, A.cmat(), opB, B.cmat(),
                                     cs.data_ptr(), cm.data_ptr(), nlc, e.data_ptr(), f.data_ptr(),
                                     ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
+    _keep_for(stream, cs, cm, e, f, ws if new_ws else None)
     return cs, cm, e, f
 
 
@@ -397,17 +429,22 @@ def gemm_backward(plan: Plan, saved, W: DeviceMP, want_a: bool = True, want_b: b
     M, N = W.shape
     K = plan.K
     dev = W.sign.device
+    fresh = []
     if want_a and dA is None:
         dA = empty_mp(M, K, plan.p, device=dev)
+        fresh += [dA.sign, dA.exp, dA.limbs]
     if want_b and dB is None:
         dB = empty_mp(K, N, plan.p, device=dev)
+        fresh += [dB.sign, dB.exp, dB.limbs]
     if ws is None:
         ws = torch.empty(max(plan.backward_workspace_size(), 256), dtype=torch.uint8, device=dev)
+        fresh.append(ws)
     ma = ctypes.byref(dA.mat()) if want_a else None
     mb = ctypes.byref(dB.mat()) if want_b else None
     _check(lib().oz2h_gemm_backward(plan.handle, M, N, K, saved.data_ptr(), saved.numel(),
                                     W.cmat(), ma, mb, ws.data_ptr(), ws.numel(),
                                     _stream_ptr(stream)))
+    _keep_for(stream, *fresh)
     return (dA if want_a else None), (dB if want_b else None)
 
 

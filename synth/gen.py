@@ -47,6 +47,17 @@ def splitmix64(seed: int, start: int, count: int) -> np.ndarray:
     return z
 
 
+def splitmix64_at(seed: int, counters: np.ndarray) -> np.ndarray:
+    """Outputs number c + 1 of SplitMix64 seeded with `seed`, for each counter c."""
+    n = np.asarray(counters, dtype=np.uint64) + np.uint64(1)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed & MASK64) + n * GAMMA
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
 @dataclass
 class MPMatrix:
     """A rows x cols matrix of p-bit numbers in the operand format above."""
@@ -115,6 +126,39 @@ def mp_random(seed: int, rows: int, cols: int, p: int, elo: int, ehi: int,
         limbs[e0:e0 + ne] = lb
     return MPMatrix(sign.reshape(rows, cols), exp.reshape(rows, cols),
                     limbs.reshape(rows, cols, nl), p)
+
+
+def mp_block(seed: int, rows: int, cols: int, p: int, elo: int, ehi: int, r0: int, r1: int,
+             c0: int, c1: int, counter: int = 0) -> MPMatrix:
+    """Block [r0:r1, c0:c1] of mp_random(seed, rows, cols, p, elo, ehi, counter), drawn
+    from its counters directly (no need to draw the whole matrix)."""
+    if p < 2:
+        raise ValueError("p must be >= 2")
+    nl = limbs_for(p)
+    per = 2 + nl
+    r = np.arange(r0, r1, dtype=np.uint64)[:, None]
+    c = np.arange(c0, c1, dtype=np.uint64)[None, :]
+    base = np.uint64(counter) + (r * np.uint64(cols) + c) * np.uint64(per)      # [nr, nc]
+    d = splitmix64_at(seed, base[..., None] + np.arange(per, dtype=np.uint64))  # [nr, nc, per]
+    top_bits = p - 64 * (nl - 1)
+    top_mask = np.uint64(MASK64 >> (64 - top_bits))
+    top_set = np.uint64(1 << (top_bits - 1))
+    span = np.uint64(ehi - elo + 1)
+    sign = np.where((d[..., 0] & np.uint64(1)) == 1, -1, 1).astype(np.int8)
+    exp = (np.int64(elo) + (d[..., 1] % span).astype(np.int64)).astype(np.int32)
+    limbs = np.ascontiguousarray(d[..., 2:])
+    limbs[..., nl - 1] = (limbs[..., nl - 1] & top_mask) | top_set
+    return MPMatrix(sign, exp, limbs, p)
+
+
+def operand_blocks_for(seed: int, M: int, N: int, K: int, p: int, elo: int, ehi: int,
+                       rows_a: range, cols_b: range):
+    """Rows `rows_a` of A (all of K) and columns `cols_b` of B (all of K) of
+    operands_for(seed, M, N, K, p, elo, ehi), drawn from their counters."""
+    per = 2 + limbs_for(p)
+    A = mp_block(seed, M, K, p, elo, ehi, rows_a.start, rows_a.stop, 0, K, counter=0)
+    B = mp_block(seed, K, N, p, elo, ehi, 0, K, cols_b.start, cols_b.stop, counter=M * K * per)
+    return A, B
 
 
 def mp_unit_uniform(seed: int, rows: int, cols: int, p: int, counter: int = 0,

@@ -121,3 +121,57 @@ def test_batched_autotune(oz):
     # a second plan with the same shapes picks the tuned configuration up
     bp2 = oz.BatchedPlan(probs)
     assert bp2.config()["tile"] == cfg["tile"] and bp2.config()["blocks_per_cu"] == cfg["blocks_per_cu"]
+
+
+def test_batched_full_workload(oz, c_oracle):
+    """The full batched workload (64 products, M, N, K log-uniform in [128, 4096],
+    p in {53, 113, 256, 512}, exponents U[-4, 4], the generator and seed the bench uses):
+    graph replay bit-identical to the loop of plain calls, and every product against the
+    oracle on sampled entries (its four corners plus seeded random ones)."""
+    import time
+    import torch
+    t0 = time.time()
+    seed = synth.CONFIG_SEED_BASE + 4
+    u = synth.splitmix64(seed, 0, 4 * 64).reshape(64, 4)
+    spec = []
+    for i in range(64):
+        f = (u[i, :3] >> np.uint64(11)).astype(np.float64) / float(1 << 53)
+        M, N, K = (int(round(128 * 32.0 ** x)) for x in f)
+        spec.append((M, N, K, (53, 113, 256, 512)[int(u[i, 3] % np.uint64(4))], seed * 1000 + i))
+    rng = np.random.default_rng(4)
+    probs, samples = [], []
+    for (M, N, K, p, sd) in spec:
+        A, B = synth.operands_for(sd, M, N, K, p, -4, 4)
+        si = np.array([0, 0, M - 1, M - 1] + list(rng.integers(0, M, 12)), np.int64)
+        sj = np.array([0, N - 1, 0, N - 1] + list(rng.integers(0, N, 12)), np.int64)
+        ref = c_oracle.gemm(A, B, sel=(si, sj), want_chat=False)
+        samples.append((si, sj, ref))
+        probs.append((dev_mp(A), dev_mp(B), oz.empty_mp(M, N, p), 0, 0))
+        del A, B
+    print(f"batched full workload: inputs and oracle samples {time.time() - t0:.1f}s", flush=True)
+    bp = oz.BatchedPlan(probs)
+    ws = bp.workspace()
+    bp.tune(ws)
+    bp.run(ws)
+    torch.cuda.synchronize()
+    got = [tuple(x.clone() for x in (C.sign, C.exp, C.limbs)) for (_, _, C, _, _) in probs]
+    print(f"batched full workload: graph done {time.time() - t0:.1f}s {bp.config()}", flush=True)
+    wsz = 256
+    plans = []
+    for (Ad, Bd, C, _, _) in probs:
+        pl = oz.Plan.create(Ad.p, Ad.shape[1])
+        plans.append(pl)
+        wsz = max(wsz, pl.workspace_size(Ad.shape[0], Bd.shape[1]))
+    ws1 = torch.empty(wsz, dtype=torch.uint8, device="cuda")
+    for i, (pl, (Ad, Bd, C, _, _)) in enumerate(zip(plans, probs)):
+        Cp = oz.gemm(pl, Ad, Bd, ws=ws1)
+        for a, b in zip(got[i], (Cp.sign, Cp.exp, Cp.limbs)):
+            assert torch.equal(a, b), f"product {i}"
+        si, sj, ref = samples[i]
+        ti, tj = torch.from_numpy(si).cuda(), torch.from_numpy(sj).cuda()
+        assert np.array_equal(got[i][0][ti, tj].cpu().numpy(), ref["c_sign"]), f"product {i}"
+        assert np.array_equal(got[i][1][ti, tj].cpu().numpy(), ref["c_exp"]), f"product {i}"
+        assert np.array_equal(got[i][2][ti, tj].cpu().numpy().view(np.uint64), ref["c_limbs"]), \
+            f"product {i}"
+    print(f"batched full workload: loop compared {time.time() - t0:.1f}s", flush=True)
+    bp.destroy()

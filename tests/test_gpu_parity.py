@@ -71,6 +71,18 @@ CASES = [
     ("tile256x128_p256", 110, 300, 200, 150, 256, -32, 32, 0.02, 0, 0, 2),
     ("tile128x256_p512", 111, 130, 260, 70, 512, -32, 32, 0.0, 0, 1, 3),
     ("tile128x128_p113", 112, 260, 140, 333, 113, -16, 16, 0.0, 1, 0, 1),
+    # the matrix-core CRT variant over its whole digit range: p = 384 (28 digits, 6
+    # contraction steps) and p = 440 (32 digits, 7 steps, 4 row blocks), and the VALU kernel
+    ("p384_mma_variants", 114, 96, 80, 256, 384, -8, 8, 0.0, 0, 0, 0, 3),
+    ("p440_mma_variants", 115, 70, 130, 256, 440, -8, 8, 0.02, 0, 0, 0, 3),
+    ("p440_valu", 115, 70, 130, 256, 440, -8, 8, 0.02, 0, 0, 0, 0),
+    ("p384_crt_mma_only", 116, 129, 64, 200, 384, -30, 30, 0.0, 0, 1, 0, 2),
+    # the matrix-core variants of stages 2 and 4 on cases above
+    ("cfg1_mma_variants", synth.CONFIG_SEED_BASE + 1, 256, 256, 256, 128, -4, 4, 0.0, 0, 0, 0, 3),
+    ("ragged_p256_mma_variants", 101, 200, 130, 77, 256, -32, 32, 0.05, 0, 0, 0, 3),
+    ("p1024_mma_variants", 107, 64, 70, 33, 1024, -40, 40, 0.0, 0, 0, 0, 3),
+    ("p2048_mma_variants", 108, 20, 30, 17, 2048, -16, 16, 0.0, 0, 0, 0, 3),
+    ("p3250_residues_mma", 113, 9, 12, 7, 3250, -8, 8, 0.0, 0, 1, 0, 1),
 ]
 
 
@@ -78,6 +90,7 @@ CASES = [
 def test_gemm_matches_oracle_elementwise(oz, c_oracle, case):
     name, seed, M, N, K, p, lo, hi, zf, opA, opB = case[:11]
     tile = case[11] if len(case) > 11 else 0
+    flags = case[12] if len(case) > 12 else 0
     A, B = synth.operands_for(seed, M, N, K, p, lo, hi)
     if zf:
         _zeros(A, zf, seed)
@@ -85,8 +98,8 @@ def test_gemm_matches_oracle_elementwise(oz, c_oracle, case):
     if M > 3 and N > 3:
         A.sign[M // 2, :] = 0       # an all-zero row of A and column of B
         B.sign[:, N // 3] = 0
-    print(f"parity {name}: M={M} N={N} K={K} p={p} tile={tile}", flush=True)
-    plan = oz.Plan.create(p, K, oz.default_opts(tile=tile))
+    print(f"parity {name}: M={M} N={N} K={K} p={p} tile={tile} flags={flags}", flush=True)
+    plan = oz.Plan.create(p, K, oz.default_opts(tile=tile, flags=flags))
     ref = c_oracle.gemm(A, B)
     got = _run_gpu(oz, plan, A, B, opA, opB)
     _compare_full(got, ref, ref["nlc"])

@@ -213,7 +213,7 @@ def test_crt_worked_example(oz):
     import torch
     from tests.gpu_util import read_worked_example
     ex = read_worked_example()
-    plan = oz.Plan.custom(8, 4, 3, [5, 7, 9])
+    plan = oz.Plan.custom(8, 2, 3, [5, 7, 9])   # P = 315 > 2^(2t + ceil(log2 K) + 1) = 128
     assert list(plan.moduli) == [5, 7, 9]
     u = np.zeros((3, 1, 1), np.uint16)
     for li, m in enumerate([5, 7, 9]):

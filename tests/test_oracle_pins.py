@@ -375,3 +375,66 @@ def test_pins_catch_planted_mistakes():
     assert _pins_fail(R) == 0
     for name, mod in _mutants().items():
         assert _pins_fail(mod) > 0, f"pins missed the planted mistake {name}"
+
+
+def _brute_integerize(X, t, side):
+    """Shared exponents and integers of one operand from the VALUES: e = the largest
+    exponent (smallest e with |x| < 2^e) over the nonzero entries of a row of A or a
+    column of B, 0 when there is none, and a^ = Python round() (ties to even) of the
+    exact rational x 2^(t - e) (Eq. 1)."""
+    p = X.p
+    R_, C_ = X.sign.shape
+    lines = range(R_) if side == "A" else range(C_)
+    es, ints = [], []
+    for r in lines:
+        idx = [(r, k) for k in range(C_)] if side == "A" else [(k, r) for k in range(R_)]
+        vals = [val(*X.value_parts(i, j), p) for (i, j) in idx]
+        nz = [exp_of(v) for v in vals if v != 0]
+        e = max(nz) if nz else 0
+        es.append(e)
+        ints.append([round(v * Fraction(2) ** (t - e)) for v in vals])
+    return es, ints
+
+
+@pytest.mark.parametrize("side", ["A", "B"])
+@pytest.mark.parametrize("p,lo,hi,shape", [(2, -30, 30, (5, 7)), (53, -200, 200, (6, 9)),
+                                           (130, -4, 4, (4, 5)), (64, -80, 80, (7, 3))])
+def test_c_integerize_against_values(c_oracle, side, p, lo, hi, shape):
+    """The C oracle's integerization (the checker of the stage-1/2 GPU tests) against
+    Fractions, on both sides (row exponents of A, column exponents of B and its strided
+    layout), with wide exponent spreads (many entries round to 0 or to ties), an all-zero
+    line and bits above p set in the stored significands."""
+    rows, cols = shape
+    X = synth.mp_random(7 * p + rows, rows, cols, p, lo, hi)
+    X.sign[1, :] = 0                      # an all-zero row (a zero line of side A)
+    X.sign[:, 2] = 0                      # an all-zero column (side B)
+    nl = X.limbs.shape[-1]
+    top = p - 64 * (nl - 1)
+    if top < 64:                          # garbage above bit p - 1 is ignored
+        X.limbs[0, 0, nl - 1] |= np.uint64(1) << np.uint64(top)
+    t = R.internal_width(p, cols if side == "A" else rows)
+    e, sg, mag = c_oracle.integerize(X, t, side)
+    be, bints = _brute_integerize(X, t, side)
+    assert e.tolist() == be
+    got = [[int(s) * int(sum(int(x) << (64 * l) for l, x in enumerate(m))) for s, m in zip(srow, mrow)]
+           for srow, mrow in zip(sg, mag)]
+    assert got == bints
+    # the invariant of Eq. 1
+    assert all(abs(v) <= 1 << t for row in got for v in row)
+
+
+def test_c_integerize_ties():
+    """Constructed ties of the integerization (2.5 -> 2, 3.5 -> 4, 1.5 -> 2, 0.5 -> 0)
+    through the C oracle, both sides, against Python's round()."""
+    from oracle import c_oracle
+    cases = tie_cases()
+    for (A, B) in cases:
+        p = A.p
+        K = A.sign.shape[1]
+        t = R.internal_width(p, K)
+        for X, side in ((A, "A"), (B, "B")):
+            e, sg, mag = c_oracle.integerize(X, t, side)
+            be, bints = _brute_integerize(X, t, side)
+            got = [[int(s) * int(sum(int(x) << (64 * l) for l, x in enumerate(m)))
+                    for s, m in zip(srow, mrow)] for srow, mrow in zip(sg, mag)]
+            assert e.tolist() == be and got == bints
