@@ -30,6 +30,7 @@ struct oz2h_plan {
     void *dbuf = nullptr;
     ModInfo *d_info = nullptr;
     double *d_resid = nullptr;
+    double *d_resid_row = nullptr;
     ResGroup *d_rgrp = nullptr;
     int8_t *d_rmma_w = nullptr;
     ResRowBlock *d_rmma_rb = nullptr;
@@ -219,7 +220,17 @@ int launch_residues(const oz2h_plan *pl, int64_t rows, int64_t count, const uint
 #undef OZ2H_RES_MMA
         return check_launch("residues");
     }
-    int rb = h.nw32 <= 64 ? 4 : (h.nw32 <= 128 ? 2 : 1);   // word columns <= 64 KiB per block
+    if (h.nw32 >= kResRowMinWords && res_row_lds(h.rnwp) <= 65536) {
+        // VALU kernel with row broadcasts: blocks of 128 entries of one row
+        const int64_t nblk = (kpad / 128) * rpad;
+        if (nblk > INT32_MAX) return fail(OZ2H_ERANGE, "residues: operand too large for one launch");
+        const ResRowArgs a{limbs, exp, sign, rs, cs, rows, count, kpad, ps, erow, koff,
+                           h.p, nl, t, h.nw32, h.rnwp, h.L, h.rg16, pl->d_resid_row, pl->d_info, planes};
+        k_residues_row<<<dim3((unsigned)nblk), 256, res_row_lds(h.rnwp), s>>>(a);
+        return check_launch("residues");
+    }
+    // entry-per-thread VALU kernel, word columns <= 64 KiB per block
+    const int rb = h.nw32 <= 64 ? 4 : (h.nw32 <= 128 ? 2 : 1);
     const int kw = res_waves_k(rb);
     const int64_t nblk = (kpad / (64 * kw)) * (rpad / (rb / kw));
     if (nblk > INT32_MAX) return fail(OZ2H_ERANGE, "residues: operand too large for one launch");
@@ -227,15 +238,15 @@ int launch_residues(const oz2h_plan *pl, int64_t rows, int64_t count, const uint
     const size_t lds = (size_t)h.nw32 * 64 * rb * sizeof(uint32_t);
     const ResArgs a{limbs, exp, sign, rs, cs, rows, count, kpad, ps, erow, h.p, nl, t, h.nw32,
                     pl->d_resid, pl->d_rgrp, h.L, h.lgroups, planes, koff};
-    if (h.kg == kModGroupWide) {
-        if (rb == 4) k_residues<4, kModGroupWide><<<grid, 256, lds, s>>>(a);
-        else if (rb == 2) k_residues<2, kModGroupWide><<<grid, 128, lds, s>>>(a);
-        else k_residues<1, kModGroupWide><<<grid, 64, lds, s>>>(a);
-    } else {
-        if (rb == 4) k_residues<4, kModGroup><<<grid, 256, lds, s>>>(a);
-        else if (rb == 2) k_residues<2, kModGroup><<<grid, 128, lds, s>>>(a);
-        else k_residues<1, kModGroup><<<grid, 64, lds, s>>>(a);
-    }
+#define OZ2H_RES(KG)                                                                   \
+    do {                                                                               \
+        if (rb == 4) k_residues<4, KG, 1><<<grid, 256, lds, s>>>(a);                   \
+        else if (rb == 2) k_residues<2, KG, 1><<<grid, 128, lds, s>>>(a);              \
+        else k_residues<1, KG, 1><<<grid, 64, lds, s>>>(a);                            \
+    } while (0)
+    if (h.kg == kModGroupWide) OZ2H_RES(kModGroupWide);
+    else OZ2H_RES(kModGroup);
+#undef OZ2H_RES
     return check_launch("residues");
 }
 
@@ -389,6 +400,7 @@ int upload_plan(oz2h_plan *pl) {
     const PlanHost &h = pl->h;
     const size_t n_info = sizeof(ModInfo) * h.L;
     const size_t n_res = sizeof(double) * h.resid_tab.size();
+    const size_t n_rrow = sizeof(double) * h.resid_row.size();
     const size_t n_crt = sizeof(double) * h.crt_digits.size();
     const size_t n_pd = sizeof(uint32_t) * h.nd32;
     size_t off = 0;
@@ -396,6 +408,8 @@ int upload_plan(oz2h_plan *pl) {
     off = align_up(off + n_info);
     const size_t o_res = off;
     off = align_up(off + n_res);
+    const size_t o_rrow = off;
+    off = align_up(off + n_rrow);
     const size_t n_rg = sizeof(ResGroup) * h.resgrp.size();
     const size_t o_rg = off;
     off = align_up(off + n_rg);
@@ -419,6 +433,7 @@ int upload_plan(oz2h_plan *pl) {
     char *b = (char *)buf;
     pl->d_info = (ModInfo *)(b + o_info);
     pl->d_resid = (double *)(b + o_res);
+    pl->d_resid_row = (double *)(b + o_rrow);
     pl->d_rgrp = (ResGroup *)(b + o_rg);
     pl->d_rmma_w = (int8_t *)(b + o_rw);
     pl->d_rmma_rb = (ResRowBlock *)(b + o_rrb);
@@ -428,6 +443,7 @@ int upload_plan(oz2h_plan *pl) {
     pl->d_phd = (uint32_t *)(b + o_phd);
     OZ2H_HIP(hipMemcpy(pl->d_info, h.info.data(), n_info, hipMemcpyHostToDevice));
     OZ2H_HIP(hipMemcpy(pl->d_resid, h.resid_tab.data(), n_res, hipMemcpyHostToDevice));
+    OZ2H_HIP(hipMemcpy(pl->d_resid_row, h.resid_row.data(), n_rrow, hipMemcpyHostToDevice));
     OZ2H_HIP(hipMemcpy(pl->d_rgrp, h.resgrp.data(), n_rg, hipMemcpyHostToDevice));
     OZ2H_HIP(hipMemcpy(pl->d_rmma_w, h.rmma_w.data(), n_rw, hipMemcpyHostToDevice));
     OZ2H_HIP(hipMemcpy(pl->d_rmma_rb, h.rmma_rb.data(), n_rrb, hipMemcpyHostToDevice));

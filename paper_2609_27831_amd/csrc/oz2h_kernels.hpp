@@ -118,29 +118,29 @@ __device__ __forceinline__ ModInfo load_info(OZ2H_G(ModInfo) *p) {
 // alignbit(m_j, m_{j-1}, 32 - r); for sh < 0 the same pass collects the round bit
 // (position -sh - 1) and the sticky bits below it, and a round-up carries through the
 // words.  A shift below -(32 nd + 2) drops every bit, the round bit included (a^ = 0).
+// The limbs stream through a ring of four registers, loaded four limbs ahead with
+// clamped unconditional loads, so that the loads of one entry overlap.
 __device__ __forceinline__ int build_words(OZ2H_G(uint64_t) *__restrict__ sl, int s, int64_t sh,
                                            int p, int nw, uint32_t *col, int st) {
     for (int w = 0; w < nw; ++w) col[w * st] = 0u;
     if (s == 0) return 0;
-    OZ2H_G(uint32_t) *m = (OZ2H_G(uint32_t) *)sl;
+    const int nlimb = (p + 63) >> 6;
     const int nd = (p + 31) >> 5;
-    const uint32_t topm = (p & 31) ? (1u << (p & 31)) - 1u : ~0u;
+    const uint64_t topm = (p & 63) ? (1ull << (p & 63)) - 1ull : ~0ull;
     const int shc = (int)max(sh, (int64_t)-(32 * nd + 2));
     const int q = (shc - 1) >> 5;        // floor((sh - 1) / 32)
     const int sa = 32 * (q + 1) - shc;   // 32 - r, in [0, 31]
     const int rp = -shc - 1;             // round bit position (sh < 0)
     uint32_t prev = 0u, nz = 0u;
     bool rbit = false, sticky = false;
-    for (int j = 0; j <= nd; ++j) {
-        uint32_t cur = 0u;
-        if (j < nd) cur = j == nd - 1 ? (m[j] & topm) : m[j];
+    auto word = [&](int j, uint32_t cur) {   // word j of the significand (0 above it)
         const int w = q + j;
         if (w >= 0 && w < nw) {
             const uint32_t v = __builtin_amdgcn_alignbit(cur, prev, sa);
             col[w * st] = v;
             nz |= v;
         }
-        if (shc < 0 && j < nd) {
+        if (shc < 0) {
             const int b = rp - 32 * j;   // the round bit's position within word j
             if (b >= 32) {
                 sticky |= cur != 0u;
@@ -150,7 +150,24 @@ __device__ __forceinline__ int build_words(OZ2H_G(uint64_t) *__restrict__ sl, in
             }
         }
         prev = cur;
+    };
+    auto ld = [&](int l) { return sl[min(l, nlimb - 1)]; };
+    uint64_t r0 = ld(0), r1 = ld(1), r2 = ld(2), r3 = ld(3);
+    auto limb = [&](int l, uint64_t &r) {
+        uint64_t x = l < nlimb ? r : 0ull;
+        if (l == nlimb - 1) x &= topm;
+        r = ld(l + 4);
+        word(2 * l, (uint32_t)x);
+        word(2 * l + 1, (uint32_t)(x >> 32));
+    };
+    // limbs 0 .. nlimb - 1, then one more word of zeros for the carry-out of the shift
+    for (int l = 0; l < nlimb; l += 4) {
+        limb(l, r0);
+        limb(l + 1, r1);
+        limb(l + 2, r2);
+        limb(l + 3, r3);
     }
+    word(2 * ((nlimb + 3) & ~3), 0u);
     if (rbit && (sticky || (col[0] & 1u))) {   // round half to even: add one
         for (int w = 0; w < nw; ++w) {
             const uint32_t v = col[w * st] + 1u;
@@ -230,11 +247,18 @@ __device__ __forceinline__ uint32_t quad_transpose_bytes(uint32_t w, QuadSel sel
 // different L2s.  Grids: (kpad / (64 KW)) x (rpad / (RB / KW)) blocks, launched as a 1-D grid
 // with the k blocks fastest (no 65535 limit on the rows).
 __host__ __device__ constexpr int res_waves_k(int rb) { return rb >= 2 ? 2 : 1; }
+// The VALU kernel with EPT entries per thread: a wave covers 64 EPT consecutive k of one
+// row (EPT = 2: a whole 128-byte plane line, one wave per row).
+__host__ __device__ constexpr int res_kw(int rb, int ept) { return ept >= 2 ? 1 : res_waves_k(rb); }
+// k entries a block covers
+__host__ __device__ constexpr int res_block_k(int rb, int ept) { return 64 * ept * res_kw(rb, ept); }
 
 // The pointers are passed as __restrict__ parameters (kept as scoped no-alias
 // information when inlined), so the compiler knows that the plane stores do
 // not clobber the constant tables and reads those with scalar loads.
-template <int RB, int KG>
+// EPT entries per thread share every constant the thread reads: entry e of a lane is
+// k = kbase + 64 e + lane, its words in the LDS column words + e BD + tid (stride EPT BD).
+template <int RB, int KG, int EPT = 1>
 __device__ __forceinline__ void residue_block_r(
     const uint64_t *__restrict__ limbs, const int32_t *__restrict__ exps,
     const int8_t *__restrict__ signs, const int32_t *__restrict__ erow,
@@ -243,26 +267,31 @@ __device__ __forceinline__ void residue_block_r(
     int64_t rows, int64_t count, int64_t kpad, int64_t plane_stride, int p, int nl, int t,
     int nw32, int L, int lgroups, int64_t bx, int64_t by, uint32_t *words) {
     constexpr int BD = 64 * RB;
+    constexpr int ST = BD * EPT;   // word stride of an LDS column
     const int tid = threadIdx.x;
-    // KW waves of a block side by side along k (res_waves_k): the block writes whole
-    // 128-byte lines of each plane row, so both halves of a line meet in one L2
-    constexpr int KW = res_waves_k(RB);
-    const int64_t k = (bx * KW + (tid >> 6) % KW) * 64 + (tid & 63);
+    constexpr int KW = res_kw(RB, EPT);
+    const int lane = tid & 63;
+    const int64_t kbase = (bx * KW + (tid >> 6) % KW) * 64 * EPT;
     const int64_t r = by * (RB / KW) + (tid >> 6) / KW;
 
     OZ2H_G(int8_t) *gsigns = (OZ2H_G(int8_t) *)signs;
     OZ2H_G(int32_t) *gexps = (OZ2H_G(int32_t) *)exps;
     OZ2H_G(int32_t) *gerow = (OZ2H_G(int32_t) *)erow;
     OZ2H_G(int32_t) *gkoff = (OZ2H_G(int32_t) *)koff;
-    uint32_t *col = words + tid;
-    int s = 0;
-    int64_t sh = 0, idx = 0;
-    if (r < rows && k < count) {
-        idx = r * rs + k * cs;
-        s = gsigns[idx];
-        sh = (int64_t)t - p + gexps[idx] + (koff ? gkoff[k] : 0) - gerow[r];
+    double sgn[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int64_t k = kbase + 64 * e + lane;
+        int s = 0;
+        int64_t sh = 0, idx = 0;
+        if (r < rows && k < count) {
+            idx = r * rs + k * cs;
+            s = gsigns[idx];
+            sh = (int64_t)t - p + gexps[idx] + (koff ? gkoff[k] : 0) - gerow[r];
+        }
+        s = build_words((OZ2H_G(uint64_t) *)limbs + idx * nl, s, sh, p, nw32, words + e * BD + tid, ST);
+        sgn[e] = s < 0 ? -1.0 : 1.0;
     }
-    s = build_words((OZ2H_G(uint64_t) *)limbs + idx * nl, s, sh, p, nw32, col, BD);
 
     // the tables live in global memory: say so, so that pointers read from a
     // descriptor (the grouped kernels) still qualify for scalar loads
@@ -272,23 +301,30 @@ __device__ __forceinline__ void residue_block_r(
     // per-plane base of this block's region (uniform, 64-bit) + a 32-bit lane offset within
     // it (below (RB / KW) kpad + 128 < 2^32 whatever the plane size): scalar-base stores, no
     // per-lane 64-bit address arithmetic
-    const int64_t r0b = by * (RB / KW), k0b = bx * KW * 64;
+    const int64_t r0b = by * (RB / KW), k0b = bx * res_block_k(RB, EPT);
     planes += r0b * kpad + k0b;
-    const uint32_t loff = (uint32_t)((r - r0b) * kpad + (k - k0b));
+    const uint32_t loff = (uint32_t)((r - r0b) * kpad + (kbase + lane - k0b));   // entry 0
     // packed stores: lane 4 a + q writes entries 4 a .. 4 a + 3 of plane q of four
-    const int lane = tid & 63;
     const QuadSel qsel = quad_sel(lane);
     const int64_t qoff = (int64_t)(lane & 3) * plane_stride + (int64_t)(loff & ~3u);
-    const double sgn = s < 0 ? -1.0 : 1.0;
+    const uint32_t *col = words + tid;
     for (int grp = 0; grp < lgroups; ++grp) {
-        double acc[KG];
+        double acc[EPT][KG];
 #pragma unroll
-        for (int g = 0; g < KG; ++g) acc[g] = 0.0;
+        for (int e = 0; e < EPT; ++e)
+#pragma unroll
+            for (int g = 0; g < KG; ++g) acc[e][g] = 0.0;
         gdouble *c = gtab + (size_t)grp * nw32 * KG;   // uniform: scalar loads
         for (int w = 0; w < nw32; ++w) {
-            const double x = (double)col[w * BD];
+            double x[EPT];
 #pragma unroll
-            for (int g = 0; g < KG; ++g) acc[g] = fma(x, c[w * KG + g], acc[g]);
+            for (int e = 0; e < EPT; ++e) x[e] = (double)col[e * BD + w * ST];
+#pragma unroll
+            for (int g = 0; g < KG; ++g) {
+                const double cg = c[w * KG + g];
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) acc[e][g] = fma(x[e], cg, acc[e][g]);
+            }
         }
         OZ2H_G(ResGroup) *R = grec + grp;
         const uint32_t two = R->two;
@@ -296,66 +332,274 @@ __device__ __forceinline__ void residue_block_r(
         // dword stores after a quad byte transpose, four planes per store
         if ((grp + 1) * KG <= L && (two == 0u || two == (1u << KG) - 1u)) {
             const uint32_t gb = R->g0[0];
-            int ri[KG];
 #pragma unroll
-            for (int g = 0; g < KG; ++g) {
-                const double a = acc[g] * sgn;
-                ri[g] = (int)fma(-rint(a * R->inv_m[g]), R->md[g], a);
-            }
-            auto store4 = [&](uint32_t gp, int b0, int b1, int b2, int b3) {
-                g_i8 *pb = uniform_ptr((g_i8 *)planes + (int64_t)gp * plane_stride);
-                *(g_u32 *)(pb + qoff) = quad_transpose_bytes(pack_bytes(b0, b1, b2, b3), qsel);
-            };
-            if (two == 0u) {
-#pragma unroll
-                for (int g = 0; g < KG; g += 4) store4(gb + g, ri[g], ri[g + 1], ri[g + 2], ri[g + 3]);
-            } else {
-                int pl[3 * KG];   // (r0, r1, r0 + r1) of each modulus, in plane order
+            for (int e = 0; e < EPT; ++e) {
+                int ri[KG];
 #pragma unroll
                 for (int g = 0; g < KG; ++g) {
-                    const int r0 = ((ri[g] + 64) & 127) - 64;   // balanced base-128 split
-                    const int r1 = (ri[g] - r0) >> 7;
-                    pl[3 * g] = r0;
-                    pl[3 * g + 1] = r1;
-                    pl[3 * g + 2] = r0 + r1;
+                    const double a = acc[e][g] * sgn[e];
+                    ri[g] = (int)fma(-rint(a * R->inv_m[g]), R->md[g], a);
                 }
+                auto store4 = [&](uint32_t gp, int b0, int b1, int b2, int b3) {
+                    g_i8 *pb = uniform_ptr((g_i8 *)planes + (int64_t)gp * plane_stride);
+                    *(g_u32 *)(pb + qoff + 64 * e) = quad_transpose_bytes(pack_bytes(b0, b1, b2, b3), qsel);
+                };
+                if (two == 0u) {
 #pragma unroll
-                for (int j = 0; j < 3 * KG; j += 4) store4(gb + j, pl[j], pl[j + 1], pl[j + 2], pl[j + 3]);
+                    for (int g = 0; g < KG; g += 4) store4(gb + g, ri[g], ri[g + 1], ri[g + 2], ri[g + 3]);
+                } else {
+                    int pl[3 * KG];   // (r0, r1, r0 + r1) of each modulus, in plane order
+#pragma unroll
+                    for (int g = 0; g < KG; ++g) {
+                        const int r0 = ((ri[g] + 64) & 127) - 64;   // balanced base-128 split
+                        const int r1 = (ri[g] - r0) >> 7;
+                        pl[3 * g] = r0;
+                        pl[3 * g + 1] = r1;
+                        pl[3 * g + 2] = r0 + r1;
+                    }
+#pragma unroll
+                    for (int j = 0; j < 3 * KG; j += 4) store4(gb + j, pl[j], pl[j + 1], pl[j + 2], pl[j + 3]);
+                }
             }
             continue;
         }
 #pragma unroll
         for (int g = 0; g < KG; ++g) {
             if (grp * KG + g >= L) break;
-            const double a = acc[g] * sgn;
-            const int ri = (int)fma(-rint(a * R->inv_m[g]), R->md[g], a);
             g_i8 *pb = (g_i8 *)planes + (int64_t)R->g0[g] * plane_stride;
-            if (!((two >> g) & 1u)) {
-                pb[loff] = (int8_t)ri;
-            } else {
-                const int r0 = ((ri + 64) & 127) - 64;   // balanced base-128 split
-                const int r1 = (ri - r0) >> 7;
-                pb[loff] = (int8_t)r0;
-                pb[plane_stride + loff] = (int8_t)r1;
-                pb[2 * plane_stride + loff] = (int8_t)(r0 + r1);
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const double a = acc[e][g] * sgn[e];
+                const int ri = (int)fma(-rint(a * R->inv_m[g]), R->md[g], a);
+                const uint32_t lo = loff + 64 * e;
+                if (!((two >> g) & 1u)) {
+                    pb[lo] = (int8_t)ri;
+                } else {
+                    const int r0 = ((ri + 64) & 127) - 64;   // balanced base-128 split
+                    const int r1 = (ri - r0) >> 7;
+                    pb[lo] = (int8_t)r0;
+                    pb[plane_stride + lo] = (int8_t)r1;
+                    pb[2 * plane_stride + lo] = (int8_t)(r0 + r1);
+                }
             }
         }
     }
 }
 
-template <int RB, int KG>
+template <int RB, int KG, int EPT = 1>
 __device__ __forceinline__ void residue_block(const ResArgs &a, int64_t bx, int64_t by,
                                               uint32_t *words) {
-    residue_block_r<RB, KG>(a.limbs, a.exps, a.signs, a.erow, a.koff, a.tab, a.rgrp, a.planes, a.rs,
-                        a.cs, a.rows, a.count, a.kpad, a.plane_stride, a.p, a.nl, a.t, a.nw32,
-                        a.L, a.lgroups, bx, by, words);
+    residue_block_r<RB, KG, EPT>(a.limbs, a.exps, a.signs, a.erow, a.koff, a.tab, a.rgrp, a.planes,
+                                 a.rs, a.cs, a.rows, a.count, a.kpad, a.plane_stride, a.p, a.nl, a.t,
+                                 a.nw32, a.L, a.lgroups, bx, by, words);
 }
 
-template <int RB, int KG>
+template <int RB, int KG, int EPT>
 __global__ __launch_bounds__(64 * RB) void k_residues(ResArgs a) {
     extern __shared__ uint32_t words[];
-    const int64_t nbx = a.kpad / (64 * res_waves_k(RB));
-    residue_block<RB, KG>(a, (int64_t)blockIdx.x % nbx, (int64_t)blockIdx.x / nbx, words);
+    const int64_t nbx = a.kpad / res_block_k(RB, EPT);
+    residue_block<RB, KG, EPT>(a, (int64_t)blockIdx.x % nbx, (int64_t)blockIdx.x / nbx, words);
+}
+
+// lanes of one wave hand data over through LDS: keep the compiler from moving LDS
+// accesses across this point (LDS itself serves a wave's instructions in order)
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Residues of a^ on the vector ALUs with row broadcasts (stage 2, no MFMA).  The residue
+// of a^ = sum_w x_w 2^(32 w) modulo m is sum_w x_w c_w with the centred c_w = 2^(32 w) mod m
+// (an exact fp64 integer, |sum| < 2^53), then a^ - rint(a^/m) m.  Each lane of a 16-lane row
+// owns one modulus of a group of 16 and keeps that modulus's weights c_w in registers; the
+// row works on one entry at a time, its 32-bit words spread over the row's lanes (lane j
+// holds word 16 c + j of chunk c), and each multiply-add takes the word from lane w % 16 by
+// a DPP row broadcast (v_fmac_f64 with row_newbcast): no constant loads in the inner loop.
+// A block of four waves covers 128 consecutive k of one row of the operand side:
+//   phase 1: threads 0-127 build their entry's words into LDS (word w of entry e at
+//            words[w * kResRowS + e]: a row of 16 lanes reading 16 words of one entry, and
+//            the four rows four entries 16 apart, hit 64 different banks);
+//   phase 2: wave v takes entry half h = v & 1 (entries 64 h ..) and the moduli groups
+//            g = v >> 1, v >> 1 + 2, ..; row q of the wave takes entries 64 h + 16 q + i,
+//            i < 16, four at a time (four independent accumulators per lane);
+//   stores:  the residue bytes of a group go through an LDS staging area [plane][64 entries]
+//            and leave as 64-byte plane segments, four planes per store instruction.
+constexpr int kResRowS = 129;   // LDS word stride of the row-broadcast residue kernel
+constexpr int kResRowStage = 48 * 64;   // staging bytes per wave: up to 48 planes x 64 entries
+
+// v_fmac_f64 with its first source broadcast from lane LANE of each row of 16 lanes (DPP
+// row_newbcast).  The DPP source must not be written by a VALU instruction in the two
+// instructions before; the words come from asm blocks that end with s_nop 1.
+template <int LANE>
+__device__ __forceinline__ void fmac_rowbcast(double &acc, double x, double c) {
+    asm volatile("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+                 : "+v"(acc)
+                 : "v"(x), "v"(c), "n"(LANE));
+}
+
+// four words as doubles, followed by the two wait states a DPP read of them needs
+__device__ __forceinline__ void cvt4_words(uint32_t a, uint32_t b, uint32_t c, uint32_t d, double &x0,
+                                           double &x1, double &x2, double &x3) {
+    asm volatile(
+        "v_cvt_f64_u32 %0, %4\n\t"
+        "v_cvt_f64_u32 %1, %5\n\t"
+        "v_cvt_f64_u32 %2, %6\n\t"
+        "v_cvt_f64_u32 %3, %7\n\t"
+        "s_nop 1"
+        : "=&v"(x0), "=&v"(x1), "=&v"(x2), "=&v"(x3)
+        : "v"(a), "v"(b), "v"(c), "v"(d));
+}
+
+// words NC-word chunk (NC = 16 or 4) into the four accumulators: lane j's weights c[i] are
+// word w0 + i's; word w0 + i of entry q comes from lane i of the row
+template <int NC, int I = 0>
+__device__ __forceinline__ void row_fmas(double (&a)[4], const double (&x)[4], const double *c) {
+    if constexpr (I < NC) {
+        fmac_rowbcast<I>(a[0], x[0], c[I]);
+        fmac_rowbcast<I>(a[1], x[1], c[I]);
+        fmac_rowbcast<I>(a[2], x[2], c[I]);
+        fmac_rowbcast<I>(a[3], x[3], c[I]);
+        row_fmas<NC, I + 1>(a, x, c);
+    }
+}
+
+struct ResRowArgs {
+    const uint64_t *limbs;
+    const int32_t *exps;
+    const int8_t *signs;
+    int64_t rs, cs, rows, count, kpad, plane_stride;
+    const int32_t *erow;
+    const int32_t *koff;   // nullable per-contraction exponent offsets (exponent folding)
+    int p, nl, t, nw32, nwp, L, rg16;
+    const double *tab;     // [rg16][16][nwp]
+    const ModInfo *mi;
+    int8_t *planes;
+};
+
+__host__ __device__ constexpr size_t res_row_lds(int nwp) {
+    return (size_t)nwp * kResRowS * 4 + 128 * 8 + 4 * kResRowStage;
+}
+
+// EPR entries per row of a wave and group (16: wave v takes the entry half v & 1 and the
+// groups v >> 1, v >> 1 + 2, ..; 32: wave v takes all 128 entries and the groups v, v + 4,
+// .., so that every weight it loads serves twice the multiply-adds).  Row q's entries are
+// 64 s + 16 q + i (i < 16) for its half(s) s.  (Measured at 4096^2: EPR 32 is 4 % faster
+// than 16 at p = 2048; loading the next chunk's weights ahead was slower, and spilled.)
+template <int EPR>
+__device__ __forceinline__ void residues_row_block(const ResRowArgs &a, uint32_t *smem) {
+    constexpr int NH = EPR / 16;   // entry halves per wave
+    uint32_t *words = smem;
+    double *sgn = (double *)(smem + (size_t)a.nwp * kResRowS);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t nbx = a.kpad / 128;
+    const int64_t bx = (int64_t)blockIdx.x % nbx, r = (int64_t)blockIdx.x / nbx;
+    const int64_t k0 = bx * 128;
+
+    // phase 1: the words of the block's 128 entries
+    if (tid < 128) {
+        OZ2H_G(int8_t) *gsigns = (OZ2H_G(int8_t) *)a.signs;
+        OZ2H_G(int32_t) *gexps = (OZ2H_G(int32_t) *)a.exps;
+        const int64_t k = k0 + tid;
+        int s = 0;
+        int64_t sh = 0, idx = 0;
+        if (r < a.rows && k < a.count) {
+            idx = r * a.rs + k * a.cs;
+            s = gsigns[idx];
+            sh = (int64_t)a.t - a.p + gexps[idx] + (a.koff ? a.koff[k] : 0) - a.erow[r];
+        }
+        s = build_words((OZ2H_G(uint64_t) *)a.limbs + idx * a.nl, s, sh, a.p, a.nwp, words + tid,
+                        kResRowS);
+        sgn[tid] = s < 0 ? -1.0 : 1.0;
+    }
+    __syncthreads();
+
+    // phase 2
+    const int j = lane & 15, q = lane >> 4;
+    const int h0 = NH == 2 ? 0 : (wv & 1);        // first entry half of this wave
+    const int g0w = NH == 2 ? wv : (wv >> 1), gstep = NH == 2 ? 4 : 2;
+    uint8_t *stg = (uint8_t *)(sgn + 128) + (size_t)wv * kResRowStage;
+    const int nfull = a.nw32 >> 4, ntail = ((a.nw32 & 15) + 3) >> 2;
+    int8_t *prow = a.planes + r * a.kpad + k0;   // the block's segment of plane 0
+    for (int g = g0w; g < a.rg16; g += gstep) {
+        const int l = 16 * g + j;
+        const bool live = l < a.L;
+        const ModInfo mi = live ? load_info((OZ2H_G(ModInfo) *)a.mi + l) : ModInfo{};
+        const ModInfo m0 = load_info((OZ2H_G(ModInfo) *)a.mi + 16 * g);
+        const int llast = min(16 * g + 15, a.L - 1);
+        const ModInfo ml = load_info((OZ2H_G(ModInfo) *)a.mi + llast);
+        const int gp0 = (int)m0.g0, np = (int)(ml.g0 + ml.nprod) - gp0;   // this group's planes
+        const double *crow = a.tab + ((size_t)g * 16 + j) * a.nwp;
+        double acc[EPR];
+#pragma unroll
+        for (int i = 0; i < EPR; ++i) acc[i] = 0.0;
+        // one NC-word chunk (NC = 16 or 4) from word w0 with the weights c
+        auto chunk = [&](auto nc_, int w0, const double *c) {
+            constexpr int NC = decltype(nc_)::value;
+            const uint32_t *wr = words + (size_t)(w0 + (NC == 16 ? j : (j & 3))) * kResRowS + 16 * q;
+#pragma unroll
+            for (int eb = 0; eb < EPR / 4; ++eb) {
+                const int e = 64 * (h0 + eb / 4) + 4 * (eb % 4);   // + 16 q, entries e .. e + 3
+                double x[4], a4[4];
+                cvt4_words(wr[e], wr[e + 1], wr[e + 2], wr[e + 3], x[0], x[1], x[2], x[3]);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) a4[u] = acc[4 * eb + u];
+                row_fmas<NC>(a4, x, c);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[4 * eb + u] = a4[u];
+            }
+        };
+        for (int c = 0; c < nfull; ++c) {
+            double cc[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) cc[i] = crow[16 * c + i];
+            chunk(std::integral_constant<int, 16>{}, 16 * c, cc);
+        }
+        for (int c = 0; c < ntail; ++c) {
+            double c4[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) c4[i] = crow[16 * nfull + 4 * c + i];
+            chunk(std::integral_constant<int, 4>{}, 16 * nfull + 4 * c, c4);
+        }
+
+        // per entry half: centred residues into the staging area (plane (g0 - gp0) [+ 1, + 2]
+        // of entry 16 q + i), then 64-byte plane segments, lane (q, j) storing bytes
+        // 4 j .. 4 j + 3 of plane 4 it + q
+#pragma unroll
+        for (int hh = 0; hh < NH; ++hh) {
+            const int hs = h0 + hh;
+            if (live) {
+                const int po = (int)mi.g0 - gp0;
+                const double md = (double)mi.m;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const double x = acc[16 * hh + i] * sgn[64 * hs + 16 * q + i];
+                    const int ri = (int)fma(-rint(x * mi.inv_m), md, x);
+                    uint8_t *d = stg + (size_t)po * 64 + 16 * q + i;
+                    if (mi.nprod == 1) {
+                        d[0] = (uint8_t)ri;
+                    } else {
+                        const int r0 = ((ri + 64) & 127) - 64;   // balanced base-128 split
+                        const int r1 = (ri - r0) >> 7;
+                        d[0] = (uint8_t)r0;
+                        d[64] = (uint8_t)r1;
+                        d[128] = (uint8_t)(r0 + r1);
+                    }
+                }
+            }
+            wave_lds_sync();
+            for (int pp = q; pp < np; pp += 4) {
+                const uint32_t v = *(const uint32_t *)(stg + (size_t)pp * 64 + 4 * j);
+                *(g_u32 *)((g_i8 *)prow + (int64_t)(gp0 + pp) * a.plane_stride + 64 * hs + 4 * j) = v;
+            }
+            wave_lds_sync();
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_residues_row(ResRowArgs a) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t smem_rr[];
+    residues_row_block<32>(a, smem_rr);
 }
 
 // Residues of a^ on the matrix cores (stage 2).  For every modulus the residue of an
@@ -402,13 +646,6 @@ __host__ __device__ constexpr int res_mma_wave_lds(int nq) {
     return 64 * res_mma_es(nq) * 4 > 64 * kResScratchRow ? 64 * res_mma_es(nq) * 4 : 64 * kResScratchRow;
 }
 
-// lanes of one wave hand data over through LDS: keep the compiler from moving LDS
-// accesses across this point (LDS itself serves a wave's instructions in order)
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // At most NQ k-steps: entry and weight fragments live in registers (up to kResMmaPfQ
 // k-steps the weights of the next block of rows are prefetched while one block is

@@ -463,6 +463,21 @@ int build_plan(int p, int t, int64_t K, const std::vector<uint32_t> &mods_in, Pl
             x = ((x << 32) % m);
         }
     }
+    // the VALU kernel's table: per group of 16 moduli, one row of rnwp words per modulus,
+    // which the lane of that modulus reads in 16-word chunks
+    h.rnwp = (h.nw32 + 3) / 4 * 4;
+    h.rg16 = (h.L + 15) / 16;
+    h.resid_row.assign((size_t)h.rg16 * 16 * h.rnwp, 0.0);
+    for (int l = 0; l < h.L; ++l) {
+        const uint64_t m = mods[l];
+        uint64_t x = 1 % m;
+        for (int w = 0; w < h.nw32; ++w) {
+            int64_t c = (int64_t)x;
+            if (c > (int64_t)((m - 1) / 2)) c -= (int64_t)m;
+            h.resid_row[(size_t)l * h.rnwp + w] = (double)c;
+            x = (x << 32) % m;
+        }
+    }
     build_residue_mma_tables(h, mods);
     return 0;
 }

@@ -14,6 +14,9 @@ constexpr int kWideL = 96;
 constexpr int kResMmaMinWords = 8;    // with the matrix-core residue variant selected, integers
                                       // of >= this many 32-bit words (t >= 224) take it, narrower
                                       // ones the fp64 kernel
+constexpr int kResRowMinWords = 32;  // VALU residues: integers of >= this many words (t >= 992)
+                                      // take the row-broadcast kernel (faster from about there
+                                      // on at 4096^2), narrower ones the entry-per-thread kernel
 constexpr int kMaxModuli = 512;       // fp64-exact CRT digit sums need L * 2^44 < 2^53
 constexpr int kMaxWords = 256;        // fp64-exact residue sums need nw32 * 2^45 < 2^53
 constexpr int64_t kMaxK = 133000;     // K * 127^2 < 2^31, the cap the paper's implementation uses
@@ -80,6 +83,10 @@ struct PlanHost {
     std::vector<uint32_t> moduli;    // L, one-limb first
     std::vector<ModInfo> info;       // L
     std::vector<double> resid_tab;   // [lgroups][nw32][kg]: centred 2^(32w) mod m
+    int rnwp = 0;          // VALU residues: words per integer padded to a multiple of 4
+    int rg16 = 0;          // ... groups of 16 moduli
+    std::vector<double> resid_row;   // [rg16][16 moduli][rnwp words]: centred 2^(32w) mod m
+                                     // (0 past L and past nw32)
     std::vector<ResGroup> resgrp;    // [lgroups]
     int rnb = 0;           // MFMA residues: magnitude bytes (4 nw32), then two correction bytes
     int rnq = 0;           // ... 32-byte k-steps covering rnb + 2 bytes

@@ -70,16 +70,21 @@ def rng_idx(r, c, frac, seed=0):
     return rng.random((r, c)) < frac
 
 
-@pytest.mark.parametrize("p,lo,hi,side", [(128, -4, 4, "A"), (256, -32, 32, "B"),
-                                          (2048, -16, 16, "A"), (53, -300, 300, "B"),
-                                          (113, -64, 64, "A"), (1024, -300, 300, "B")])
-def test_residue_planes(oz, c_oracle, p, lo, hi, side):
+@pytest.mark.parametrize("p,lo,hi,side,flags", [
+    (128, -4, 4, "A", 0), (256, -32, 32, "B", 0), (2048, -16, 16, "A", 0), (53, -300, 300, "B", 0),
+    (113, -64, 64, "A", 0), (1024, -300, 300, "B", 0),
+    # the row-broadcast VALU kernel (integers of 32 words or more) on both sides, and the
+    # matrix-core variant
+    (2048, -16, 16, "B", 0), (1536, -40, 40, "A", 0), (960, -8, 8, "A", 0), (3000, -8, 8, "B", 0),
+    (2048, -16, 16, "A", 1), (512, -32, 32, "B", 1)])
+def test_residue_planes(oz, c_oracle, p, lo, hi, side, flags):
     """Stage 2 vs Python-int centred residues of the oracle's integers a^."""
     R, C = (70, 150) if side == "A" else (150, 70)
     X = synth.mp_random(11 + p, R, C, p, lo, hi)
     X.sign[rng_idx(R, C, 0.05, p)] = 0
     K = C if side == "A" else R
-    check_residue_planes(oz, c_oracle, oz.Plan.create(p, K), X, side, K, f"p={p} side={side}")
+    check_residue_planes(oz, c_oracle, oz.Plan.create(p, K, oz.default_opts(flags=flags)), X, side, K,
+                         f"p={p} side={side} flags={flags}")
 
 
 def test_residue_planes_wide_set_narrow_integers(oz, c_oracle):
