@@ -134,11 +134,18 @@ def device_operands(cfg, seed):
 
 
 def kernel_names(plan, flags):
-    """The stage-2 / stage-4 kernels a plain call of this plan launches."""
+    """The stage-2 / stage-4 kernels a plain call of this plan launches (the dominant one
+    where a stage has two)."""
     from paper_2609_27831_amd import oz2h
-    res = "k_residues_mma" if (flags & oz2h.FLAG_RESIDUES_MMA) and plan.nw32 >= 8 else "k_residues"
-    crt_mma = (flags & oz2h.FLAG_CRT_MMA) and 16 <= plan.nd32 <= 32 and plan.L <= 127
-    return res, "k_crt_mma" if crt_mma else "k_crt"
+    if (flags & oz2h.FLAG_RESIDUES_MMA) and plan.nw32 >= 8:
+        res = "k_residues_mma"
+    else:
+        res = "k_residues_row" if plan.nw32 >= 32 else "k_residues"
+    if (flags & oz2h.FLAG_CRT_MMA) and 16 <= plan.nd32 <= 32 and plan.L <= 127:
+        crt = "k_crt_mma"
+    else:
+        crt = "k_crt_row_sums" if plan.nd32 > 32 else "k_crt"
+    return res, crt
 
 
 def time_plain(name, Ad, Bd, steps, warmup, flags=0):
@@ -187,13 +194,13 @@ def time_plain(name, Ad, Bd, steps, warmup, flags=0):
     gemm_tops = gemm_ops / sec["gemm"] / 1e12
     phases["residues"].update({
         "kernel": res_k, "hbm_gbs": round(res_bytes / sec["residues"] / 1e9, 1),
-        "fp64_tflops": round(2.0 * res_fma / sec["residues"] / 1e12, 2) if res_k == "k_residues" else None,
+        "fp64_tflops": round(2.0 * res_fma / sec["residues"] / 1e12, 2) if not res_k.endswith("_mma") else None,
         "counter_hbm_gbs": None})
     phases["gemm"].update({"kernel": "k_resgemm", "int8_tops": round(gemm_tops, 1),
                            "int8_mfma_pct_of_peak": round(100.0 * gemm_tops / PEAK_INT8_TOPS, 2)})
     phases["crt"].update({
         "kernel": crt_k, "hbm_gbs": round(crt_bytes / sec["crt"] / 1e9, 1),
-        "fp64_tflops": round(2.0 * crt_fma / sec["crt"] / 1e12, 2) if crt_k == "k_crt" else None,
+        "fp64_tflops": round(2.0 * crt_fma / sec["crt"] / 1e12, 2) if not crt_k.endswith("_mma") else None,
         "counter_hbm_gbs": None})
     for ph, kern in (("residues", res_k), ("crt", crt_k)):
         tb = measured_traffic(kern, name)

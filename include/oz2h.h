@@ -342,14 +342,22 @@ int oz2h_i8gemm(int64_t M, int64_t N, int64_t K, const int8_t *A, const int8_t *
  * multiple-precision division"): from u_l = c^ mod m_l (int16, any
  * representative with |u_l| < m_l, plane l at u[l*plane_stride + i*ldu + j])
  * reconstructs c^ with |c^| < P/2 as chat_sign[i*N + j] and nlc magnitude limbs
- * chat_mag[(i*N + j)*nlc + l].  The kernel is the plan's stage-4 variant (the
- * matrix-core one under OZ2H_FLAG_CRT_MMA where it applies).  Every c^ in
- * (-P/2, P/2) is reconstructed, those next to +-P/2 through the paper's
- * alpha - 1 sequence; for even P the class of P/2 comes back as +P/2.
+ * chat_mag[(i*N + j)*nlc + l].  Every c^ in (-P/2, P/2) is reconstructed, those
+ * next to +-P/2 through the paper's alpha - 1 sequence; for even P the class of
+ * P/2 comes back as +P/2.
+ * Kernel: the plan's stage-4 variant (the matrix-core one under OZ2H_FLAG_CRT_MMA
+ * where it applies).  For CRTs of more than 32 digits, a device workspace of
+ * oz2h_crt_workspace_size(plan, M, ldu) bytes (256-byte aligned; scratch) selects
+ * the row-broadcast VALU kernels, which need ldu % 16 == 0, plane_stride >=
+ * M*ldu, plane_stride % 16 == 0 and u 32-byte aligned, and read all M*ldu
+ * entries of every plane; workspace = NULL (or a layout outside these
+ * conditions) takes the entry-per-thread VALU kernel.  A non-NULL workspace below
+ * the size is OZ2H_ENOMEM.
  */
+size_t oz2h_crt_workspace_size(const oz2h_plan *plan, int64_t M, int64_t ldu);
 int oz2h_crt(const oz2h_plan *plan, int64_t M, int64_t N, const int16_t *u, int64_t ldu,
              int64_t plane_stride, int8_t *chat_sign, uint64_t *chat_mag, int32_t nlc,
-             hipStream_t stream);
+             void *workspace, size_t ws_bytes, hipStream_t stream);
 
 /* ---------------- batched form ---------------- */
 

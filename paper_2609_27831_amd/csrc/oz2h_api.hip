@@ -36,6 +36,7 @@ struct oz2h_plan {
     ResRowBlock *d_rmma_rb = nullptr;
     int8_t *d_crt_afr = nullptr;
     double *d_crt = nullptr;
+    double *d_crt_row = nullptr;
     uint32_t *d_pd = nullptr;
     uint32_t *d_phd = nullptr;
 };
@@ -324,7 +325,28 @@ bool crt_mma_eligible(const PlanHost &h, const CrtCfg &c) {
            h.nd32 >= kCrtMmaMinDigits;
 }
 
+// The row-broadcast CRT (wide moduli sets): entries e' = i * ldv + j over M rows of v planes
+// of leading dimension ldv, tiles of 64, digits and carry-outs in a workspace.
+struct RowCrtCfg {
+    int64_t nent, estride;
+    int ntiles;
+    size_t bytes;
+};
+
+bool row_crt_eligible(const PlanHost &h) { return h.nd32 > kCrtRowMinDigits && !h.crt_row.empty(); }
+
+RowCrtCfg row_crt_config(const PlanHost &h, int64_t M, int64_t ldv) {
+    RowCrtCfg c{};
+    c.nent = M * ldv;
+    c.ntiles = (int)((c.nent + 2047) / 2048 * 32);   // a multiple of 32 (four tiles per block,
+                                                      // one block per XCD)
+    c.estride = (int64_t)c.ntiles * 64;
+    c.bytes = (size_t)(16 + 1) * h.crt_ndg * (size_t)c.estride * sizeof(uint32_t);
+    return c;
+}
+
 size_t crt_gdig_bytes(const PlanHost &h, int64_t M, int64_t N) {
+    if (row_crt_eligible(h)) return row_crt_config(h, M, round_up(std::max<int64_t>(N, 1), 256)).bytes;
     const CrtCfg c = crt_config(h, M, N, true);
     return c.gdig ? (size_t)h.nd32 * (size_t)c.gstride * sizeof(uint32_t) : 0;
 }
@@ -345,6 +367,27 @@ int launch_crt(const oz2h_plan *pl, int64_t M, int64_t N, const int16_t *u, int6
                      pl->d_pd, pl->d_phd, e, f, tsum, h.p, osign, oexp, olimbs, ldc, chat, nlc, c.LB,
                      c.gdig ? gdig : nullptr, c.gstride, pl->d_crt_afr, h.crt_nbk, h.crt_kq,
                      h.crt_nt, h.crt_inv_ptop};
+    if (gdig && row_crt_eligible(h) && !crt_mma_eligible(h, c)) {
+        // row-broadcast CRT: the planes must hold M * ldu entries each, 32-byte aligned rows
+        const RowCrtCfg rc = row_crt_config(h, M, ldu);
+        if (ldu % 16 == 0 && u_ps >= M * ldu && u_ps % 16 == 0 && ((uintptr_t)u % 32) == 0) {
+            uint32_t *dig = gdig;
+            int32_t *cout = (int32_t *)(gdig + (size_t)16 * h.crt_ndg * rc.estride);
+            const CrtRowArgs ra{u, u_ps, rc.nent, ldu, h.L, h.crt_lpad, h.crt_ndg, h.nd32,
+                                pl->d_crt_row, pl->d_info, dig, cout, rc.estride, rc.ntiles};
+            const unsigned nb1 = (unsigned)((int64_t)rc.ntiles / 4 * h.crt_ndg);
+            const size_t lds1 = kCrtRowSumsLds;
+            if (weight) k_crt_row_sums<true><<<nb1, 256, lds1, s>>>(ra);
+            else k_crt_row_sums<false><<<nb1, 256, lds1, s>>>(ra);
+            int st = check_launch("CRT digit sums");
+            if (st) return st;
+            const unsigned nb2 = (unsigned)((rc.nent + 63) / 64);
+            const size_t lds2 = (size_t)64 * h.nd32 * sizeof(uint32_t);
+            if (round) k_crt_row_finish<true><<<nb2, 64, lds2, s>>>(ca, ra);
+            else k_crt_row_finish<false><<<nb2, 64, lds2, s>>>(ca, ra);
+            return check_launch("CRT finish");
+        }
+    }
     if (crt_mma_eligible(h, c)) {
         // matrix-core digit sums: 256 entries per block, one LDS digit column each
         const unsigned nbm = (unsigned)((M * N + 255) / 256);
@@ -402,6 +445,7 @@ int upload_plan(oz2h_plan *pl) {
     const size_t n_res = sizeof(double) * h.resid_tab.size();
     const size_t n_rrow = sizeof(double) * h.resid_row.size();
     const size_t n_crt = sizeof(double) * h.crt_digits.size();
+    const size_t n_crow = sizeof(double) * h.crt_row.size();
     const size_t n_pd = sizeof(uint32_t) * h.nd32;
     size_t off = 0;
     const size_t o_info = off;
@@ -423,6 +467,8 @@ int upload_plan(oz2h_plan *pl) {
     off = align_up(off + n_cafr);
     const size_t o_crt = off;
     off = align_up(off + n_crt);
+    const size_t o_crow = off;
+    off = align_up(off + n_crow);
     const size_t o_pd = off;
     off = align_up(off + n_pd);
     const size_t o_phd = off;
@@ -439,6 +485,7 @@ int upload_plan(oz2h_plan *pl) {
     pl->d_rmma_rb = (ResRowBlock *)(b + o_rrb);
     pl->d_crt_afr = (int8_t *)(b + o_cafr);
     pl->d_crt = (double *)(b + o_crt);
+    pl->d_crt_row = (double *)(b + o_crow);
     pl->d_pd = (uint32_t *)(b + o_pd);
     pl->d_phd = (uint32_t *)(b + o_phd);
     OZ2H_HIP(hipMemcpy(pl->d_info, h.info.data(), n_info, hipMemcpyHostToDevice));
@@ -449,6 +496,7 @@ int upload_plan(oz2h_plan *pl) {
     OZ2H_HIP(hipMemcpy(pl->d_rmma_rb, h.rmma_rb.data(), n_rrb, hipMemcpyHostToDevice));
     if (n_cafr) OZ2H_HIP(hipMemcpy(pl->d_crt_afr, h.crt_afr.data(), n_cafr, hipMemcpyHostToDevice));
     OZ2H_HIP(hipMemcpy(pl->d_crt, h.crt_digits.data(), n_crt, hipMemcpyHostToDevice));
+    if (n_crow) OZ2H_HIP(hipMemcpy(pl->d_crt_row, h.crt_row.data(), n_crow, hipMemcpyHostToDevice));
     OZ2H_HIP(hipMemcpy(pl->d_pd, h.p_digits.data(), n_pd, hipMemcpyHostToDevice));
     OZ2H_HIP(hipMemcpy(pl->d_phd, h.ph_digits.data(), n_pd, hipMemcpyHostToDevice));
     return OZ2H_OK;
@@ -1007,9 +1055,14 @@ int oz2h_i8gemm(int64_t M, int64_t N, int64_t K, const int8_t *A, const int8_t *
     return st ? st : ok();
 }
 
+size_t oz2h_crt_workspace_size(const oz2h_plan *plan, int64_t M, int64_t ldu) {
+    if (!plan || M < 0 || ldu < 0 || !row_crt_eligible(plan->h)) return 0;
+    return row_crt_config(plan->h, M, ldu).bytes;
+}
+
 int oz2h_crt(const oz2h_plan *plan, int64_t M, int64_t N, const int16_t *u, int64_t ldu,
              int64_t plane_stride, int8_t *chat_sign, uint64_t *chat_mag, int32_t nlc,
-             hipStream_t stream) {
+             void *workspace, size_t ws_bytes, hipStream_t stream) {
     int st = check_plan(plan);
     if (st) return st;
     if (M < 0 || N < 0) return fail(OZ2H_EINVAL, "negative dimension");
@@ -1017,8 +1070,16 @@ int oz2h_crt(const oz2h_plan *plan, int64_t M, int64_t N, const int16_t *u, int6
     if (!u || !chat_sign || !chat_mag) return fail(OZ2H_EINVAL, "NULL pointer");
     if (ldu < N || plane_stride < (M - 1) * ldu + N) return fail(OZ2H_EINVAL, "bad u layout");
     if ((int64_t)nlc * 64 < plan->h.pbits) return fail(OZ2H_EINVAL, "nlc too small");
+    uint32_t *gdig = nullptr;
+    if (workspace) {
+        if (((uintptr_t)workspace) % kAlign) return fail(OZ2H_EINVAL, "workspace must be 256-byte aligned");
+        if (ws_bytes < oz2h_crt_workspace_size(plan, M, ldu))
+            return fail(OZ2H_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes,
+                        oz2h_crt_workspace_size(plan, M, ldu));
+        gdig = (uint32_t *)workspace;
+    }
     st = launch_crt(plan, M, N, u, plane_stride, ldu, nullptr, nullptr, false, true, chat_sign,
-                    nullptr, nullptr, N, chat_mag, nlc, stream);
+                    nullptr, nullptr, N, chat_mag, nlc, stream, -1, gdig);
     return st ? st : ok();
 }
 

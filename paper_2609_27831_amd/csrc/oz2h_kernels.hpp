@@ -118,8 +118,8 @@ __device__ __forceinline__ ModInfo load_info(OZ2H_G(ModInfo) *p) {
 // alignbit(m_j, m_{j-1}, 32 - r); for sh < 0 the same pass collects the round bit
 // (position -sh - 1) and the sticky bits below it, and a round-up carries through the
 // words.  A shift below -(32 nd + 2) drops every bit, the round bit included (a^ = 0).
-// The limbs stream through a ring of four registers, loaded four limbs ahead with
-// clamped unconditional loads, so that the loads of one entry overlap.
+// The limbs stream through a ring of two registers, loaded two limbs ahead with clamped
+// unconditional loads, so that the loads of one entry overlap.
 __device__ __forceinline__ int build_words(OZ2H_G(uint64_t) *__restrict__ sl, int s, int64_t sh,
                                            int p, int nw, uint32_t *col, int st) {
     for (int w = 0; w < nw; ++w) col[w * st] = 0u;
@@ -152,22 +152,20 @@ __device__ __forceinline__ int build_words(OZ2H_G(uint64_t) *__restrict__ sl, in
         prev = cur;
     };
     auto ld = [&](int l) { return sl[min(l, nlimb - 1)]; };
-    uint64_t r0 = ld(0), r1 = ld(1), r2 = ld(2), r3 = ld(3);
+    uint64_t r0 = ld(0), r1 = ld(1);
     auto limb = [&](int l, uint64_t &r) {
         uint64_t x = l < nlimb ? r : 0ull;
         if (l == nlimb - 1) x &= topm;
-        r = ld(l + 4);
+        r = ld(l + 2);
         word(2 * l, (uint32_t)x);
         word(2 * l + 1, (uint32_t)(x >> 32));
     };
     // limbs 0 .. nlimb - 1, then one more word of zeros for the carry-out of the shift
-    for (int l = 0; l < nlimb; l += 4) {
+    for (int l = 0; l < nlimb; l += 2) {
         limb(l, r0);
         limb(l + 1, r1);
-        limb(l + 2, r2);
-        limb(l + 3, r3);
     }
-    word(2 * ((nlimb + 3) & ~3), 0u);
+    word(2 * ((nlimb + 1) & ~1), 0u);
     if (rbit && (sticky || (col[0] & 1u))) {   // round half to even: add one
         for (int w = 0; w < nw; ++w) {
             const uint32_t v = col[w * st] + 1u;
@@ -451,16 +449,15 @@ __device__ __forceinline__ void cvt4_words(uint32_t a, uint32_t b, uint32_t c, u
         : "v"(a), "v"(b), "v"(c), "v"(d));
 }
 
-// words NC-word chunk (NC = 16 or 4) into the four accumulators: lane j's weights c[i] are
-// word w0 + i's; word w0 + i of entry q comes from lane i of the row
-template <int NC, int I = 0>
-__device__ __forceinline__ void row_fmas(double (&a)[4], const double (&x)[4], const double *c) {
+// an NC-word chunk (NC = 16 or 4) into NE accumulators: lane j's weights c[i] are word
+// w0 + i's; word w0 + i of entry u comes from lane i of the row.  For each broadcast lane the
+// NE entries follow each other, so that consecutive multiply-adds are independent.
+template <int NC, int NE, int I = 0>
+__device__ __forceinline__ void row_fmas(double (&a)[NE], const double (&x)[NE], const double *c) {
     if constexpr (I < NC) {
-        fmac_rowbcast<I>(a[0], x[0], c[I]);
-        fmac_rowbcast<I>(a[1], x[1], c[I]);
-        fmac_rowbcast<I>(a[2], x[2], c[I]);
-        fmac_rowbcast<I>(a[3], x[3], c[I]);
-        row_fmas<NC, I + 1>(a, x, c);
+#pragma unroll
+        for (int u = 0; u < NE; ++u) fmac_rowbcast<I>(a[u], x[u], c[I]);
+        row_fmas<NC, NE, I + 1>(a, x, c);
     }
 }
 
@@ -538,15 +535,16 @@ __device__ __forceinline__ void residues_row_block(const ResRowArgs &a, uint32_t
             constexpr int NC = decltype(nc_)::value;
             const uint32_t *wr = words + (size_t)(w0 + (NC == 16 ? j : (j & 3))) * kResRowS + 16 * q;
 #pragma unroll
-            for (int eb = 0; eb < EPR / 4; ++eb) {
-                const int e = 64 * (h0 + eb / 4) + 4 * (eb % 4);   // + 16 q, entries e .. e + 3
-                double x[4], a4[4];
+            for (int eb = 0; eb < EPR / 8; ++eb) {
+                const int e = 64 * (h0 + eb / 2) + 8 * (eb % 2);   // + 16 q, entries e .. e + 7
+                double x[8], a8[8];
                 cvt4_words(wr[e], wr[e + 1], wr[e + 2], wr[e + 3], x[0], x[1], x[2], x[3]);
+                cvt4_words(wr[e + 4], wr[e + 5], wr[e + 6], wr[e + 7], x[4], x[5], x[6], x[7]);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) a4[u] = acc[4 * eb + u];
-                row_fmas<NC>(a4, x, c);
+                for (int u = 0; u < 8; ++u) a8[u] = acc[8 * eb + u];
+                row_fmas<NC, 8>(a8, x, c);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) acc[4 * eb + u] = a4[u];
+                for (int u = 0; u < 8; ++u) acc[8 * eb + u] = a8[u];
             }
         };
         for (int c = 0; c < nfull; ++c) {
@@ -1645,6 +1643,237 @@ template <int KQ, bool ROUND, bool WEIGHT>
 __global__ __launch_bounds__(256) void k_crt_mma(CrtArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint32_t sdig[];
     crt_mma_block<KQ, ROUND, WEIGHT>(a, blockIdx.x, sdig);
+}
+
+// Direct CRT for wide moduli sets on the vector ALUs with row broadcasts (no MFMA), in two
+// kernels.  S = sum_l v_l M_l, M_l = P / m_l in balanced base-2^32 digits D[d][l]: each digit
+// sum S_d = sum_l v_l D[d][l] is an exact fp64 integer (|S_d| < L 2^44 < 2^53).
+//   k_crt_row_sums: a wave takes 64 consecutive entries and one group of 16 digits.  Lane j
+//     of row q owns digit 16 dg + j of the row's entries 16 q + i (i < 16) and keeps, per
+//     chunk of 16 moduli, their 16 digit constants in registers; lane m of the row loads v of
+//     modulus 16 c + m for the row's 16 entries, and each multiply-add takes v from lane m by
+//     a DPP row broadcast.  The 16 sums of an entry then go through LDS to one lane, which
+//     carries them into 16 digits in [0, 2^32) and a carry-out (digit-major in the
+//     workspace: digit k of entry e at dig[k * estride + e]).  Blocks are one wave; the
+//     digit groups of a tile run on one XCD (block b goes to XCD b mod 8), so that the tile's
+//     v planes are read from HBM once and then from that XCD's L2.
+//   k_crt_row_finish: one entry per thread: the groups' carry-outs are added in, S's nd32
+//     digits land in an LDS column, and from there as in the matrix-core CRT: beta from the
+//     top digits (the paper's alpha - 1 when the estimate is within 2^-30 of a half-integer),
+//     S - beta P, and crt_finish (symmetric lift, one rounding).
+struct CrtRowArgs {
+    const int16_t *V;
+    int64_t v_ps;       // plane stride of v; entry e' = i * ldv + j of a plane is at V + e'
+    int64_t nent;       // entries e' covered: M * ldv
+    int64_t ldv;
+    int L, lpad, ndg, nd32;
+    const double *drow;   // [16 ndg][lpad]
+    const ModInfo *mi;    // WEIGHT: plain residues u_l, weighted here
+    uint32_t *dig;        // [16 ndg][estride]
+    int32_t *cout;        // [ndg][estride]
+    int64_t estride;      // >= 64 * ntiles
+    int ntiles;           // tiles of 64 entries (a multiple of 32: four per block, one block
+                          // per XCD)
+};
+
+// 16 values as doubles, followed by the two wait states a DPP read of them needs
+__device__ __forceinline__ void dpp_ready16(double (&x)[16]) {
+    asm volatile("s_nop 1"
+                 : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(x[5]),
+                   "+v"(x[6]), "+v"(x[7]), "+v"(x[8]), "+v"(x[9]), "+v"(x[10]), "+v"(x[11]),
+                   "+v"(x[12]), "+v"(x[13]), "+v"(x[14]), "+v"(x[15]));
+}
+
+// 16 x 16 multiply-adds: for each broadcast lane m (modulus 16 c + m), the 16 entries'
+// accumulators in turn, so that consecutive multiply-adds are independent
+template <int M = 0>
+__device__ __forceinline__ void crt_row_fmas(double (&acc)[16], const double (&x)[16], const double (&c)[16]) {
+    if constexpr (M < 16) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) fmac_rowbcast<M>(acc[i], x[i], c[M]);
+        crt_row_fmas<M + 1>(acc, x, c);
+    }
+}
+
+// The digit constants of the block's digit group are staged in LDS kCrtRowStage moduli at a
+// time (row jj = digit 16 dg + jj), with a row stride = 2 mod 32 doubles, so that the 16 rows
+// a ds_read_b128 of 16 lanes touches start on 16 different 4-bank groups.
+constexpr int kCrtRowStage = 192;
+constexpr int kCrtRowDStride = kCrtRowStage + 2;
+constexpr size_t kCrtRowSumsLds = (size_t)16 * kCrtRowDStride * 8 + (size_t)4 * 32 * 17 * 8;
+
+// blocks of four waves: four consecutive tiles of 64 entries, one digit group; block b runs
+// on XCD b mod 8 and the digit groups of a tile quad go to one XCD.  Every wave takes part
+// in the staging barriers; a wave past the last tile computes on tile 0 and stores nothing.
+template <bool WEIGHT>
+__global__ __launch_bounds__(256) void k_crt_row_sums(CrtRowArgs a) {
+    extern __shared__ __attribute__((aligned(16))) double smem_crs[];
+    double *Dl = smem_crs;   // [16][kCrtRowDStride]
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double *T = smem_crs + (size_t)16 * kCrtRowDStride + (size_t)wv * 32 * 17;   // transpose
+    const uint32_t b = blockIdx.x, x8 = b & 7u, s = b >> 3;
+    const int dg = (int)(s % (uint32_t)a.ndg);
+    const int64_t tile0 = ((int64_t)(s / (uint32_t)a.ndg) * 8 + x8) * 4 + wv;
+    const bool live = tile0 * 64 < a.nent;
+    const int64_t tile = live ? tile0 : 0;
+    const int q = lane >> 4, j = lane & 15;
+    const int64_t e_row = tile * 64 + 16 * q;   // this row's entries e_row + i
+    typedef const __attribute__((address_space(1))) v4i gv4i;
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const double *gsrc = a.drow + (size_t)16 * dg * a.lpad;
+    double acc[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.0;
+    const int nch = a.lpad >> 4;
+    // chunk c of 16 moduli: v of modulus min(16 c + j, L - 1) for the row's 16 entries (32
+    // bytes; nent is a multiple of 64 and the launch checks that every plane holds nent
+    // entries), loaded one chunk ahead; the 16 digit constants of this lane's digit from LDS
+    // (zero past L)
+    auto loadv = [&](int c, v4i &w0, v4i &w1) {
+        const int lc = min(16 * c + j, a.L - 1);
+        gv4i *src = (gv4i *)(a.V + (int64_t)lc * a.v_ps + e_row);
+        w0 = src[0];
+        w1 = src[1];
+    };
+    auto mult = [&](int c, int l0, const v4i &w0, const v4i &w1) {
+        const double *drow = Dl + j * kCrtRowDStride + (16 * c - l0);
+        double dc[16];
+#pragma unroll
+        for (int m = 0; m < 16; m += 2) {
+            const d2 t = *(const d2 *)(drow + m);
+            dc[m] = t.x;
+            dc[m + 1] = t.y;
+        }
+        double vd[16];
+        const int raw[8] = {w0[0], w0[1], w0[2], w0[3], w1[0], w1[1], w1[2], w1[3]};
+        ModInfo mi{};
+        if constexpr (WEIGHT) mi = load_info((OZ2H_G(ModInfo) *)a.mi + min(16 * c + j, a.L - 1));
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int lo = (raw[t] << 16) >> 16, hi = raw[t] >> 16;
+            if constexpr (WEIGHT) {
+                vd[2 * t] = (double)centred_mod((double)lo * (double)mi.minv, (double)mi.m, mi.inv_m);
+                vd[2 * t + 1] = (double)centred_mod((double)hi * (double)mi.minv, (double)mi.m, mi.inv_m);
+            } else {
+                vd[2 * t] = (double)lo;
+                vd[2 * t + 1] = (double)hi;
+            }
+        }
+        dpp_ready16(vd);
+        crt_row_fmas(acc, vd, dc);
+    };
+    v4i aw0, aw1, bw0, bw1;
+    loadv(0, aw0, aw1);
+    for (int l0 = 0; l0 < a.lpad; l0 += kCrtRowStage) {
+        const int nl = min(kCrtRowStage, a.lpad - l0);
+        __syncthreads();   // the previous stage has been read by every wave
+        for (int t = threadIdx.x; t < 16 * nl; t += 256) {
+            const int jj = t / nl, l = t - jj * nl;
+            Dl[jj * kCrtRowDStride + l] = gsrc[(size_t)jj * a.lpad + l0 + l];
+        }
+        __syncthreads();
+        const int c1 = (l0 + nl) >> 4;
+        int c = l0 >> 4;
+        for (; c + 2 <= c1; c += 2) {
+            loadv(min(c + 1, nch - 1), bw0, bw1);
+            mult(c, l0, aw0, aw1);
+            loadv(min(c + 2, nch - 1), aw0, aw1);
+            mult(c + 1, l0, bw0, bw1);
+        }
+        if (c < c1) {
+            mult(c, l0, aw0, aw1);
+            loadv(min(c + 1, nch - 1), aw0, aw1);
+        }
+    }
+    // two halves of 32 entries: entry 16 q + i of the half's rows gets digit sum j at
+    // T[(16 (q & 1) + i) * 17 + j]; lane 32 h + e then carries entry 32 h + e's 16 sums into
+    // digits in [0, 2^32) and a carry-out
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        wave_lds_sync();
+        if ((q >> 1) == h) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) T[(16 * (q & 1) + i) * 17 + j] = acc[i];
+        }
+        wave_lds_sync();
+        if ((lane >> 5) == h) {
+            const int el = lane & 31;
+            const int64_t e = tile * 64 + lane;
+            double cy = 0.0;
+            uint32_t dv[16];
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) {
+                const double xv = T[el * 17 + jj] + cy;
+                cy = floor(xv * 0x1p-32);
+                dv[jj] = (uint32_t)(xv - cy * 0x1p32);
+            }
+            if (live) {
+#pragma unroll
+                for (int jj = 0; jj < 16; ++jj) a.dig[(int64_t)(16 * dg + jj) * a.estride + e] = dv[jj];
+                a.cout[(int64_t)dg * a.estride + e] = (int32_t)cy;
+            }
+        }
+    }
+}
+
+// N columns of valid entries per row of ldv: entry e' = i * ldv + j, output (i, j) if j < N
+template <bool ROUND>
+__global__ __launch_bounds__(64) void k_crt_row_finish(CrtArgs a, CrtRowArgs r) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t sdig[];
+    const int tid = threadIdx.x;
+    const int64_t ep = (int64_t)blockIdx.x * 64 + tid;
+    const int64_t i = ep / r.ldv, jj = ep - i * r.ldv;
+    if (ep >= r.nent || jj >= a.N) return;
+    const int nd32 = a.nd32;
+    uint32_t *col = sdig + tid;   // digit k at col[64 k]
+    // the digits of a group load together (16 loads in flight), the next group's while one
+    // is carried through (two register sets)
+    const int ng = min(r.ndg, (nd32 + 15) / 16);
+    auto ldg = [&](int g, uint32_t (&dv)[16], int32_t &co) {
+        const int gc = min(g, ng - 1);
+#pragma unroll
+        for (int jj2 = 0; jj2 < 16; ++jj2) dv[jj2] = r.dig[(int64_t)(16 * gc + jj2) * r.estride + ep];
+        co = gc > 0 ? r.cout[(int64_t)(gc - 1) * r.estride + ep] : 0;
+    };
+    int64_t carry = 0;
+    auto ripple = [&](int g, const uint32_t (&dv)[16], int32_t co) {
+        carry += co;
+#pragma unroll
+        for (int jj2 = 0; jj2 < 16; ++jj2) {
+            const int k = 16 * g + jj2;
+            const int64_t xv = (int64_t)dv[jj2] + carry;
+            if (k < nd32) col[64 * k] = (uint32_t)xv;
+            carry = xv >> 32;
+        }
+    };
+    uint32_t da[16], db[16];
+    int32_t ca, cb;
+    ldg(0, da, ca);
+    int g = 0;
+    for (; g + 2 <= ng; g += 2) {
+        ldg(g + 1, db, cb);
+        ripple(g, da, ca);
+        ldg(g + 2, da, ca);
+        ripple(g + 1, db, cb);
+    }
+    if (g < ng) ripple(g, da, ca);
+    // S < L P keeps the two top digits as sign extension: the column holds S in two's
+    // complement and the carry beyond it is S's sign
+    const int64_t sgn = (int32_t)col[64 * (nd32 - 1)] < 0 ? -1 : 0;
+    double val = (double)(int32_t)col[64 * (nd32 - 1)];
+    for (int k = nd32 - 2; k >= nd32 - a.nt; --k) val = val * 4294967296.0 + (double)col[64 * k];
+    const double est = val * a.inv_ptop, rr = rint(est);
+    const bool slow = fabs(est - rr) > 0.5 - 0x1p-30;
+    const int64_t beta = slow ? (int64_t)floor(est) - 1 : (int64_t)rr;
+    typedef const __attribute__((address_space(4))) uint32_t cu32;
+    cu32 *Pd = (cu32 *)a.Pd;
+    int64_t cy = 0;
+    for (int k = 0; k < nd32; ++k) {
+        const int64_t xv = (int64_t)col[64 * k] - beta * (int64_t)Pd[k] + cy;
+        col[64 * k] = (uint32_t)xv;
+        cy = xv >> 32;
+    }
+    crt_finish<ROUND>(a, i * a.N + jj, col, 64, slow, cy + sgn);
 }
 
 // planes [G][R][C] (int8, row stride ldi) -> [G][Co][Ro] (row stride Ro), zero where

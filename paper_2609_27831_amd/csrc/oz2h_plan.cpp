@@ -241,11 +241,6 @@ void build_crt_mma_tables(PlanHost &h, const std::vector<uint32_t> &mods, const 
                 for (int e = 0; e < 16; ++e)
                     h.crt_afr[(((size_t)r * h.crt_kq + q) * 64 + lane) * 16 + e] =
                         T[(size_t)(32 * r + lane % 32) * kk + 32 * q + 16 * (lane / 32) + e];
-    // S/P from the top crt_nt digits of S: S_top 2^(32 (nd32 - nt)) / P
-    h.crt_nt = std::min(h.nd32, 5);
-    double pd = 0.0;
-    for (size_t i = P.size(); i-- > 0;) pd = pd * 4294967296.0 + (double)P[i];
-    h.crt_inv_ptop = std::ldexp(1.0, 32 * (h.nd32 - h.crt_nt)) / pd;
     h.crt_mma = true;
 }
 
@@ -427,6 +422,22 @@ int build_plan(int p, int t, int64_t K, const std::vector<uint32_t> &mods_in, Pl
             return -1;
         }
     }
+    // S/P from the top crt_nt digits of S: S_top / P_top with X_top = X / 2^(32 (nd32 - nt))
+    // (P's digits below the top nt are dropped: P_top keeps at least 64 of P's bits)
+    h.crt_nt = std::min(h.nd32, 5);
+    {
+        double ptop = 0.0;
+        for (int k = h.nd32 - 1; k >= h.nd32 - h.crt_nt; --k)
+            ptop = ptop * 4294967296.0 + (double)(k < (int)P.size() ? P[k] : 0u);
+        h.crt_inv_ptop = 1.0 / ptop;
+    }
+    // the row-broadcast CRT's table: digit d of M_l at [d][l], 16 digits per lane row group
+    h.crt_ndg = (h.nd32 + 15) / 16;
+    h.crt_lpad = (h.L + 15) / 16 * 16;
+    h.crt_row.assign((size_t)16 * h.crt_ndg * h.crt_lpad, 0.0);
+    for (int l = 0; l < h.L; ++l)
+        for (int d = 0; d < h.nd32 && d < h.crt_ndpad; ++d)
+            h.crt_row[(size_t)d * h.crt_lpad + l] = h.crt_digits[(size_t)l * h.crt_ndpad + d];
     build_crt_mma_tables(h, mods, P);
     h.p_digits.assign(h.nd32, 0);
     h.ph_digits.assign(h.nd32, 0);

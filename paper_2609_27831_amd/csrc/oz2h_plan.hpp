@@ -17,6 +17,7 @@ constexpr int kResMmaMinWords = 8;    // with the matrix-core residue variant se
 constexpr int kResRowMinWords = 32;  // VALU residues: integers of >= this many words (t >= 992)
                                       // take the row-broadcast kernel (faster from about there
                                       // on at 4096^2), narrower ones the entry-per-thread kernel
+constexpr int kCrtRowMinDigits = 32;  // CRTs of more digits take the row-broadcast kernels
 constexpr int kMaxModuli = 512;       // fp64-exact CRT digit sums need L * 2^44 < 2^53
 constexpr int kMaxWords = 256;        // fp64-exact residue sums need nw32 * 2^45 < 2^53
 constexpr int64_t kMaxK = 133000;     // K * 127^2 < 2^31, the cap the paper's implementation uses
@@ -94,11 +95,14 @@ struct PlanHost {
     std::vector<int8_t> rmma_w;          // [rnrb][rnq][64 lanes][16]: MFMA A fragments
     std::vector<ResRowBlock> rmma_rb;    // [rnrb]
     std::vector<double> crt_digits;  // [L][crt_ndpad]: balanced base-2^32 digits of P/m
+    int crt_ndg = 0;       // row-broadcast CRT: groups of 16 digits
+    int crt_lpad = 0;      // ... moduli padded to a multiple of 16
+    std::vector<double> crt_row;     // [16 crt_ndg][crt_lpad]: digit d of P/m_l at [d][l]
     bool crt_mma = false;  // matrix-core CRT tables built (nd32 <= 32, L <= 127)
     int crt_nbk = 0;       // ... blocks of 32 byte rows of S
     int crt_kq = 0;        // ... 32-byte contraction steps (2 L + 1 bytes)
-    int crt_nt = 0;        // ... top digits of S that estimate S / P
-    double crt_inv_ptop = 0;           // ... 2^(32 (nd32 - crt_nt)) / P
+    int crt_nt = 0;        // top digits of S that estimate S / P (every CRT kernel)
+    double crt_inv_ptop = 0;           // 1 / P_top, P_top = P / 2^(32 (nd32 - crt_nt))
     std::vector<int8_t> crt_afr;       // [crt_nbk][crt_kq][64 lanes][16]: MFMA A fragments
     std::vector<uint32_t> p_digits;  // [nd32] digits of P
     std::vector<uint32_t> ph_digits; // [nd32] digits of floor(P/2)

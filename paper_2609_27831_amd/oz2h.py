@@ -92,7 +92,8 @@ SIGNATURES = {
     "oz2h_residues": (ctypes.c_int, [_P, _I64, _I64, _P, _P, _P, _I64, _I64, _P, _I64, _I64, _P, _P]),
     "oz2h_residue_gemm": (ctypes.c_int, [_P, _I64, _I64, _I64, _P, _P, _P, _P]),
     "oz2h_i8gemm": (ctypes.c_int, [_I64, _I64, _I64, _P, _P, _P, _I32, _P]),
-    "oz2h_crt": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _I64, _P, _P, _I32, _P]),
+    "oz2h_crt": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _I64, _P, _P, _I32, _P, _SZ, _P]),
+    "oz2h_crt_workspace_size": (_SZ, [_P, _I64, _I64]),
     "oz2h_batched_plan_create": (ctypes.c_int, [_I32, _P, ctypes.POINTER(Opts), ctypes.POINTER(_P)]),
     "oz2h_batched_workspace_size": (_SZ, [_P]),
     "oz2h_batched_tune": (ctypes.c_int, [_P, _P, _SZ, _P]),
@@ -406,16 +407,22 @@ def i8gemm(A, B, tile: int = TILE_AUTO, stream=None):
     return C
 
 
-def crt(plan: Plan, u, M: int, N: int, nlc: Optional[int] = None, stream=None):
-    """u: uint16 planes as a torch int16 tensor [L, rows, ld]."""
+def crt(plan: Plan, u, M: int, N: int, nlc: Optional[int] = None, stream=None, ws=None):
+    """u: uint16 planes as a torch int16 tensor [L, rows, ld].  ws: None (no workspace),
+    "auto" (allocate oz2h_crt_workspace_size bytes), or a device uint8 tensor."""
     torch = _torch()
     L, rows, ldu = u.shape
     if nlc is None:
         nlc = (int(np.ceil(plan.log2P)) + 1 + 63) // 64
     cs = torch.empty((M, N), dtype=torch.int8, device=u.device)
     cm = torch.empty((M, N, nlc), dtype=torch.int64, device=u.device)
+    if isinstance(ws, str) and ws == "auto":
+        n = int(lib().oz2h_crt_workspace_size(plan.handle, M, ldu))
+        ws = torch.empty(max(n, 256), dtype=torch.uint8, device=u.device) if n else None
+    wp, wn = (ws.data_ptr(), ws.numel()) if ws is not None else (None, 0)
     _check(lib().oz2h_crt(plan.handle, M, N, u.data_ptr(), ldu, rows * ldu, cs.data_ptr(),
-                          cm.data_ptr(), nlc, _stream_ptr(stream)))
+                          cm.data_ptr(), nlc, wp, wn, _stream_ptr(stream)))
+    _keep_for(stream, cs, cm)
     return cs, cm
 
 

@@ -49,13 +49,16 @@ def _crt_values(P, rng, n_random=40):
     return vals
 
 
-def _run_crt(oz, plan, vals, rng, ncols=7):
+def _run_crt(oz, plan, vals, rng, ncols=7, row=False):
+    """row: planes with a leading dimension padded to 128 and a workspace, which selects
+    the row-broadcast CRT kernels for CRTs of more than 32 digits."""
     import torch
     ms = plan.moduli.tolist()
     n = len(vals)
     M = (n + ncols - 1) // ncols
     vals = vals + [0] * (M * ncols - n)
-    u = np.zeros((len(ms), M, ncols), np.int16)
+    ldu = 128 if row else ncols
+    u = np.zeros((len(ms), M, ldu), np.int16)
     for li, m in enumerate(ms):
         # any representative with |u| < m: the least nonnegative one, the centred one, or u - m
         res = []
@@ -67,8 +70,8 @@ def _run_crt(oz, plan, vals, rng, ncols=7):
             elif kind == 2 and r > 0:
                 r -= m
             res.append(r)
-        u[li] = np.array(res, np.int64).reshape(M, ncols)
-    cs, cm = oz.crt(plan, torch.from_numpy(u).cuda(), M, ncols)
+        u[li, :, :ncols] = np.array(res, np.int64).reshape(M, ncols)
+    cs, cm = oz.crt(plan, torch.from_numpy(u).cuda(), M, ncols, ws="auto" if row else None)
     got = oz.limbs_to_ints(cm.cpu().numpy(), cs.cpu().numpy())
     return got[:n], vals[:n]
 
@@ -86,21 +89,25 @@ def _custom_sets(oz):
         ("mixed_70", 256, 283, 2048, one + two[:16]),             # cfg 2's set
         ("mixed_96_32_digits", 440, 464, 256, one + two[:42]),    # 32 CRT digits
         ("wide_200", 1024, 1100, 64, one + two[:146]),            # wide digit columns
+        ("wide_329_cfg3a", 2048, 2076, 4096, one + two),          # cfg 3a's set, 133 digits
+        ("wide_33_digits", 440, 480, 256, one + two[:44]),        # just past 32 digits
     ]
 
 
-@pytest.mark.parametrize("flags", [0, 2], ids=["valu_crt", "mma_crt"])
-def test_crt_paper_sequence_near_half_P(oz, flags):
+@pytest.mark.parametrize("flags,row", [(0, False), (2, False), (0, True)],
+                         ids=["valu_crt", "mma_crt", "row_crt"])
+def test_crt_paper_sequence_near_half_P(oz, flags, row):
     """c^ = +-floor(P/2), +-(floor(P/2) - 1), values within P 2^-31 of +-P/2 and random
-    values round-trip through the CRT entry point, for odd and even P, on the fp64 kernel
-    and on the matrix-core variant (where its digit range applies)."""
+    values round-trip through the CRT entry point, for odd and even P, on the fp64 kernel,
+    on the matrix-core variant (where its digit range applies) and on the row-broadcast
+    kernels (CRTs of more than 32 digits, given a workspace)."""
     for label, p, t, K, ms in _custom_sets(oz):
         plan = oz.Plan.custom(p, t, K, ms).set_flags(flags)
         P = _prod(plan.moduli)
         rng = random.Random(hash(label) & 0xFFFF)
         vals = _crt_values(P, rng)
-        print(f"crt near P/2: {label} L={plan.L} nd32={plan.nd32} flags={flags}", flush=True)
-        got, want = _run_crt(oz, plan, vals, rng)
+        print(f"crt near P/2: {label} L={plan.L} nd32={plan.nd32} flags={flags} row={row}", flush=True)
+        got, want = _run_crt(oz, plan, vals, rng, row=row)
         assert got == want, label
 
 

@@ -235,9 +235,11 @@ def test_crt_worked_example(oz):
         assert sum(x * y for x, y in zip(ra, rb)) == ex["dot"][m]
 
 
-@pytest.mark.parametrize("t", list(range(40, 1121, 8)))
-def test_crt_random_exact_integers(oz, t):
-    """Direct CRT sweep over t = 40..1120 in steps of 8 (Correctness section)."""
+@pytest.mark.parametrize("t,row", [(t, False) for t in range(40, 1121, 8)] +
+                         [(t, True) for t in range(480, 1121, 40)])
+def test_crt_random_exact_integers(oz, t, row):
+    """Direct CRT sweep over t = 40..1120 in steps of 8 (Correctness section); row: the
+    row-broadcast kernels (planes padded to 128 columns, with a workspace)."""
     import torch
     plan = oz.Plan.create(max(2, t - 28), 4096, oz.default_opts(t_bits=t))
     P = 1
@@ -256,10 +258,11 @@ def test_crt_random_exact_integers(oz, t):
         if k % 11 == 5:
             v = 0
         vals.append(-v if rng.integers(0, 2) else v)
-    u = np.zeros((plan.L, M, N), np.uint16)
+    ldu = 128 if row else N
+    u = np.zeros((plan.L, M, ldu), np.uint16)
     for li, m in enumerate(plan.moduli.tolist()):
-        u[li] = np.array([v % m for v in vals], np.uint16).reshape(M, N)
-    print(f"crt sweep t={t}", flush=True)
-    cs, cm = oz.crt(plan, torch.from_numpy(u.view(np.int16)).cuda(), M, N)
+        u[li, :, :N] = np.array([v % m for v in vals], np.uint16).reshape(M, N)
+    print(f"crt sweep t={t} row={row}", flush=True)
+    cs, cm = oz.crt(plan, torch.from_numpy(u.view(np.int16)).cuda(), M, N, ws="auto" if row else None)
     got = oz.limbs_to_ints(cm.cpu().numpy(), cs.cpu().numpy())
     assert got == vals
