@@ -224,6 +224,45 @@ int oz2h_gemm_integers(const oz2h_plan *plan, int64_t M, int64_t N, int64_t K,
                        int32_t *e, int32_t *f,
                        void *workspace, size_t ws_bytes, hipStream_t stream);
 
+/* ---------------- operand reuse: residue handles ---------------- */
+
+/*
+ * Operand reuse (the paper's Conclusions and Future Work, "Operand reuse"): stages
+ * 1-2 of one operand -- its shared exponents (Eq. 1) and its G INT8 residue planes
+ * -- computed once and kept in a library-owned handle, so that products with many
+ * right-hand sides (or left-hand sides) skip them.  Side A: X is op(A), rows x K,
+ * each row owns an exponent; side B: X is op(B), K x rows, each column owns one.
+ * The planes are bit-identical to those a plain call writes, so every product
+ * from residues equals oz2h_gemm on the same operands bit for bit.
+ */
+typedef enum { OZ2H_SIDE_A = 0, OZ2H_SIDE_B = 1 } oz2h_side;
+typedef struct oz2h_saved_residues oz2h_saved_residues;
+
+/*
+ * Computes the residues of X (stored as the op says: side A, op N: rows x K; side
+ * B, op N: K x rows; OZ2H_OP_T the transposes) with the plan's moduli, into device
+ * memory the handle owns (one hipMalloc of about G * round_up(rows, 256) *
+ * round_up(K, 128) bytes).  The kernels run asynchronously on `stream`; the
+ * handle is ready for launches ordered after them.  X is not read afterwards.
+ */
+int oz2h_residues_create(const oz2h_plan *plan, int32_t side, int64_t rows, oz2h_op op, oz2h_cmat X,
+                         hipStream_t stream, oz2h_saved_residues **out);
+
+/*
+ * C = op(A) op(B) as oz2h_gemm, with side A taken from `ra` and/or side B from `rb`
+ * (either may be NULL, not both; the operand of a side given by a handle is not
+ * read and may be empty).  Each handle must come from a plan with the same p, t,
+ * K and moduli on the same device, of side A with M rows / side B with N rows.
+ * Workspace: oz2h_gemm_workspace_size(plan, M, N) bytes.
+ */
+int oz2h_gemm_from_residues(const oz2h_plan *plan, int64_t M, int64_t N, int64_t K,
+                            const oz2h_saved_residues *ra, oz2h_op opA, oz2h_cmat A,
+                            const oz2h_saved_residues *rb, oz2h_op opB, oz2h_cmat B, oz2h_mat C,
+                            void *workspace, size_t ws_bytes, hipStream_t stream);
+
+/* Frees the handle's memory; no launch that reads it may still be pending. */
+void oz2h_residues_destroy(oz2h_saved_residues *r);
+
 /* ---------------- autograd form: backward products ---------------- */
 
 /*

@@ -277,12 +277,15 @@ int launch_gemm_kernel(GemmCfg cfg, dim3 grid, const int8_t *a, const int8_t *b,
     return check_launch("residue GEMM");
 }
 
+// a_ps / b_ps: plane strides of the A and B planes (0: mpad * kpad, npad * kpad)
 int launch_resgemm(const oz2h_plan *pl, GemmCfg cfg, int64_t mpad, int64_t npad, int64_t kpad,
-                   const int8_t *a, const int8_t *b, int16_t *v, hipStream_t s) {
+                   const int8_t *a, const int8_t *b, int16_t *v, hipStream_t s, int64_t a_ps = 0,
+                   int64_t b_ps = 0) {
     const PlanHost &h = pl->h;
     dim3 grid((unsigned)(npad / cfg.bn), (unsigned)(mpad / cfg.bm), (unsigned)h.L);
-    return launch_gemm_kernel<false>(cfg, grid, a, b, kpad, mpad * kpad, npad * kpad, pl->d_info,
-                                     h.L, v, mpad * npad, npad, nullptr, s);
+    return launch_gemm_kernel<false>(cfg, grid, a, b, kpad, a_ps ? a_ps : mpad * kpad,
+                                     b_ps ? b_ps : npad * kpad, pl->d_info, h.L, v, mpad * npad,
+                                     npad, nullptr, s);
 }
 
 // CRT launch shape.  Up to 32 digits per entry the digit columns live in LDS
@@ -522,11 +525,21 @@ int check_cmat(const oz2h_cmat &X, const char *name, int64_t rows, int64_t cols)
     return OZ2H_OK;
 }
 
-// shared body of oz2h_gemm and oz2h_gemm_integers
+// Stages 1-2 of one operand side kept from an earlier call (a residue handle): its shared
+// exponents and its G planes of rpad x kpad (rpad a multiple of 256, so >= any tile padding).
+struct SideCache {
+    const int32_t *e;
+    const int8_t *planes;
+    int64_t rpad;
+};
+
+// shared body of oz2h_gemm, oz2h_gemm_integers and oz2h_gemm_from_residues; ca / cb
+// (nullable): cached stages 1-2 of side A / B, whose operand is then not read
 int run_pipeline(const oz2h_plan *pl, int64_t M, int64_t N, int64_t K, oz2h_op opA,
                  oz2h_cmat A, oz2h_op opB, oz2h_cmat B, bool round, oz2h_mat *C, int8_t *chat_sign,
                  uint64_t *chat_mag, int nlc, int32_t *e_out, int32_t *f_out, void *ws,
-                 size_t ws_bytes, hipStream_t s, hipEvent_t *ev = nullptr) {
+                 size_t ws_bytes, hipStream_t s, hipEvent_t *ev = nullptr,
+                 const SideCache *ca = nullptr, const SideCache *cb = nullptr) {
     int st = check_plan(pl);
     if (st) return st;
     const PlanHost &h = pl->h;
@@ -554,10 +567,8 @@ int run_pipeline(const oz2h_plan *pl, int64_t M, int64_t N, int64_t K, oz2h_op o
     }
     if (K != h.K) return fail(OZ2H_EINVAL, "K = %lld but the plan was built for K = %lld",
                               (long long)K, (long long)h.K);
-    st = check_cmat(A, "A", opA == OZ2H_OP_N ? M : K, opA == OZ2H_OP_N ? K : M);
-    if (st) return st;
-    st = check_cmat(B, "B", opB == OZ2H_OP_N ? K : N, opB == OZ2H_OP_N ? N : K);
-    if (st) return st;
+    if (!ca && (st = check_cmat(A, "A", opA == OZ2H_OP_N ? M : K, opA == OZ2H_OP_N ? K : M))) return st;
+    if (!cb && (st = check_cmat(B, "B", opB == OZ2H_OP_N ? K : N, opB == OZ2H_OP_N ? N : K))) return st;
     const Layout w = layout_for(h, M, N);
     if (!ws) return fail(OZ2H_EINVAL, "workspace is NULL");
     if (((uintptr_t)ws) % kAlign) return fail(OZ2H_EINVAL, "workspace must be 256-byte aligned");
@@ -569,31 +580,34 @@ int run_pipeline(const oz2h_plan *pl, int64_t M, int64_t N, int64_t K, oz2h_op o
     int8_t *ap = (int8_t *)(wb + w.off_a);
     int8_t *bp = (int8_t *)(wb + w.off_b);
     int16_t *u = (int16_t *)(wb + w.off_u);
+    const int32_t *ec = ca ? ca->e : e, *fc = cb ? cb->e : f;
+    const int8_t *apc = ca ? ca->planes : ap, *bpc = cb ? cb->planes : bp;
+    const int64_t a_ps = ca ? ca->rpad * w.kpad : 0, b_ps = cb ? cb->rpad * w.kpad : 0;
 
     // logical side strides: rows own the exponent, k is the contraction
     const int64_t a_rs = opA == OZ2H_OP_N ? A.ld : 1, a_cs = opA == OZ2H_OP_N ? 1 : A.ld;
     const int64_t b_rs = opB == OZ2H_OP_N ? 1 : B.ld, b_cs = opB == OZ2H_OP_N ? B.ld : 1;
 
     if (ev) OZ2H_HIP(hipEventRecord(ev[0], s));
-    if ((st = launch_exponents(M, K, A.sign, A.exp, a_rs, a_cs, nullptr, e, s))) return st;
-    if ((st = launch_exponents(N, K, B.sign, B.exp, b_rs, b_cs, nullptr, f, s))) return st;
+    if (!ca && (st = launch_exponents(M, K, A.sign, A.exp, a_rs, a_cs, nullptr, e, s))) return st;
+    if (!cb && (st = launch_exponents(N, K, B.sign, B.exp, b_rs, b_cs, nullptr, f, s))) return st;
     if (ev) OZ2H_HIP(hipEventRecord(ev[1], s));
-    if ((st = launch_residues(pl, M, K, A.limbs, A.exp, A.sign, a_rs, a_cs, e, w.mpad, w.kpad, ap, s)))
+    if (!ca && (st = launch_residues(pl, M, K, A.limbs, A.exp, A.sign, a_rs, a_cs, e, w.mpad, w.kpad, ap, s)))
         return st;
-    if ((st = launch_residues(pl, N, K, B.limbs, B.exp, B.sign, b_rs, b_cs, f, w.npad, w.kpad, bp, s)))
+    if (!cb && (st = launch_residues(pl, N, K, B.limbs, B.exp, B.sign, b_rs, b_cs, f, w.npad, w.kpad, bp, s)))
         return st;
     if (ev) OZ2H_HIP(hipEventRecord(ev[2], s));
-    if ((st = launch_resgemm(pl, w.cfg, w.mpad, w.npad, w.kpad, ap, bp, u, s))) return st;
+    if ((st = launch_resgemm(pl, w.cfg, w.mpad, w.npad, w.kpad, apc, bpc, u, s, a_ps, b_ps))) return st;
     if (ev) OZ2H_HIP(hipEventRecord(ev[3], s));
     if (round) {
-        st = launch_crt(pl, M, N, u, w.mpad * w.npad, w.npad, e, f, true, false, C->sign,
+        st = launch_crt(pl, M, N, u, w.mpad * w.npad, w.npad, ec, fc, true, false, C->sign,
                         C->exp, C->limbs, C->ld, nullptr, 0, s, -1, (uint32_t *)(wb + w.off_dig));
     } else {
-        st = launch_crt(pl, M, N, u, w.mpad * w.npad, w.npad, e, f, false, false, chat_sign,
+        st = launch_crt(pl, M, N, u, w.mpad * w.npad, w.npad, ec, fc, false, false, chat_sign,
                         nullptr, nullptr, N, chat_mag, nlc, s, -1, (uint32_t *)(wb + w.off_dig));
         if (!st) {
-            OZ2H_HIP(hipMemcpyAsync(e_out, e, sizeof(int32_t) * M, hipMemcpyDeviceToDevice, s));
-            OZ2H_HIP(hipMemcpyAsync(f_out, f, sizeof(int32_t) * N, hipMemcpyDeviceToDevice, s));
+            OZ2H_HIP(hipMemcpyAsync(e_out, ec, sizeof(int32_t) * M, hipMemcpyDeviceToDevice, s));
+            OZ2H_HIP(hipMemcpyAsync(f_out, fc, sizeof(int32_t) * N, hipMemcpyDeviceToDevice, s));
         }
     }
     if (st) return st;
@@ -779,6 +793,109 @@ int oz2h_gemm_integers(const oz2h_plan *plan, int64_t M, int64_t N, int64_t K, o
     return run_pipeline(plan, M, N, K, opA, A, opB, B, false, nullptr, chat_sign, chat_mag, nlc,
                         e, f, workspace, ws_bytes, stream);
 }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- residue handles
+
+struct oz2h_saved_residues {
+    int device = -1;
+    int side = 0;              // OZ2H_SIDE_A or OZ2H_SIDE_B
+    int64_t rows = 0, K = 0, rpad = 0, kpad = 0;
+    int p = 0, t = 0, G = 0;
+    std::vector<uint32_t> moduli;
+    void *dbuf = nullptr;
+    int32_t *e = nullptr;
+    int8_t *planes = nullptr;
+};
+
+namespace {
+
+// the handle was made with a plan of the same precision, width and moduli on this device
+int check_residues(const oz2h_plan *pl, const oz2h_saved_residues *r, int side, int64_t rows, const char *name) {
+    if (r->side != side) return fail(OZ2H_EINVAL, "%s: residues of the other operand side", name);
+    if (r->device != pl->device) return fail(OZ2H_EINVAL, "%s: residues of another device", name);
+    if (r->rows != rows) return fail(OZ2H_EINVAL, "%s: residues of %lld rows, the product needs %lld",
+                                     name, (long long)r->rows, (long long)rows);
+    if (r->p != pl->h.p || r->t != pl->h.t || r->K != pl->h.K || r->moduli != pl->h.moduli)
+        return fail(OZ2H_EINVAL, "%s: residues were made with a different plan (p, t, K or moduli)", name);
+    return OZ2H_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int oz2h_residues_create(const oz2h_plan *plan, int32_t side, int64_t rows, oz2h_op op, oz2h_cmat X,
+                         hipStream_t stream, oz2h_saved_residues **out) {
+    if (!out) return fail(OZ2H_EINVAL, "out is NULL");
+    *out = nullptr;
+    int st = check_plan(plan);
+    if (st) return st;
+    const PlanHost &h = plan->h;
+    if (side != OZ2H_SIDE_A && side != OZ2H_SIDE_B) return fail(OZ2H_EINVAL, "side must be OZ2H_SIDE_A or OZ2H_SIDE_B");
+    if (op != OZ2H_OP_N && op != OZ2H_OP_T) return fail(OZ2H_EINVAL, "op must be OZ2H_OP_N or OZ2H_OP_T");
+    if (rows < 1) return fail(OZ2H_EINVAL, "rows must be >= 1");
+    const int64_t K = h.K;
+    // stored shape: side A op N: rows x K; side B op N: K x rows; op T swaps
+    const bool rows_first = (side == OZ2H_SIDE_A) == (op == OZ2H_OP_N);
+    if ((st = check_cmat(X, "X", rows_first ? rows : K, rows_first ? K : rows))) return st;
+    auto r = std::make_unique<oz2h_saved_residues>();
+    r->device = plan->device;
+    r->side = side;
+    r->rows = rows;
+    r->K = K;
+    r->rpad = round_up(rows, 256);
+    r->kpad = round_up(K, GBK);
+    r->p = h.p;
+    r->t = h.t;
+    r->G = h.G;
+    r->moduli = h.moduli;
+    const size_t off_p = align_up(sizeof(int32_t) * r->rpad);
+    const size_t bytes = off_p + (size_t)h.G * r->rpad * r->kpad;
+    if (hipMalloc(&r->dbuf, bytes) != hipSuccess) return fail(OZ2H_ENOMEM, "residues: hipMalloc of %zu bytes failed", bytes);
+    r->e = (int32_t *)r->dbuf;
+    r->planes = (int8_t *)r->dbuf + off_p;
+    const int64_t rs = rows_first ? X.ld : 1, cs = rows_first ? 1 : X.ld;
+    st = launch_exponents(rows, K, X.sign, X.exp, rs, cs, nullptr, r->e, stream);
+    if (!st) st = launch_residues(plan, rows, K, X.limbs, X.exp, X.sign, rs, cs, r->e, r->rpad, r->kpad,
+                                  r->planes, stream);
+    if (st) {
+        (void)hipFree(r->dbuf);
+        return st;
+    }
+    *out = r.release();
+    return ok();
+}
+
+void oz2h_residues_destroy(oz2h_saved_residues *r) {
+    if (!r) return;
+    if (r->dbuf) (void)hipFree(r->dbuf);
+    delete r;
+}
+
+int oz2h_gemm_from_residues(const oz2h_plan *plan, int64_t M, int64_t N, int64_t K,
+                            const oz2h_saved_residues *ra, oz2h_op opA, oz2h_cmat A,
+                            const oz2h_saved_residues *rb, oz2h_op opB, oz2h_cmat B, oz2h_mat C,
+                            void *workspace, size_t ws_bytes, hipStream_t stream) {
+    int st = check_plan(plan);
+    if (st) return st;
+    if (!ra && !rb) return fail(OZ2H_EINVAL, "no residue handle given (use oz2h_gemm)");
+    SideCache sa{}, sb{};
+    if (ra) {
+        if ((st = check_residues(plan, ra, OZ2H_SIDE_A, M, "A"))) return st;
+        sa = SideCache{ra->e, ra->planes, ra->rpad};
+    }
+    if (rb) {
+        if ((st = check_residues(plan, rb, OZ2H_SIDE_B, N, "B"))) return st;
+        sb = SideCache{rb->e, rb->planes, rb->rpad};
+    }
+    return run_pipeline(plan, M, N, K, opA, A, opB, B, true, &C, nullptr, nullptr, 0, nullptr,
+                        nullptr, workspace, ws_bytes, stream, nullptr, ra ? &sa : nullptr,
+                        rb ? &sb : nullptr);
+}
+
+
 
 }  // extern "C"
 

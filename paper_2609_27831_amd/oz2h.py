@@ -94,6 +94,10 @@ SIGNATURES = {
     "oz2h_i8gemm": (ctypes.c_int, [_I64, _I64, _I64, _P, _P, _P, _I32, _P]),
     "oz2h_crt": (ctypes.c_int, [_P, _I64, _I64, _P, _I64, _I64, _P, _P, _I32, _P, _SZ, _P]),
     "oz2h_crt_workspace_size": (_SZ, [_P, _I64, _I64]),
+    "oz2h_residues_create": (ctypes.c_int, [_P, _I32, _I64, ctypes.c_int, CMat, _P, ctypes.POINTER(_P)]),
+    "oz2h_gemm_from_residues": (ctypes.c_int, [_P, _I64, _I64, _I64, _P, ctypes.c_int, CMat, _P,
+                                               ctypes.c_int, CMat, Mat, _P, _SZ, _P]),
+    "oz2h_residues_destroy": (None, [_P]),
     "oz2h_batched_plan_create": (ctypes.c_int, [_I32, _P, ctypes.POINTER(Opts), ctypes.POINTER(_P)]),
     "oz2h_batched_workspace_size": (_SZ, [_P]),
     "oz2h_batched_tune": (ctypes.c_int, [_P, _P, _SZ, _P]),
@@ -322,6 +326,70 @@ def gemm(plan: Plan, A: DeviceMP, B: DeviceMP, opA: int = OP_N, opB: int = OP_N,
         ws = workspace(plan, M, N, device=A.sign.device)
     _check(lib().oz2h_gemm(plan.handle, M, N, K, opA, A.cmat(), opB, B.cmat(), out.mat(),
                            ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
+    if new_out:
+        _keep_for(stream, out.sign, out.exp, out.limbs)
+    if new_ws:
+        _keep_for(stream, ws)
+    return out
+
+
+SIDE_A, SIDE_B = 0, 1
+
+
+class Residues:
+    """Stages 1-2 of one operand kept on the device (oz2h_residues_create), for operand
+    reuse: side SIDE_A (X is op(A), rows x K) or SIDE_B (X is op(B), K x rows)."""
+
+    def __init__(self, plan: Plan, X: "DeviceMP", side: int, op: int = OP_N, stream=None):
+        r, c = X.shape
+        rows_first = (side == SIDE_A) == (op == OP_N)
+        rows = r if rows_first else c
+        h = ctypes.c_void_p()
+        _check(lib().oz2h_residues_create(plan.handle, side, rows, op, X.cmat(), _stream_ptr(stream),
+                                          ctypes.byref(h)))
+        self.handle, self.side, self.rows = h.value, side, rows
+
+    def destroy(self):
+        if self.handle:
+            lib().oz2h_residues_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def _empty_cmat() -> CMat:
+    return CMat(None, None, None, 1)
+
+
+def gemm_from_residues(plan: Plan, A=None, B=None, ra: Optional[Residues] = None,
+                       rb: Optional[Residues] = None, opA: int = OP_N, opB: int = OP_N,
+                       M: Optional[int] = None, N: Optional[int] = None,
+                       out: Optional["DeviceMP"] = None, ws=None, stream=None) -> "DeviceMP":
+    """C = op(A) op(B) with side A from `ra` and/or side B from `rb` (oz2h_gemm_from_residues)."""
+    K = plan.K
+    if ra is not None:
+        M = ra.rows
+    elif M is None:
+        M = A.shape[0] if opA == OP_N else A.shape[1]
+    if rb is not None:
+        N = rb.rows
+    elif N is None:
+        N = B.shape[1] if opB == OP_N else B.shape[0]
+    dev = (A.sign.device if A is not None else B.sign.device if B is not None else "cuda")
+    new_out, new_ws = out is None, ws is None
+    if out is None:
+        out = empty_mp(M, N, plan.p, device=dev)
+    if ws is None:
+        ws = workspace(plan, M, N, device=dev)
+    _check(lib().oz2h_gemm_from_residues(plan.handle, M, N, K, ra.handle if ra else None, opA,
+                                         A.cmat() if A is not None else _empty_cmat(),
+                                         rb.handle if rb else None, opB,
+                                         B.cmat() if B is not None else _empty_cmat(), out.mat(),
+                                         ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
     if new_out:
         _keep_for(stream, out.sign, out.exp, out.limbs)
     if new_ws:
