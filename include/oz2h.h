@@ -263,6 +263,25 @@ int oz2h_gemm_from_residues(const oz2h_plan *plan, int64_t M, int64_t N, int64_t
 /* Frees the handle's memory; no launch that reads it may still be pending. */
 void oz2h_residues_destroy(oz2h_saved_residues *r);
 
+/* ---------------- without allocations ---------------- */
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): oz2h_gemm without a
+ * workspace argument.  Its scratch is a file-scope device array of
+ * oz2h_gemm_noalloc_max_bytes() bytes (128 MiB) that every GPU the library runs on
+ * holds until the process ends; the call itself allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine).  Products whose workspace
+ * (oz2h_gemm_workspace_size) exceeds that size return OZ2H_ERANGE.  Every call on
+ * one GPU shares that GPU's scratch: calls that overlap on one GPU (other streams,
+ * other threads) race, so callers serialise them.  Nothing in the scratch needs to
+ * start at zero (every stage writes what the next one reads).
+ */
+size_t oz2h_gemm_noalloc_max_bytes(void);
+int oz2h_gemm_noalloc(const oz2h_plan *plan, int64_t M, int64_t N, int64_t K,
+                      oz2h_op opA, oz2h_cmat A, oz2h_op opB, oz2h_cmat B, oz2h_mat C,
+                      hipStream_t stream);
+
 /* ---------------- autograd form: backward products ---------------- */
 
 /*

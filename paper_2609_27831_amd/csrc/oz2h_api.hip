@@ -895,6 +895,57 @@ int oz2h_gemm_from_residues(const oz2h_plan *plan, int64_t M, int64_t N, int64_t
                         rb ? &sb : nullptr);
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------- without allocations
+
+namespace {
+
+// Scratch of oz2h_gemm_noalloc: a file-scope device array (each device holds its own copy
+// for the life of the process).  Host code never passes the array's name to a kernel: its
+// device address comes from hipGetSymbolAddress, once per device, kept in g_scratch_ptr.
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch_ptr;   // per device, nullptr until resolved
+
+int scratch_for(int dev, void **ptr) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(OZ2H_EDEVICE, "scratch: hipGetSymbolAddress failed: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return OZ2H_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t oz2h_gemm_noalloc_max_bytes(void) { return kScratchBytes; }
+
+int oz2h_gemm_noalloc(const oz2h_plan *plan, int64_t M, int64_t N, int64_t K, oz2h_op opA,
+                      oz2h_cmat A, oz2h_op opB, oz2h_cmat B, oz2h_mat C, hipStream_t stream) {
+    int st = check_plan(plan);
+    if (st) return st;
+    if (M > 0 && N > 0 && K > 0) {
+        const size_t need = layout_for(plan->h, M, N).total;
+        if (need > kScratchBytes)
+            return fail(OZ2H_ERANGE, "product needs %zu bytes of scratch, the static scratch holds %zu",
+                        need, kScratchBytes);
+    }
+    void *ws = nullptr;
+    if ((st = scratch_for(plan->device, &ws))) return st;
+    return run_pipeline(plan, M, N, K, opA, A, opB, B, true, &C, nullptr, nullptr, 0, nullptr,
+                        nullptr, ws, kScratchBytes, stream);
+}
+
 
 
 }  // extern "C"

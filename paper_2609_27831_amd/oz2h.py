@@ -98,6 +98,9 @@ SIGNATURES = {
     "oz2h_gemm_from_residues": (ctypes.c_int, [_P, _I64, _I64, _I64, _P, ctypes.c_int, CMat, _P,
                                                ctypes.c_int, CMat, Mat, _P, _SZ, _P]),
     "oz2h_residues_destroy": (None, [_P]),
+    "oz2h_gemm_noalloc_max_bytes": (_SZ, []),
+    "oz2h_gemm_noalloc": (ctypes.c_int, [_P, _I64, _I64, _I64, ctypes.c_int, CMat, ctypes.c_int, CMat,
+                                         Mat, _P]),
     "oz2h_batched_plan_create": (ctypes.c_int, [_I32, _P, ctypes.POINTER(Opts), ctypes.POINTER(_P)]),
     "oz2h_batched_workspace_size": (_SZ, [_P]),
     "oz2h_batched_tune": (ctypes.c_int, [_P, _P, _SZ, _P]),
@@ -394,6 +397,21 @@ def gemm_from_residues(plan: Plan, A=None, B=None, ra: Optional[Residues] = None
         _keep_for(stream, out.sign, out.exp, out.limbs)
     if new_ws:
         _keep_for(stream, ws)
+    return out
+
+
+def gemm_noalloc(plan: Plan, A: DeviceMP, B: DeviceMP, opA: int = OP_N, opB: int = OP_N,
+                 out: DeviceMP = None, stream=None) -> DeviceMP:
+    """oz2h_gemm_noalloc: the library's static per-device scratch instead of a workspace.
+    `out` must be given by callers that allocate nothing themselves."""
+    M, N, K = _dims(A, B, opA, opB)
+    new_out = out is None
+    if out is None:
+        out = empty_mp(M, N, plan.p, device=A.sign.device)
+    _check(lib().oz2h_gemm_noalloc(plan.handle, M, N, K, opA, A.cmat(), opB, B.cmat(), out.mat(),
+                                   _stream_ptr(stream)))
+    if new_out:
+        _keep_for(stream, out.sign, out.exp, out.limbs)
     return out
 
 
