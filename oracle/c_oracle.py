@@ -237,3 +237,37 @@ def limbs_to_int(limbs) -> int:
     for x in reversed([int(y) for y in limbs]):
         v = (v << 64) | x
     return v
+
+
+def _hcat(X, Y, negate_y: bool = False):
+    """[X | Y] (or [X | -Y]) as one matrix of X's own type."""
+    MPMatrix = type(X)
+    ys = -Y.sign if negate_y else Y.sign
+    return MPMatrix(np.ascontiguousarray(np.concatenate([X.sign, ys], axis=1)),
+                    np.ascontiguousarray(np.concatenate([X.exp, Y.exp], axis=1)),
+                    np.ascontiguousarray(np.concatenate([X.limbs, Y.limbs], axis=1)), X.p)
+
+
+def _vcat(X, Y, negate_y: bool = False):
+    """[X ; Y] (or [X ; -Y]) as one matrix of X's own type."""
+    MPMatrix = type(X)
+    ys = -Y.sign if negate_y else Y.sign
+    return MPMatrix(np.ascontiguousarray(np.concatenate([X.sign, ys], axis=0)),
+                    np.ascontiguousarray(np.concatenate([X.exp, Y.exp], axis=0)),
+                    np.ascontiguousarray(np.concatenate([X.limbs, Y.limbs], axis=0)), X.p)
+
+
+def zgemm(Ar, Ai, Br, Bi, guard_bits: int = 16, t_bits: int = 0, sel=None,
+          want_chat: bool = False, want_c: bool = True):
+    """Complex reference product (the definition of oz2_ref.oz2_zgemm_ref) through the
+    real C oracle: with A' = [Ar | Ai] (M x 2K),
+      Re C = A' [Br ; -Bi]   and   Im C = A' [Bi ; Br]
+    as real products of contraction length 2K.  Row i of A' holds row i of both parts,
+    so its shared exponent is the complex one; column j of either right operand holds
+    column j of both parts of B (negation does not change an exponent, and the
+    nearest-even rounding of Eq. 1 is odd in its argument).  Returns (re, im), each the
+    dictionary of gemm()."""
+    Ac = _hcat(Ar, Ai)
+    re = gemm(Ac, _vcat(Br, Bi, negate_y=True), guard_bits, t_bits, sel, want_chat, want_c)
+    im = gemm(Ac, _vcat(Bi, Br), guard_bits, t_bits, sel, want_chat, want_c)
+    return re, im

@@ -166,3 +166,47 @@ def oz2_grad_ref(A, B, W, guard_bits: int = 16, t_bits: int = 0):
           for k in range(K)]
     return {"t": t, "tw": (twa, twb), "e": e, "f": f, "h": h, "g": g,
             "chat_a": chat_a, "chat_b": chat_b, "dA": dA, "dB": dB}
+
+
+def oz2_zgemm_ref(Ar, Ai, Br, Bi, guard_bits: int = 16, t_bits: int = 0):
+    """Complex product C = A B with A = Ar + i Ai, B = Br + i Bi (Conclusions, "Complex
+    matrix products": the 3M/4M schemes turn it into real products).
+
+    Reading: the real and imaginary parts of a row of A share one exponent, and so do
+    those of a column of B, so that each part of C is one exact integer of the kind
+    Eq. 2 defines, rounded once:
+      t      = p + g + ceil(log2 2K)        (Eq. 3 for the 2K products summed per entry)
+      e_i    = max exp over the nonzero entries of row i of Ar and of Ai   (Eq. 1)
+      f_j    = max exp over the nonzero entries of column j of Br and of Bi
+      ar^, ai^, br^, bi^ = the entries rounded to integers at those exponents (Eq. 1)
+      cr^_ij = sum_k ar^_ik br^_kj - ai^_ik bi^_kj
+      ci^_ij = sum_k ar^_ik bi^_kj + ai^_ik br^_kj
+      Cr_ij, Ci_ij = round_p(cr^_ij 2^(e_i + f_j - 2t)), round_p(ci^_ij 2^(...))
+    The 3M and 4M forms compute these same integers; they differ only in which real
+    integer products they sum.
+    """
+    p = Ar.p
+    M, K = Ar.sign.shape
+    K2, N = Br.sign.shape
+    assert K == K2 and Ai.sign.shape == (M, K) and Bi.sign.shape == (K, N)
+    assert Ai.p == p and Br.p == p and Bi.p == p
+    t = internal_width(p, 2 * K, guard_bits, t_bits)
+    ar = [[Ar.value_parts(i, k) for k in range(K)] for i in range(M)]
+    ai = [[Ai.value_parts(i, k) for k in range(K)] for i in range(M)]
+    br = [[Br.value_parts(k, j) for k in range(K)] for j in range(N)]
+    bi = [[Bi.value_parts(k, j) for k in range(K)] for j in range(N)]
+    e = [shared_exponent(ar[i] + ai[i]) for i in range(M)]
+    f = [shared_exponent(br[j] + bi[j]) for j in range(N)]
+    arh = [[integerize(s, m, x, e[i], t, p) for (s, m, x) in ar[i]] for i in range(M)]
+    aih = [[integerize(s, m, x, e[i], t, p) for (s, m, x) in ai[i]] for i in range(M)]
+    brh = [[integerize(s, m, x, f[j], t, p) for (s, m, x) in br[j]] for j in range(N)]
+    bih = [[integerize(s, m, x, f[j], t, p) for (s, m, x) in bi[j]] for j in range(N)]
+    cre = [[sum(arh[i][k] * brh[j][k] - aih[i][k] * bih[j][k] for k in range(K))
+            for j in range(N)] for i in range(M)]
+    cim = [[sum(arh[i][k] * bih[j][k] + aih[i][k] * brh[j][k] for k in range(K))
+            for j in range(N)] for i in range(M)]
+    Cr = [[round_to_precision(cre[i][j], e[i] + f[j] - 2 * t, p) for j in range(N)]
+          for i in range(M)]
+    Ci = [[round_to_precision(cim[i][j], e[i] + f[j] - 2 * t, p) for j in range(N)]
+          for i in range(M)]
+    return {"t": t, "e": e, "f": f, "chat_re": cre, "chat_im": cim, "Cr": Cr, "Ci": Ci}
