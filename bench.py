@@ -31,6 +31,7 @@ import hashlib
 import json
 import os
 import platform
+import struct
 import sys
 import time
 
@@ -53,7 +54,6 @@ PEAK_INT8_TOPS = 5000.0      # dense INT8 MFMA, TOP/s
 PEAK_HBM_GBS = 8000.0        # HBM3E, GB/s
 PEAK_FP64_TFLOPS = 78.6      # FP64 vector, TFLOP/s (FMA = 2 flops)
 
-CSRC = os.path.join(ROOT, "paper_2609_27831_amd", "csrc")
 PHASES = ["exponents", "residues", "gemm", "crt"]
 
 
@@ -87,26 +87,91 @@ class Hip:
             self.h.hipEventDestroy(ev)
 
 
-def source_digest() -> str:
+LIBOZ2H = os.path.join(ROOT, "paper_2609_27831_amd", "liboz2h.so")
+
+
+def _gfx950_code_object(path: str):
+    """The gfx950 code object of a library built here (clang offload bundle: magic,
+    entry count, then (offset, size, triple length, triple) per entry)."""
+    with open(path, "rb") as fh:
+        d = fh.read()
+    i = d.find(b"__CLANG_OFFLOAD_BUNDLE__")
+    if i < 0:
+        return None
+    n = struct.unpack_from("<Q", d, i + 24)[0]
+    o = i + 32
+    for _ in range(n):
+        off, size, tl = struct.unpack_from("<QQQ", d, o)
+        o += 24
+        triple = d[o:o + tl].decode(errors="replace")
+        o += tl
+        if triple.endswith("gfx950") and size:
+            return d[i + off:i + off + size]
+    return None
+
+
+def _elf_function_bytes(co: bytes, names):
+    """{symbol: bytes} of the named symbols (kernel code and kernel descriptor) of an
+    ELF64 code object."""
+    shoff = struct.unpack_from("<Q", co, 0x28)[0]
+    shentsize, shnum = struct.unpack_from("<HH", co, 0x3A)
+    secs = [struct.unpack_from("<IIQQQQIIQQ", co, shoff + k * shentsize) for k in range(shnum)]
+    out = {}
+    for sec in secs:
+        if sec[1] != 2:   # SHT_SYMTAB
+            continue
+        stroff = secs[sec[6]][4]
+        for k in range(sec[5] // 24):
+            st_name, _info, _other, shndx, value, size = struct.unpack_from(
+                "<IBBHQQ", co, sec[4] + 24 * k)
+            end = co.index(b"\0", stroff + st_name)
+            name = co[stroff + st_name:end].decode(errors="replace")
+            if name in names and 0 < shndx < shnum:
+                host = secs[shndx]
+                fo = host[4] + (value - host[3])
+                out[name] = co[fo:fo + size]
+    return out
+
+
+def kernel_code_digest(symbol: str):
+    """sha256 of one kernel's gfx950 machine code and kernel descriptor in the built
+    library, or None: a counter record is valid only for the code it was taken on."""
+    try:
+        co = _gfx950_code_object(LIBOZ2H)
+        if co is None:
+            return None
+        got = _elf_function_bytes(co, {symbol, symbol + ".kd"})
+    except (OSError, struct.error, ValueError):
+        return None
+    if symbol not in got or symbol + ".kd" not in got:
+        return None
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        with open(os.path.join(CSRC, name), "rb") as fh:
-            h.update(name.encode())
-            h.update(fh.read())
+    h.update(got[symbol])
+    h.update(got[symbol + ".kd"])
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, config: str):
-    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel of known
-    size) from a committed rocprofv3 PMC summary, if it was taken from these sources."""
+def measured_traffic(kernel: str, config: str, field: str = "hbm_bytes_per_launch"):
+    """HBM bytes (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel of known size) from a
+    committed rocprofv3 PMC summary, if every kernel it covers still has the machine
+    code the counters were taken on.  field: "hbm_bytes_per_launch" (the named kernel)
+    or "phase_hbm_bytes_per_step" (every kernel of its stage, one step)."""
+    rec = measured_record(kernel, config)
+    return rec.get(field) if rec else None
+
+
+def measured_record(kernel: str, config: str):
+    """The committed counter record of a kernel at a workload, or None when it is absent
+    or was taken on other machine code."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{config}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("source_digest") != source_digest():
+    digests = rec.get("code_digests") or {}
+    if not digests or any(kernel_code_digest(sym) != d for sym, d in digests.items()):
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec
 
 
 def cpu_model() -> str:
@@ -203,7 +268,7 @@ def time_plain(name, Ad, Bd, steps, warmup, flags=0):
         "fp64_tflops": round(2.0 * crt_fma / sec["crt"] / 1e12, 2) if not crt_k.endswith("_mma") else None,
         "counter_hbm_gbs": None})
     for ph, kern in (("residues", res_k), ("crt", crt_k)):
-        tb = measured_traffic(kern, name)
+        tb = measured_traffic(kern, name, "phase_hbm_bytes_per_step")
         if tb:
             phases[ph]["counter_hbm_gbs"] = round(tb / sec[ph] / 1e9, 1)
 
@@ -223,7 +288,13 @@ def time_plain(name, Ad, Bd, steps, warmup, flags=0):
             if kern.endswith("_mma"):   # a matrix-core variant: no fp64 work to rate
                 r = {"kernel": kern, "bound": "alu", "achieved": None, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": None}
-        r["traffic"] = measured_traffic(kern, name)
+        # counter bytes over the same span as `achieved`: the GEMM's one launch per step,
+        # the other stages' launches of one step
+        r["traffic"] = measured_traffic(kern, name, "hbm_bytes_per_launch" if ph == "gemm"
+                                        else "phase_hbm_bytes_per_step")
+        rec = measured_record(kern, name)
+        if rec and "sq" in rec:
+            r["counters"] = {k: rec["sq"][k] for k in ("mfma_busy_pct", "wait_pct", "clock_ghz")}
         return r
 
     dominant = max(("residues", "gemm", "crt"), key=lambda n: phase_ms[n])
