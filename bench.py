@@ -135,7 +135,9 @@ def _elf_function_bytes(co: bytes, names):
 
 def kernel_code_digest(symbol: str):
     """sha256 of one kernel's gfx950 machine code and kernel descriptor in the built
-    library, or None: a counter record is valid only for the code it was taken on."""
+    library (the descriptor's code-entry offset masked: it moves with the layout of
+    the code object, not with the kernel), or None: a counter record is valid only for
+    the code it was taken on."""
     try:
         co = _gfx950_code_object(LIBOZ2H)
         if co is None:
@@ -145,9 +147,11 @@ def kernel_code_digest(symbol: str):
         return None
     if symbol not in got or symbol + ".kd" not in got:
         return None
+    kd = bytearray(got[symbol + ".kd"])
+    kd[16:24] = bytes(8)   # kernel_code_entry_byte_offset: relative to where the linker put it
     h = hashlib.sha256()
     h.update(got[symbol])
-    h.update(got[symbol + ".kd"])
+    h.update(bytes(kd))
     return h.hexdigest()[:16]
 
 
