@@ -224,6 +224,43 @@ int oz2h_gemm_integers(const oz2h_plan *plan, int64_t M, int64_t N, int64_t K,
                        int32_t *e, int32_t *f,
                        void *workspace, size_t ws_bytes, hipStream_t stream);
 
+/* ---------------- complex products ---------------- */
+
+/*
+ * Complex product C = op(A) op(B) with A = Ar + i Ai, B = Br + i Bi, each part a
+ * p-bit matrix in the operand format (the paper's Conclusions and Future Work,
+ * "Complex matrix products": the 3M/4M schemes reduce it to real products).
+ * op is the plain transpose (no conjugation: to conjugate, negate the signs of
+ * the imaginary part).
+ *
+ * Row i of op(A) owns one exponent over its real AND imaginary entries, column j
+ * of op(B) likewise (Eq. 1), so that Re C_ij and Im C_ij are the exact integers
+ *   sum_k ar^ br^ - ai^ bi^   and   sum_k ar^ bi^ + ai^ br^
+ * each rounded once to p bits at the scale 2^(e_i + f_j - 2t): every entry is the
+ * real Ozaki-II product of contraction length 2K of [Ar | Ai] with [Br ; -Bi] and
+ * with [Bi ; Br].  The plan is therefore a plan for contraction length 2K
+ * (oz2h_plan_create(p, 2K, ...), so t and the moduli follow Eqs. 3 and crtcond
+ * for 2K products; K <= 66500).
+ *
+ * scheme 4 (4M): four residue GEMMs per modulus (Ar Br, Ai Bi, Ar Bi, Ai Br)
+ * combined mod m_l in their epilogues.  scheme 3 (3M, Gauss): the residue planes
+ * of Ar + Ai and Br + Bi are formed mod m_l from those of the parts, and three
+ * GEMMs T1 = Ar Br, T2 = Ai Bi, T3 = (Ar + Ai)(Br + Bi) give Re = T1 - T2 and
+ * Im = T3 - T1 - T2 mod m_l (a quarter fewer MFMA operations).  Both schemes give
+ * bit-identical results: the combinations are exact in residue space.
+ *
+ * Cr and Ci are p-bit outputs (ld >= N) and may not alias any input or each
+ * other.  Workspace: oz2h_zgemm_workspace_size(plan, scheme, M, N) bytes of device
+ * memory, 256-byte aligned (about (2 or 3) G (M + N) K + 4 L M N bytes).  K = 0
+ * writes zeros; M = 0 or N = 0 is a no-op.  Errors: OZ2H_EINVAL (scheme not 3 or
+ * 4, a NULL pointer, ld too small, K not half the plan's K), OZ2H_ENOMEM (workspace
+ * too small).  Asynchronous on `stream`.
+ */
+size_t oz2h_zgemm_workspace_size(const oz2h_plan *plan, int32_t scheme, int64_t M, int64_t N);
+int oz2h_zgemm(const oz2h_plan *plan, int32_t scheme, int64_t M, int64_t N, int64_t K,
+               oz2h_op opA, oz2h_cmat Ar, oz2h_cmat Ai, oz2h_op opB, oz2h_cmat Br, oz2h_cmat Bi,
+               oz2h_mat Cr, oz2h_mat Ci, void *workspace, size_t ws_bytes, hipStream_t stream);
+
 /* ---------------- operand reuse: residue handles ---------------- */
 
 /*

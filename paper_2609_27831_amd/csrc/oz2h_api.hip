@@ -251,13 +251,10 @@ int launch_residues(const oz2h_plan *pl, int64_t rows, int64_t count, const uint
     return check_launch("residues");
 }
 
-template <bool RAW>
-int launch_gemm_kernel(GemmCfg cfg, dim3 grid, const int8_t *a, const int8_t *b, int64_t kpad,
-                       int64_t a_ps, int64_t b_ps, const ModInfo *mi, int L, int16_t *v,
-                       int64_t v_ps, int64_t ldv, int32_t *craw, hipStream_t s) {
-    const GemmArgs g{a, b, kpad, a_ps, b_ps, mi, v, v_ps, ldv, craw};
-    // XCD map: split each modulus's ny x nx tiles into 8 rectangles (ry x rx of them) with
-    // the smallest A + B footprint per XCD; keep the 3-D grid when no split divides evenly
+// XCD map: split each modulus's ny x nx tiles into 8 rectangles (ry x rx of them) with
+// the smallest A + B footprint per XCD; keep the 3-D grid when no split divides evenly
+// (grid is flattened to 1-D when a map applies)
+XcdMap xcd_map_for(GemmCfg cfg, dim3 &grid) {
     XcdMap xm{0, 1, 1, 1};
     size_t best = SIZE_MAX;
     for (uint32_t ry = 1; ry <= 8; ry *= 2) {
@@ -271,6 +268,15 @@ int launch_gemm_kernel(GemmCfg cfg, dim3 grid, const int8_t *a, const int8_t *b,
         }
     }
     if (xm.on) grid = dim3(grid.x * grid.y * grid.z, 1, 1);
+    return xm;
+}
+
+template <bool RAW>
+int launch_gemm_kernel(GemmCfg cfg, dim3 grid, const int8_t *a, const int8_t *b, int64_t kpad,
+                       int64_t a_ps, int64_t b_ps, const ModInfo *mi, int L, int16_t *v,
+                       int64_t v_ps, int64_t ldv, int32_t *craw, hipStream_t s) {
+    const GemmArgs g{a, b, kpad, a_ps, b_ps, mi, v, v_ps, ldv, craw};
+    const XcdMap xm = xcd_map_for(cfg, grid);
     if (cfg.bm == 256 && cfg.bn == 128) k_resgemm<128, 64, RAW><<<grid, 256, 0, s>>>(g, L, xm);
     else if (cfg.bm == 128 && cfg.bn == 256) k_resgemm<64, 128, RAW><<<grid, 256, 0, s>>>(g, L, xm);
     else k_resgemm<64, 64, RAW><<<grid, 256, 0, s>>>(g, L, xm);
@@ -893,6 +899,200 @@ int oz2h_gemm_from_residues(const oz2h_plan *plan, int64_t M, int64_t N, int64_t
     return run_pipeline(plan, M, N, K, opA, A, opB, B, true, &C, nullptr, nullptr, 0, nullptr,
                         nullptr, workspace, ws_bytes, stream, nullptr, ra ? &sa : nullptr,
                         rb ? &sb : nullptr);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- complex products
+
+namespace {
+
+// the exponent scan of two operands into one shared exponent per row (atomicMax
+// combines the partial maxima of both)
+int launch_exponents2(int64_t rows, int64_t count, const oz2h_cmat &X, const oz2h_cmat &Y,
+                      int64_t xrs, int64_t xcs, int64_t yrs, int64_t ycs, int32_t *out, hipStream_t s) {
+    if (rows <= 0) return OZ2H_OK;
+    const unsigned nb = (unsigned)((rows + 255) / 256);
+    k_fill_i32<<<nb, 256, 0, s>>>(out, rows, INT_MIN);
+    if (count > 0) {
+        for (int part = 0; part < 2; ++part) {
+            const oz2h_cmat &Z = part ? Y : X;
+            const int64_t rs = part ? yrs : xrs, cs = part ? ycs : xcs;
+            if (cs == 1) {
+                dim3 grid((unsigned)((rows + 3) / 4), (unsigned)((count + kExpChunk - 1) / kExpChunk));
+                k_exp_kcontig<<<grid, 256, 0, s>>>(Z.sign, Z.exp, rows, count, rs, nullptr, out);
+            } else {
+                dim3 grid(nb, (unsigned)((count + kExpRowsK - 1) / kExpRowsK));
+                k_exp_generic<<<grid, 256, 0, s>>>(Z.sign, Z.exp, rows, count, rs, cs, nullptr, out);
+            }
+        }
+    }
+    k_exp_fix<<<nb, 256, 0, s>>>(out, rows);
+    return check_launch("exponent scan");
+}
+
+struct ZLayout {
+    GemmCfg cfg;
+    int64_t mpad, npad, kpad;
+    int nsets;   // plane sets per side: 2 (4M: X_re, X_im) or 3 (3M: and X_re + X_im)
+    size_t off_e, off_f, off_a, off_b, off_vr, off_vi, off_dig, total;
+};
+
+ZLayout zlayout_for(const PlanHost &h, int scheme, int64_t M, int64_t N, int64_t K) {
+    ZLayout w{};
+    w.cfg = choose_gemm(std::max<int64_t>(M, 1), std::max<int64_t>(N, 1), h.tile);
+    w.mpad = round_up(std::max<int64_t>(M, 1), w.cfg.bm);
+    w.npad = round_up(std::max<int64_t>(N, 1), w.cfg.bn);
+    w.kpad = round_up(std::max<int64_t>(K, 1), GBK);
+    w.nsets = scheme == 3 ? 3 : 2;
+    size_t off = 0;
+    w.off_e = off;
+    off = align_up(off + sizeof(int32_t) * w.mpad);
+    w.off_f = off;
+    off = align_up(off + sizeof(int32_t) * w.npad);
+    w.off_a = off;
+    off = align_up(off + (size_t)w.nsets * h.G * w.mpad * w.kpad);
+    w.off_b = off;
+    off = align_up(off + (size_t)w.nsets * h.G * w.npad * w.kpad);
+    w.off_vr = off;
+    off = align_up(off + sizeof(int16_t) * (size_t)h.L * w.mpad * w.npad);
+    w.off_vi = off;
+    off = align_up(off + sizeof(int16_t) * (size_t)h.L * w.mpad * w.npad);
+    // the CRT digit columns reuse the planes (dead once the GEMMs are done) when they fit
+    const size_t dig = crt_gdig_bytes(h, M, N);
+    w.off_dig = w.off_a;
+    if (dig > w.off_vr - w.off_a) {
+        w.off_dig = off;
+        off = align_up(off + dig);
+    }
+    w.total = off;
+    return w;
+}
+
+int launch_resgemm_z(const oz2h_plan *pl, GemmCfg cfg, int64_t mpad, int64_t npad, int64_t kpad,
+                     const int8_t *a, const int8_t *b, int16_t *v, int16_t *v2, int mode,
+                     hipStream_t s) {
+    if (mode == ZSTORE) return launch_resgemm(pl, cfg, mpad, npad, kpad, a, b, v, s);
+    const PlanHost &h = pl->h;
+    dim3 grid((unsigned)(npad / cfg.bn), (unsigned)(mpad / cfg.bm), (unsigned)h.L);
+    const GemmArgsZ g{{a, b, kpad, mpad * kpad, npad * kpad, pl->d_info, v, mpad * npad, npad, nullptr}, v2};
+    const XcdMap xm = xcd_map_for(cfg, grid);
+#define OZ2H_ZG(WM, WN)                                                                        \
+    do {                                                                                       \
+        if (mode == ZADD) k_resgemm_z<WM, WN, ZADD><<<grid, 256, 0, s>>>(g, h.L, xm);          \
+        else if (mode == ZSUB) k_resgemm_z<WM, WN, ZSUB><<<grid, 256, 0, s>>>(g, h.L, xm);     \
+        else k_resgemm_z<WM, WN, ZGAUSS><<<grid, 256, 0, s>>>(g, h.L, xm);                     \
+    } while (0)
+    if (cfg.bm == 256 && cfg.bn == 128) OZ2H_ZG(128, 64);
+    else if (cfg.bm == 128 && cfg.bn == 256) OZ2H_ZG(64, 128);
+    else OZ2H_ZG(64, 64);
+#undef OZ2H_ZG
+    return check_launch("complex residue GEMM");
+}
+
+int launch_plane_sum(const oz2h_plan *pl, const int8_t *x, const int8_t *y, int8_t *out, int64_t ps,
+                     hipStream_t s) {
+    if (ps % 4096) return fail(OZ2H_EINVAL, "plane sum: plane stride not a multiple of 4096");
+    const int64_t nb = ps / 4096;
+    if (nb > INT32_MAX) return fail(OZ2H_ERANGE, "plane sum: planes too large for one launch");
+    k_plane_sum<<<dim3((unsigned)nb, (unsigned)pl->h.L), 256, 0, s>>>(x, y, out, ps, pl->d_info);
+    return check_launch("plane sum");
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t oz2h_zgemm_workspace_size(const oz2h_plan *plan, int32_t scheme, int64_t M, int64_t N) {
+    if (!plan || (scheme != 3 && scheme != 4) || M < 0 || N < 0) return 0;
+    return zlayout_for(plan->h, scheme, M, N, plan->h.K / 2).total;
+}
+
+int oz2h_zgemm(const oz2h_plan *plan, int32_t scheme, int64_t M, int64_t N, int64_t K, oz2h_op opA,
+               oz2h_cmat Ar, oz2h_cmat Ai, oz2h_op opB, oz2h_cmat Br, oz2h_cmat Bi, oz2h_mat Cr,
+               oz2h_mat Ci, void *ws, size_t ws_bytes, hipStream_t s) {
+    int st = check_plan(plan);
+    if (st) return st;
+    const PlanHost &h = plan->h;
+    if (scheme != 3 && scheme != 4) return fail(OZ2H_EINVAL, "scheme must be 3 (3M) or 4 (4M)");
+    if (M < 0 || N < 0 || K < 0) return fail(OZ2H_EINVAL, "negative dimension");
+    if ((opA != OZ2H_OP_N && opA != OZ2H_OP_T) || (opB != OZ2H_OP_N && opB != OZ2H_OP_T))
+        return fail(OZ2H_EINVAL, "op must be OZ2H_OP_N or OZ2H_OP_T");
+    if (M == 0 || N == 0) return ok();
+    for (const oz2h_mat *C : {&Cr, &Ci}) {
+        if (!C->limbs || !C->exp || !C->sign) return fail(OZ2H_EINVAL, "C: NULL pointer");
+        if (C->ld < N) return fail(OZ2H_EINVAL, "C: ld < N");
+    }
+    if (K == 0) {
+        const int nl = (h.p + 63) / 64;
+        for (const oz2h_mat *C : {&Cr, &Ci})
+            k_zero_out<<<(unsigned)((M * N + 255) / 256), 256, 0, s>>>(C->sign, C->exp, C->limbs,
+                                                                       M, N, C->ld, nl);
+        st = check_launch("zero output");
+        return st ? st : ok();
+    }
+    if (2 * K != h.K)
+        return fail(OZ2H_EINVAL, "a complex product of contraction length K = %lld needs a plan "
+                    "built for 2K = %lld (the plan's K is %lld)", (long long)K, (long long)(2 * K),
+                    (long long)h.K);
+    const int64_t ar = opA == OZ2H_OP_N ? M : K, ac = opA == OZ2H_OP_N ? K : M;
+    const int64_t br = opB == OZ2H_OP_N ? K : N, bc = opB == OZ2H_OP_N ? N : K;
+    if ((st = check_cmat(Ar, "Ar", ar, ac)) || (st = check_cmat(Ai, "Ai", ar, ac)) ||
+        (st = check_cmat(Br, "Br", br, bc)) || (st = check_cmat(Bi, "Bi", br, bc)))
+        return st;
+    const ZLayout w = zlayout_for(h, scheme, M, N, K);
+    if (!ws) return fail(OZ2H_EINVAL, "workspace is NULL");
+    if (((uintptr_t)ws) % kAlign) return fail(OZ2H_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < w.total)
+        return fail(OZ2H_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, w.total);
+    char *wb = (char *)ws;
+    int32_t *e = (int32_t *)(wb + w.off_e);
+    int32_t *f = (int32_t *)(wb + w.off_f);
+    const int64_t aps = (int64_t)h.G * w.mpad * w.kpad, bps = (int64_t)h.G * w.npad * w.kpad;
+    int8_t *ap[3], *bp[3];
+    for (int k = 0; k < 3; ++k) {
+        ap[k] = (int8_t *)(wb + w.off_a) + k * aps;
+        bp[k] = (int8_t *)(wb + w.off_b) + k * bps;
+    }
+    int16_t *vr = (int16_t *)(wb + w.off_vr), *vi = (int16_t *)(wb + w.off_vi);
+
+    // stage 1: one exponent per row of A over both parts, one per column of B
+    const int64_t a_rs = opA == OZ2H_OP_N ? Ar.ld : 1, a_cs = opA == OZ2H_OP_N ? 1 : Ar.ld;
+    const int64_t ai_rs = opA == OZ2H_OP_N ? Ai.ld : 1, ai_cs = opA == OZ2H_OP_N ? 1 : Ai.ld;
+    const int64_t b_rs = opB == OZ2H_OP_N ? 1 : Br.ld, b_cs = opB == OZ2H_OP_N ? Br.ld : 1;
+    const int64_t bi_rs = opB == OZ2H_OP_N ? 1 : Bi.ld, bi_cs = opB == OZ2H_OP_N ? Bi.ld : 1;
+    if ((st = launch_exponents2(M, K, Ar, Ai, a_rs, a_cs, ai_rs, ai_cs, e, s))) return st;
+    if ((st = launch_exponents2(N, K, Br, Bi, b_rs, b_cs, bi_rs, bi_cs, f, s))) return st;
+    // stage 2: the residue planes of each part at those exponents
+    if ((st = launch_residues(plan, M, K, Ar.limbs, Ar.exp, Ar.sign, a_rs, a_cs, e, w.mpad, w.kpad, ap[0], s)) ||
+        (st = launch_residues(plan, M, K, Ai.limbs, Ai.exp, Ai.sign, ai_rs, ai_cs, e, w.mpad, w.kpad, ap[1], s)) ||
+        (st = launch_residues(plan, N, K, Br.limbs, Br.exp, Br.sign, b_rs, b_cs, f, w.npad, w.kpad, bp[0], s)) ||
+        (st = launch_residues(plan, N, K, Bi.limbs, Bi.exp, Bi.sign, bi_rs, bi_cs, f, w.npad, w.kpad, bp[1], s)))
+        return st;
+    // stage 3: Re = Ar Br - Ai Bi and Im = Ar Bi + Ai Br, combined mod m_l
+    const auto gemm = [&](int ia, int ib, int16_t *v, int16_t *v2, int mode) {
+        return launch_resgemm_z(plan, w.cfg, w.mpad, w.npad, w.kpad, ap[ia], bp[ib], v, v2, mode, s);
+    };
+    if (scheme == 3) {
+        // 3M: T1 = Ar Br, T2 = Ai Bi, T3 = (Ar + Ai)(Br + Bi); Re = T1 - T2, Im = T3 - T1 - T2
+        if ((st = launch_plane_sum(plan, ap[0], ap[1], ap[2], w.mpad * w.kpad, s)) ||
+            (st = launch_plane_sum(plan, bp[0], bp[1], bp[2], w.npad * w.kpad, s)) ||
+            (st = gemm(0, 0, vr, nullptr, ZSTORE)) || (st = gemm(1, 1, vi, nullptr, ZSTORE)) ||
+            (st = gemm(2, 2, vr, vi, ZGAUSS)))
+            return st;
+    } else {
+        if ((st = gemm(0, 0, vr, nullptr, ZSTORE)) || (st = gemm(1, 1, vr, nullptr, ZSUB)) ||
+            (st = gemm(0, 1, vi, nullptr, ZSTORE)) || (st = gemm(1, 0, vi, nullptr, ZADD)))
+            return st;
+    }
+    // stages 4-5: one direct CRT and rounding per part, at the shared scale 2^(e_i + f_j - 2t)
+    uint32_t *dig = (uint32_t *)(wb + w.off_dig);
+    if ((st = launch_crt(plan, M, N, vr, w.mpad * w.npad, w.npad, e, f, true, false, Cr.sign, Cr.exp,
+                         Cr.limbs, Cr.ld, nullptr, 0, s, -1, dig)) ||
+        (st = launch_crt(plan, M, N, vi, w.mpad * w.npad, w.npad, e, f, true, false, Ci.sign, Ci.exp,
+                         Ci.limbs, Ci.ld, nullptr, 0, s, -1, dig)))
+        return st;
+    return ok();
 }
 
 }  // extern "C"

@@ -915,9 +915,21 @@ __device__ __forceinline__ int8_t *gemm_stage() {
 // (LDS/scalar and export counters left at their maximum)
 constexpr int vmcnt_imm(int vm) { return (vm & 0xF) | (((vm >> 4) & 3) << 14) | (0x7 << 4) | (0xF << 8); }
 
+// Arguments of the products that combine into an existing output (complex products):
+// V2 is a second output set with the same strides as V.
+struct GemmArgsZ : GemmArgs {
+    int16_t *V2;
+};
+
+// output combination of a complex product's residue GEMMs (x = this product's weighted
+// residue, all values centred mod m_l):
+//   ZSTORE  V = x;   ZADD  V = V + x;   ZSUB  V = V - x;
+//   ZGAUSS  (t1, t2) = (V, V2);  V = t1 - t2;  V2 = x - t1 - t2   (3M's last product)
+enum GemmMode { ZSTORE = 0, ZADD = 1, ZSUB = 2, ZGAUSS = 3 };
+
 // one output tile (mt, nt) of modulus l with an NS-stage LDS ring, NS - 1 tiles ahead
-template <int WM, int WN, bool RAW, int NS = 3>
-__device__ __forceinline__ void gemm_tile(const GemmArgs &args, int64_t mt, int64_t nt, int l) {
+template <int WM, int WN, bool RAW, int NS = 3, int MODE = ZSTORE, class Args = GemmArgs>
+__device__ __forceinline__ void gemm_tile(const Args &args, int64_t mt, int64_t nt, int l) {
     static_assert(NS == 2 || NS == 3, "two or three LDS stages");
     constexpr int BM = 2 * WM, BN = 2 * WN, FM = WM / 32, FN = WN / 32;
     constexpr int NLA = BM / 32, NL = (BM + BN) / 32;   // direct loads per wave per k-tile
@@ -1070,13 +1082,36 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &args, int64_t mt, int6
         return;
     }
     int16_t *base = args.V + (int64_t)l * args.v_ps + lane_off;
+    if constexpr (MODE == ZSTORE) {
 #pragma unroll
-    for (int x = 0; x < FM; ++x)
+        for (int x = 0; x < FM; ++x)
 #pragma unroll
-        for (int y = 0; y < FN; ++y)
+            for (int y = 0; y < FN; ++y)
 #pragma unroll
-            for (int e = 0; e < 16; ++e)
-                base[(int64_t)(x * 32 + 8 * (e >> 2) + (e & 3)) * ldv + y * 32] = (int16_t)acc[x][y][e];
+                for (int e = 0; e < 16; ++e)
+                    base[(int64_t)(x * 32 + 8 * (e >> 2) + (e & 3)) * ldv + y * 32] = (int16_t)acc[x][y][e];
+    } else {
+        int16_t *base2 = nullptr;
+        if constexpr (MODE == ZGAUSS) base2 = args.V2 + (int64_t)l * args.v_ps + lane_off;
+#pragma unroll
+        for (int x = 0; x < FM; ++x)
+#pragma unroll
+            for (int y = 0; y < FN; ++y)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int64_t o = (int64_t)(x * 32 + 8 * (e >> 2) + (e & 3)) * ldv + y * 32;
+                    const int32_t v = acc[x][y][e], t1 = base[o];
+                    if constexpr (MODE == ZADD) {
+                        base[o] = (int16_t)centred_mod((double)(t1 + v), md, inv_m);
+                    } else if constexpr (MODE == ZSUB) {
+                        base[o] = (int16_t)centred_mod((double)(t1 - v), md, inv_m);
+                    } else {
+                        const int32_t t2 = base2[o];
+                        base[o] = (int16_t)centred_mod((double)(t1 - t2), md, inv_m);
+                        base2[o] = (int16_t)centred_mod((double)(v - t1 - t2), md, inv_m);
+                    }
+                }
+    }
 }
 
 // XCD-aware block order of the plain launch.  Blocks are dealt to the 8 XCDs round-robin
@@ -1102,6 +1137,68 @@ __global__ __launch_bounds__(256) void k_resgemm(GemmArgs args, int L, XcdMap xm
     }
     const int l = RAW ? 0 : L - 1 - (int)zi;
     gemm_tile<WM, WN, RAW>(args, mt, nt, l);
+}
+
+// one residue GEMM of a complex product (the 3M / 4M schemes): the plain launch's block
+// order and tiles, the output combined into V (and V2) by MODE
+template <int WM, int WN, int MODE>
+__global__ __launch_bounds__(256) void k_resgemm_z(GemmArgsZ args, int L, XcdMap xm) {
+    uint32_t mt = blockIdx.y, nt = blockIdx.x, zi = blockIdx.z;
+    if (xm.on) {
+        const uint32_t b = blockIdx.x, x = b & 7u, s = b >> 3, t8 = xm.h * xm.w;
+        zi = s / t8;
+        const uint32_t u = s - zi * t8;
+        mt = (x / xm.rx) * xm.h + u / xm.w;
+        nt = (x % xm.rx) * xm.w + u % xm.w;
+    }
+    gemm_tile<WM, WN, false, 3, MODE, GemmArgsZ>(args, mt, nt, L - 1 - (int)zi);
+}
+
+// Residue planes of a sum of two operands (3M: Ar + Ai, Br + Bi) from the planes of
+// each: per modulus l, s = x + y reduced to the centred residue s - rint(s/m) m (the
+// quotient in fp32 is exact: |s| <= m + 3 < 2^15 and s/m is at least 1/(2m) from a
+// half-integer for odd m; for the even one-limb modulus 128 either tie is a valid
+// representative with |r| <= 64), then split like the residue kernels (one byte, or
+// the balanced base-128 limbs (r0, r1, r0 + r1)).  One thread per 16 bytes of a plane;
+// grid (ps / 4096 blocks of 256 threads, L).  ps is a multiple of 4096.
+__global__ __launch_bounds__(256) void k_plane_sum(const int8_t *__restrict__ X,
+                                                   const int8_t *__restrict__ Y,
+                                                   int8_t *__restrict__ S, int64_t ps,
+                                                   const ModInfo *__restrict__ mi) {
+    const ModInfo info = load_info((OZ2H_G(ModInfo) *)(mi + blockIdx.y));
+    const int64_t o = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 16;
+    if (o >= ps) return;
+    const float inv_m = (float)info.inv_m;
+    const int64_t b0 = (int64_t)info.g0 * ps + o;
+    auto reduce = [&](int sv) { return sv - (int)rintf((float)sv * inv_m) * (int)info.m; };
+    if (info.nprod == 1) {
+        const int4 xa = *(const int4 *)(X + b0), ya = *(const int4 *)(Y + b0);
+        const int8_t *xb = (const int8_t *)&xa, *yb = (const int8_t *)&ya;
+        int4 out;
+        int8_t *ob = (int8_t *)&out;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) ob[i] = (int8_t)reduce((int)xb[i] + (int)yb[i]);
+        *(int4 *)(S + b0) = out;
+        return;
+    }
+    const int4 x0 = *(const int4 *)(X + b0), x1 = *(const int4 *)(X + b0 + ps);
+    const int4 y0 = *(const int4 *)(Y + b0), y1 = *(const int4 *)(Y + b0 + ps);
+    const int8_t *x0b = (const int8_t *)&x0, *x1b = (const int8_t *)&x1;
+    const int8_t *y0b = (const int8_t *)&y0, *y1b = (const int8_t *)&y1;
+    int4 o0, o1, o2;
+    int8_t *o0b = (int8_t *)&o0, *o1b = (int8_t *)&o1, *o2b = (int8_t *)&o2;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int r = reduce((int)x0b[i] + 128 * (int)x1b[i] + (int)y0b[i] + 128 * (int)y1b[i]);
+        const int r0 = ((r + 64) & 127) - 64;   // balanced base-128 split
+        const int r1 = (r - r0) >> 7;
+        o0b[i] = (int8_t)r0;
+        o1b[i] = (int8_t)r1;
+        o2b[i] = (int8_t)(r0 + r1);
+    }
+    *(int4 *)(S + b0) = o0;
+    *(int4 *)(S + b0 + ps) = o1;
+    *(int4 *)(S + b0 + 2 * ps) = o2;
 }
 
 // ---------------------------------------------------------------- stage 4 + 5

@@ -98,6 +98,9 @@ SIGNATURES = {
     "oz2h_gemm_from_residues": (ctypes.c_int, [_P, _I64, _I64, _I64, _P, ctypes.c_int, CMat, _P,
                                                ctypes.c_int, CMat, Mat, _P, _SZ, _P]),
     "oz2h_residues_destroy": (None, [_P]),
+    "oz2h_zgemm_workspace_size": (_SZ, [_P, _I32, _I64, _I64]),
+    "oz2h_zgemm": (ctypes.c_int, [_P, _I32, _I64, _I64, _I64, ctypes.c_int, CMat, CMat, ctypes.c_int,
+                                  CMat, CMat, Mat, Mat, _P, _SZ, _P]),
     "oz2h_gemm_noalloc_max_bytes": (_SZ, []),
     "oz2h_gemm_noalloc": (ctypes.c_int, [_P, _I64, _I64, _I64, ctypes.c_int, CMat, ctypes.c_int, CMat,
                                          Mat, _P]),
@@ -334,6 +337,36 @@ def gemm(plan: Plan, A: DeviceMP, B: DeviceMP, opA: int = OP_N, opB: int = OP_N,
     if new_ws:
         _keep_for(stream, ws)
     return out
+
+
+ZGEMM_3M, ZGEMM_4M = 3, 4
+
+
+def zgemm(plan: Plan, Ar: DeviceMP, Ai: DeviceMP, Br: DeviceMP, Bi: DeviceMP, scheme: int = ZGEMM_3M,
+          opA: int = OP_N, opB: int = OP_N, out=None, ws=None, stream=None):
+    """(Re C, Im C) of C = op(A) op(B), A = Ar + i Ai, B = Br + i Bi (oz2h_zgemm); the plan
+    is built for contraction length 2K.  out: optional (Cr, Ci) pair."""
+    M, N, K = _dims(Ar, Br, opA, opB)
+    if _dims(Ai, Bi, opA, opB) != (M, N, K):
+        raise ValueError("real and imaginary parts differ in shape")
+    new_out, new_ws = out is None, ws is None
+    dev = Ar.sign.device
+    if out is None:
+        out = (empty_mp(M, N, plan.p, device=dev), empty_mp(M, N, plan.p, device=dev))
+    if ws is None:
+        torch = _torch()
+        n = lib().oz2h_zgemm_workspace_size(plan.handle, scheme, M, N)
+        ws = torch.empty(max(n, 256), dtype=torch.uint8, device=dev)
+    Cr, Ci = out
+    _check(lib().oz2h_zgemm(plan.handle, scheme, M, N, K, opA, Ar.cmat(), Ai.cmat(), opB, Br.cmat(),
+                            Bi.cmat(), Cr.mat(), Ci.mat(), ws.data_ptr(), ws.numel(),
+                            _stream_ptr(stream)))
+    if new_out:
+        for C in out:
+            _keep_for(stream, C.sign, C.exp, C.limbs)
+    if new_ws:
+        _keep_for(stream, ws)
+    return Cr, Ci
 
 
 SIDE_A, SIDE_B = 0, 1
