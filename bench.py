@@ -13,10 +13,12 @@ p = 2048 bits (exponents uniform in [-16, 16]), and carries as extra keys:
   - the batched form (64 uneven products, one graph) against the loop of plain
     calls ("speedup_vs_loop"), and the autograd form's residue reuse against
     recomputation ("reuse_vs_recompute");
+  - complex products at M = N = K = 4096, p = 256: the 3M scheme against 4M
+    ("complex");
   - the oracle on the host cores over a bounded block of outputs, which also
     checks the timed GPU output on that block bit for bit.
 
-  python bench.py [--steps K] [--warmup W] [--config cfg3|cfg1|cfg2|cfg3a|cfg3b|cfg4|cfg5]
+  python bench.py [--steps K] [--warmup W] [--config cfg3|cfg1|cfg2|cfg3a|cfg3b|cfg4|cfg5|complex]
                   [--cpu-seconds S] [--no-cpu-baseline] [--no-extras]
 
 Per-stage times come from HIP events that the library records on the launch
@@ -478,6 +480,47 @@ def measure_autograd(steps, warmup):
             "backward_entry_point_ms": round(ms_bwd, 4)}
 
 
+def measure_complex(steps, warmup):
+    """Complex products C = A B (A = Ar + i Ai, B = Br + i Bi) at M = N = K = 4096, p = 256
+    through oz2h_zgemm: the 3M scheme (three residue GEMMs per modulus) against 4M (four),
+    with the two outputs checked bit for bit against each other."""
+    import torch
+
+    import synth
+    from paper_2609_27831_amd import oz2h
+    M = N = K = 4096
+    p = 256
+    cfg = ("", M, N, K, p, -16, 16, 0)
+    Ar, Br = device_operands(cfg, synth.CONFIG_SEED_BASE + 61)
+    Ai, Bi = device_operands(cfg, synth.CONFIG_SEED_BASE + 62)
+    plan = oz2h.Plan.create(p, 2 * K)
+    flops = 8.0 * M * N * K      # real flops of a complex product
+    out, res = {}, {}
+    for scheme, name in ((oz2h.ZGEMM_3M, "3M"), (oz2h.ZGEMM_4M, "4M")):
+        n = oz2h.lib().oz2h_zgemm_workspace_size(plan.handle, scheme, M, N)
+        ws = torch.empty(n, dtype=torch.uint8, device="cuda")
+        C = (oz2h.empty_mp(M, N, p), oz2h.empty_mp(M, N, p))
+        for _ in range(warmup):
+            oz2h.zgemm(plan, Ar, Ai, Br, Bi, scheme=scheme, out=C, ws=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            oz2h.zgemm(plan, Ar, Ai, Br, Bi, scheme=scheme, out=C, ws=ws)
+        torch.cuda.synchronize()
+        out[name] = (time.perf_counter() - t0) * 1e3 / steps
+        res[name] = C
+        del ws
+        torch.cuda.empty_cache()
+    same = all(bool(torch.equal(getattr(x, f), getattr(y, f)))
+               for x, y in zip(res["3M"], res["4M"]) for f in ("sign", "exp", "limbs"))
+    plan.destroy()
+    return {"workload": "complex Ozaki-II, M=N=K=4096, p=256, exponents U[-16,16]",
+            "ms_3m": round(out["3M"], 4), "ms_4m": round(out["4M"], 4),
+            "speedup_3m_vs_4m": round(out["4M"] / out["3M"], 3),
+            "value_3m": round(flops / (out["3M"] * 1e-3) / 1e9, 3),
+            "unit": "GFlop/s (8MNK/s)", "bit_identical_3m_4m": same}
+
+
 def copy_calibration():
     """A plain device copy of known size, for the HBM-counter scale factors."""
     import torch
@@ -500,7 +543,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="cfg3",
-                    choices=sorted(CONFIGS) + ["cfg3", "cfg4", "cfg5"])
+                    choices=sorted(CONFIGS) + ["cfg3", "cfg4", "cfg5", "complex"])
     ap.add_argument("--flags", type=int, default=0,
                     help="OZ2H_FLAG_* bits of the timed plain products (default 0: MFMA-free "
                          "stages 2 and 4)")
@@ -527,11 +570,14 @@ def main():
             "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "i8", "data": "synthetic"}
 
-    if args.config in ("cfg4", "cfg5"):
+    if args.config in ("cfg4", "cfg5", "complex"):
         log(f"{args.config}")
-        r = (measure_batched if args.config == "cfg4" else measure_autograd)(args.steps, args.warmup)
-        line = dict(base, value=r.pop("value"),
-                    ms_per_step=r.get("graph_ms", r.get("reuse_ms_per_step")),
+        fn = {"cfg4": measure_batched, "cfg5": measure_autograd, "complex": measure_complex}[args.config]
+        r = fn(args.steps, args.warmup)
+        if args.config == "complex":
+            r["value"] = r["value_3m"]
+        ms = r.get("graph_ms", r.get("reuse_ms_per_step", r.get("ms_3m")))
+        line = dict(base, value=r.pop("value"), ms_per_step=ms,
                     config={"workload": r.pop("workload")}, **r)
         print(json.dumps(line), flush=True)
         return
@@ -582,6 +628,9 @@ def main():
         log("cfg5: autograd reuse vs recompute")
         line["autograd"] = measure_autograd(max(2, args.steps // 2), 1)
         line["reuse_vs_recompute"] = line["autograd"]["reuse_vs_recompute"]
+        torch.cuda.empty_cache()
+        log("complex products: 3M vs 4M")
+        line["complex"] = measure_complex(max(2, args.steps // 2), 1)
     print(json.dumps(line), flush=True)
 
 
