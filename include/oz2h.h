@@ -93,10 +93,30 @@ typedef struct {
  *   OZ2H_FLAG_CRT_MMA       CRT digit sums as (bytes of v_l) x (bytes of P/m_l)
  *                           INT8 products; taken when the CRT has 16..32 digits
  *                           and L <= 127, the VALU kernel otherwise.
- * Both variants give bit-identical results.  Any other bit is rejected.
+ * Both variants give bit-identical results.
+ *
+ * Backend flags (read when the plan is created; oz2h_plan_set_flags cannot change
+ * them), following the paper's subsection "(b) binary64 backend" and its Future
+ * Work item "Mixed backends":
+ *   OZ2H_FLAG_BACKEND_F64    binary64 backend: moduli are the primes below
+ *                            sqrt(2^55 / K) (Eq. fp64bound; also below 2^22) in
+ *                            decreasing order, taken until Eq. crtcond holds; the
+ *                            residues are exact binary64 values and each
+ *                            modulus's product runs on the fp64 matrix cores
+ *                            (exact: every partial sum is an integer below 2^53).
+ *   OZ2H_FLAG_BACKEND_MIXED  INT8 one-limb moduli (largest first) for up to half
+ *                            the bits Eq. crtcond needs, binary64 moduli for the
+ *                            rest; one direct CRT over both.
+ * The two exclude each other.  Since the CRT reconstructs the same exact integer
+ * c^ from any moduli set with P large enough, every backend gives bit-identical
+ * results.  Plans of these backends serve oz2h_gemm, oz2h_gemm_timed and
+ * oz2h_gemm_integers; the other entry points need an INT8-backend plan
+ * (OZ2H_EUNSUPPORTED otherwise).  Any other bit is rejected.
  */
 #define OZ2H_FLAG_RESIDUES_MMA 0x1u
 #define OZ2H_FLAG_CRT_MMA 0x2u
+#define OZ2H_FLAG_BACKEND_F64 0x4u
+#define OZ2H_FLAG_BACKEND_MIXED 0x8u
 
 /* Input matrix (device pointers). */
 typedef struct {
@@ -120,16 +140,18 @@ typedef struct {
     int32_t p;          /* significand bits                                          */
     int32_t t;          /* internal width, Eq. 3                                     */
     int64_t K;          /* contraction length the moduli were chosen for            */
-    int32_t L;          /* number of moduli                                          */
-    int32_t L1;         /* one-limb moduli (m <= 255), listed first                  */
-    int32_t L2;         /* two-limb moduli (255 < m <= 16191)                        */
-    int32_t G;          /* INT8 GEMMs = L1 + 3*L2                                    */
+    int32_t L;          /* number of moduli (of both parts of a mixed plan)          */
+    int32_t L1;         /* one-limb INT8 moduli (m <= 255), listed first             */
+    int32_t L2;         /* two-limb INT8 moduli (255 < m <= 16191)                   */
+    int32_t G;          /* GEMMs: INT8 GEMMs L1 + 3*L2, plus one per binary64 modulus */
     int32_t nw32;       /* 32-bit words of an integer significand (t+1 bits)         */
     int32_t nd32;       /* 32-bit digits of the CRT accumulator: ceil(log2 P/32) + 2 */
     double log2P;       /* log2 of the moduli product P                              */
     int32_t tw_a, tw_b; /* plans of oz2h_plan_create_grad: widths of the upstream
                            gradient for dA and dB (0 otherwise)                      */
     int64_t grad_M, grad_N; /* and the forward's M and N (0 otherwise)              */
+    int32_t backend;    /* 0 INT8, 1 binary64, 2 mixed                               */
+    int32_t Lf;         /* binary64 moduli (listed after the INT8 ones)              */
 } oz2h_plan_info;
 
 /* Default options: guard_bits 16, t_bits 0, crt_margin 2, tile AUTO, flags 0
@@ -151,6 +173,15 @@ const char *oz2h_last_error(void);
  */
 int oz2h_plan_moduli(int32_t p, int64_t K, const oz2h_opts *o, int32_t *L, int32_t *L1,
                      int32_t *G, int32_t *t, double *log2P, uint16_t *moduli);
+
+/*
+ * The same for every backend (o->flags may hold a backend flag; binary64 moduli
+ * need 32 bits): writes L (all moduli), L8 (the INT8 moduli, listed first), G
+ * (INT8 GEMMs plus one GEMM per binary64 modulus), t and log2 P, and the moduli
+ * if `moduli` is non-null.  Errors as oz2h_plan_moduli.
+ */
+int oz2h_plan_moduli32(int32_t p, int64_t K, const oz2h_opts *o, int32_t *L, int32_t *L8,
+                       int32_t *G, int32_t *t, double *log2P, uint32_t *moduli);
 
 /*
  * Build the constant tables for precision p and contraction length K and
@@ -182,8 +213,10 @@ int oz2h_plan_set_flags(oz2h_plan *plan, uint32_t flags);
 
 void oz2h_plan_destroy(oz2h_plan *plan);
 int oz2h_plan_get_info(const oz2h_plan *plan, oz2h_plan_info *info);
-/* The plan's moduli in the order the library uses (L entries). */
+/* The plan's moduli in the order the library uses (L entries); OZ2H_EUNSUPPORTED
+   for a plan with binary64 moduli, whose moduli oz2h_plan_get_moduli32 returns. */
 int oz2h_plan_get_moduli(const oz2h_plan *plan, uint16_t *moduli);
+int oz2h_plan_get_moduli32(const oz2h_plan *plan, uint32_t *moduli);
 
 /* Bytes of device workspace oz2h_gemm / oz2h_gemm_integers need for M x N. */
 size_t oz2h_gemm_workspace_size(const oz2h_plan *plan, int64_t M, int64_t N);

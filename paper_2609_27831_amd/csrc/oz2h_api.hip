@@ -19,6 +19,7 @@
 
 #include "oz2h.h"
 #include "oz2h_batched.hpp"
+#include "oz2h_f64.hpp"
 #include "oz2h_kernels.hpp"
 #include "oz2h_plan.hpp"
 
@@ -39,6 +40,10 @@ struct oz2h_plan {
     double *d_crt_row = nullptr;
     uint32_t *d_pd = nullptr;
     uint32_t *d_phd = nullptr;
+    F64Mod *d_f64 = nullptr;        // binary64 moduli (binary64 and mixed plans)
+    double *d_f64_rw = nullptr;
+    oz2h_plan *i8 = nullptr;        // mixed plans: the INT8 moduli's plan (weights against
+                                    // the whole P; its CRT tables unused)
 };
 
 namespace {
@@ -93,10 +98,13 @@ int check_device(int *dev_out) {
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
-constexpr uint32_t kAllFlags = OZ2H_FLAG_RESIDUES_MMA | OZ2H_FLAG_CRT_MMA;
+constexpr uint32_t kBackendFlags = OZ2H_FLAG_BACKEND_F64 | OZ2H_FLAG_BACKEND_MIXED;
+constexpr uint32_t kAllFlags = OZ2H_FLAG_RESIDUES_MMA | OZ2H_FLAG_CRT_MMA | kBackendFlags;
 
 int check_flags(uint32_t flags) {
     if (flags & ~kAllFlags) return fail(OZ2H_EINVAL, "unknown option flags 0x%x", flags & ~kAllFlags);
+    if ((flags & kBackendFlags) == kBackendFlags)
+        return fail(OZ2H_EINVAL, "OZ2H_FLAG_BACKEND_F64 and OZ2H_FLAG_BACKEND_MIXED exclude each other");
     return OZ2H_OK;
 }
 
@@ -482,6 +490,11 @@ int upload_plan(oz2h_plan *pl) {
     off = align_up(off + n_pd);
     const size_t o_phd = off;
     off = align_up(off + n_pd);
+    const size_t n_f64 = sizeof(F64Mod) * h.f64.size(), n_frw = sizeof(double) * h.f64_rw.size();
+    const size_t o_f64 = off;
+    off = align_up(off + n_f64);
+    const size_t o_frw = off;
+    off = align_up(off + n_frw);
     void *buf = nullptr;
     if (hipMalloc(&buf, off) != hipSuccess) return fail(OZ2H_ENOMEM, "plan tables: hipMalloc failed");
     pl->dbuf = buf;
@@ -497,12 +510,16 @@ int upload_plan(oz2h_plan *pl) {
     pl->d_crt_row = (double *)(b + o_crow);
     pl->d_pd = (uint32_t *)(b + o_pd);
     pl->d_phd = (uint32_t *)(b + o_phd);
+    pl->d_f64 = (F64Mod *)(b + o_f64);
+    pl->d_f64_rw = (double *)(b + o_frw);
+    if (n_f64) OZ2H_HIP(hipMemcpy(pl->d_f64, h.f64.data(), n_f64, hipMemcpyHostToDevice));
+    if (n_frw) OZ2H_HIP(hipMemcpy(pl->d_f64_rw, h.f64_rw.data(), n_frw, hipMemcpyHostToDevice));
     OZ2H_HIP(hipMemcpy(pl->d_info, h.info.data(), n_info, hipMemcpyHostToDevice));
-    OZ2H_HIP(hipMemcpy(pl->d_resid, h.resid_tab.data(), n_res, hipMemcpyHostToDevice));
-    OZ2H_HIP(hipMemcpy(pl->d_resid_row, h.resid_row.data(), n_rrow, hipMemcpyHostToDevice));
-    OZ2H_HIP(hipMemcpy(pl->d_rgrp, h.resgrp.data(), n_rg, hipMemcpyHostToDevice));
-    OZ2H_HIP(hipMemcpy(pl->d_rmma_w, h.rmma_w.data(), n_rw, hipMemcpyHostToDevice));
-    OZ2H_HIP(hipMemcpy(pl->d_rmma_rb, h.rmma_rb.data(), n_rrb, hipMemcpyHostToDevice));
+    if (n_res) OZ2H_HIP(hipMemcpy(pl->d_resid, h.resid_tab.data(), n_res, hipMemcpyHostToDevice));
+    if (n_rrow) OZ2H_HIP(hipMemcpy(pl->d_resid_row, h.resid_row.data(), n_rrow, hipMemcpyHostToDevice));
+    if (n_rg) OZ2H_HIP(hipMemcpy(pl->d_rgrp, h.resgrp.data(), n_rg, hipMemcpyHostToDevice));
+    if (n_rw) OZ2H_HIP(hipMemcpy(pl->d_rmma_w, h.rmma_w.data(), n_rw, hipMemcpyHostToDevice));
+    if (n_rrb) OZ2H_HIP(hipMemcpy(pl->d_rmma_rb, h.rmma_rb.data(), n_rrb, hipMemcpyHostToDevice));
     if (n_cafr) OZ2H_HIP(hipMemcpy(pl->d_crt_afr, h.crt_afr.data(), n_cafr, hipMemcpyHostToDevice));
     OZ2H_HIP(hipMemcpy(pl->d_crt, h.crt_digits.data(), n_crt, hipMemcpyHostToDevice));
     if (n_crow) OZ2H_HIP(hipMemcpy(pl->d_crt_row, h.crt_row.data(), n_crow, hipMemcpyHostToDevice));
@@ -521,6 +538,13 @@ int check_plan(const oz2h_plan *pl) {
     return OZ2H_OK;
 }
 
+// entry points built on the INT8 residue planes only
+int need_int8(const oz2h_plan *pl, const char *what) {
+    if (pl->h.backend != kBackendInt8)
+        return fail(OZ2H_EUNSUPPORTED, "%s needs an INT8-backend plan", what);
+    return OZ2H_OK;
+}
+
 int check_cmat(const oz2h_cmat &X, const char *name, int64_t rows, int64_t cols) {
     // rows x cols is the STORED shape
     if (!X.limbs || !X.exp || !X.sign) return fail(OZ2H_EINVAL, "%s: NULL pointer", name);
@@ -529,6 +553,128 @@ int check_cmat(const oz2h_cmat &X, const char *name, int64_t rows, int64_t cols)
                     (long long)cols);
     (void)rows;
     return OZ2H_OK;
+}
+
+// ---- binary64 and mixed backends
+
+// workspace of a binary64 / mixed product: exponents, the INT8 moduli's planes (mixed),
+// the binary64 planes (doubles), the CRT terms' int16 planes, the CRT digit columns
+struct F64Layout {
+    GemmCfg cfg;
+    int64_t mpad, npad, kpad;
+    size_t off_e, off_f, off_a8, off_b8, off_af, off_bf, off_u, off_dig, total;
+};
+
+F64Layout layout_f64(const oz2h_plan *pl, int64_t M, int64_t N) {
+    const PlanHost &h = pl->h;
+    const PlanHost *h8 = pl->i8 ? &pl->i8->h : nullptr;
+    F64Layout w{};
+    w.cfg = h8 ? choose_gemm(std::max<int64_t>(M, 1), std::max<int64_t>(N, 1), h8->tile) : GemmCfg{128, 128};
+    w.mpad = round_up(std::max<int64_t>(M, 1), w.cfg.bm);
+    w.npad = round_up(std::max<int64_t>(N, 1), w.cfg.bn);
+    w.kpad = round_up(std::max<int64_t>(h.K, 1), GBK);
+    const size_t g8 = h8 ? (size_t)h8->G : 0;
+    size_t off = 0;
+    w.off_e = off;
+    off = align_up(off + sizeof(int32_t) * w.mpad);
+    w.off_f = off;
+    off = align_up(off + sizeof(int32_t) * w.npad);
+    w.off_a8 = off;
+    off = align_up(off + g8 * w.mpad * w.kpad);
+    w.off_b8 = off;
+    off = align_up(off + g8 * w.npad * w.kpad);
+    w.off_af = off;
+    off = align_up(off + sizeof(double) * (size_t)h.Lf * w.mpad * w.kpad);
+    w.off_bf = off;
+    off = align_up(off + sizeof(double) * (size_t)h.Lf * w.npad * w.kpad);
+    w.off_u = off;
+    off = align_up(off + sizeof(int16_t) * (size_t)h.L * w.mpad * w.npad);
+    const size_t dig = crt_gdig_bytes(h, M, N);
+    w.off_dig = w.off_a8;   // the planes are dead once the GEMMs are done
+    if (dig > w.off_u - w.off_a8) {
+        w.off_dig = off;
+        off = align_up(off + dig);
+    }
+    w.total = off;
+    return w;
+}
+
+int launch_residues_f64(const oz2h_plan *pl, int64_t rows, int64_t count, const uint64_t *limbs,
+                        const int32_t *exp, const int8_t *sign, int64_t rs, int64_t cs,
+                        const int32_t *erow, int64_t rpad, int64_t kpad, double *planes, hipStream_t s) {
+    const PlanHost &h = pl->h;
+    const int64_t nblk = rpad * (kpad / kResF64Block);
+    if (nblk > INT32_MAX) return fail(OZ2H_ERANGE, "binary64 residues: operand too large for one launch");
+    const size_t lds = (size_t)h.nw32 * kResF64Block * sizeof(uint32_t);
+    if (lds > 65536) return fail(OZ2H_EUNSUPPORTED, "binary64 residues: integers of %d words", h.nw32);
+    const ResF64Args a{limbs, exp, sign, rs, cs, rows, count, kpad, rpad * kpad, erow,
+                       h.p, (h.p + 63) / 64, h.t, h.nw32, h.Lf, h.fnh, pl->d_f64_rw, pl->d_f64, planes};
+    k_residues_f64<<<dim3((unsigned)nblk), kResF64Block, lds, s>>>(a);
+    return check_launch("binary64 residues");
+}
+
+int launch_dgemm(const oz2h_plan *pl, int64_t mpad, int64_t npad, int64_t kpad, const double *a,
+                 const double *b, int16_t *u, hipStream_t s) {
+    const PlanHost &h = pl->h;
+    if (mpad % 128 || npad % 128 || kpad % kDgemmBK) return fail(OZ2H_EINVAL, "binary64 GEMM: bad padding");
+    if (mpad / 128 > 65535) return fail(OZ2H_ERANGE, "binary64 GEMM: M too large for one launch");
+    const DgemmArgs g{a, b, kpad, mpad * kpad, npad * kpad, pl->d_f64, u, mpad * npad, npad, h.L8};
+    k_dgemm_res<<<dim3((unsigned)(npad / 128), (unsigned)(mpad / 128), (unsigned)h.Lf), 256, 0, s>>>(g);
+    return check_launch("binary64 residue GEMM");
+}
+
+// the product on a binary64 / mixed plan (arguments checked by run_pipeline)
+int run_pipeline_f64(const oz2h_plan *pl, int64_t M, int64_t N, int64_t K, oz2h_op opA,
+                     oz2h_cmat A, oz2h_op opB, oz2h_cmat B, bool round, oz2h_mat *C,
+                     int8_t *chat_sign, uint64_t *chat_mag, int nlc, int32_t *e_out, int32_t *f_out,
+                     void *ws, size_t ws_bytes, hipStream_t s, hipEvent_t *ev) {
+    const PlanHost &h = pl->h;
+    const F64Layout w = layout_f64(pl, M, N);
+    if (!ws) return fail(OZ2H_EINVAL, "workspace is NULL");
+    if (((uintptr_t)ws) % kAlign) return fail(OZ2H_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < w.total)
+        return fail(OZ2H_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, w.total);
+    char *wb = (char *)ws;
+    int32_t *e = (int32_t *)(wb + w.off_e);
+    int32_t *f = (int32_t *)(wb + w.off_f);
+    int8_t *a8 = (int8_t *)(wb + w.off_a8), *b8 = (int8_t *)(wb + w.off_b8);
+    double *af = (double *)(wb + w.off_af), *bf = (double *)(wb + w.off_bf);
+    int16_t *u = (int16_t *)(wb + w.off_u);
+    const int64_t a_rs = opA == OZ2H_OP_N ? A.ld : 1, a_cs = opA == OZ2H_OP_N ? 1 : A.ld;
+    const int64_t b_rs = opB == OZ2H_OP_N ? 1 : B.ld, b_cs = opB == OZ2H_OP_N ? B.ld : 1;
+    int st;
+    if (ev) OZ2H_HIP(hipEventRecord(ev[0], s));
+    if ((st = launch_exponents(M, K, A.sign, A.exp, a_rs, a_cs, nullptr, e, s)) ||
+        (st = launch_exponents(N, K, B.sign, B.exp, b_rs, b_cs, nullptr, f, s)))
+        return st;
+    if (ev) OZ2H_HIP(hipEventRecord(ev[1], s));
+    if (pl->i8 &&
+        ((st = launch_residues(pl->i8, M, K, A.limbs, A.exp, A.sign, a_rs, a_cs, e, w.mpad, w.kpad, a8, s)) ||
+         (st = launch_residues(pl->i8, N, K, B.limbs, B.exp, B.sign, b_rs, b_cs, f, w.npad, w.kpad, b8, s))))
+        return st;
+    if ((st = launch_residues_f64(pl, M, K, A.limbs, A.exp, A.sign, a_rs, a_cs, e, w.mpad, w.kpad, af, s)) ||
+        (st = launch_residues_f64(pl, N, K, B.limbs, B.exp, B.sign, b_rs, b_cs, f, w.npad, w.kpad, bf, s)))
+        return st;
+    if (ev) OZ2H_HIP(hipEventRecord(ev[2], s));
+    // INT8 moduli write CRT terms 0 .. L8 - 1, binary64 moduli the terms after them
+    if (pl->i8 && (st = launch_resgemm(pl->i8, w.cfg, w.mpad, w.npad, w.kpad, a8, b8, u, s))) return st;
+    if ((st = launch_dgemm(pl, w.mpad, w.npad, w.kpad, af, bf, u, s))) return st;
+    if (ev) OZ2H_HIP(hipEventRecord(ev[3], s));
+    uint32_t *dig = (uint32_t *)(wb + w.off_dig);
+    if (round) {
+        st = launch_crt(pl, M, N, u, w.mpad * w.npad, w.npad, e, f, true, false, C->sign, C->exp,
+                        C->limbs, C->ld, nullptr, 0, s, -1, dig);
+    } else {
+        st = launch_crt(pl, M, N, u, w.mpad * w.npad, w.npad, e, f, false, false, chat_sign, nullptr,
+                        nullptr, N, chat_mag, nlc, s, -1, dig);
+        if (!st) {
+            OZ2H_HIP(hipMemcpyAsync(e_out, e, sizeof(int32_t) * M, hipMemcpyDeviceToDevice, s));
+            OZ2H_HIP(hipMemcpyAsync(f_out, f, sizeof(int32_t) * N, hipMemcpyDeviceToDevice, s));
+        }
+    }
+    if (st) return st;
+    if (ev) OZ2H_HIP(hipEventRecord(ev[4], s));
+    return ok();
 }
 
 // Stages 1-2 of one operand side kept from an earlier call (a residue handle): its shared
@@ -575,6 +721,11 @@ int run_pipeline(const oz2h_plan *pl, int64_t M, int64_t N, int64_t K, oz2h_op o
                               (long long)K, (long long)h.K);
     if (!ca && (st = check_cmat(A, "A", opA == OZ2H_OP_N ? M : K, opA == OZ2H_OP_N ? K : M))) return st;
     if (!cb && (st = check_cmat(B, "B", opB == OZ2H_OP_N ? K : N, opB == OZ2H_OP_N ? N : K))) return st;
+    if (h.backend != kBackendInt8) {
+        if (ca || cb) return fail(OZ2H_EUNSUPPORTED, "residue handles need an INT8-backend plan");
+        return run_pipeline_f64(pl, M, N, K, opA, A, opB, B, round, C, chat_sign, chat_mag, nlc, e_out,
+                                f_out, ws, ws_bytes, s, ev);
+    }
     const Layout w = layout_for(h, M, N);
     if (!ws) return fail(OZ2H_EINVAL, "workspace is NULL");
     if (((uintptr_t)ws) % kAlign) return fail(OZ2H_EINVAL, "workspace must be 256-byte aligned");
@@ -642,6 +793,8 @@ int oz2h_plan_moduli(int32_t p, int64_t K, const oz2h_opts *o, int32_t *L, int32
     oz2h_opts_default(&d);
     if (!o) o = &d;
     if (check_flags(o->flags)) return OZ2H_EINVAL;
+    if (o->flags & kBackendFlags)
+        return fail(OZ2H_EUNSUPPORTED, "binary64 moduli do not fit 16 bits: use oz2h_plan_moduli32");
     std::vector<uint32_t> mods;
     int tt = 0;
     double lp = 0;
@@ -663,6 +816,39 @@ int oz2h_plan_moduli(int32_t p, int64_t K, const oz2h_opts *o, int32_t *L, int32
     return ok();
 }
 
+int oz2h_plan_moduli32(int32_t p, int64_t K, const oz2h_opts *o, int32_t *L, int32_t *L8,
+                       int32_t *G, int32_t *t, double *log2P, uint32_t *moduli) {
+    oz2h_opts d;
+    oz2h_opts_default(&d);
+    if (!o) o = &d;
+    if (check_flags(o->flags)) return OZ2H_EINVAL;
+    std::vector<uint32_t> m8, m64;
+    int tt = 0;
+    double lp = 0;
+    std::string err;
+    int st;
+    if (o->flags & kBackendFlags) {
+        st = select_moduli_f64(p, K, o->guard_bits, o->t_bits, o->crt_margin,
+                               (o->flags & OZ2H_FLAG_BACKEND_MIXED) != 0, m8, m64, tt, lp, err);
+    } else {
+        st = select_moduli(p, K, o->guard_bits, o->t_bits, o->crt_margin, m8, tt, lp, err);
+    }
+    if (st) return fail(st, "%s", err.c_str());
+    int g = 0;
+    for (uint32_t m : m8) g += m <= kOneLimbMax ? 1 : 3;
+    if (L) *L = (int32_t)(m8.size() + m64.size());
+    if (L8) *L8 = (int32_t)m8.size();
+    if (G) *G = g + (int32_t)m64.size();
+    if (t) *t = tt;
+    if (log2P) *log2P = lp;
+    if (moduli) {
+        size_t i = 0;
+        for (uint32_t m : m8) moduli[i++] = m;
+        for (uint32_t m : m64) moduli[i++] = m;
+    }
+    return ok();
+}
+
 static int plan_finish(oz2h_plan *pl, oz2h_plan **out) {
     int dev = -1;
     int st = check_device(&dev);
@@ -672,13 +858,43 @@ static int plan_finish(oz2h_plan *pl, oz2h_plan **out) {
     }
     pl->device = dev;
     st = upload_plan(pl);
+    if (!st && pl->i8) {
+        pl->i8->device = dev;
+        st = upload_plan(pl->i8);
+    }
     if (st) {
-        if (pl->dbuf) (void)hipFree(pl->dbuf);
-        delete pl;
+        oz2h_plan_destroy(pl);
         return st;
     }
     *out = pl;
     return ok();
+}
+
+// plans of the binary64 and mixed backends (OZ2H_FLAG_BACKEND_F64 / _MIXED)
+static int plan_create_f64(int32_t p, int64_t K, const oz2h_opts *o, oz2h_plan **out) {
+    const bool mixed = (o->flags & OZ2H_FLAG_BACKEND_MIXED) != 0;
+    std::vector<uint32_t> m8, m64;
+    int t = 0;
+    double lp = 0;
+    std::string err;
+    int st = select_moduli_f64(p, K, o->guard_bits, o->t_bits, o->crt_margin, mixed, m8, m64, t, lp, err);
+    if (st) return fail(st, "%s", err.c_str());
+    oz2h_plan *pl = new oz2h_plan();
+    PlanHost h8;
+    st = build_plan_f64(p, t, K, m8, m64, pl->h, &h8, err);
+    if (st) {
+        delete pl;
+        return fail(st, "%s", err.c_str());
+    }
+    pl->h.tile = o->tile;
+    pl->h.flags = o->flags;
+    if (!m8.empty()) {
+        pl->i8 = new oz2h_plan();
+        pl->i8->h = std::move(h8);
+        pl->i8->h.tile = o->tile;
+        pl->i8->h.flags = o->flags & ~kBackendFlags;
+    }
+    return plan_finish(pl, out);
 }
 
 int oz2h_plan_create(int32_t p, int64_t K, const oz2h_opts *o, oz2h_plan **out) {
@@ -688,13 +904,14 @@ int oz2h_plan_create(int32_t p, int64_t K, const oz2h_opts *o, oz2h_plan **out) 
     oz2h_opts_default(&d);
     if (!o) o = &d;
     if (check_flags(o->flags)) return OZ2H_EINVAL;
+    if (o->tile < OZ2H_TILE_AUTO || o->tile > OZ2H_TILE_128x256) return fail(OZ2H_EINVAL, "bad tile");
+    if (o->flags & kBackendFlags) return plan_create_f64(p, K, o, out);
     std::vector<uint32_t> mods;
     int t = 0;
     double lp = 0;
     std::string err;
     int st = select_moduli(p, K, o->guard_bits, o->t_bits, o->crt_margin, mods, t, lp, err);
     if (st) return fail(st, "%s", err.c_str());
-    if (o->tile < OZ2H_TILE_AUTO || o->tile > OZ2H_TILE_128x256) return fail(OZ2H_EINVAL, "bad tile");
     oz2h_plan *pl = new oz2h_plan();
     st = build_plan(p, t, K, mods, pl->h, err);
     if (st) {
@@ -734,12 +951,16 @@ int oz2h_plan_create_custom(int32_t p, int32_t t, int64_t K, int32_t L, const ui
 int oz2h_plan_set_flags(oz2h_plan *plan, uint32_t flags) {
     if (!plan) return fail(OZ2H_EINVAL, "plan is NULL");
     if (check_flags(flags)) return OZ2H_EINVAL;
+    if ((flags & kBackendFlags) != (plan->h.flags & kBackendFlags))
+        return fail(OZ2H_EINVAL, "the backend flags are fixed when the plan is created");
     plan->h.flags = flags;
+    if (plan->i8) plan->i8->h.flags = flags & ~kBackendFlags;
     return ok();
 }
 
 void oz2h_plan_destroy(oz2h_plan *plan) {
     if (!plan) return;
+    if (plan->i8) oz2h_plan_destroy(plan->i8);
     if (plan->dbuf) (void)hipFree(plan->dbuf);
     delete plan;
 }
@@ -761,17 +982,36 @@ int oz2h_plan_get_info(const oz2h_plan *plan, oz2h_plan_info *info) {
     info->tw_b = h.grad ? h.tw[1] : 0;
     info->grad_M = h.grad ? h.gM : 0;
     info->grad_N = h.grad ? h.gN : 0;
+    info->backend = h.backend;
+    info->Lf = h.Lf;
+    if (h.backend != kBackendInt8) {
+        // moduli and GEMMs of both parts (CRT terms are an internal matter)
+        const PlanHost *h8 = plan->i8 ? &plan->i8->h : nullptr;
+        info->L = h.L8 + h.Lf;
+        info->L1 = h8 ? h8->L1 : 0;
+        info->L2 = h8 ? h8->L2 : 0;
+        info->G = (h8 ? h8->G : 0) + h.Lf;
+    }
     return ok();
 }
 
 int oz2h_plan_get_moduli(const oz2h_plan *plan, uint16_t *moduli) {
     if (!plan || !moduli) return fail(OZ2H_EINVAL, "NULL pointer");
+    if (plan->h.backend != kBackendInt8)
+        return fail(OZ2H_EUNSUPPORTED, "binary64 moduli do not fit 16 bits: use oz2h_plan_get_moduli32");
     for (int l = 0; l < plan->h.L; ++l) moduli[l] = (uint16_t)plan->h.moduli[l];
+    return ok();
+}
+
+int oz2h_plan_get_moduli32(const oz2h_plan *plan, uint32_t *moduli) {
+    if (!plan || !moduli) return fail(OZ2H_EINVAL, "NULL pointer");
+    for (size_t l = 0; l < plan->h.moduli.size(); ++l) moduli[l] = plan->h.moduli[l];
     return ok();
 }
 
 size_t oz2h_gemm_workspace_size(const oz2h_plan *plan, int64_t M, int64_t N) {
     if (!plan || M < 0 || N < 0) return 0;
+    if (plan->h.backend != kBackendInt8) return layout_f64(plan, M, N).total;
     return layout_for(plan->h, M, N).total;
 }
 
@@ -837,7 +1077,7 @@ int oz2h_residues_create(const oz2h_plan *plan, int32_t side, int64_t rows, oz2h
     if (!out) return fail(OZ2H_EINVAL, "out is NULL");
     *out = nullptr;
     int st = check_plan(plan);
-    if (st) return st;
+    if (st || (st = need_int8(plan, "oz2h_residues_create"))) return st;
     const PlanHost &h = plan->h;
     if (side != OZ2H_SIDE_A && side != OZ2H_SIDE_B) return fail(OZ2H_EINVAL, "side must be OZ2H_SIDE_A or OZ2H_SIDE_B");
     if (op != OZ2H_OP_N && op != OZ2H_OP_T) return fail(OZ2H_EINVAL, "op must be OZ2H_OP_N or OZ2H_OP_T");
@@ -1012,7 +1252,7 @@ int oz2h_zgemm(const oz2h_plan *plan, int32_t scheme, int64_t M, int64_t N, int6
                oz2h_cmat Ar, oz2h_cmat Ai, oz2h_op opB, oz2h_cmat Br, oz2h_cmat Bi, oz2h_mat Cr,
                oz2h_mat Ci, void *ws, size_t ws_bytes, hipStream_t s) {
     int st = check_plan(plan);
-    if (st) return st;
+    if (st || (st = need_int8(plan, "oz2h_zgemm"))) return st;
     const PlanHost &h = plan->h;
     if (scheme != 3 && scheme != 4) return fail(OZ2H_EINVAL, "scheme must be 3 (3M) or 4 (4M)");
     if (M < 0 || N < 0 || K < 0) return fail(OZ2H_EINVAL, "negative dimension");
@@ -1133,7 +1373,7 @@ size_t oz2h_gemm_noalloc_max_bytes(void) { return kScratchBytes; }
 int oz2h_gemm_noalloc(const oz2h_plan *plan, int64_t M, int64_t N, int64_t K, oz2h_op opA,
                       oz2h_cmat A, oz2h_op opB, oz2h_cmat B, oz2h_mat C, hipStream_t stream) {
     int st = check_plan(plan);
-    if (st) return st;
+    if (st || (st = need_int8(plan, "oz2h_gemm_noalloc"))) return st;
     if (M > 0 && N > 0 && K > 0) {
         const size_t need = layout_for(plan->h, M, N).total;
         if (need > kScratchBytes)
@@ -1222,6 +1462,7 @@ int oz2h_plan_create_grad(int32_t p, int64_t M, int64_t N, int64_t K, const oz2h
     oz2h_opts_default(&d);
     if (!o) o = &d;
     if (check_flags(o->flags)) return OZ2H_EINVAL;
+    if (o->flags & kBackendFlags) return fail(OZ2H_EUNSUPPORTED, "backward plans use the INT8 backend");
     if (o->tile < OZ2H_TILE_AUTO || o->tile > OZ2H_TILE_128x256) return fail(OZ2H_EINVAL, "bad tile");
     if (M < 1 || N < 1) return fail(OZ2H_EINVAL, "M and N must be >= 1");
     if (M > kMaxK || N > kMaxK)
@@ -1378,7 +1619,7 @@ int oz2h_residues(const oz2h_plan *plan, int64_t rows, int64_t count, const uint
                   const int32_t *erow, int64_t rpad, int64_t kpad, int8_t *planes,
                   hipStream_t stream) {
     int st = check_plan(plan);
-    if (st) return st;
+    if (st || (st = need_int8(plan, "oz2h_residues"))) return st;
     if (rows < 0 || count < 0) return fail(OZ2H_EINVAL, "negative dimension");
     if (rpad % 128 || kpad % GBK || rpad < rows || kpad < count || rpad <= 0 || kpad <= 0)
         return fail(OZ2H_EINVAL, "rpad must be a positive multiple of 128 >= rows, kpad of 128 >= count");
@@ -1393,7 +1634,7 @@ int oz2h_residue_gemm(const oz2h_plan *plan, int64_t mpad, int64_t npad, int64_t
                       const int8_t *a_planes, const int8_t *b_planes, int16_t *v,
                       hipStream_t stream) {
     int st = check_plan(plan);
-    if (st) return st;
+    if (st || (st = need_int8(plan, "oz2h_residue_gemm"))) return st;
     if (mpad <= 0 || npad <= 0 || kpad <= 0 || mpad % 128 || npad % 128 || kpad % GBK)
         return fail(OZ2H_EINVAL, "mpad, npad must be positive multiples of 128 and kpad of 128");
     if (kpad > kMaxK + GBK) return fail(OZ2H_ERANGE, "K too large for exact INT32 accumulation");
@@ -1432,7 +1673,7 @@ int oz2h_crt(const oz2h_plan *plan, int64_t M, int64_t N, const int16_t *u, int6
              int64_t plane_stride, int8_t *chat_sign, uint64_t *chat_mag, int32_t nlc,
              void *workspace, size_t ws_bytes, hipStream_t stream) {
     int st = check_plan(plan);
-    if (st) return st;
+    if (st || (st = need_int8(plan, "oz2h_crt"))) return st;
     if (M < 0 || N < 0) return fail(OZ2H_EINVAL, "negative dimension");
     if (M == 0 || N == 0) return ok();
     if (!u || !chat_sign || !chat_mag) return fail(OZ2H_EINVAL, "NULL pointer");
@@ -1682,6 +1923,7 @@ int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2
     oz2h_opts_default(&d);
     if (!o) o = &d;
     if (check_flags(o->flags)) return OZ2H_EINVAL;
+    if (o->flags & kBackendFlags) return fail(OZ2H_EUNSUPPORTED, "the batched form uses the INT8 backend");
     int dev = -1;
     int st = check_device(&dev);
     if (st) return st;

@@ -244,6 +244,62 @@ void build_crt_mma_tables(PlanHost &h, const std::vector<uint32_t> &mods, const 
     h.crt_mma = true;
 }
 
+// Digit tables of the direct CRT over h.L terms: S = sum_l v_l coef_l with coef_l = P / m_l
+// (or a multiple of it), as balanced base-2^32 digits (|d| <= 2^31), plus P's digits and
+// the top-digit estimate of S / P.
+int crt_tables(PlanHost &h, const Nat &P, const std::vector<Nat> &coef, std::string &err) {
+    h.pbits = nat_bitlen(P);
+    h.nd32 = (h.pbits + 31) / 32 + 2;   // two digits of headroom (subsection on the batched CRT)
+    h.crt_nc = (h.nd32 + 31) / 32;
+    int per = (h.nd32 + h.crt_nc - 1) / h.crt_nc;
+    h.crt_dc = ((per + 3) / 4) * 4;   // a multiple of 4 (two digits per LDS read, little padding)
+    h.crt_ndpad = h.crt_dc * h.crt_nc;
+    h.crt_digits.assign((size_t)h.L * h.crt_ndpad, 0.0);
+    for (int l = 0; l < h.L; ++l) {
+        const Nat &Ml = coef[l];
+        int64_t carry = 0;
+        for (int k = 0; k < h.crt_ndpad; ++k) {
+            int64_t x = (k < (int)Ml.size() ? (int64_t)Ml[k] : 0) + carry;
+            if (x >= (int64_t)1 << 31) {
+                x -= (int64_t)1 << 32;
+                carry = 1;
+            } else {
+                carry = 0;
+            }
+            h.crt_digits[(size_t)l * h.crt_ndpad + k] = (double)x;
+        }
+        if (carry || (int)Ml.size() > h.crt_ndpad) {
+            err = "internal error: CRT digit table too short";
+            return -1;
+        }
+    }
+    // S/P from the top crt_nt digits of S: S_top / P_top with X_top = X / 2^(32 (nd32 - nt))
+    // (P's digits below the top nt are dropped: P_top keeps at least 64 of P's bits)
+    h.crt_nt = std::min(h.nd32, 5);
+    {
+        double ptop = 0.0;
+        for (int k = h.nd32 - 1; k >= h.nd32 - h.crt_nt; --k)
+            ptop = ptop * 4294967296.0 + (double)(k < (int)P.size() ? P[k] : 0u);
+        h.crt_inv_ptop = 1.0 / ptop;
+    }
+    // the row-broadcast CRT's table: digit d of coef_l at [d][l], 16 digits per lane row group
+    h.crt_ndg = (h.nd32 + 15) / 16;
+    h.crt_lpad = (h.L + 15) / 16 * 16;
+    h.crt_row.assign((size_t)16 * h.crt_ndg * h.crt_lpad, 0.0);
+    for (int l = 0; l < h.L; ++l)
+        for (int d = 0; d < h.nd32 && d < h.crt_ndpad; ++d)
+            h.crt_row[(size_t)d * h.crt_lpad + l] = h.crt_digits[(size_t)l * h.crt_ndpad + d];
+    h.p_digits.assign(h.nd32, 0);
+    h.ph_digits.assign(h.nd32, 0);
+    for (int k = 0; k < h.nd32 && k < (int)P.size(); ++k) h.p_digits[k] = P[k];
+    for (int k = 0; k < h.nd32; ++k) {
+        uint32_t lo = h.p_digits[k] >> 1;
+        uint32_t hi = (k + 1 < h.nd32) ? (h.p_digits[k + 1] & 1u) << 31 : 0;
+        h.ph_digits[k] = lo | hi;
+    }
+    return 0;
+}
+
 // Tables of the MFMA residue kernel.  The residue of a magnitude |a| = sum_j b_j 256^j
 // (bytes b_j, j < nb) is sum_j b_j w_j mod m with w_j the centred 256^j mod m: an int8
 // product of the byte string and a weight row (two rows of balanced base-128 halves for
@@ -312,7 +368,7 @@ void build_residue_mma_tables(PlanHost &h, const std::vector<uint32_t> &mods) {
 }
 
 int build_plan(int p, int t, int64_t K, const std::vector<uint32_t> &mods_in, PlanHost &h,
-               std::string &err, int wmax, bool allow_wide) {
+               std::string &err, int wmax, bool allow_wide, const std::vector<uint32_t> *extra) {
     if (mods_in.empty() || (int)mods_in.size() > kMaxModuli) {
         err = "need 1..512 moduli";
         return -1;
@@ -363,18 +419,16 @@ int build_plan(int p, int t, int64_t K, const std::vector<uint32_t> &mods_in, Pl
         else ++h.L2;
     }
     h.G = (int)g;
-    h.pbits = nat_bitlen(P);
-    h.nd32 = (h.pbits + 31) / 32 + 2;   // two digits of headroom (subsection on the batched CRT)
 
-    // direct-CRT weights: M_l = P / m_l, minv = M_l^-1 mod m_l
-    h.crt_nc = (h.nd32 + 31) / 32;
-    int per = (h.nd32 + h.crt_nc - 1) / h.crt_nc;
-    h.crt_dc = ((per + 3) / 4) * 4;   // a multiple of 4 (two digits per LDS read, little padding)
-    h.crt_ndpad = h.crt_dc * h.crt_nc;
-    h.crt_digits.assign((size_t)h.L * h.crt_ndpad, 0.0);
+    // direct-CRT weights: M_l = P_all / m_l, minv = M_l^-1 mod m_l, with P_all the product of
+    // every modulus of the CRT (times the extra moduli of a mixed plan)
+    Nat Pw = P;
+    if (extra)
+        for (uint32_t m : *extra) nat_mul_small(Pw, m);
+    std::vector<Nat> coef(h.L);
     for (int l = 0; l < h.L; ++l) {
         const uint32_t m = mods[l];
-        Nat Ml = nat_divexact_small(P, m);
+        const Nat Ml = nat_divexact_small(Pw, m);
         uint32_t minv = inv_mod(nat_mod_small(Ml, m), m);
         if (!minv && m != 1) {
             err = "internal error: M_l not invertible";
@@ -405,48 +459,11 @@ int build_plan(int p, int t, int64_t K, const std::vector<uint32_t> &mods_in, Pl
             h.info[l].kc[1] = centred(((c2 + m) % m) * (int64_t)csi);
             h.info[l].kc[2] = centred(cs);
         }
-        // balanced base-2^32 digits, |d| <= 2^31
-        int64_t carry = 0;
-        for (int k = 0; k < h.crt_ndpad; ++k) {
-            int64_t x = (k < (int)Ml.size() ? (int64_t)Ml[k] : 0) + carry;
-            if (x >= (int64_t)1 << 31) {
-                x -= (int64_t)1 << 32;
-                carry = 1;
-            } else {
-                carry = 0;
-            }
-            h.crt_digits[(size_t)l * h.crt_ndpad + k] = (double)x;
-        }
-        if (carry) {
-            err = "internal error: CRT digit table too short";
-            return -1;
-        }
+        coef[l] = nat_divexact_small(P, m);
     }
-    // S/P from the top crt_nt digits of S: S_top / P_top with X_top = X / 2^(32 (nd32 - nt))
-    // (P's digits below the top nt are dropped: P_top keeps at least 64 of P's bits)
-    h.crt_nt = std::min(h.nd32, 5);
-    {
-        double ptop = 0.0;
-        for (int k = h.nd32 - 1; k >= h.nd32 - h.crt_nt; --k)
-            ptop = ptop * 4294967296.0 + (double)(k < (int)P.size() ? P[k] : 0u);
-        h.crt_inv_ptop = 1.0 / ptop;
-    }
-    // the row-broadcast CRT's table: digit d of M_l at [d][l], 16 digits per lane row group
-    h.crt_ndg = (h.nd32 + 15) / 16;
-    h.crt_lpad = (h.L + 15) / 16 * 16;
-    h.crt_row.assign((size_t)16 * h.crt_ndg * h.crt_lpad, 0.0);
-    for (int l = 0; l < h.L; ++l)
-        for (int d = 0; d < h.nd32 && d < h.crt_ndpad; ++d)
-            h.crt_row[(size_t)d * h.crt_lpad + l] = h.crt_digits[(size_t)l * h.crt_ndpad + d];
+    const int cst = crt_tables(h, P, coef, err);
+    if (cst) return cst;
     build_crt_mma_tables(h, mods, P);
-    h.p_digits.assign(h.nd32, 0);
-    h.ph_digits.assign(h.nd32, 0);
-    for (int k = 0; k < h.nd32 && k < (int)P.size(); ++k) h.p_digits[k] = P[k];
-    for (int k = 0; k < h.nd32; ++k) {
-        uint32_t lo = h.p_digits[k] >> 1;
-        uint32_t hi = (k + 1 < h.nd32) ? (h.p_digits[k + 1] & 1u) << 31 : 0;
-        h.ph_digits[k] = lo | hi;
-    }
 
     // residue weights: centred 2^(32 w) mod m, grouped by kg moduli (16 for wide sets:
     // each word read then feeds twice the FMAs)
@@ -490,6 +507,163 @@ int build_plan(int p, int t, int64_t K, const std::vector<uint32_t> &mods_in, Pl
         }
     }
     build_residue_mma_tables(h, mods);
+    return 0;
+}
+
+uint32_t f64_modulus_bound(int64_t K) {
+    // m <= sqrt(2^55 / K) (Eq. fp64bound): then K ((m - 1)/2)^2 < 2^53, so every residue
+    // product sum of a binary64 GEMM is an exact integer
+    const long double b = std::sqrt((long double)36028797018963968.0L / (long double)K);
+    uint64_t m = (uint64_t)b;
+    while ((long double)(m + 1) * (m + 1) * K <= 36028797018963968.0L) ++m;
+    while (m > 0 && (long double)m * m * K > 36028797018963968.0L) --m;
+    return (uint32_t)std::min<uint64_t>(m, kF64MaxModulus);
+}
+
+namespace {
+bool is_prime(uint32_t x) {
+    if (x < 2) return false;
+    if (x % 2 == 0) return x == 2;
+    for (uint32_t f = 3; (uint64_t)f * f <= x; f += 2)
+        if (x % f == 0) return false;
+    return true;
+}
+}  // namespace
+
+int select_moduli_f64(int p, int64_t K, int guard_bits, int t_bits, int margin, bool mixed,
+                      std::vector<uint32_t> &m8, std::vector<uint32_t> &m64, int &t,
+                      double &log2P, std::string &err) {
+    if (p < 2) {
+        err = "p must be >= 2";
+        return -1;
+    }
+    if (K < 1 || K > kMaxK) {
+        err = "K must be in [1, 133000]";
+        return K < 1 ? -1 : -2;
+    }
+    if (guard_bits < 0 || t_bits < 0 || margin < 1) {
+        err = "guard_bits and t_bits must be >= 0 and crt_margin >= 1";
+        return -1;
+    }
+    t = t_bits ? t_bits : p + guard_bits + ceil_log2(K);
+    if (t < 1) {
+        err = "internal width t must be >= 1";
+        return -1;
+    }
+    const double need = 2.0 * t + ceil_log2(K) + margin;   // Eq. crtcond
+    m8.clear();
+    m64.clear();
+    log2P = 0;
+    if (mixed) {
+        // INT8 takes the one-limb prime powers (the most bits per GEMM) up to half the bits
+        // needed, binary64 moduli the rest, so that both backends always take part
+        for (uint32_t m : global_moduli()) {
+            if (m > kOneLimbMax || log2P + std::log2((double)m) > 0.5 * need) break;
+            m8.push_back(m);
+            log2P += std::log2((double)m);
+        }
+    }
+    for (uint32_t m = f64_modulus_bound(K); m > kTwoLimbMax && !(log2P > need); --m) {
+        if (!is_prime(m)) continue;
+        if ((int)(m8.size() + 2 * (m64.size() + 1)) > kMaxModuli) break;
+        m64.push_back(m);
+        log2P += std::log2((double)m);
+    }
+    if (!(log2P > need)) {
+        err = "precision too large for the binary64 moduli set (at most 512 CRT terms)";
+        return -2;
+    }
+    return 0;
+}
+
+int build_plan_f64(int p, int t, int64_t K, const std::vector<uint32_t> &m8,
+                   const std::vector<uint32_t> &m64, PlanHost &h, PlanHost *h8, std::string &err) {
+    const int terms = (int)(m8.size() + 2 * m64.size());
+    if (m64.empty() || terms > kMaxModuli) {
+        err = "need 1 to 256 binary64 moduli (at most 512 CRT terms)";
+        return -1;
+    }
+    const uint32_t bound = f64_modulus_bound(K);
+    std::vector<uint32_t> all(m8);
+    all.insert(all.end(), m64.begin(), m64.end());
+    for (size_t a = 0; a < all.size(); ++a) {
+        const bool f = a >= m8.size();
+        if (all[a] < 2 || (f && all[a] > bound) || (!f && all[a] > kTwoLimbMax)) {
+            err = "binary64 moduli must lie in [2, sqrt(2^55 / K)] (and below 2^22)";
+            return -1;
+        }
+        for (size_t b = 0; b < a; ++b)
+            if (std::gcd(all[a], all[b]) != 1) {
+                err = "moduli must be pairwise coprime";
+                return -1;
+            }
+    }
+    if (!m8.empty()) {
+        const int st = build_plan(p, t, K, m8, *h8, err, 0, true, &m64);
+        if (st) return st;
+    }
+    h = PlanHost{};
+    h.backend = m8.empty() ? kBackendF64 : kBackendMixed;
+    h.p = p;
+    h.t = t;
+    h.K = K;
+    h.L8 = (int)m8.size();
+    h.Lf = (int)m64.size();
+    h.L = terms;
+    h.moduli = all;
+    h.f64_moduli = m64;
+    h.nw32 = (t + 1 + 31) / 32;
+    if (h.nw32 > kMaxWords) {
+        err = "internal width t too large for the residue kernel";
+        return -2;
+    }
+    Nat P{1};
+    for (uint32_t m : all) {
+        nat_mul_small(P, m);
+        h.log2P += std::log2((double)m);
+    }
+    // CRT terms: v_l M_l for an INT8 modulus; v = lo + 2^11 hi, lo, hi < 2^11, as the two
+    // terms lo M_l and hi (2^11 M_l) for a binary64 modulus (so that every term's digit
+    // products stay below 2^42, as with the INT8 moduli's int16 residues)
+    std::vector<Nat> coef;
+    for (uint32_t m : all) {
+        const Nat Ml = nat_divexact_small(P, m);
+        const uint32_t minv = inv_mod(nat_mod_small(Ml, m), m);
+        ModInfo mi{};
+        mi.m = m;
+        mi.nprod = 0;
+        mi.minv = minv;
+        mi.inv_m = 1.0 / (double)m;
+        h.info.push_back(mi);
+        coef.push_back(Ml);
+        if (m > kTwoLimbMax || std::find(m64.begin(), m64.end(), m) != m64.end()) {
+            Nat hi = Ml;
+            nat_mul_small(hi, 1u << kF64Split);
+            mi.inv_m = (double)(1u << kF64Split) * (1.0 / (double)m);
+            h.info.push_back(mi);
+            coef.push_back(hi);
+            F64Mod fm{};
+            fm.m = (double)m;
+            fm.inv_m = 1.0 / (double)m;
+            fm.minv = (double)minv;
+            h.f64.push_back(fm);
+        }
+    }
+    const int cst = crt_tables(h, P, coef, err);
+    if (cst) return cst;
+    // binary64 residues: the magnitude's 16-bit halves times centred 2^(16 j) mod m
+    h.fnh = 2 * h.nw32;
+    h.f64_rw.assign((size_t)h.Lf * h.fnh, 0.0);
+    for (int j = 0; j < h.Lf; ++j) {
+        const uint64_t m = m64[j];
+        uint64_t x = 1 % m;
+        for (int w = 0; w < h.fnh; ++w) {
+            int64_t c = (int64_t)x;
+            if (c > (int64_t)((m - 1) / 2)) c -= (int64_t)m;
+            h.f64_rw[(size_t)j * h.fnh + w] = (double)c;
+            x = (x << 16) % m;
+        }
+    }
     return 0;
 }
 

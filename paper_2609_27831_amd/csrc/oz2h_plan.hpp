@@ -62,7 +62,31 @@ struct ResRowBlock {
 };
 static_assert(sizeof(ResRowBlock) == 768, "ResRowBlock layout");
 
+// One modulus of the binary64 backend as its kernels read it (32 bytes).
+struct F64Mod {
+    double m;       // the modulus (a prime below 2^22 with K ((m - 1)/2)^2 <= 2^53)
+    double inv_m;   // fl(1/m)
+    double minv;    // (P / m)^-1 mod m, the direct-CRT weight
+    double pad;
+};
+static_assert(sizeof(F64Mod) == 32, "F64Mod layout");
+
+constexpr int kF64Split = 11;               // CRT terms of a binary64 modulus: v = lo + 2^11 hi
+constexpr uint32_t kF64MaxModulus = (1u << 22) - 1;   // so that hi < 2^11 as well
+
+// Backends of a plan: INT8 residue GEMMs (the default), binary64 residue GEMMs (the paper's
+// "(b) binary64 backend"), or both over one moduli set (its "Mixed backends").
+enum PlanBackend { kBackendInt8 = 0, kBackendF64 = 1, kBackendMixed = 2 };
+
 struct PlanHost {
+    int backend = kBackendInt8;
+    int Lf = 0;            // binary64 moduli (kBackendF64 / kBackendMixed)
+    int L8 = 0;            // ... INT8 moduli ahead of them (kBackendMixed); their CRT terms
+                           // come first, then two per binary64 modulus (low, high 11 bits)
+    std::vector<uint32_t> f64_moduli;   // Lf
+    std::vector<F64Mod> f64;            // Lf
+    int fnh = 0;                        // 16-bit halves of an integer significand (2 nw32)
+    std::vector<double> f64_rw;         // [Lf][fnh]: centred 2^(16 h) mod m
     int p = 0, t = 0;
     int tile = 0;          // oz2h_tile hint of the residue GEMMs (0 = automatic)
     uint32_t flags = 0;    // OZ2H_FLAG_* bits: matrix-core variants of stages 2 and 4
@@ -123,8 +147,28 @@ int select_moduli(int p, int64_t K, int guard_bits, int t_bits, int margin,
 int select_moduli_bits(double need, std::vector<uint32_t> &mods, double &log2P, std::string &err);
 
 // Fill every table for the given moduli (one-limb moduli must come first);
-// integer significands are up to max(t, wmax) + 1 bits wide.
+// integer significands are up to max(t, wmax) + 1 bits wide.  extra (nullable): further
+// moduli of the same CRT (a mixed plan's binary64 moduli), whose product enters the
+// direct-CRT weights (P / m_l)^-1 mod m_l.
 int build_plan(int p, int t, int64_t K, const std::vector<uint32_t> &mods, PlanHost &out,
-               std::string &err, int wmax = 0, bool allow_wide = true);
+               std::string &err, int wmax = 0, bool allow_wide = true,
+               const std::vector<uint32_t> *extra = nullptr);
+
+// Largest binary64 modulus for contraction length K (Eq. fp64bound, capped so that a
+// residue splits into two 11-bit CRT terms).
+uint32_t f64_modulus_bound(int64_t K);
+
+// Moduli of a binary64 plan (mixed = false: primes below f64_modulus_bound in decreasing
+// order) or of a mixed plan (one-limb INT8 moduli, largest first, up to half the needed
+// bits, then those primes), greedy until log2 P > 2t + ceil(log2 K) + margin.
+int select_moduli_f64(int p, int64_t K, int guard_bits, int t_bits, int margin, bool mixed,
+                      std::vector<uint32_t> &m8, std::vector<uint32_t> &m64, int &t,
+                      double &log2P, std::string &err);
+
+// The CRT plan of a binary64 or mixed moduli set: CRT terms (one per INT8 modulus, two per
+// binary64 modulus) with their digit tables, and the binary64 moduli's tables.  With INT8
+// moduli, h8 receives their plan (residue and GEMM tables, weights against the whole P).
+int build_plan_f64(int p, int t, int64_t K, const std::vector<uint32_t> &m8,
+                   const std::vector<uint32_t> &m64, PlanHost &h, PlanHost *h8, std::string &err);
 
 }  // namespace oz2h

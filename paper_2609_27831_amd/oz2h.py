@@ -29,6 +29,7 @@ class Oz2hError(RuntimeError):
 TILE_AUTO, TILE_128x128, TILE_256x128, TILE_128x256 = 0, 1, 2, 3
 # option flags: the matrix-core variants of stage 2 (residues) and stage 4 (CRT)
 FLAG_RESIDUES_MMA, FLAG_CRT_MMA = 0x1, 0x2
+FLAG_BACKEND_F64, FLAG_BACKEND_MIXED = 0x4, 0x8
 TILE_SHAPES = {TILE_128x128: (128, 128), TILE_256x128: (256, 128), TILE_128x256: (128, 256)}
 
 
@@ -53,7 +54,8 @@ class PlanInfo(ctypes.Structure):
                 ("L", ctypes.c_int32), ("L1", ctypes.c_int32), ("L2", ctypes.c_int32),
                 ("G", ctypes.c_int32), ("nw32", ctypes.c_int32), ("nd32", ctypes.c_int32),
                 ("log2P", ctypes.c_double), ("tw_a", ctypes.c_int32), ("tw_b", ctypes.c_int32),
-                ("grad_M", ctypes.c_int64), ("grad_N", ctypes.c_int64)]
+                ("grad_M", ctypes.c_int64), ("grad_N", ctypes.c_int64),
+                ("backend", ctypes.c_int32), ("Lf", ctypes.c_int32)]
 
 
 class Problem(ctypes.Structure):
@@ -74,6 +76,8 @@ SIGNATURES = {
     "oz2h_plan_destroy": (None, [_P]),
     "oz2h_plan_get_info": (ctypes.c_int, [_P, ctypes.POINTER(PlanInfo)]),
     "oz2h_plan_get_moduli": (ctypes.c_int, [_P, _P]),
+    "oz2h_plan_get_moduli32": (ctypes.c_int, [_P, _P]),
+    "oz2h_plan_moduli32": (ctypes.c_int, [_I32, _I64, ctypes.POINTER(Opts), _P, _P, _P, _P, _P, _P]),
     "oz2h_gemm_workspace_size": (_SZ, [_P, _I64, _I64]),
     "oz2h_gemm": (ctypes.c_int, [_P, _I64, _I64, _I64, ctypes.c_int, CMat, ctypes.c_int, CMat,
                                  Mat, _P, _SZ, _P]),
@@ -170,6 +174,20 @@ def plan_moduli(p: int, K: int, opts: Optional[Opts] = None):
             "moduli": mods}
 
 
+def plan_moduli32(p: int, K: int, opts: Optional[Opts] = None):
+    """Host-only moduli selection of any backend: dict(L, L8, G, t, log2P, moduli)."""
+    L, L8, G, t = (ctypes.c_int32() for _ in range(4))
+    lp = ctypes.c_double()
+    o = opts or default_opts()
+    _check(lib().oz2h_plan_moduli32(p, K, ctypes.byref(o), ctypes.addressof(L), ctypes.addressof(L8),
+                                    ctypes.addressof(G), ctypes.addressof(t), ctypes.addressof(lp), None))
+    mods = np.zeros(L.value, np.uint32)
+    _check(lib().oz2h_plan_moduli32(p, K, ctypes.byref(o), None, None, None, None, None,
+                                    mods.ctypes.data))
+    return {"L": L.value, "L8": L8.value, "G": G.value, "t": t.value, "log2P": lp.value,
+            "moduli": mods}
+
+
 class Plan:
     """Moduli set + device constant tables for one (p, K) on the current device."""
 
@@ -178,9 +196,9 @@ class Plan:
         info = PlanInfo()
         _check(lib().oz2h_plan_get_info(handle, ctypes.byref(info)))
         self.info = {f: getattr(info, f) for f, _ in PlanInfo._fields_}
-        mods = np.zeros(self.info["L"], np.uint16)
-        _check(lib().oz2h_plan_get_moduli(handle, mods.ctypes.data))
-        self.moduli = mods
+        mods = np.zeros(self.info["L"], np.uint32)
+        _check(lib().oz2h_plan_get_moduli32(handle, mods.ctypes.data))
+        self.moduli = mods if self.info["backend"] else mods.astype(np.uint16)
 
     @classmethod
     def create(cls, p: int, K: int, opts: Optional[Opts] = None) -> "Plan":

@@ -110,3 +110,80 @@ def test_plan_moduli_errors(oz):
     with pytest.raises(oz.Oz2hError) as ei:
         oz.plan_moduli(64, 16, oz.default_opts(crt_margin=0))
     assert ei.value.code == oz.EINVAL
+
+
+# ---------------------------------------------------------------- binary64 and mixed backends
+
+GOLDEN_F64 = os.path.join(ROOT, "tests", "golden", "tab_moduli_binary64.txt")
+
+
+def _is_prime(n):
+    if n < 2:
+        return False
+    f = 2
+    while f * f <= n:
+        if n % f == 0:
+            return False
+        f += 1
+    return True
+
+
+def test_plan_moduli_reproduces_the_binary64_half(oz):
+    """Table "Moduli configuration", binary64 columns: L, DGEMMs and log2 P (rounded up)
+    at K = 4096, with the moduli bounded by Eq. fp64bound."""
+    rows = [tuple(int(x) for x in l.split("#")[0].split())
+            for l in open(GOLDEN_F64) if l.split("#")[0].strip()]
+    assert len(rows) == 8
+    o = oz.default_opts(flags=oz.FLAG_BACKEND_F64)
+    for (p, t, L, G, log2p_up) in rows:
+        r = oz.plan_moduli32(p, 4096, o)
+        assert (r["t"], r["L"], r["G"], r["L8"]) == (t, L, G, 0), p
+        assert math.ceil(r["log2P"]) == log2p_up, p
+    mods = [int(m) for m in oz.plan_moduli32(2048, 4096, o)["moduli"]]
+    # Eq. fp64bound: m <= sqrt(2^55 / K) = 2965821 (text of the same subsection)
+    assert mods[0] <= 2965821 and mods == sorted(mods, reverse=True)
+    assert all(_is_prime(m) for m in mods[:12])
+    assert all(4096 * ((m - 1) // 2) ** 2 < 2 ** 53 for m in mods)
+    assert len(set(mods)) == len(mods)
+
+
+def test_binary64_bound_follows_K(oz):
+    o = oz.default_opts(flags=oz.FLAG_BACKEND_F64)
+    for K in (1, 1000, 2048, 4096, 65536, 133000):
+        m = int(oz.plan_moduli32(53, K, o)["moduli"][0])
+        assert K * ((m - 1) // 2) ** 2 < 2 ** 53
+        assert m < 2 ** 22                    # two 11-bit CRT terms per residue
+        # the largest prime under the bound (and under 2^22)
+        bound = min(math.isqrt(2 ** 55 // K), 2 ** 22 - 1)
+        while not _is_prime(bound):
+            bound -= 1
+        assert m == bound, K
+
+
+def test_mixed_moduli(oz):
+    o = oz.default_opts(flags=oz.FLAG_BACKEND_MIXED)
+    for p in (53, 256, 2048):
+        r = oz.plan_moduli32(p, 4096, o)
+        mods = [int(m) for m in r["moduli"]]
+        m8, m64 = mods[:r["L8"]], mods[r["L8"]:]
+        need = 2 * r["t"] + 12 + 2
+        assert m8 and m64 and all(m <= 255 for m in m8) and all(m > 16191 for m in m64)
+        assert sum(math.log2(m) for m in m8) <= need / 2
+        assert r["log2P"] > need and r["G"] == len(m8) + len(m64)
+        for i, a in enumerate(mods):
+            for b in mods[:i]:
+                assert math.gcd(a, b) == 1
+    with pytest.raises(oz.Oz2hError):
+        oz.plan_moduli32(53, 4096, oz.default_opts(flags=oz.FLAG_BACKEND_F64 | oz.FLAG_BACKEND_MIXED))
+    with pytest.raises(oz.Oz2hError) as ei:
+        oz.plan_moduli(53, 4096, oz.default_opts(flags=oz.FLAG_BACKEND_F64))
+    assert ei.value.code == oz.EUNSUPPORTED
+
+
+def test_backend_flags_rejected_where_unsupported(oz):
+    """Backward and batched plans are built on the INT8 residue planes: the backend flags
+    are refused before any device work (host-side check)."""
+    for flags in (oz.FLAG_BACKEND_F64, oz.FLAG_BACKEND_MIXED):
+        with pytest.raises(oz.Oz2hError) as ei:
+            oz.Plan.create_grad(64, 8, 8, 8, oz.default_opts(flags=flags))
+        assert ei.value.code == oz.EUNSUPPORTED
