@@ -15,10 +15,12 @@ p = 2048 bits (exponents uniform in [-16, 16]), and carries as extra keys:
     recomputation ("reuse_vs_recompute");
   - complex products at M = N = K = 4096, p = 256: the 3M scheme against 4M
     ("complex");
+  - the binary64 and mixed backends against INT8 at M = N = K = 4096, p = 113
+    ("backends");
   - the oracle on the host cores over a bounded block of outputs, which also
     checks the timed GPU output on that block bit for bit.
 
-  python bench.py [--steps K] [--warmup W] [--config cfg3|cfg1|cfg2|cfg3a|cfg3b|cfg4|cfg5|complex]
+  python bench.py [--steps K] [--warmup W] [--config cfg3|cfg1|cfg2|cfg3a|cfg3b|cfg4|cfg5|complex|backends]
                   [--cpu-seconds S] [--no-cpu-baseline] [--no-extras]
 
 Per-stage times come from HIP events that the library records on the launch
@@ -521,6 +523,58 @@ def measure_complex(steps, warmup):
             "unit": "GFlop/s (8MNK/s)", "bit_identical_3m_4m": same}
 
 
+def measure_backends(steps, warmup):
+    """The INT8, binary64 and mixed backends on one product, M = N = K = 4096 at p = 113
+    (Table "Moduli configuration": 42 INT8 GEMMs against 14 binary64 GEMMs): time per
+    product, per-stage times, the fp64 matrix-core rate of the binary64 residue GEMMs,
+    and a bit-for-bit check that the three outputs agree."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2609_27831_amd import oz2h
+    M = N = K = 4096
+    p = 113
+    Ad, Bd = device_operands(("", M, N, K, p, -16, 16, 0), synth.CONFIG_SEED_BASE + 71)
+    hip = Hip()
+    stream = torch.cuda.current_stream()
+    out, res = {}, {}
+    for name, flags in (("int8", 0), ("binary64", oz2h.FLAG_BACKEND_F64),
+                        ("mixed", oz2h.FLAG_BACKEND_MIXED)):
+        plan = oz2h.Plan.create(p, K, oz2h.default_opts(flags=flags))
+        ws = oz2h.workspace(plan, M, N)
+        C = oz2h.empty_mp(M, N, p)
+        evs = [hip.events(5) for _ in range(steps)]
+        for _ in range(warmup):
+            oz2h.gemm(plan, Ad, Bd, out=C, ws=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(steps):
+            oz2h.gemm_timed(plan, Ad, Bd, C, ws, evs[s], stream=stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        ph = {n: round(float(np.mean([hip.elapsed_ms(e[k], e[k + 1]) for e in evs])), 4)
+              for k, n in enumerate(PHASES)}
+        for e in evs:
+            hip.destroy(e)
+        r = {"ms_per_step": round(ms, 4), "moduli": plan.L, "gemms": plan.G,
+             "binary64_moduli": plan.Lf, "log2P": round(plan.log2P, 1), "phases_ms": ph}
+        if flags == oz2h.FLAG_BACKEND_F64:
+            kpad = (K + 127) // 128 * 128
+            tf = 2.0 * plan.Lf * M * N * kpad / (ph["gemm"] * 1e-3) / 1e12
+            r["fp64_mfma_tflops"] = round(tf, 2)
+            r["fp64_pct_of_peak"] = round(100.0 * tf / PEAK_FP64_TFLOPS, 1)
+        out[name] = r
+        res[name] = C
+        del ws
+        plan.destroy()
+        torch.cuda.empty_cache()
+    same = all(bool(torch.equal(getattr(res[n], f), getattr(res["int8"], f)))
+               for n in ("binary64", "mixed") for f in ("sign", "exp", "limbs"))
+    return {"workload": "plain Ozaki-II on three backends, M=N=K=4096, p=113, exponents U[-16,16]",
+            **out, "bit_identical": same}
+
+
 def copy_calibration():
     """A plain device copy of known size, for the HBM-counter scale factors."""
     import torch
@@ -543,7 +597,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="cfg3",
-                    choices=sorted(CONFIGS) + ["cfg3", "cfg4", "cfg5", "complex"])
+                    choices=sorted(CONFIGS) + ["cfg3", "cfg4", "cfg5", "complex", "backends"])
     ap.add_argument("--flags", type=int, default=0,
                     help="OZ2H_FLAG_* bits of the timed plain products (default 0: MFMA-free "
                          "stages 2 and 4)")
@@ -570,13 +624,18 @@ def main():
             "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "i8", "data": "synthetic"}
 
-    if args.config in ("cfg4", "cfg5", "complex"):
+    if args.config in ("cfg4", "cfg5", "complex", "backends"):
         log(f"{args.config}")
-        fn = {"cfg4": measure_batched, "cfg5": measure_autograd, "complex": measure_complex}[args.config]
+        fn = {"cfg4": measure_batched, "cfg5": measure_autograd, "complex": measure_complex,
+              "backends": measure_backends}[args.config]
         r = fn(args.steps, args.warmup)
         if args.config == "complex":
             r["value"] = r["value_3m"]
+        if args.config == "backends":
+            r["value"] = round(2.0 * 4096 ** 3 / (r["binary64"]["ms_per_step"] * 1e-3) / 1e9, 3)
         ms = r.get("graph_ms", r.get("reuse_ms_per_step", r.get("ms_3m")))
+        if args.config == "backends":
+            ms = r["binary64"]["ms_per_step"]
         line = dict(base, value=r.pop("value"), ms_per_step=ms,
                     config={"workload": r.pop("workload")}, **r)
         print(json.dumps(line), flush=True)
@@ -631,6 +690,9 @@ def main():
         torch.cuda.empty_cache()
         log("complex products: 3M vs 4M")
         line["complex"] = measure_complex(max(2, args.steps // 2), 1)
+        torch.cuda.empty_cache()
+        log("backends: INT8, binary64, mixed")
+        line["backends"] = measure_backends(max(2, args.steps // 2), 1)
     print(json.dumps(line), flush=True)
 
 
