@@ -509,23 +509,26 @@ typedef struct oz2h_batched_plan oz2h_batched_plan;
  * products at once, one grouped launch per stage (shared exponents, residues,
  * and the CRT/rounding, the latter one launch per digit-chunk class) and the
  * residue GEMMs of all products and moduli as ONE persistent grouped launch
- * over a cost-sorted list of (product, modulus, output tile) work items.
- * o->tile fixes the block tile; OZ2H_TILE_AUTO takes a previously tuned
- * configuration for the same shapes if the process has one (see
- * oz2h_batched_tune), else 128 x 128 with 2 blocks per compute unit.
+ * over a cost-sorted list of (product, modulus, output tile) work items (one
+ * launch per block tile in use), ordered so that each XCD works on one rectangle
+ * of every large (product, modulus) tile grid.  o->tile fixes the block tile of
+ * every product; OZ2H_TILE_AUTO takes a previously tuned configuration for the
+ * same shapes if the process has one (see oz2h_batched_tune), else the tile a
+ * plain call would choose for each product, one block per work item.
  */
 int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2h_opts *o,
                              oz2h_batched_plan **out);
 /* Device workspace bytes a run needs (256-byte aligned, contents scratch). */
 size_t oz2h_batched_workspace_size(const oz2h_batched_plan *plan);
 /*
- * Autotuner: runs stages 1-2 once, then times the grouped GEMM for every
- * block tile (128x128, 256x128, 128x256) and every persistent schedule (1, 2
+ * Autotuner: times whole runs for every block tile setting of the grouped GEMM
+ * (per product as plain calls choose, or 128x128, 256x128, 128x256 for all)
+ * and every persistent schedule (1, 2
  * or 4 resident blocks per compute unit, or one block per work item), keeps the fastest and records it in
  * an in-process cache keyed by the batch's shapes (and, if the environment
  * variable OZ2H_TUNE_CACHE names a file, appends it there; plans created later
- * with OZ2H_TILE_AUTO pick it up).  Synchronizes `stream`; the outputs C are
- * not written.
+ * with OZ2H_TILE_AUTO pick it up).  Synchronizes `stream`; the runs write the
+ * outputs C (with the product's results).
  */
 int oz2h_batched_tune(oz2h_batched_plan *plan, void *workspace, size_t ws_bytes,
                       hipStream_t stream);
@@ -540,11 +543,12 @@ int oz2h_batched_run(oz2h_batched_plan *plan, void *workspace, size_t ws_bytes,
 /* The same launches issued directly on `stream` (no graph). */
 int oz2h_batched_run_eager(oz2h_batched_plan *plan, void *workspace, size_t ws_bytes,
                            hipStream_t stream);
-/* Current block tile (oz2h_tile), resident blocks per compute unit (0: one block per
-   work item instead of a persistent grid), GEMM work items. */
+/* Current block tile setting (oz2h_tile; OZ2H_TILE_AUTO: per product), resident blocks
+   per compute unit (0: one block per work item instead of a persistent grid), GEMM work
+   items (placeholders that keep the XCD alignment included). */
 int oz2h_batched_get_config(const oz2h_batched_plan *plan, int32_t *tile, int32_t *blocks_per_cu,
                             int64_t *gemm_items);
-/* Sets the tile (1..3) and blocks per compute unit (0..16) by hand. */
+/* Sets the tile setting (0..3) and blocks per compute unit (0..16) by hand. */
 int oz2h_batched_set_config(oz2h_batched_plan *plan, int32_t tile, int32_t blocks_per_cu);
 void oz2h_batched_plan_destroy(oz2h_batched_plan *plan);
 

@@ -1696,6 +1696,36 @@ int oz2h_crt(const oz2h_plan *plan, int64_t M, int64_t N, const int16_t *u, int6
 
 // ====================================================================== batched form
 
+// one CRT launch class of the batched form: the products of a chunk with one digit-chunk
+// width, entries per thread and digit-column placement (or the matrix-core CRT)
+struct BatchCrtClass {
+    int dc, ept, bd, LB;
+    bool gdig, mma;
+    size_t lds;
+    Seg *d_segs;
+    int nseg;
+    int64_t blocks;
+};
+
+// The launches of one chunk of a batch (a subset of its products).  A batch of two or more
+// products runs as two chunks on two streams: the second chunk's residues beside the first
+// chunk's GEMMs, its GEMMs beside the first chunk's CRT, so that the matrix cores and the
+// vector ALUs of a compute unit work at the same time.
+struct BatchChunk {
+    std::vector<int> prods;
+    Seg *d_fill_segs = nullptr, *d_exp_segs = nullptr;
+    int n_fill_segs = 0, n_exp_segs = 0;
+    int64_t fill_blocks = 0, exp_blocks = 0;
+    // residues: one launch per moduli group width (classes kModGroup, kModGroupWide)
+    Seg *d_res_segs[2] = {nullptr, nullptr};
+    int n_res_segs[2] = {0, 0};
+    int64_t res_blocks[2] = {0, 0};
+    std::vector<BatchCrtClass> crt;
+    // grouped GEMM: one item list (and launch) per block tile class c = oz2h_tile - 1
+    GemmItem *d_items[3] = {nullptr, nullptr, nullptr};
+    int nitems[3] = {0, 0, 0};
+};
+
 struct oz2h_batched_plan {
     int count = 0;
     int device = -1;
@@ -1706,26 +1736,17 @@ struct oz2h_batched_plan {
     // device buffers: tables + descriptors + segment tables, one allocation
     void *dbuf = nullptr;
     ProbDev *d_probs = nullptr;
-    Seg *d_exp_segs = nullptr, *d_res_segs = nullptr;
-    int n_exp_segs = 0, n_res_segs = 0;
-    int64_t exp_blocks = 0, res_blocks = 0;
+    std::vector<BatchChunk> chunks;
     int res_rb = 4;
     size_t res_lds = 0;
-    struct CrtClass {
-        int dc, ept, bd, LB;
-        bool gdig, mma;
-        size_t lds;
-        Seg *d_segs;
-        int nseg;
-        int64_t blocks;
-    };
-    std::vector<CrtClass> crt;
-    // grouped GEMM: work items for the current tile
+    // grouped GEMM: tile setting (OZ2H_TILE_AUTO: each product in the class a plain call
+    // would choose for it) and resident blocks per compute unit (0: one block per item)
     int tile = OZ2H_TILE_128x128;
     int bpc = 2;
-    GemmItem *d_items = nullptr;
-    int nitems = 0;
     size_t ws_bytes = 0;
+    // the second chunk's stream and the events that order the two chunks
+    hipStream_t side = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     // graph
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
@@ -1772,39 +1793,93 @@ void tune_store(uint64_t sig, int tile, int bpc) {
 
 // work items of the grouped GEMM for a tile shape, heaviest first (two-limb moduli and
 // long contractions), then product, modulus and tile order for L2 locality
-std::vector<GemmItem> make_items(const oz2h_batched_plan *bp, GemmCfg cfg) {
-    struct Key {
+// Items of the persistent grouped GEMM.  Blocks take items i, i + grid, ... with a grid that is
+// a multiple of 8, and blocks are dealt to the 8 XCDs round-robin, so item i runs on XCD i % 8.
+// The tiles of a (product, modulus) group of at least 8 tiles are split into 8 rectangles
+// (the split with the smallest A + B footprint, as in the plain launch) and interleaved: the
+// group starts at a multiple of 8 and its item 8 u + x is the u-th tile of rectangle x (padded
+// with skipped items), so each XCD's L2 holds only its rectangle's rows of A and columns of B.
+// Groups go in decreasing cost (longer k-loops first); groups of fewer than 8 tiles, which
+// have no such locality to gain, follow at the end in the same order.
+// tile class (oz2h_tile - 1) of product b under the plan's tile setting
+int item_class(const oz2h_batched_plan *bp, int b) {
+    if (bp->tile != OZ2H_TILE_AUTO) return bp->tile - 1;
+    const GemmCfg c = choose_gemm(bp->probs[b].M, bp->probs[b].N, OZ2H_TILE_AUTO);
+    return c.bm == 256 ? OZ2H_TILE_256x128 - 1 : (c.bn == 256 ? OZ2H_TILE_128x256 - 1 : OZ2H_TILE_128x128 - 1);
+}
+
+std::vector<GemmItem> make_items(const oz2h_batched_plan *bp, const BatchChunk &ch, GemmCfg cfg, int cls) {
+    struct Group {
         int64_t cost;
-        GemmItem it;
+        int b, l;
+        int64_t tm, tn;
     };
-    std::vector<Key> keys;
-    for (int b = 0; b < bp->count; ++b) {
+    std::vector<Group> groups;
+    for (int b : ch.prods) {
+        if (item_class(bp, b) != cls) continue;
         const PlanHost &h = bp->hosts[b];
         const int64_t tm = (bp->probs[b].M + cfg.bm - 1) / cfg.bm;
         const int64_t tn = (bp->probs[b].N + cfg.bn - 1) / cfg.bn;
-        for (int l = 0; l < h.L; ++l) {
-            const int64_t cost = (int64_t)h.info[l].nprod * bp->pd[b].kpad;
-            for (int64_t mt = 0; mt < tm; ++mt)
-                for (int64_t nt = 0; nt < tn; ++nt)
-                    keys.push_back({cost, GemmItem{(uint16_t)b, (uint16_t)l, (uint16_t)mt, (uint16_t)nt}});
-        }
+        for (int l = 0; l < h.L; ++l)
+            groups.push_back(Group{(int64_t)h.info[l].nprod * bp->pd[b].kpad, b, l, tm, tn});
     }
-    std::stable_sort(keys.begin(), keys.end(), [](const Key &a, const Key &b) { return a.cost > b.cost; });
-    std::vector<GemmItem> out;
-    out.reserve(keys.size());
-    for (auto &k : keys) out.push_back(k.it);
+    std::stable_sort(groups.begin(), groups.end(), [](const Group &a, const Group &b) { return a.cost > b.cost; });
+    std::vector<GemmItem> out, small;
+    for (const Group &g : groups) {
+        auto item = [&](int64_t mt, int64_t nt) {
+            return GemmItem{(uint16_t)g.b, (uint16_t)g.l, (uint16_t)mt, (uint16_t)nt};
+        };
+        if (g.tm * g.tn < 8) {
+            for (int64_t mt = 0; mt < g.tm; ++mt)
+                for (int64_t nt = 0; nt < g.tn; ++nt) small.push_back(item(mt, nt));
+            continue;
+        }
+        int ry = 1, rx = 8;
+        int64_t best = INT64_MAX;
+        for (int y = 1; y <= 8; y *= 2) {
+            const int x = 8 / y;
+            if (y > g.tm || x > g.tn) continue;
+            const int64_t foot = (g.tm + y - 1) / y * cfg.bm + (g.tn + x - 1) / x * cfg.bn;
+            if (foot < best) {
+                best = foot;
+                ry = y;
+                rx = x;
+            }
+        }
+        if (best == INT64_MAX) {   // a thin group (fewer than 8 tile rows and columns both ways)
+            ry = (int)std::min<int64_t>(g.tm, 8);
+            rx = (int)std::max<int64_t>(1, std::min<int64_t>(g.tn, 8 / ry));
+        }
+        std::vector<std::vector<GemmItem>> rect(8);
+        for (int64_t mt = 0; mt < g.tm; ++mt)
+            for (int64_t nt = 0; nt < g.tn; ++nt) {
+                const int x = (int)(mt * ry / g.tm) * rx + (int)(nt * rx / g.tn);
+                rect[x].push_back(item(mt, nt));
+            }
+        size_t u_max = 0;
+        for (auto &r : rect) u_max = std::max(u_max, r.size());
+        for (size_t u = 0; u < u_max; ++u)
+            for (int x = 0; x < 8; ++x)
+                out.push_back(u < rect[x].size() ? rect[x][u] : GemmItem{kSkipItem, 0, 0, 0});
+    }
+    out.insert(out.end(), small.begin(), small.end());
     return out;
 }
 
 int upload_items(oz2h_batched_plan *bp) {
-    std::vector<GemmItem> items = make_items(bp, tile_cfg(bp->tile));
-    if (bp->d_items) (void)hipFree(bp->d_items);
-    bp->d_items = nullptr;
-    bp->nitems = (int)items.size();
-    if (items.empty()) return OZ2H_OK;
-    if (hipMalloc(&bp->d_items, items.size() * sizeof(GemmItem)) != hipSuccess)
-        return fail(OZ2H_ENOMEM, "batched plan: item list allocation failed");
-    OZ2H_HIP(hipMemcpy(bp->d_items, items.data(), items.size() * sizeof(GemmItem), hipMemcpyHostToDevice));
+    for (BatchChunk &ch : bp->chunks)
+        for (int c = 0; c < 3; ++c) {
+            std::vector<GemmItem> items = make_items(bp, ch, tile_cfg(c + 1), c);
+            if (ch.d_items[c]) (void)hipFree(ch.d_items[c]);
+            ch.d_items[c] = nullptr;
+            if (items.size() > INT32_MAX) return fail(OZ2H_ERANGE, "batched plan: too many GEMM work items");
+            ch.nitems[c] = (int)items.size();
+            if (items.empty()) continue;
+            if (hipMalloc(&ch.d_items[c], items.size() * sizeof(GemmItem)) != hipSuccess)
+                return fail(OZ2H_ENOMEM, "batched plan: item list allocation failed");
+            OZ2H_HIP(hipMemcpy(ch.d_items[c], items.data(), items.size() * sizeof(GemmItem),
+                               hipMemcpyHostToDevice));
+        }
     return OZ2H_OK;
 }
 
@@ -1816,45 +1891,55 @@ void drop_graph(oz2h_batched_plan *bp) {
     bp->cap_ws = nullptr;
 }
 
-int launch_batched_gemm(oz2h_batched_plan *bp, char *ws, hipStream_t s) {
-    if (!bp->nitems) return OZ2H_OK;
-    // bpc > 0: a persistent grid of bpc blocks per compute unit; bpc = 0: one block per item
-    const int grid = bp->bpc > 0 ? (int)std::min<int64_t>(bp->nitems, (int64_t)bp->ncu * bp->bpc)
-                                 : bp->nitems;
-    switch (bp->tile) {
-        case OZ2H_TILE_256x128:
-            k_resgemm_grouped<128, 64><<<grid, 256, 0, s>>>(bp->d_probs, bp->d_items, bp->nitems, ws);
-            break;
-        case OZ2H_TILE_128x256:
-            k_resgemm_grouped<64, 128><<<grid, 256, 0, s>>>(bp->d_probs, bp->d_items, bp->nitems, ws);
-            break;
-        default:
-            k_resgemm_grouped<64, 64><<<grid, 256, 0, s>>>(bp->d_probs, bp->d_items, bp->nitems, ws);
-            break;
+int launch_batched_gemm(oz2h_batched_plan *bp, const BatchChunk &ch, char *ws, hipStream_t s) {
+    for (int c = 0; c < 3; ++c) {
+        const int n = ch.nitems[c];
+        if (!n) continue;
+        // bpc > 0: a persistent grid of bpc blocks per compute unit; bpc = 0: one block per item
+        const int grid = bp->bpc > 0 ? (int)std::min<int64_t>(n, (int64_t)bp->ncu * bp->bpc) : n;
+        const GemmItem *it = ch.d_items[c];
+        if (c == OZ2H_TILE_256x128 - 1) k_resgemm_grouped<128, 64><<<grid, 256, 0, s>>>(bp->d_probs, it, n, ws);
+        else if (c == OZ2H_TILE_128x256 - 1) k_resgemm_grouped<64, 128><<<grid, 256, 0, s>>>(bp->d_probs, it, n, ws);
+        else k_resgemm_grouped<64, 64><<<grid, 256, 0, s>>>(bp->d_probs, it, n, ws);
+        int st = check_launch("grouped residue GEMM");
+        if (st) return st;
     }
-    return check_launch("grouped residue GEMM");
+    return OZ2H_OK;
 }
 
 // stages 1-2 (exponents, residues) for every product
-int launch_batched_front(oz2h_batched_plan *bp, char *ws, hipStream_t s) {
-    if (bp->exp_blocks)
-        k_exp_grouped<<<(unsigned)bp->exp_blocks, 256, 0, s>>>(bp->d_probs, bp->d_exp_segs, bp->n_exp_segs, ws);
+int launch_batched_front(oz2h_batched_plan *bp, const BatchChunk &ch, char *ws, hipStream_t s) {
+    if (ch.fill_blocks) {
+        const unsigned nf = (unsigned)ch.fill_blocks;
+        k_exp_fill_grouped<<<nf, 256, 0, s>>>(bp->d_probs, ch.d_fill_segs, ch.n_fill_segs, ws, 0);
+        if (ch.exp_blocks)
+            k_exp_scan_grouped<<<(unsigned)ch.exp_blocks, 256, 0, s>>>(bp->d_probs, ch.d_exp_segs,
+                                                                         ch.n_exp_segs, ws);
+        k_exp_fill_grouped<<<nf, 256, 0, s>>>(bp->d_probs, ch.d_fill_segs, ch.n_fill_segs, ws, 1);
+    }
     int st = check_launch("grouped exponents");
     if (st) return st;
-    if (bp->res_blocks) {
-        const unsigned nb = (unsigned)bp->res_blocks;
-        if (bp->res_rb == 4)
-            k_residues_grouped<4><<<nb, 256, bp->res_lds, s>>>(bp->d_probs, bp->d_res_segs, bp->n_res_segs, ws);
-        else if (bp->res_rb == 2)
-            k_residues_grouped<2><<<nb, 128, bp->res_lds, s>>>(bp->d_probs, bp->d_res_segs, bp->n_res_segs, ws);
-        else
-            k_residues_grouped<1><<<nb, 64, bp->res_lds, s>>>(bp->d_probs, bp->d_res_segs, bp->n_res_segs, ws);
+    for (int c = 0; c < 2; ++c) {
+        if (!ch.res_blocks[c]) continue;
+        const unsigned nb = (unsigned)ch.res_blocks[c];
+        const Seg *sg = ch.d_res_segs[c];
+        const int ns = ch.n_res_segs[c];
+#define OZ2H_GRES(KG)                                                                             \
+    do {                                                                                          \
+        if (bp->res_rb == 4) k_residues_grouped<4, KG><<<nb, 256, bp->res_lds, s>>>(bp->d_probs, sg, ns, ws); \
+        else if (bp->res_rb == 2) k_residues_grouped<2, KG><<<nb, 128, bp->res_lds, s>>>(bp->d_probs, sg, ns, ws); \
+        else k_residues_grouped<1, KG><<<nb, 64, bp->res_lds, s>>>(bp->d_probs, sg, ns, ws);      \
+    } while (0)
+        if (c == 0) OZ2H_GRES(kModGroup);
+        else OZ2H_GRES(kModGroupWide);
+#undef OZ2H_GRES
+        if ((st = check_launch("grouped residues"))) return st;
     }
-    return check_launch("grouped residues");
+    return OZ2H_OK;
 }
 
-int launch_batched_crt(oz2h_batched_plan *bp, char *ws, hipStream_t s) {
-    for (auto &c : bp->crt) {
+int launch_batched_crt(oz2h_batched_plan *bp, const BatchChunk &ch, char *ws, hipStream_t s) {
+    for (auto &c : ch.crt) {
         if (!c.blocks) continue;
         const unsigned nb = (unsigned)c.blocks;
 #define OZ2H_GCRT(DC, E, G) \
@@ -1891,11 +1976,36 @@ int launch_batched_crt(oz2h_batched_plan *bp, char *ws, hipStream_t s) {
     return OZ2H_OK;
 }
 
+// One chunk: its three stages in order.  Two chunks: chunk 0 on s, chunk 1 on the side
+// stream, each stage of chunk 1 after the same stage of chunk 0 (so that the stages of the
+// two chunks that run together are residues beside GEMMs and GEMMs beside the CRT), and s
+// waits for chunk 1 at the end.  Under graph capture the side stream joins the capture
+// through the first event and leaves it through the last.
 int launch_batched_all(oz2h_batched_plan *bp, char *ws, hipStream_t s) {
-    int st = launch_batched_front(bp, ws, s);
-    if (!st) st = launch_batched_gemm(bp, ws, s);
-    if (!st) st = launch_batched_crt(bp, ws, s);
-    return st;
+    int st;
+    if (bp->chunks.size() == 1) {
+        const BatchChunk &c0 = bp->chunks[0];
+        if ((st = launch_batched_front(bp, c0, ws, s)) || (st = launch_batched_gemm(bp, c0, ws, s)))
+            return st;
+        return launch_batched_crt(bp, c0, ws, s);
+    }
+    const BatchChunk &c0 = bp->chunks[0], &c1 = bp->chunks[1];
+    hipStream_t s1 = bp->side;
+    if ((st = launch_batched_front(bp, c0, ws, s))) return st;
+    OZ2H_HIP(hipEventRecord(bp->ev[0], s));
+    OZ2H_HIP(hipStreamWaitEvent(s1, bp->ev[0], 0));
+    if ((st = launch_batched_front(bp, c1, ws, s1))) return st;
+    if ((st = launch_batched_gemm(bp, c0, ws, s))) return st;
+    OZ2H_HIP(hipEventRecord(bp->ev[1], s));
+    OZ2H_HIP(hipStreamWaitEvent(s1, bp->ev[1], 0));
+    if ((st = launch_batched_gemm(bp, c1, ws, s1))) return st;
+    if ((st = launch_batched_crt(bp, c0, ws, s))) return st;
+    OZ2H_HIP(hipEventRecord(bp->ev[2], s));
+    OZ2H_HIP(hipStreamWaitEvent(s1, bp->ev[2], 0));
+    if ((st = launch_batched_crt(bp, c1, ws, s1))) return st;
+    OZ2H_HIP(hipEventRecord(bp->ev[3], s1));
+    OZ2H_HIP(hipStreamWaitEvent(s, bp->ev[3], 0));
+    return OZ2H_OK;
 }
 
 int check_batched_run(oz2h_batched_plan *bp, void *ws, size_t ws_bytes) {
@@ -1927,7 +2037,9 @@ int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2
     int dev = -1;
     int st = check_device(&dev);
     if (st) return st;
-    auto bp = std::make_unique<oz2h_batched_plan>();
+    // owned until returned: every error path frees what was allocated so far
+    std::unique_ptr<oz2h_batched_plan, void (*)(oz2h_batched_plan *)> bp(new oz2h_batched_plan(),
+                                                                          oz2h_batched_plan_destroy);
     bp->count = count;
     bp->device = dev;
     hipDeviceProp_t prop;
@@ -1955,7 +2067,7 @@ int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2
         std::string err;
         st = select_moduli(q.p, q.K, o->guard_bits, o->t_bits, o->crt_margin, mods, t, lp, err);
         if (st) return fail(st, "problem %d: %s", b, err.c_str());
-        st = build_plan(q.p, t, q.K, mods, bp->hosts[b], err, 0, false);
+        st = build_plan(q.p, t, q.K, mods, bp->hosts[b], err);
         if (st) return fail(st, "problem %d: %s", b, err.c_str());
         bp->hosts[b].flags = o->flags;
     }
@@ -2035,88 +2147,137 @@ int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2
         w = align_up(w + sizeof(int16_t) * (size_t)h.L * P.rpad[0] * P.rpad[1]);
     }
 
-    // segment tables
-    std::vector<Seg> exp_segs, res_segs;
+    // chunks: one for a single product, else two of about equal work (products in
+    // decreasing order of their INT8 operations plus CRT digit products, each to the lighter)
+    const int nchunks = count >= 2 ? 2 : 1;
+    bp->chunks.resize(nchunks);
+    {
+        std::vector<std::pair<double, int>> work;
+        for (int b = 0; b < count; ++b) {
+            const PlanHost &h = bp->hosts[b];
+            const double mn = (double)probs[b].M * probs[b].N;
+            work.push_back({mn * (2.0 * h.G * probs[b].K + 8.0 * h.L * h.nd32), b});
+        }
+        std::sort(work.begin(), work.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+        double load[2] = {0.0, 0.0};
+        for (auto &wb : work) {
+            const int c = nchunks == 1 ? 0 : (load[0] <= load[1] ? 0 : 1);
+            load[c] += wb.first;
+            bp->chunks[c].prods.push_back(wb.second);
+        }
+        for (BatchChunk &ch : bp->chunks) std::sort(ch.prods.begin(), ch.prods.end());
+    }
+
+    // segment tables per chunk: exponent fill/fix (256 rows per block), exponent scan (row
+    // blocks x contraction chunks, as the plain scan), residues per moduli group width
     int maxw = 1;
     for (int b = 0; b < count; ++b) maxw = std::max(maxw, bp->pd[b].nw32);
     bp->res_rb = maxw <= 64 ? 4 : (maxw <= 128 ? 2 : 1);
     bp->res_lds = (size_t)maxw * 64 * bp->res_rb * sizeof(uint32_t);
-    for (int b = 0; b < count; ++b)
-        for (int sd = 0; sd < 2; ++sd) {
-            const ProbDev &P = bp->pd[b];
-            const int64_t nbe = P.cs[sd] == 1 ? (P.rows[sd] + 3) / 4 : (P.rows[sd] + 255) / 256;
-            exp_segs.push_back(Seg{bp->exp_blocks, b, sd, nbe});
-            bp->exp_blocks += nbe;
-            const int kw = res_waves_k(bp->res_rb);
-            const int64_t nbx = P.kpad / (64 * kw), nby = P.rpad[sd] / (bp->res_rb / kw);
-            res_segs.push_back(Seg{bp->res_blocks, b, sd, nbx});
-            bp->res_blocks += nbx * nby;
+    struct ChunkSegs {
+        std::vector<Seg> fill, exp, res[2];
+        std::vector<std::vector<Seg>> crt;
+    };
+    std::vector<ChunkSegs> csegs(nchunks);
+    for (int ci = 0; ci < nchunks; ++ci) {
+        BatchChunk &ch = bp->chunks[ci];
+        ChunkSegs &cs = csegs[ci];
+        for (int b : ch.prods)
+            for (int sd = 0; sd < 2; ++sd) {
+                const ProbDev &P = bp->pd[b];
+                const int64_t nbf = (P.rows[sd] + 255) / 256;
+                cs.fill.push_back(Seg{ch.fill_blocks, b, sd, nbf});
+                ch.fill_blocks += nbf;
+                const bool contig = P.cs[sd] == 1;
+                const int64_t nbr = contig ? (P.rows[sd] + 3) / 4 : nbf;
+                const int64_t nbk = contig ? (P.K + kExpChunk - 1) / kExpChunk : (P.K + kExpRowsK - 1) / kExpRowsK;
+                cs.exp.push_back(Seg{ch.exp_blocks, b, sd, nbr});
+                ch.exp_blocks += nbr * nbk;
+                const int c = bp->hosts[b].kg == kModGroupWide ? 1 : 0;
+                const int kw = res_waves_k(bp->res_rb);
+                const int64_t nbx = P.kpad / (64 * kw), nby = P.rpad[sd] / (bp->res_rb / kw);
+                cs.res[c].push_back(Seg{ch.res_blocks[c], b, sd, nbx});
+                ch.res_blocks[c] += nbx * nby;
+            }
+        if (ch.exp_blocks > INT32_MAX || ch.res_blocks[0] > INT32_MAX || ch.res_blocks[1] > INT32_MAX)
+            return fail(OZ2H_ERANGE, "batched plan: too many blocks for one launch");
+        // CRT classes: (digit chunk, entries per thread, digit columns in LDS or global
+        // memory), the same shapes a plain call would take (crt_config); digit chunk -1: the
+        // matrix-core CRT, under the rule a plain call applies
+        std::map<std::tuple<int, int, int>, std::vector<int>> classes;
+        for (int b : ch.prods) {
+            const PlanHost &h = bp->hosts[b];
+            const CrtCfg cc = crt_config(h, probs[b].M, probs[b].N, true);
+            if (crt_mma_eligible(h, cc)) classes[std::make_tuple(-1, 1, 0)].push_back(b);
+            else classes[std::make_tuple(h.crt_dc, cc.ept, (int)cc.gdig)].push_back(b);
         }
-    // CRT classes: (digit chunk, entries per thread, digit columns in LDS or global
-    // memory), the same shapes a plain call would take (crt_config)
-    // (digit chunk -1: the matrix-core CRT, under the rule a plain call applies)
-    std::map<std::tuple<int, int, int>, std::vector<int>> classes;
-    for (int b = 0; b < count; ++b) {
-        const PlanHost &h = bp->hosts[b];
-        const CrtCfg cc = crt_config(h, probs[b].M, probs[b].N, true);
-        if (crt_mma_eligible(h, cc)) classes[std::make_tuple(-1, 1, 0)].push_back(b);
-        else classes[std::make_tuple(h.crt_dc, cc.ept, (int)cc.gdig)].push_back(b);
-    }
-    std::vector<std::vector<Seg>> crt_segs;
-    for (auto &kv : classes) {
-        oz2h_batched_plan::CrtClass c{};
-        c.dc = std::get<0>(kv.first);
-        c.ept = std::get<1>(kv.first);
-        c.gdig = std::get<2>(kv.first) != 0;
-        int maxnd = 1, maxL = 1;
-        for (int b : kv.second) {
-            maxnd = std::max(maxnd, bp->hosts[b].nd32);
-            maxL = std::max(maxL, bp->hosts[b].L);
-        }
-        c.mma = c.dc < 0;
-        c.bd = 256;
-        size_t cols = 0;
-        if (c.mma) {
-            cols = (size_t)256 * maxnd * 4;   // 256 entries per block, one column each
-        } else if (!c.gdig) {
-            while (c.bd > 64 && (size_t)maxnd * c.bd * c.ept * 4 > 49152) c.bd /= 2;
-            cols = (((size_t)maxnd * c.bd * c.ept + 3) & ~(size_t)3) * 4;
-        }
-        c.LB = c.gdig ? std::max(1, std::min(maxL, (int)(32768 / (sizeof(double) * (c.dc + 1))))) : maxL;
-        c.lds = c.gdig ? (size_t)c.LB * (c.dc + 1) * sizeof(double) : cols;
-        std::vector<Seg> segs;
-        for (int b : kv.second) {
-            const int64_t per = (int64_t)c.bd * c.ept;
-            const int64_t nb = (probs[b].M * probs[b].N + per - 1) / per;
-            segs.push_back(Seg{c.blocks, b, 0, nb});
-            c.blocks += nb;
-            ProbDev &P = bp->pd[b];
-            P.dig_off = 0;
-            P.dig_stride = nb * per;
-            if (c.gdig) {   // over the product's residue planes (dead after the GEMMs) if they fit
-                const size_t dig = (size_t)bp->hosts[b].nd32 * (size_t)P.dig_stride * sizeof(uint32_t);
-                const size_t planes = P.v_off - P.planes_off[0];
-                if (dig <= planes) {
-                    P.dig_off = P.planes_off[0];
-                } else {
-                    P.dig_off = w;
-                    w = align_up(w + dig);
+        for (auto &kv : classes) {
+            BatchCrtClass c{};
+            c.dc = std::get<0>(kv.first);
+            c.ept = std::get<1>(kv.first);
+            c.gdig = std::get<2>(kv.first) != 0;
+            int maxnd = 1, maxL = 1;
+            for (int b : kv.second) {
+                maxnd = std::max(maxnd, bp->hosts[b].nd32);
+                maxL = std::max(maxL, bp->hosts[b].L);
+            }
+            c.mma = c.dc < 0;
+            c.bd = 256;
+            size_t cols = 0;
+            if (c.mma) {
+                cols = (size_t)256 * maxnd * 4;   // 256 entries per block, one column each
+            } else if (!c.gdig) {
+                while (c.bd > 64 && (size_t)maxnd * c.bd * c.ept * 4 > 49152) c.bd /= 2;
+                cols = (((size_t)maxnd * c.bd * c.ept + 3) & ~(size_t)3) * 4;
+            }
+            c.LB = c.gdig ? std::max(1, std::min(maxL, (int)(32768 / (sizeof(double) * (c.dc + 1))))) : maxL;
+            c.lds = c.gdig ? (size_t)c.LB * (c.dc + 1) * sizeof(double) : cols;
+            std::vector<Seg> segs;
+            for (int b : kv.second) {
+                const int64_t per = (int64_t)c.bd * c.ept;
+                const int64_t nb = (probs[b].M * probs[b].N + per - 1) / per;
+                segs.push_back(Seg{c.blocks, b, 0, nb});
+                c.blocks += nb;
+                ProbDev &P = bp->pd[b];
+                P.dig_off = 0;
+                P.dig_stride = nb * per;
+                if (c.gdig) {   // over the product's residue planes (dead after the GEMMs) if they fit
+                    const size_t dig = (size_t)bp->hosts[b].nd32 * (size_t)P.dig_stride * sizeof(uint32_t);
+                    const size_t planes = P.v_off - P.planes_off[0];
+                    if (dig <= planes) {
+                        P.dig_off = P.planes_off[0];
+                    } else {
+                        P.dig_off = w;
+                        w = align_up(w + dig);
+                    }
                 }
             }
+            c.nseg = (int)segs.size();
+            ch.crt.push_back(c);
+            cs.crt.push_back(segs);
         }
-        c.nseg = (int)segs.size();
-        bp->crt.push_back(c);
-        crt_segs.push_back(segs);
     }
     bp->ws_bytes = w;
-    const size_t o_exp = off;
-    off = align_up(off + sizeof(Seg) * exp_segs.size());
-    const size_t o_rs = off;
-    off = align_up(off + sizeof(Seg) * res_segs.size());
-    std::vector<size_t> o_cs;
-    for (auto &v : crt_segs) {
-        o_cs.push_back(off);
-        off = align_up(off + sizeof(Seg) * v.size());
+    struct ChunkOffs {
+        size_t fill, exp, res[2];
+        std::vector<size_t> crt;
+    };
+    std::vector<ChunkOffs> coffs(nchunks);
+    for (int ci = 0; ci < nchunks; ++ci) {
+        ChunkOffs &co = coffs[ci];
+        const ChunkSegs &cs = csegs[ci];
+        co.fill = off;
+        off = align_up(off + sizeof(Seg) * cs.fill.size());
+        co.exp = off;
+        off = align_up(off + sizeof(Seg) * cs.exp.size());
+        for (int c = 0; c < 2; ++c) {
+            co.res[c] = off;
+            off = align_up(off + sizeof(Seg) * cs.res[c].size());
+        }
+        for (auto &v : cs.crt) {
+            co.crt.push_back(off);
+            off = align_up(off + sizeof(Seg) * v.size());
+        }
     }
 
     void *buf = nullptr;
@@ -2148,15 +2309,29 @@ int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2
     }
     bp->d_probs = (ProbDev *)(db + o_probs);
     OZ2H_HIP(hipMemcpy(bp->d_probs, bp->pd.data(), sizeof(ProbDev) * count, hipMemcpyHostToDevice));
-    bp->d_exp_segs = (Seg *)(db + o_exp);
-    bp->n_exp_segs = (int)exp_segs.size();
-    OZ2H_HIP(hipMemcpy(bp->d_exp_segs, exp_segs.data(), sizeof(Seg) * exp_segs.size(), hipMemcpyHostToDevice));
-    bp->d_res_segs = (Seg *)(db + o_rs);
-    bp->n_res_segs = (int)res_segs.size();
-    OZ2H_HIP(hipMemcpy(bp->d_res_segs, res_segs.data(), sizeof(Seg) * res_segs.size(), hipMemcpyHostToDevice));
-    for (size_t c = 0; c < bp->crt.size(); ++c) {
-        bp->crt[c].d_segs = (Seg *)(db + o_cs[c]);
-        OZ2H_HIP(hipMemcpy(bp->crt[c].d_segs, crt_segs[c].data(), sizeof(Seg) * crt_segs[c].size(), hipMemcpyHostToDevice));
+    auto put = [&](Seg **dst, size_t o, const std::vector<Seg> &v) -> int {
+        *dst = (Seg *)(db + o);
+        if (!v.empty()) OZ2H_HIP(hipMemcpy(*dst, v.data(), sizeof(Seg) * v.size(), hipMemcpyHostToDevice));
+        return OZ2H_OK;
+    };
+    for (int ci = 0; ci < nchunks; ++ci) {
+        BatchChunk &ch = bp->chunks[ci];
+        const ChunkSegs &cs = csegs[ci];
+        const ChunkOffs &co = coffs[ci];
+        if ((st = put(&ch.d_fill_segs, co.fill, cs.fill)) || (st = put(&ch.d_exp_segs, co.exp, cs.exp)))
+            return st;
+        ch.n_fill_segs = (int)cs.fill.size();
+        ch.n_exp_segs = (int)cs.exp.size();
+        for (int c = 0; c < 2; ++c) {
+            if ((st = put(&ch.d_res_segs[c], co.res[c], cs.res[c]))) return st;
+            ch.n_res_segs[c] = (int)cs.res[c].size();
+        }
+        for (size_t c = 0; c < ch.crt.size(); ++c)
+            if ((st = put(&ch.crt[c].d_segs, co.crt[c], cs.crt[c]))) return st;
+    }
+    if (nchunks > 1) {
+        OZ2H_HIP(hipStreamCreateWithFlags(&bp->side, hipStreamNonBlocking));
+        for (hipEvent_t &e : bp->ev) OZ2H_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     }
 
     // shape signature for the autotuner cache; default schedule unless tuned before
@@ -2167,8 +2342,8 @@ int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2
     }
     const int32_t okey[3] = {o->guard_bits, o->t_bits, o->crt_margin};
     bp->signature = fnv1a(okey, sizeof okey, sig);
-    bp->tile = o->tile == OZ2H_TILE_AUTO ? OZ2H_TILE_128x128 : o->tile;
-    bp->bpc = 2;
+    bp->tile = o->tile;   // OZ2H_TILE_AUTO: per product, as a plain call chooses
+    bp->bpc = 0;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         tune_load();
@@ -2191,13 +2366,17 @@ int oz2h_batched_get_config(const oz2h_batched_plan *plan, int32_t *tile, int32_
     if (!plan) return fail(OZ2H_EINVAL, "plan is NULL");
     if (tile) *tile = plan->tile;
     if (blocks_per_cu) *blocks_per_cu = plan->bpc;
-    if (gemm_items) *gemm_items = plan->nitems;
+    if (gemm_items) {
+        int64_t n = 0;
+        for (const BatchChunk &ch : plan->chunks) n += (int64_t)ch.nitems[0] + ch.nitems[1] + ch.nitems[2];
+        *gemm_items = n;
+    }
     return ok();
 }
 
 int oz2h_batched_set_config(oz2h_batched_plan *plan, int32_t tile, int32_t blocks_per_cu) {
     if (!plan) return fail(OZ2H_EINVAL, "plan is NULL");
-    if (tile < OZ2H_TILE_128x128 || tile > OZ2H_TILE_128x256 || blocks_per_cu < 0 || blocks_per_cu > 16)
+    if (tile < OZ2H_TILE_AUTO || tile > OZ2H_TILE_128x256 || blocks_per_cu < 0 || blocks_per_cu > 16)
         return fail(OZ2H_EINVAL, "bad tile or blocks_per_cu");
     if (tile != plan->tile || blocks_per_cu != plan->bpc) {
         plan->tile = tile;
@@ -2241,25 +2420,26 @@ int oz2h_batched_run(oz2h_batched_plan *plan, void *ws, size_t ws_bytes, hipStre
 int oz2h_batched_tune(oz2h_batched_plan *plan, void *ws, size_t ws_bytes, hipStream_t stream) {
     int st = check_batched_run(plan, ws, ws_bytes);
     if (st) return st;
-    // the residue planes the candidates multiply
-    if ((st = launch_batched_front(plan, (char *)ws, stream))) return st;
+    // each candidate is timed over whole runs (with two chunks the GEMMs share the compute
+    // units with the other chunk's residues and CRT, so a GEMM timed alone would mislead)
+    auto gemm_all = [&]() { return launch_batched_all(plan, (char *)ws, stream); };
     hipEvent_t e0, e1;
     OZ2H_HIP(hipEventCreate(&e0));
     OZ2H_HIP(hipEventCreate(&e1));
     float best = 1e30f;
     int bt = plan->tile, bb = plan->bpc;
-    const int tiles[3] = {OZ2H_TILE_128x128, OZ2H_TILE_256x128, OZ2H_TILE_128x256};
+    const int tiles[4] = {OZ2H_TILE_AUTO, OZ2H_TILE_128x128, OZ2H_TILE_256x128, OZ2H_TILE_128x256};
     const int bpcs[4] = {1, 2, 4, 0};
     for (int ti : tiles)
         for (int bc : bpcs) {
             plan->tile = ti;
             plan->bpc = bc;
             if ((st = upload_items(plan))) break;
-            if ((st = launch_batched_gemm(plan, (char *)ws, stream))) break;   // warm-up
+            if ((st = gemm_all())) break;   // warm-up
             float acc = 0;
             for (int rep = 0; rep < 3 && !st; ++rep) {
                 (void)hipEventRecord(e0, stream);
-                st = launch_batched_gemm(plan, (char *)ws, stream);
+                st = gemm_all();
                 (void)hipEventRecord(e1, stream);
                 if (hipEventSynchronize(e1) != hipSuccess) st = fail(OZ2H_EDEVICE, "tuning run failed");
                 float ms = 0;
@@ -2291,7 +2471,12 @@ void oz2h_batched_plan_destroy(oz2h_batched_plan *plan) {
     if (!plan) return;
     drop_graph(plan);
     if (plan->cap) (void)hipStreamDestroy(plan->cap);
-    if (plan->d_items) (void)hipFree(plan->d_items);
+    if (plan->side) (void)hipStreamDestroy(plan->side);
+    for (hipEvent_t e : plan->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (BatchChunk &ch : plan->chunks)
+        for (GemmItem *d : ch.d_items)
+            if (d) (void)hipFree(d);
     if (plan->dbuf) (void)hipFree(plan->dbuf);
     delete plan;
 }

@@ -54,41 +54,64 @@ __device__ __forceinline__ int find_seg(const Seg *__restrict__ segs, int nseg, 
     return lo;
 }
 
-// stage 1, grouped: segment (prod, side); a side whose contraction is contiguous
-// (cs == 1) gets one wave per row (4 rows per block), any other one thread per
-// row (256 rows per block); each row is reduced completely, so no atomics
-__global__ __launch_bounds__(256) void k_exp_grouped(const ProbDev *__restrict__ probs,
-                                                     const Seg *__restrict__ segs, int nseg,
-                                                     char *ws) {
+// stage 1, grouped, in three passes like the plain scan: fill every output row with
+// INT_MIN, combine partial maxima with atomicMax, then give all-zero rows exponent 0.
+// Fill / fix: segment (prod, side) is a 1-D grid of blocks of 256 rows.
+__global__ __launch_bounds__(256) void k_exp_fill_grouped(const ProbDev *__restrict__ probs,
+                                                          const Seg *__restrict__ segs, int nseg,
+                                                          char *ws, int fix) {
+    const int si = find_seg(segs, nseg, blockIdx.x);
+    const Seg sg = segs[si];
+    const ProbDev &P = probs[sg.prod];
+    const int64_t r = ((int64_t)blockIdx.x - sg.first) * 256 + threadIdx.x;
+    if (r >= P.rows[sg.side]) return;
+    int32_t *out = (int32_t *)(ws + P.erow_off[sg.side]) + r;
+    if (!fix) *out = INT_MIN;
+    else if (*out == INT_MIN) *out = 0;
+}
+
+// Scan: segment (prod, side) is an nbx x (k chunks) grid of blocks, row blocks fastest.  A
+// side whose contraction is contiguous (cs == 1) gets one wave per row (4 rows per block)
+// over kExpChunk entries; any other side one thread per row (256 rows per block) over
+// kExpRowsK entries, loads unrolled so that they are in flight together.
+__global__ __launch_bounds__(256) void k_exp_scan_grouped(const ProbDev *__restrict__ probs,
+                                                          const Seg *__restrict__ segs, int nseg,
+                                                          char *ws) {
     const int si = find_seg(segs, nseg, blockIdx.x);
     const Seg sg = segs[si];
     const ProbDev &P = probs[sg.prod];
     const int side = sg.side;
     const int64_t lb = (int64_t)blockIdx.x - sg.first;
+    const int64_t rb = lb % sg.nbx, kb = lb / sg.nbx;
     const int8_t *__restrict__ sign = P.signs[side];
     const int32_t *__restrict__ exps = P.exps[side];
     const int64_t rows = P.rows[side], K = P.K, rs = P.rs[side], cs = P.cs[side];
     int32_t *out = (int32_t *)(ws + P.erow_off[side]);
+    int m = INT_MIN;
     if (cs == 1) {
         const int lane = threadIdx.x & 63;
-        const int64_t r = lb * 4 + (threadIdx.x >> 6);
+        const int64_t r = rb * 4 + (threadIdx.x >> 6);
         if (r >= rows) return;   // whole wave
-        int m = INT_MIN;
-        for (int64_t k = lane; k < K; k += 64) {
+        const int64_t k0 = kb * kExpChunk, k1 = min(K, k0 + kExpChunk);
+        for (int64_t k = k0 + lane; k < k1; k += 64) {
             const int64_t idx = r * rs + k;
             if (sign[idx]) m = max(m, exps[idx]);
         }
         for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off));
-        if (lane == 0) out[r] = m == INT_MIN ? 0 : m;
+        if (lane == 0 && m != INT_MIN) atomicMax(out + r, m);
     } else {
-        const int64_t r = lb * 256 + threadIdx.x;
+        const int64_t r = rb * 256 + threadIdx.x;
         if (r >= rows) return;
-        int m = INT_MIN;
-        for (int64_t k = 0; k < K; ++k) {
-            const int64_t idx = r * rs + k * cs;
-            if (sign[idx]) m = max(m, exps[idx]);
+        const int64_t k0 = kb * kExpRowsK;
+#pragma unroll
+        for (int u = 0; u < kExpRowsK; ++u) {
+            const int64_t k = k0 + u;
+            if (k < K) {
+                const int64_t idx = r * rs + k * cs;
+                if (sign[idx]) m = max(m, exps[idx]);
+            }
         }
-        out[r] = m == INT_MIN ? 0 : m;
+        if (m != INT_MIN) atomicMax(out + r, m);
     }
 }
 
@@ -100,8 +123,8 @@ __device__ __forceinline__ ResArgs res_args(const ProbDev &P, int side, char *ws
 }
 
 // stage 2, grouped: segment (prod, side) is a (kpad / (64 KW)) x (rpad / (RB / KW)) grid of
-// blocks, KW = res_waves_k(RB)
-template <int RB>
+// blocks, KW = res_waves_k(RB); one launch per moduli group width KG (the plans' kg)
+template <int RB, int KG>
 __global__ __launch_bounds__(64 * RB) void k_residues_grouped(const ProbDev *__restrict__ probs,
                                                               const Seg *__restrict__ segs,
                                                               int nseg, char *ws) {
@@ -110,13 +133,15 @@ __global__ __launch_bounds__(64 * RB) void k_residues_grouped(const ProbDev *__r
     const Seg sg = segs[si];
     const int64_t lb = (int64_t)blockIdx.x - sg.first;
     const ResArgs a = res_args(probs[sg.prod], sg.side, ws);
-    residue_block<RB, kModGroup>(a, lb % sg.nbx, lb / sg.nbx, words);
+    residue_block<RB, KG>(a, lb % sg.nbx, lb / sg.nbx, words);
 }
 
 // one work item of the grouped GEMM: output tile (mt, nt) of modulus l of product prod
+// (prod = kSkipItem: a placeholder that keeps the item list's XCD alignment)
 struct GemmItem {
     uint16_t prod, l, mt, nt;
 };
+constexpr uint16_t kSkipItem = 0xFFFF;
 
 // stage 3, persistent grouped launch: a grid of a few blocks per compute unit
 // walks the cost-sorted item list with a grid stride
@@ -126,6 +151,7 @@ __global__ __launch_bounds__(256) void k_resgemm_grouped(const ProbDev *__restri
                                                          int nitems, char *ws) {
     for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
         const GemmItem it = items[i];
+        if (it.prod == kSkipItem) continue;   // uniform over the block
         const ProbDev &P = probs[it.prod];
         const GemmArgs g{(const int8_t *)(ws + P.planes_off[0]), (const int8_t *)(ws + P.planes_off[1]),
                          P.kpad, P.rpad[0] * P.kpad, P.rpad[1] * P.kpad, P.mi,

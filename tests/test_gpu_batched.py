@@ -84,7 +84,7 @@ def test_batched_matches_plain_calls(oz, c_oracle):
     bp.destroy()
 
 
-@pytest.mark.parametrize("tile,bpc", [(1, 1), (2, 2), (3, 4), (2, 0)])
+@pytest.mark.parametrize("tile,bpc", [(1, 1), (2, 2), (3, 4), (2, 0), (0, 0), (0, 2)])
 def test_batched_tiles_and_schedules(oz, tile, bpc):
     import torch
     batch = make_batch(11, 10, 100, 700, ps=(113, 512))
@@ -110,7 +110,7 @@ def test_batched_autotune(oz):
     ws = bp.workspace()
     cfg = bp.tune(ws)
     print("tuned", cfg, flush=True)
-    assert cfg["tile"] in (1, 2, 3) and cfg["blocks_per_cu"] in (0, 1, 2, 4)
+    assert cfg["tile"] in (0, 1, 2, 3) and cfg["blocks_per_cu"] in (0, 1, 2, 4)
     bp.run(ws)
     torch.cuda.synchronize()
     for i, (Ad, Bd, C, _, _) in enumerate(probs):
