@@ -17,6 +17,8 @@ p = 2048 bits (exponents uniform in [-16, 16]), and carries as extra keys:
     ("complex");
   - the binary64 and mixed backends against INT8 at M = N = K = 4096, p = 113
     ("backends");
+  - operand reuse: one A (4096^2, p = 2048) against 8 right-hand sides of 4096 x 256,
+    residue handle against plain calls ("operand_reuse");
   - the oracle on the host cores over a bounded block of outputs, which also
     checks the timed GPU output on that block bit for bit.
 
@@ -575,6 +577,57 @@ def measure_backends(steps, warmup):
             **out, "bit_identical": same}
 
 
+def measure_operand_reuse(steps, warmup):
+    """Operand reuse (residue handles): one A of 4096 x 4096 at p = 2048 against 8 right-hand
+    sides of 4096 x 256, as 8 plain calls against one residue handle for A plus 8 products
+    from it (its creation inside the timed region); outputs checked bit for bit."""
+    import torch
+
+    import synth
+    from paper_2609_27831_amd import oz2h
+    M = K = 4096
+    N, p, nrhs = 256, 2048, 8
+    cfg = ("", M, N, K, p, -16, 16, 0)
+    from synth.gen_torch import mp_random_torch
+    A, B0 = device_operands(cfg, synth.CONFIG_SEED_BASE + 81)
+    Bs = [B0] + [oz2h.DeviceMP(*mp_random_torch(synth.CONFIG_SEED_BASE + 82 + r, K, N, p, -16, 16), p)
+                 for r in range(nrhs - 1)]
+    plan = oz2h.Plan.create(p, K)
+    ws = oz2h.workspace(plan, M, N)
+    Cp = [oz2h.empty_mp(M, N, p) for _ in range(nrhs)]
+    Cr = [oz2h.empty_mp(M, N, p) for _ in range(nrhs)]
+
+    def plain():
+        for b, c in zip(Bs, Cp):
+            oz2h.gemm(plan, A, b, out=c, ws=ws)
+
+    def reuse():
+        ra = oz2h.Residues(plan, A, oz2h.SIDE_A)
+        for b, c in zip(Bs, Cr):
+            oz2h.gemm_from_residues(plan, B=b, ra=ra, out=c, ws=ws)
+        torch.cuda.synchronize()   # the handle's planes are read until here
+        ra.destroy()
+
+    out = {}
+    for name, fn in (("plain", plain), ("reuse", reuse)):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        out[name] = (time.perf_counter() - t0) * 1e3 / steps
+    same = all(bool(torch.equal(getattr(x, f), getattr(y, f)))
+               for x, y in zip(Cp, Cr) for f in ("sign", "exp", "limbs"))
+    plan.destroy()
+    return {"workload": "A 4096 x 4096 at p = 2048 against 8 right-hand sides of 4096 x 256, "
+                        "exponents U[-16,16]",
+            "plain_ms": round(out["plain"], 4), "reuse_ms": round(out["reuse"], 4),
+            "reuse_vs_plain": round(out["plain"] / out["reuse"], 3),
+            "ms_per_product_amortized": round(out["reuse"] / nrhs, 4), "bit_identical": same}
+
+
 def copy_calibration():
     """A plain device copy of known size, for the HBM-counter scale factors."""
     import torch
@@ -693,6 +746,9 @@ def main():
         torch.cuda.empty_cache()
         log("backends: INT8, binary64, mixed")
         line["backends"] = measure_backends(max(2, args.steps // 2), 1)
+        torch.cuda.empty_cache()
+        log("operand reuse: residue handles against plain calls")
+        line["operand_reuse"] = measure_operand_reuse(max(2, args.steps // 2), 1)
     print(json.dumps(line), flush=True)
 
 
