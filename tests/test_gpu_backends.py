@@ -107,3 +107,17 @@ def test_backend_plan_rules(oz):
     info = oz.plan_moduli32(64, 16, oz.default_opts(flags=F64))
     assert plan.L == info["L"] and list(plan.moduli) == list(info["moduli"])
     plan.destroy()
+
+
+@pytest.mark.parametrize("flags", [F64, MIXED])
+def test_backend_largest_K(oz, c_oracle, flags):
+    """K = 133000, the largest contraction: the binary64 moduli shrink to about 5.2e5 so that
+    K ((m - 1)/2)^2 stays below 2^53; every product sum is then still exact."""
+    M, N, K, p = 9, 7, 133000, 53
+    print(f"backend K={K} flags={flags}", flush=True)
+    A, B = synth.operands_for(230 + flags, M, N, K, p, -4, 4)
+    plan = oz.Plan.create(p, K, oz.default_opts(flags=flags))
+    assert all(K * ((int(m) - 1) // 2) ** 2 < 2 ** 53 for m in plan.moduli[plan.L - plan.Lf:])
+    ref = c_oracle.gemm(A, B)
+    _compare_full(_run_gpu(oz, plan, A, B), ref, ref["nlc"])
+    plan.destroy()

@@ -128,3 +128,18 @@ def test_zgemm_edges(oz):
     oz.zgemm(plan, e0[0], e0[1], dB[0], dB[1])
     bad.destroy()
     plan.destroy()
+
+
+@pytest.mark.parametrize("scheme", [3, 4])
+def test_zgemm_largest_K(oz, c_oracle, scheme):
+    """K = 66500, the largest complex contraction (a plan of length 2K = 133000): each real
+    residue GEMM accumulates K products of centred residues in INT32."""
+    M, N, K, p = 5, 6, 66500, 64
+    print(f"zgemm K={K} scheme={scheme}", flush=True)
+    ops = zoperands(41 + scheme, M, N, K, p, -4, 4)
+    plan = oz.Plan.create(p, 2 * K)
+    re, im = c_oracle.zgemm(*ops)
+    gr, gi = _run(oz, plan, ops, scheme)
+    _same(gr, re)
+    _same(gi, im)
+    plan.destroy()
