@@ -434,7 +434,8 @@ def measure_batched(steps, warmup):
 
 def measure_autograd(steps, warmup):
     """Autograd form: forward C = A B plus both backward products (dA = W B^T, dB = A^T W)
-    at 4096^2, p = 256, through torch.autograd (float64 carriers), reuse vs recompute."""
+    at 4096^2, p = 256, through torch.autograd (float64 carriers), reuse vs recompute; and the
+    same at 2048^2, p = 1024."""
     import torch
 
     import synth
@@ -443,24 +444,34 @@ def measure_autograd(steps, warmup):
     M = N = K = 4096
     p = 256
     A, B, W = synth.grad_operands_for(synth.CONFIG_SEED_BASE + 5, M, N, K, p, -4, 4)
-    a0, b0, w = ag.to_carrier(A), ag.to_carrier(B), ag.to_carrier(W)
     flops = 3 * 2.0 * M * N * K
-    out = {}
-    for mode in ("reuse", "recompute"):
-        def step():
-            a = a0.detach().requires_grad_()
-            b = b0.detach().requires_grad_()
-            c = ag.oz_matmul(a, b, p, mode=mode)
-            c.backward(w)
-            return a.grad, b.grad
-        for _ in range(warmup):
-            step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            step()
-        torch.cuda.synchronize()
-        out[mode] = (time.perf_counter() - t0) * 1e3 / steps
+
+    def modes(A, B, W, p):
+        a0, b0, w = ag.to_carrier(A), ag.to_carrier(B), ag.to_carrier(W)
+        res = {}
+        for mode in ("reuse", "recompute"):
+            def step():
+                a = a0.detach().requires_grad_()
+                b = b0.detach().requires_grad_()
+                c = ag.oz_matmul(a, b, p, mode=mode)
+                c.backward(w)
+                return a.grad, b.grad
+            for _ in range(warmup):
+                step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                step()
+            torch.cuda.synchronize()
+            res[mode] = (time.perf_counter() - t0) * 1e3 / steps
+        return res
+
+    out = modes(A, B, W, p)
+    # a higher precision, where a residue pass is a larger share of a product
+    M2, p2 = 2048, 1024
+    A2, B2, W2 = synth.grad_operands_for(synth.CONFIG_SEED_BASE + 6, M2, M2, M2, p2, -4, 4)
+    out2 = modes(A2, B2, W2, p2)
+    del A2, B2, W2
     plan = oz2h.Plan.create_grad(p, M, N, K)
     Ad, Bd, Wd = oz2h.to_device(A), oz2h.to_device(B), oz2h.to_device(W)
     ws = oz2h.workspace(plan, M, N)
@@ -481,7 +492,10 @@ def measure_autograd(steps, warmup):
             "recompute_ms_per_step": round(out["recompute"], 4),
             "reuse_vs_recompute": round(out["recompute"] / out["reuse"], 3),
             "value": round(flops / (out["reuse"] * 1e-3) / 1e9, 3),
-            "backward_entry_point_ms": round(ms_bwd, 4)}
+            "backward_entry_point_ms": round(ms_bwd, 4),
+            "at_2048_p1024": {"reuse_ms_per_step": round(out2["reuse"], 4),
+                              "recompute_ms_per_step": round(out2["recompute"], 4),
+                              "reuse_vs_recompute": round(out2["recompute"] / out2["reuse"], 3)}}
 
 
 def measure_complex(steps, warmup):
