@@ -93,6 +93,8 @@ __global__ void k_exp_fix(int32_t *__restrict__ p, int64_t n) {
 #define OZ2H_G(T) const __attribute__((address_space(1))) T
 typedef __attribute__((address_space(1))) int8_t g_i8;
 typedef __attribute__((address_space(1))) uint32_t g_u32;
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) v4u g_v4u;
 
 // a ModInfo record read through a global-memory pointer (field by field: the
 // implicit copy constructor does not bind to an address-space-qualified object)
@@ -421,10 +423,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 //   phase 2: wave v takes entry half h = v & 1 (entries 64 h ..) and the moduli groups
 //            g = v >> 1, v >> 1 + 2, ..; row q of the wave takes entries 64 h + 16 q + i,
 //            i < 16, four at a time (four independent accumulators per lane);
-//   stores:  the residue bytes of a group go through an LDS staging area [plane][64 entries]
-//            and leave as 64-byte plane segments, four planes per store instruction.
+//   stores:  a lane holds its modulus's residues of 16 consecutive entries, packs their bytes
+//            in registers and stores 16 bytes per plane.
 constexpr int kResRowS = 129;   // LDS word stride of the row-broadcast residue kernel
-constexpr int kResRowStage = 48 * 64;   // staging bytes per wave: up to 48 planes x 64 entries
 
 // v_fmac_f64 with its first source broadcast from lane LANE of each row of 16 lanes (DPP
 // row_newbcast).  The DPP source must not be written by a VALU instruction in the two
@@ -475,7 +476,7 @@ struct ResRowArgs {
 };
 
 __host__ __device__ constexpr size_t res_row_lds(int nwp) {
-    return (size_t)nwp * kResRowS * 4 + 128 * 8 + 4 * kResRowStage;
+    return (size_t)nwp * kResRowS * 4 + 128 * 8;
 }
 
 // EPR entries per row of a wave and group (16: wave v takes the entry half v & 1 and the
@@ -515,17 +516,12 @@ __device__ __forceinline__ void residues_row_block(const ResRowArgs &a, uint32_t
     const int j = lane & 15, q = lane >> 4;
     const int h0 = NH == 2 ? 0 : (wv & 1);        // first entry half of this wave
     const int g0w = NH == 2 ? wv : (wv >> 1), gstep = NH == 2 ? 4 : 2;
-    uint8_t *stg = (uint8_t *)(sgn + 128) + (size_t)wv * kResRowStage;
     const int nfull = a.nw32 >> 4, ntail = ((a.nw32 & 15) + 3) >> 2;
     int8_t *prow = a.planes + r * a.kpad + k0;   // the block's segment of plane 0
     for (int g = g0w; g < a.rg16; g += gstep) {
         const int l = 16 * g + j;
         const bool live = l < a.L;
         const ModInfo mi = live ? load_info((OZ2H_G(ModInfo) *)a.mi + l) : ModInfo{};
-        const ModInfo m0 = load_info((OZ2H_G(ModInfo) *)a.mi + 16 * g);
-        const int llast = min(16 * g + 15, a.L - 1);
-        const ModInfo ml = load_info((OZ2H_G(ModInfo) *)a.mi + llast);
-        const int gp0 = (int)m0.g0, np = (int)(ml.g0 + ml.nprod) - gp0;   // this group's planes
         const double *crow = a.tab + ((size_t)g * 16 + j) * a.nwp;
         double acc[EPR];
 #pragma unroll
@@ -560,37 +556,48 @@ __device__ __forceinline__ void residues_row_block(const ResRowArgs &a, uint32_t
             chunk(std::integral_constant<int, 4>{}, 16 * nfull + 4 * c, c4);
         }
 
-        // per entry half: centred residues into the staging area (plane (g0 - gp0) [+ 1, + 2]
-        // of entry 16 q + i), then 64-byte plane segments, lane (q, j) storing bytes
-        // 4 j .. 4 j + 3 of plane 4 it + q
+        // per entry half: lane (q, j) holds the residues of its modulus for the 16 consecutive
+        // entries 64 hs + 16 q + i; their bytes are packed in registers and leave as one
+        // 16-byte store per plane (the four rows of a wave write 64 contiguous bytes of each
+        // of its planes)
 #pragma unroll
         for (int hh = 0; hh < NH; ++hh) {
             const int hs = h0 + hh;
             if (live) {
-                const int po = (int)mi.g0 - gp0;
                 const double md = (double)mi.m;
+                const double *sg = sgn + 64 * hs + 16 * q;
+                g_i8 *dst = (g_i8 *)prow + (int64_t)mi.g0 * a.plane_stride + 64 * hs + 16 * q;
+                auto resid = [&](int i) {
+                    const double x = acc[16 * hh + i] * sg[i];
+                    return (int)fma(-rint(x * mi.inv_m), md, x);
+                };
+                v4u b0;
+                if (mi.nprod == 1) {
 #pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    const double x = acc[16 * hh + i] * sgn[64 * hs + 16 * q + i];
-                    const int ri = (int)fma(-rint(x * mi.inv_m), md, x);
-                    uint8_t *d = stg + (size_t)po * 64 + 16 * q + i;
-                    if (mi.nprod == 1) {
-                        d[0] = (uint8_t)ri;
-                    } else {
-                        const int r0 = ((ri + 64) & 127) - 64;   // balanced base-128 split
-                        const int r1 = (ri - r0) >> 7;
-                        d[0] = (uint8_t)r0;
-                        d[64] = (uint8_t)r1;
-                        d[128] = (uint8_t)(r0 + r1);
+                    for (int i4 = 0; i4 < 4; ++i4)
+                        b0[i4] = pack_bytes(resid(4 * i4), resid(4 * i4 + 1), resid(4 * i4 + 2),
+                                            resid(4 * i4 + 3));
+                    *(g_v4u *)dst = b0;
+                } else {
+                    v4u b1, b2;
+#pragma unroll
+                    for (int i4 = 0; i4 < 4; ++i4) {
+                        int r0[4], r1[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int ri = resid(4 * i4 + u);
+                            r0[u] = ((ri + 64) & 127) - 64;   // balanced base-128 split
+                            r1[u] = (ri - r0[u]) >> 7;
+                        }
+                        b0[i4] = pack_bytes(r0[0], r0[1], r0[2], r0[3]);
+                        b1[i4] = pack_bytes(r1[0], r1[1], r1[2], r1[3]);
+                        b2[i4] = pack_bytes(r0[0] + r1[0], r0[1] + r1[1], r0[2] + r1[2], r0[3] + r1[3]);
                     }
+                    *(g_v4u *)dst = b0;
+                    *(g_v4u *)(dst + a.plane_stride) = b1;
+                    *(g_v4u *)(dst + 2 * a.plane_stride) = b2;
                 }
             }
-            wave_lds_sync();
-            for (int pp = q; pp < np; pp += 4) {
-                const uint32_t v = *(const uint32_t *)(stg + (size_t)pp * 64 + 4 * j);
-                *(g_u32 *)((g_i8 *)prow + (int64_t)(gp0 + pp) * a.plane_stride + 64 * hs + 4 * j) = v;
-            }
-            wave_lds_sync();
         }
     }
 }
@@ -1797,6 +1804,8 @@ __device__ __forceinline__ void crt_row_fmas(double (&acc)[16], const double (&x
 // a ds_read_b128 of 16 lanes touches start on 16 different 4-bank groups.
 constexpr int kCrtRowStage = 192;
 constexpr int kCrtRowDStride = kCrtRowStage + 2;
+constexpr int kCrtRowPairs = kCrtRowStage / 32;   // 16-byte pairs per thread and stage
+static_assert(kCrtRowStage % 32 == 0 && kCrtRowDStride % 2 == 0, "stage rows of whole pairs");
 constexpr size_t kCrtRowSumsLds = (size_t)16 * kCrtRowDStride * 8 + (size_t)4 * 32 * 17 * 8;
 
 // blocks of four waves: four consecutive tiles of 64 entries, one digit group; block b runs
@@ -1859,15 +1868,37 @@ __global__ __launch_bounds__(256) void k_crt_row_sums(CrtRowArgs a) {
         dpp_ready16(vd);
         crt_row_fmas(acc, vd, dc);
     };
+    // a stage's constants: thread t moves pairs (t & 15) + 16 i of row t >> 4 (lpad and the
+    // stage are multiples of 16, so a row of a stage is a whole number of 16-byte pairs); the
+    // next stage's pairs load into registers while the current stage is multiplied
+    const int srow = threadIdx.x >> 4, spair = threadIdx.x & 15;
+    d2 pre[kCrtRowPairs];
+    auto stage_load = [&](int l0) {
+        const int nl = min(kCrtRowStage, a.lpad - l0);
+        const double *src = gsrc + (size_t)srow * a.lpad + l0;
+#pragma unroll
+        for (int i = 0; i < kCrtRowPairs; ++i) {
+            const int l = 2 * (spair + 16 * i);
+            if (l < nl) pre[i] = *(const d2 *)(src + l);
+        }
+    };
+    auto stage_store = [&](int l0) {
+        const int nl = min(kCrtRowStage, a.lpad - l0);
+        double *dst = Dl + srow * kCrtRowDStride;
+#pragma unroll
+        for (int i = 0; i < kCrtRowPairs; ++i) {
+            const int l = 2 * (spair + 16 * i);
+            if (l < nl) *(d2 *)(dst + l) = pre[i];
+        }
+    };
     v4i aw0, aw1, bw0, bw1;
+    stage_load(0);
     loadv(0, aw0, aw1);
     for (int l0 = 0; l0 < a.lpad; l0 += kCrtRowStage) {
         const int nl = min(kCrtRowStage, a.lpad - l0);
         __syncthreads();   // the previous stage has been read by every wave
-        for (int t = threadIdx.x; t < 16 * nl; t += 256) {
-            const int jj = t / nl, l = t - jj * nl;
-            Dl[jj * kCrtRowDStride + l] = gsrc[(size_t)jj * a.lpad + l0 + l];
-        }
+        stage_store(l0);
+        if (l0 + kCrtRowStage < a.lpad) stage_load(l0 + kCrtRowStage);
         __syncthreads();
         const int c1 = (l0 + nl) >> 4;
         int c = l0 >> 4;
