@@ -1384,31 +1384,27 @@ __device__ __forceinline__ void crt_finish(const CrtArgs &a, int64_t e, uint32_t
         if ((mag.bits32(rpos) & 1u) != 0)   // round bit set: up unless an exact tie to even
             inc = mag.any_below(rpos) || (mag.bits32(sh) & 1u);
     }
-    bool allones = inc;
-    if (inc) {   // mant = 2^p - 1 rounds up to 2^p: renormalise
-        for (int w = 0; w < nl && allones; ++w) {
-            const uint64_t v = (uint64_t)mag.bits32(64 * (int64_t)w + sh) |
-                               ((uint64_t)mag.bits32(64 * (int64_t)w + 32 + sh) << 32);
-            const int bits = (w == nl - 1) ? p - 64 * (nl - 1) : 64;
-            const uint64_t mask = bits >= 64 ? ~0ull : ((1ull << bits) - 1);
-            allones = v == mask;
-        }
+    // mant = mag / 2^sh (+ 1): limb w is bits [sh + 64 w, sh + 64 w + 64) of mag, formed from
+    // three consecutive digits by funnel shifts, one pass from the bottom
+    const int64_t q0 = sh >> 5;   // floor: sh < 0 reads zero digits below the column
+    const int rsh = (int)(sh & 31);
+    uint32_t prev = mag(q0);
+    bool cy = inc;
+    uint64_t last = 0;
+    for (int w = 0; w < nl; ++w) {
+        const uint32_t d1 = mag(q0 + 2 * w + 1), d2 = mag(q0 + 2 * w + 2);
+        const uint64_t v = ((uint64_t)__builtin_amdgcn_alignbit(d2, d1, rsh) << 32) |
+                           __builtin_amdgcn_alignbit(d1, prev, rsh);
+        last = v + (cy ? 1u : 0u);
+        cy = cy && last == 0;
+        o[w] = last;
+        prev = d2;
     }
-    if (allones) {
+    const int pb = p - 64 * (nl - 1);   // bits of the top limb
+    if (pb < 64 ? (last >> pb) != 0 : cy) {   // mant = 2^p - 1 rounded up to 2^p: renormalise
         for (int w = 0; w < nl; ++w) o[w] = 0;
         o[(p - 1) >> 6] = 1ull << ((p - 1) & 63);
         nb += 1;
-    } else {
-        bool cy = inc;
-        for (int w = 0; w < nl; ++w) {
-            uint64_t v = (uint64_t)mag.bits32(64 * (int64_t)w + sh) |
-                         ((uint64_t)mag.bits32(64 * (int64_t)w + 32 + sh) << 32);
-            if (cy) {
-                v += 1;
-                cy = v == 0;
-            }
-            o[w] = v;
-        }
     }
     a.osign[oi] = neg ? -1 : 1;
     a.oexp[oi] = (int32_t)(nb + (int64_t)(a.erow ? a.erow[i] : 0) + (a.fcol ? a.fcol[j] : 0) -
@@ -1944,7 +1940,14 @@ __global__ __launch_bounds__(256) void k_crt_row_sums(CrtRowArgs a) {
     }
 }
 
-// N columns of valid entries per row of ldv: entry e' = i * ldv + j, output (i, j) if j < N
+// N columns of valid entries per row of ldv: entry e' = i * ldv + j, output (i, j) if j < N.
+// beta comes first, from S's top digits: an exact carry pass over the top two digit groups
+// (their digit sums and carry-outs) leaves out only the carry into them from the groups
+// below, at most one unit at a digit 12 or more places below the top nt, far inside the
+// 2^-30 margin of the half-integer test.  One carry pass from the bottom then forms
+// c^ = S - beta P digit by digit in binary64 (every term an integer below 2^43: exact) and
+// keeps its low nd32 digits in an LDS column, c^ in two's complement (|c^| < P/2, so the
+// top digit is sign extension); on the paper's alpha - 1 path the column holds R in [0, 3P).
 template <bool ROUND>
 __global__ __launch_bounds__(64) void k_crt_row_finish(CrtArgs a, CrtRowArgs r) {
     extern __shared__ __attribute__((aligned(16))) uint32_t sdig[];
@@ -1952,56 +1955,78 @@ __global__ __launch_bounds__(64) void k_crt_row_finish(CrtArgs a, CrtRowArgs r) 
     const int64_t ep = (int64_t)blockIdx.x * 64 + tid;
     const int64_t i = ep / r.ldv, jj = ep - i * r.ldv;
     if (ep >= r.nent || jj >= a.N) return;
-    const int nd32 = a.nd32;
+    const int nd32 = a.nd32, nt = a.nt;
     uint32_t *col = sdig + tid;   // digit k at col[64 k]
-    // the digits of a group load together (16 loads in flight), the next group's while one
-    // is carried through (two register sets)
+    // groups holding digits below nd32 (at least three: this kernel runs for nd32 > 32)
     const int ng = min(r.ndg, (nd32 + 15) / 16);
     auto ldg = [&](int g, uint32_t (&dv)[16], int32_t &co) {
         const int gc = min(g, ng - 1);
 #pragma unroll
-        for (int jj2 = 0; jj2 < 16; ++jj2) dv[jj2] = r.dig[(int64_t)(16 * gc + jj2) * r.estride + ep];
+        for (int u = 0; u < 16; ++u) dv[u] = r.dig[(int64_t)(16 * gc + u) * r.estride + ep];
         co = gc > 0 ? r.cout[(int64_t)(gc - 1) * r.estride + ep] : 0;
-    };
-    int64_t carry = 0;
-    auto ripple = [&](int g, const uint32_t (&dv)[16], int32_t co) {
-        carry += co;
-#pragma unroll
-        for (int jj2 = 0; jj2 < 16; ++jj2) {
-            const int k = 16 * g + jj2;
-            const int64_t xv = (int64_t)dv[jj2] + carry;
-            if (k < nd32) col[64 * k] = (uint32_t)xv;
-            carry = xv >> 32;
-        }
     };
     uint32_t da[16], db[16];
     int32_t ca, cb;
+
+    // S's top nt digits (the highest as a signed digit) as one binary64 value
+    ldg(ng - 2, da, ca);
+    ldg(ng - 1, db, cb);
+    double val = 0.0;
+    {
+        const int base = 16 * (ng - 2), kb = nd32 - nt;
+        uint32_t top[32];
+        int64_t cy = ca;
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+            const int64_t x = (int64_t)(u < 16 ? da[u] : db[u - 16]) + (u == 16 ? (int64_t)cb : 0) + cy;
+            top[u] = (uint32_t)x;
+            cy = x >> 32;
+        }
+        // Horner from the signed top digit down: the sign-extension digits cancel exactly
+#pragma unroll
+        for (int u = 31; u >= 0; --u) {
+            const int k = base + u;
+            if (k == nd32 - 1) val = (double)(int32_t)top[u];
+            else if (k >= kb && k < nd32) val = fma(val, 0x1p32, (double)top[u]);
+        }
+    }
+    const double est = val * a.inv_ptop, rr = rint(est);
+    const bool slow = fabs(est - rr) > 0.5 - 0x1p-30;
+    const double beta = slow ? floor(est) - 1.0 : rr;   // |beta| <= L + 2
+
+    // c^ = S - beta P from the bottom, the next group's digits loading during a group
+    typedef const __attribute__((address_space(4))) uint32_t cu32;
+    cu32 *Pd = (cu32 *)a.Pd;
+    double cy = 0.0;
+    auto digit = [&](int k, uint32_t d, double add, uint32_t pk) {
+        const double x = fma(-beta, (double)pk, (double)d + add + cy);
+        const double hi = floor(x * 0x1p-32);
+        col[64 * k] = (uint32_t)fma(-hi, 0x1p32, x);
+        cy = hi;
+    };
+    auto pass = [&](int g, const uint32_t (&dv)[16], int32_t co) {
+        if (16 * g + 16 <= nd32) {   // a whole group: its 16 digits of P in one scalar load
+            uint32_t pk[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) pk[u] = Pd[16 * g + u];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) digit(16 * g + u, dv[u], u == 0 ? (double)co : 0.0, pk[u]);
+        } else {
+            for (int u = 0; u < 16 && 16 * g + u < nd32; ++u)
+                digit(16 * g + u, dv[u], u == 0 ? (double)co : 0.0, Pd[16 * g + u]);
+        }
+    };
     ldg(0, da, ca);
     int g = 0;
     for (; g + 2 <= ng; g += 2) {
         ldg(g + 1, db, cb);
-        ripple(g, da, ca);
+        pass(g, da, ca);
         ldg(g + 2, da, ca);
-        ripple(g + 1, db, cb);
+        pass(g + 1, db, cb);
     }
-    if (g < ng) ripple(g, da, ca);
-    // S < L P keeps the two top digits as sign extension: the column holds S in two's
-    // complement and the carry beyond it is S's sign
-    const int64_t sgn = (int32_t)col[64 * (nd32 - 1)] < 0 ? -1 : 0;
-    double val = (double)(int32_t)col[64 * (nd32 - 1)];
-    for (int k = nd32 - 2; k >= nd32 - a.nt; --k) val = val * 4294967296.0 + (double)col[64 * k];
-    const double est = val * a.inv_ptop, rr = rint(est);
-    const bool slow = fabs(est - rr) > 0.5 - 0x1p-30;
-    const int64_t beta = slow ? (int64_t)floor(est) - 1 : (int64_t)rr;
-    typedef const __attribute__((address_space(4))) uint32_t cu32;
-    cu32 *Pd = (cu32 *)a.Pd;
-    int64_t cy = 0;
-    for (int k = 0; k < nd32; ++k) {
-        const int64_t xv = (int64_t)col[64 * k] - beta * (int64_t)Pd[k] + cy;
-        col[64 * k] = (uint32_t)xv;
-        cy = xv >> 32;
-    }
-    crt_finish<ROUND>(a, i * a.N + jj, col, 64, slow, cy + sgn);
+    if (g < ng) pass(g, da, ca);
+    const int64_t sgn = !slow && (int32_t)col[64 * (nd32 - 1)] < 0 ? -1 : 0;
+    crt_finish<ROUND>(a, i * a.N + jj, col, 64, slow, sgn);
 }
 
 // planes [G][R][C] (int8, row stride ldi) -> [G][Co][Ro] (row stride Ro), zero where
