@@ -247,15 +247,30 @@ int launch_residues(const oz2h_plan *pl, int64_t rows, int64_t count, const uint
     const size_t lds = (size_t)h.nw32 * 64 * rb * sizeof(uint32_t);
     const ResArgs a{limbs, exp, sign, rs, cs, rows, count, kpad, ps, erow, h.p, nl, t, h.nw32,
                     pl->d_resid, pl->d_rgrp, h.L, h.lgroups, planes, koff};
+    // integers of at most kResRegWords words keep them in registers (one instantiation per
+    // word count)
+#define OZ2H_RES_NW(KG, NW) k_residues<4, KG, 1, NW><<<grid, 256, lds, s>>>(a)
 #define OZ2H_RES(KG)                                                                   \
     do {                                                                               \
-        if (rb == 4) k_residues<4, KG, 1><<<grid, 256, lds, s>>>(a);                   \
+        if (rb == 4 && h.nw32 <= kResRegWords) {                                       \
+            switch (h.nw32) {                                                          \
+                case 1: OZ2H_RES_NW(KG, 1); break;                                     \
+                case 2: OZ2H_RES_NW(KG, 2); break;                                     \
+                case 3: OZ2H_RES_NW(KG, 3); break;                                     \
+                case 4: OZ2H_RES_NW(KG, 4); break;                                     \
+                case 5: OZ2H_RES_NW(KG, 5); break;                                     \
+                case 6: OZ2H_RES_NW(KG, 6); break;                                     \
+                case 7: OZ2H_RES_NW(KG, 7); break;                                     \
+                default: OZ2H_RES_NW(KG, 8); break;                                    \
+            }                                                                          \
+        } else if (rb == 4) k_residues<4, KG, 1><<<grid, 256, lds, s>>>(a);            \
         else if (rb == 2) k_residues<2, KG, 1><<<grid, 128, lds, s>>>(a);              \
         else k_residues<1, KG, 1><<<grid, 64, lds, s>>>(a);                            \
     } while (0)
     if (h.kg == kModGroupWide) OZ2H_RES(kModGroupWide);
     else OZ2H_RES(kModGroup);
 #undef OZ2H_RES
+#undef OZ2H_RES_NW
     return check_launch("residues");
 }
 
@@ -350,6 +365,8 @@ struct RowCrtCfg {
     size_t bytes;
 };
 
+// the row finish kernel carries the top two digit groups exactly and needs a group below them
+static_assert(kCrtRowMinDigits >= 32, "row CRT needs at least three digit groups");
 bool row_crt_eligible(const PlanHost &h) { return h.nd32 > kCrtRowMinDigits && !h.crt_row.empty(); }
 
 RowCrtCfg row_crt_config(const PlanHost &h, int64_t M, int64_t ldv) {

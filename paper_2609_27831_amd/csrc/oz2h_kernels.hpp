@@ -258,7 +258,9 @@ __host__ __device__ constexpr int res_block_k(int rb, int ept) { return 64 * ept
 // not clobber the constant tables and reads those with scalar loads.
 // EPT entries per thread share every constant the thread reads: entry e of a lane is
 // k = kbase + 64 e + lane, its words in the LDS column words + e BD + tid (stride EPT BD).
-template <int RB, int KG, int EPT = 1>
+// NW > 0 (integers of exactly NW words): the words are read from LDS once, as doubles with
+// the entry's sign applied, and stay in registers for every group of moduli.
+template <int RB, int KG, int EPT = 1, int NW = 0>
 __device__ __forceinline__ void residue_block_r(
     const uint64_t *__restrict__ limbs, const int32_t *__restrict__ exps,
     const int8_t *__restrict__ signs, const int32_t *__restrict__ erow,
@@ -308,6 +310,15 @@ __device__ __forceinline__ void residue_block_r(
     const QuadSel qsel = quad_sel(lane);
     const int64_t qoff = (int64_t)(lane & 3) * plane_stride + (int64_t)(loff & ~3u);
     const uint32_t *col = words + tid;
+    double xw[NW > 0 ? NW : 1][EPT];
+    if constexpr (NW > 0) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w)
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) xw[w][e] = (double)col[e * BD + w * ST] * sgn[e];
+    }
+    // the signed integer's multiply-add sum for modulus g of the group
+    auto sacc = [&](const double (&acc)[EPT][KG], int e, int g) { return NW > 0 ? acc[e][g] : acc[e][g] * sgn[e]; };
     for (int grp = 0; grp < lgroups; ++grp) {
         double acc[EPT][KG];
 #pragma unroll
@@ -315,15 +326,26 @@ __device__ __forceinline__ void residue_block_r(
 #pragma unroll
             for (int g = 0; g < KG; ++g) acc[e][g] = 0.0;
         gdouble *c = gtab + (size_t)grp * nw32 * KG;   // uniform: scalar loads
-        for (int w = 0; w < nw32; ++w) {
-            double x[EPT];
+        if constexpr (NW > 0) {
 #pragma unroll
-            for (int e = 0; e < EPT; ++e) x[e] = (double)col[e * BD + w * ST];
+            for (int w = 0; w < NW; ++w)
 #pragma unroll
-            for (int g = 0; g < KG; ++g) {
-                const double cg = c[w * KG + g];
+                for (int g = 0; g < KG; ++g) {
+                    const double cg = c[w * KG + g];
 #pragma unroll
-                for (int e = 0; e < EPT; ++e) acc[e][g] = fma(x[e], cg, acc[e][g]);
+                    for (int e = 0; e < EPT; ++e) acc[e][g] = fma(xw[w][e], cg, acc[e][g]);
+                }
+        } else {
+            for (int w = 0; w < nw32; ++w) {
+                double x[EPT];
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) x[e] = (double)col[e * BD + w * ST];
+#pragma unroll
+                for (int g = 0; g < KG; ++g) {
+                    const double cg = c[w * KG + g];
+#pragma unroll
+                    for (int e = 0; e < EPT; ++e) acc[e][g] = fma(x[e], cg, acc[e][g]);
+                }
             }
         }
         OZ2H_G(ResGroup) *R = grec + grp;
@@ -337,7 +359,7 @@ __device__ __forceinline__ void residue_block_r(
                 int ri[KG];
 #pragma unroll
                 for (int g = 0; g < KG; ++g) {
-                    const double a = acc[e][g] * sgn[e];
+                    const double a = sacc(acc, e, g);
                     ri[g] = (int)fma(-rint(a * R->inv_m[g]), R->md[g], a);
                 }
                 auto store4 = [&](uint32_t gp, int b0, int b1, int b2, int b3) {
@@ -369,7 +391,7 @@ __device__ __forceinline__ void residue_block_r(
             g_i8 *pb = (g_i8 *)planes + (int64_t)R->g0[g] * plane_stride;
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
-                const double a = acc[e][g] * sgn[e];
+                const double a = sacc(acc, e, g);
                 const int ri = (int)fma(-rint(a * R->inv_m[g]), R->md[g], a);
                 const uint32_t lo = loff + 64 * e;
                 if (!((two >> g) & 1u)) {
@@ -386,19 +408,19 @@ __device__ __forceinline__ void residue_block_r(
     }
 }
 
-template <int RB, int KG, int EPT = 1>
+template <int RB, int KG, int EPT = 1, int NW = 0>
 __device__ __forceinline__ void residue_block(const ResArgs &a, int64_t bx, int64_t by,
                                               uint32_t *words) {
-    residue_block_r<RB, KG, EPT>(a.limbs, a.exps, a.signs, a.erow, a.koff, a.tab, a.rgrp, a.planes,
+    residue_block_r<RB, KG, EPT, NW>(a.limbs, a.exps, a.signs, a.erow, a.koff, a.tab, a.rgrp, a.planes,
                                  a.rs, a.cs, a.rows, a.count, a.kpad, a.plane_stride, a.p, a.nl, a.t,
                                  a.nw32, a.L, a.lgroups, bx, by, words);
 }
 
-template <int RB, int KG, int EPT>
+template <int RB, int KG, int EPT, int NW = 0>
 __global__ __launch_bounds__(64 * RB) void k_residues(ResArgs a) {
     extern __shared__ uint32_t words[];
     const int64_t nbx = a.kpad / res_block_k(RB, EPT);
-    residue_block<RB, KG, EPT>(a, (int64_t)blockIdx.x % nbx, (int64_t)blockIdx.x / nbx, words);
+    residue_block<RB, KG, EPT, NW>(a, (int64_t)blockIdx.x % nbx, (int64_t)blockIdx.x / nbx, words);
 }
 
 // lanes of one wave hand data over through LDS: keep the compiler from moving LDS
