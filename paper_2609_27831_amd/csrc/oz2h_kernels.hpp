@@ -1596,16 +1596,22 @@ __device__ __forceinline__ void crt_block(const CrtArgs &a, int64_t blk, uint32_
                 slow[q] = fabs(asum[q] - r) > 0.5 - 0x1p-30;
                 beta[q] = slow[q] ? (int64_t)floor(asum[q]) - 1 : (int64_t)r;   // alpha - 1 when slow
             }
+            // digit k of S - beta P in binary64, exact: |acc| <= L 8095 2^31 < 2^53 - 2^46 for
+            // L <= 512, |beta P_k| < 2^42 and the carry is below 2^22
             uint32_t *sd = col(q);
+            double cy = (double)carry[q];
+            const double bq = (double)beta[q];
 #pragma unroll
             for (int d = 0; d < DC; ++d) {
                 const int k = c * DC + d;
                 if (k < nd32) {
-                    const int64_t x = (int64_t)acc[q][d] - beta[q] * (int64_t)Pd[k] + carry[q];
-                    sd[k * cst] = (uint32_t)x;
-                    carry[q] = x >> 32;
+                    const double x = fma(-bq, (double)Pd[k], acc[q][d] + cy);
+                    const double hi = floor(x * 0x1p-32);
+                    sd[k * cst] = (uint32_t)fma(-hi, 0x1p32, x);
+                    cy = hi;
                 }
             }
+            carry[q] = (int64_t)cy;
         }
     }
 
