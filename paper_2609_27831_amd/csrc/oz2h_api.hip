@@ -1728,15 +1728,24 @@ struct BatchCrtClass {
 // products runs as two chunks on two streams: the second chunk's residues beside the first
 // chunk's GEMMs, its GEMMs beside the first chunk's CRT, so that the matrix cores and the
 // vector ALUs of a compute unit work at the same time.
+// residue launch classes: moduli group width (kModGroup, kModGroupWide) x the word count of
+// integers that stay in registers (1 .. kResRegWords, or 0: LDS words)
+constexpr int kResClasses = 2 * (kResRegWords + 1);
+inline int res_class(int kg, int nw32, int rb) {
+    const int nw = rb == 4 && nw32 <= kResRegWords ? nw32 : 0;
+    return (kg == kModGroupWide ? 1 : 0) * (kResRegWords + 1) + nw;
+}
+
 struct BatchChunk {
     std::vector<int> prods;
     Seg *d_fill_segs = nullptr, *d_exp_segs = nullptr;
     int n_fill_segs = 0, n_exp_segs = 0;
     int64_t fill_blocks = 0, exp_blocks = 0;
-    // residues: one launch per moduli group width (classes kModGroup, kModGroupWide)
-    Seg *d_res_segs[2] = {nullptr, nullptr};
-    int n_res_segs[2] = {0, 0};
-    int64_t res_blocks[2] = {0, 0};
+    // residues: one launch per class (moduli group width, and the word count of integers
+    // that keep their words in registers: res_class)
+    Seg *d_res_segs[kResClasses] = {};
+    int n_res_segs[kResClasses] = {};
+    int64_t res_blocks[kResClasses] = {};
     std::vector<BatchCrtClass> crt;
     // grouped GEMM: one item list (and launch) per block tile class c = oz2h_tile - 1
     GemmItem *d_items[3] = {nullptr, nullptr, nullptr};
@@ -1936,20 +1945,35 @@ int launch_batched_front(oz2h_batched_plan *bp, const BatchChunk &ch, char *ws, 
     }
     int st = check_launch("grouped exponents");
     if (st) return st;
-    for (int c = 0; c < 2; ++c) {
+    for (int c = 0; c < kResClasses; ++c) {
         if (!ch.res_blocks[c]) continue;
         const unsigned nb = (unsigned)ch.res_blocks[c];
         const Seg *sg = ch.d_res_segs[c];
         const int ns = ch.n_res_segs[c];
+        const int nw = c % (kResRegWords + 1);
+#define OZ2H_GRES_NW(KG, NW) k_residues_grouped<4, KG, NW><<<nb, 256, bp->res_lds, s>>>(bp->d_probs, sg, ns, ws)
 #define OZ2H_GRES(KG)                                                                             \
     do {                                                                                          \
-        if (bp->res_rb == 4) k_residues_grouped<4, KG><<<nb, 256, bp->res_lds, s>>>(bp->d_probs, sg, ns, ws); \
-        else if (bp->res_rb == 2) k_residues_grouped<2, KG><<<nb, 128, bp->res_lds, s>>>(bp->d_probs, sg, ns, ws); \
-        else k_residues_grouped<1, KG><<<nb, 64, bp->res_lds, s>>>(bp->d_probs, sg, ns, ws);      \
+        switch (nw) {                                                                             \
+            case 1: OZ2H_GRES_NW(KG, 1); break;                                                   \
+            case 2: OZ2H_GRES_NW(KG, 2); break;                                                   \
+            case 3: OZ2H_GRES_NW(KG, 3); break;                                                   \
+            case 4: OZ2H_GRES_NW(KG, 4); break;                                                   \
+            case 5: OZ2H_GRES_NW(KG, 5); break;                                                   \
+            case 6: OZ2H_GRES_NW(KG, 6); break;                                                   \
+            case 7: OZ2H_GRES_NW(KG, 7); break;                                                   \
+            case 8: OZ2H_GRES_NW(KG, 8); break;                                                   \
+            default:                                                                              \
+                if (bp->res_rb == 4) k_residues_grouped<4, KG><<<nb, 256, bp->res_lds, s>>>(bp->d_probs, sg, ns, ws); \
+                else if (bp->res_rb == 2) k_residues_grouped<2, KG><<<nb, 128, bp->res_lds, s>>>(bp->d_probs, sg, ns, ws); \
+                else k_residues_grouped<1, KG><<<nb, 64, bp->res_lds, s>>>(bp->d_probs, sg, ns, ws); \
+        }                                                                                         \
     } while (0)
-        if (c == 0) OZ2H_GRES(kModGroup);
+        static_assert(kResRegWords == 8, "one case per word count");
+        if (c / (kResRegWords + 1) == 0) OZ2H_GRES(kModGroup);
         else OZ2H_GRES(kModGroupWide);
 #undef OZ2H_GRES
+#undef OZ2H_GRES_NW
         if ((st = check_launch("grouped residues"))) return st;
     }
     return OZ2H_OK;
@@ -2192,7 +2216,7 @@ int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2
     bp->res_rb = maxw <= 64 ? 4 : (maxw <= 128 ? 2 : 1);
     bp->res_lds = (size_t)maxw * 64 * bp->res_rb * sizeof(uint32_t);
     struct ChunkSegs {
-        std::vector<Seg> fill, exp, res[2];
+        std::vector<Seg> fill, exp, res[kResClasses];
         std::vector<std::vector<Seg>> crt;
     };
     std::vector<ChunkSegs> csegs(nchunks);
@@ -2210,14 +2234,15 @@ int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2
                 const int64_t nbk = contig ? (P.K + kExpChunk - 1) / kExpChunk : (P.K + kExpRowsK - 1) / kExpRowsK;
                 cs.exp.push_back(Seg{ch.exp_blocks, b, sd, nbr});
                 ch.exp_blocks += nbr * nbk;
-                const int c = bp->hosts[b].kg == kModGroupWide ? 1 : 0;
+                const int c = res_class(bp->hosts[b].kg, bp->pd[b].nw32, bp->res_rb);
                 const int kw = res_waves_k(bp->res_rb);
                 const int64_t nbx = P.kpad / (64 * kw), nby = P.rpad[sd] / (bp->res_rb / kw);
                 cs.res[c].push_back(Seg{ch.res_blocks[c], b, sd, nbx});
                 ch.res_blocks[c] += nbx * nby;
             }
-        if (ch.exp_blocks > INT32_MAX || ch.res_blocks[0] > INT32_MAX || ch.res_blocks[1] > INT32_MAX)
-            return fail(OZ2H_ERANGE, "batched plan: too many blocks for one launch");
+        bool big = ch.exp_blocks > INT32_MAX;
+        for (int c = 0; c < kResClasses; ++c) big = big || ch.res_blocks[c] > INT32_MAX;
+        if (big) return fail(OZ2H_ERANGE, "batched plan: too many blocks for one launch");
         // CRT classes: (digit chunk, entries per thread, digit columns in LDS or global
         // memory), the same shapes a plain call would take (crt_config); digit chunk -1: the
         // matrix-core CRT, under the rule a plain call applies
@@ -2276,7 +2301,7 @@ int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2
     }
     bp->ws_bytes = w;
     struct ChunkOffs {
-        size_t fill, exp, res[2];
+        size_t fill, exp, res[kResClasses];
         std::vector<size_t> crt;
     };
     std::vector<ChunkOffs> coffs(nchunks);
@@ -2287,7 +2312,7 @@ int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2
         off = align_up(off + sizeof(Seg) * cs.fill.size());
         co.exp = off;
         off = align_up(off + sizeof(Seg) * cs.exp.size());
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < kResClasses; ++c) {
             co.res[c] = off;
             off = align_up(off + sizeof(Seg) * cs.res[c].size());
         }
@@ -2339,7 +2364,7 @@ int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2
             return st;
         ch.n_fill_segs = (int)cs.fill.size();
         ch.n_exp_segs = (int)cs.exp.size();
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < kResClasses; ++c) {
             if ((st = put(&ch.d_res_segs[c], co.res[c], cs.res[c]))) return st;
             ch.n_res_segs[c] = (int)cs.res[c].size();
         }

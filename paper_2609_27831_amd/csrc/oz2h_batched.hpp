@@ -124,7 +124,7 @@ __device__ __forceinline__ ResArgs res_args(const ProbDev &P, int side, char *ws
 
 // stage 2, grouped: segment (prod, side) is a (kpad / (64 KW)) x (rpad / (RB / KW)) grid of
 // blocks, KW = res_waves_k(RB); one launch per moduli group width KG (the plans' kg)
-template <int RB, int KG>
+template <int RB, int KG, int NW = 0>
 __global__ __launch_bounds__(64 * RB) void k_residues_grouped(const ProbDev *__restrict__ probs,
                                                               const Seg *__restrict__ segs,
                                                               int nseg, char *ws) {
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(64 * RB) void k_residues_grouped(const ProbDev *__r
     const Seg sg = segs[si];
     const int64_t lb = (int64_t)blockIdx.x - sg.first;
     const ResArgs a = res_args(probs[sg.prod], sg.side, ws);
-    residue_block<RB, KG>(a, lb % sg.nbx, lb / sg.nbx, words);
+    residue_block<RB, KG, 1, NW>(a, lb % sg.nbx, lb / sg.nbx, words);
 }
 
 // one work item of the grouped GEMM: output tile (mt, nt) of modulus l of product prod
