@@ -1859,9 +1859,12 @@ __global__ __launch_bounds__(256) void k_crt_row_sums(CrtRowArgs a) {
     // bytes; nent is a multiple of 64 and the launch checks that every plane holds nent
     // entries), loaded one chunk ahead; the 16 digit constants of this lane's digit from LDS
     // (zero past L)
+    // plane addresses: the chunk's offset 16 c v_ps is wave-uniform (scalar arithmetic); a lane
+    // past the last modulus reads the last plane
+    const int16_t *vj = a.V + (int64_t)j * a.v_ps + e_row;
+    const int16_t *vlast = a.V + (int64_t)(a.L - 1) * a.v_ps + e_row;
     auto loadv = [&](int c, v4i &w0, v4i &w1) {
-        const int lc = min(16 * c + j, a.L - 1);
-        gv4i *src = (gv4i *)(a.V + (int64_t)lc * a.v_ps + e_row);
+        gv4i *src = (gv4i *)(16 * c + j < a.L ? vj + (int64_t)(16 * c) * a.v_ps : vlast);
         w0 = src[0];
         w1 = src[1];
     };
