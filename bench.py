@@ -22,7 +22,7 @@ p = 2048 bits (exponents uniform in [-16, 16]), and carries as extra keys:
   - the oracle on the host cores over a bounded block of outputs, which also
     checks the timed GPU output on that block bit for bit.
 
-  python bench.py [--steps K] [--warmup W] [--config cfg3|cfg1|cfg2|cfg3a|cfg3b|cfg4|cfg5|complex|backends]
+  python bench.py [--steps K] [--warmup W] [--config cfg3|cfg1|cfg2|cfg3a|cfg3b|cfg4|cfg5|complex|backends|gemm_context]
                   [--cpu-seconds S] [--no-cpu-baseline] [--no-extras]
 
 Per-stage times come from HIP events that the library records on the launch
@@ -642,6 +642,40 @@ def measure_operand_reuse(steps, warmup):
             "ms_per_product_amortized": round(out["reuse"] / nrhs, 4), "bit_identical": same}
 
 
+def measure_int8_gemm_context(steps, warmup):
+    """Context for the residue-GEMM roofline: the raw INT8 core (oz2h_i8gemm, int8 A [M][K] and
+    B [N][K], exact int32 C) against the vendor library's int8 GEMM (torch._int_mm, which
+    dispatches to hipBLASLt) on the same 8192^3 operands in the same k-contiguous layout."""
+    import torch
+
+    from paper_2609_27831_amd import oz2h
+    n = 8192
+    g = torch.Generator(device="cuda").manual_seed(20260901)
+    A = torch.randint(-127, 128, (n, n), dtype=torch.int8, device="cuda", generator=g)
+    Bt = torch.randint(-127, 128, (n, n), dtype=torch.int8, device="cuda", generator=g)   # [N][K]
+
+    def timed(fn):
+        for _ in range(max(warmup, 1)):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    tile = oz2h.TILE_256x128   # the residue GEMMs' block tile at these sizes
+    ms_core = timed(lambda: oz2h.i8gemm(A, Bt, tile))
+    ms_lib = timed(lambda: torch._int_mm(A, Bt.t()))
+    same = bool(torch.equal(oz2h.i8gemm(A, Bt, tile), torch._int_mm(A, Bt.t())))
+    ops = 2.0 * n ** 3
+    return {"workload": "int8 C = A B^T, M=N=K=8192, exact int32 results, B k-contiguous; "
+                        "the core with the 256 x 128 block tile",
+            "oz2h_i8gemm_ms": round(ms_core, 4), "oz2h_i8gemm_tops": round(ops / ms_core / 1e9, 1),
+            "library_int_mm_ms": round(ms_lib, 4), "library_int_mm_tops": round(ops / ms_lib / 1e9, 1),
+            "same_results": same}
+
+
 def copy_calibration():
     """A plain device copy of known size, for the HBM-counter scale factors."""
     import torch
@@ -664,7 +698,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="cfg3",
-                    choices=sorted(CONFIGS) + ["cfg3", "cfg4", "cfg5", "complex", "backends"])
+                    choices=sorted(CONFIGS) + ["cfg3", "cfg4", "cfg5", "complex", "backends", "gemm_context"])
     ap.add_argument("--flags", type=int, default=0,
                     help="OZ2H_FLAG_* bits of the timed plain products (default 0: MFMA-free "
                          "stages 2 and 4)")
@@ -690,6 +724,13 @@ def main():
     base = {"metric": METRIC, "unit": "GFlop/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "i8", "data": "synthetic"}
+
+    if args.config == "gemm_context":
+        r = measure_int8_gemm_context(args.steps, args.warmup)
+        line = dict(base, value=r["oz2h_i8gemm_tops"], unit="TOP/s", ms_per_step=r["oz2h_i8gemm_ms"],
+                    config={"workload": r.pop("workload")}, **r)
+        print(json.dumps(line), flush=True)
+        return
 
     if args.config in ("cfg4", "cfg5", "complex", "backends"):
         log(f"{args.config}")
@@ -763,6 +804,9 @@ def main():
         torch.cuda.empty_cache()
         log("operand reuse: residue handles against plain calls")
         line["operand_reuse"] = measure_operand_reuse(max(2, args.steps // 2), 1)
+        torch.cuda.empty_cache()
+        log("int8 GEMM context: raw core against the library")
+        line["int8_gemm_context"] = measure_int8_gemm_context(args.steps, 2)
     print(json.dumps(line), flush=True)
 
 
