@@ -261,7 +261,11 @@ int launch_residues(const oz2h_plan *pl, int64_t rows, int64_t count, const uint
                 case 5: OZ2H_RES_NW(KG, 5); break;                                     \
                 case 6: OZ2H_RES_NW(KG, 6); break;                                     \
                 case 7: OZ2H_RES_NW(KG, 7); break;                                     \
-                default: OZ2H_RES_NW(KG, 8); break;                                    \
+                case 8: OZ2H_RES_NW(KG, 8); break;                                     \
+                case 9: OZ2H_RES_NW(KG, 9); break;                                     \
+                case 10: OZ2H_RES_NW(KG, 10); break;                                     \
+                case 11: OZ2H_RES_NW(KG, 11); break;                                     \
+                default: OZ2H_RES_NW(KG, 12); break;                                   \
             }                                                                          \
         } else if (rb == 4) k_residues<4, KG, 1><<<grid, 256, lds, s>>>(a);            \
         else if (rb == 2) k_residues<2, KG, 1><<<grid, 128, lds, s>>>(a);              \
@@ -1963,13 +1967,17 @@ int launch_batched_front(oz2h_batched_plan *bp, const BatchChunk &ch, char *ws, 
             case 6: OZ2H_GRES_NW(KG, 6); break;                                                   \
             case 7: OZ2H_GRES_NW(KG, 7); break;                                                   \
             case 8: OZ2H_GRES_NW(KG, 8); break;                                                   \
+            case 9: OZ2H_GRES_NW(KG, 9); break;                                                   \
+            case 10: OZ2H_GRES_NW(KG, 10); break;                                                   \
+            case 11: OZ2H_GRES_NW(KG, 11); break;                                                   \
+            case 12: OZ2H_GRES_NW(KG, 12); break;                                                   \
             default:                                                                              \
                 if (bp->res_rb == 4) k_residues_grouped<4, KG><<<nb, 256, bp->res_lds, s>>>(bp->d_probs, sg, ns, ws); \
                 else if (bp->res_rb == 2) k_residues_grouped<2, KG><<<nb, 128, bp->res_lds, s>>>(bp->d_probs, sg, ns, ws); \
                 else k_residues_grouped<1, KG><<<nb, 64, bp->res_lds, s>>>(bp->d_probs, sg, ns, ws); \
         }                                                                                         \
     } while (0)
-        static_assert(kResRegWords == 8, "one case per word count");
+        static_assert(kResRegWords == 12, "one case per word count");
         if (c / (kResRegWords + 1) == 0) OZ2H_GRES(kModGroup);
         else OZ2H_GRES(kModGroupWide);
 #undef OZ2H_GRES

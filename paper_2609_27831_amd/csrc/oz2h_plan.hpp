@@ -15,7 +15,7 @@ constexpr int kResMmaMinWords = 8;    // with the matrix-core residue variant se
                                       // of >= this many 32-bit words (t >= 224) take it, narrower
                                       // ones the fp64 kernel
 constexpr int kResRowMinWords = 32;  // VALU residues: integers of >= this many words (t >= 992)
-constexpr int kResRegWords = 8;      // VALU residues: integers of <= this many words stay in registers
+constexpr int kResRegWords = 12;     // VALU residues: integers of <= this many words stay in registers
                                       // take the row-broadcast kernel (faster from about there
                                       // on at 4096^2), narrower ones the entry-per-thread kernel
 constexpr int kCrtRowMinDigits = 32;  // CRTs of more digits take the row-broadcast kernels
