@@ -522,21 +522,28 @@ int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2
 size_t oz2h_batched_workspace_size(const oz2h_batched_plan *plan);
 /*
  * Autotuner: times whole runs for every block tile setting of the grouped GEMM
- * (per product as plain calls choose, or 128x128, 256x128, 128x256 for all)
- * and every persistent schedule (1, 2
- * or 4 resident blocks per compute unit, or one block per work item), keeps the fastest and records it in
- * an in-process cache keyed by the batch's shapes (and, if the environment
- * variable OZ2H_TUNE_CACHE names a file, appends it there; plans created later
- * with OZ2H_TILE_AUTO pick it up).  Synchronizes `stream`; the runs write the
- * outputs C (with the product's results).
+ * (per product as plain calls choose, or 128x128, 256x128, 128x256 for all),
+ * every persistent schedule (1, 2 or 4 resident blocks per compute unit, or one
+ * block per work item) and both GEMM LDS depths (three stages, or two, which
+ * leave room on a compute unit for the other chunk's residue and CRT blocks),
+ * keeps the fastest, then times it replayed as a HIP graph against the same
+ * launches issued directly and keeps the faster mode for oz2h_batched_run.  The
+ * result goes to an in-process cache keyed by the batch's shapes (and, if the
+ * environment variable OZ2H_TUNE_CACHE names a file, is appended there, one line
+ * "signature tile blocks_per_cu stages graph"; plans created later with
+ * OZ2H_TILE_AUTO pick it up).  Synchronizes `stream`; the runs write the outputs
+ * C (with the product's results).
  */
 int oz2h_batched_tune(oz2h_batched_plan *plan, void *workspace, size_t ws_bytes,
                       hipStream_t stream);
 /*
- * Runs the whole batch as a HIP graph: the launch sequence is captured on a
- * private stream at the first call (and again whenever the workspace pointer or
- * the configuration changes) and replayed on `stream`.  Asynchronous.
- * Runs of one plan must not overlap (they share the workspace and outputs).
+ * Runs the whole batch.  In graph mode (the default, and the tuner's choice when it
+ * measured replay faster) the launch sequence is captured on a private stream at
+ * the first call (and again whenever the workspace pointer or the configuration
+ * changes) and replayed on `stream`; otherwise the launches are issued directly on
+ * `stream` (and on a second stream for the second chunk, joined by events), as
+ * oz2h_batched_run_eager does.  Asynchronous.  Runs of one plan must not overlap
+ * (they share the workspace and outputs).
  */
 int oz2h_batched_run(oz2h_batched_plan *plan, void *workspace, size_t ws_bytes,
                      hipStream_t stream);
@@ -550,6 +557,10 @@ int oz2h_batched_get_config(const oz2h_batched_plan *plan, int32_t *tile, int32_
                             int64_t *gemm_items);
 /* Sets the tile setting (0..3) and blocks per compute unit (0..16) by hand. */
 int oz2h_batched_set_config(oz2h_batched_plan *plan, int32_t tile, int32_t blocks_per_cu);
+/* LDS stages of the grouped GEMM (2 or 3) and the mode of oz2h_batched_run (1: graph
+   replay, 0: direct launches); the setter takes the same values, OZ2H_EINVAL otherwise. */
+int oz2h_batched_get_schedule(const oz2h_batched_plan *plan, int32_t *gemm_stages, int32_t *graph);
+int oz2h_batched_set_schedule(oz2h_batched_plan *plan, int32_t gemm_stages, int32_t graph);
 void oz2h_batched_plan_destroy(oz2h_batched_plan *plan);
 
 #ifdef __cplusplus

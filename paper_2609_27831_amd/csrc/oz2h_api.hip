@@ -1773,6 +1773,10 @@ struct oz2h_batched_plan {
     // would choose for it) and resident blocks per compute unit (0: one block per item)
     int tile = OZ2H_TILE_128x128;
     int bpc = 2;
+    // GEMM LDS stages (2 leaves room on a compute unit for the other chunk's residue and CRT
+    // blocks) and whether oz2h_batched_run replays a graph or launches directly
+    int stages = 3;
+    bool use_graph = true;
     size_t ws_bytes = 0;
     // the second chunk's stream and the events that order the two chunks
     hipStream_t side = nullptr;
@@ -1799,7 +1803,10 @@ uint64_t fnv1a(const void *data, size_t n, uint64_t h = 1469598103934665603ull) 
 // autotuner cache: shape signature -> (tile, blocks per CU); optionally mirrored in the
 // text file named by OZ2H_TUNE_CACHE (one "signature tile bpc" line per entry)
 std::mutex g_tune_mu;
-std::map<uint64_t, std::pair<int, int>> g_tune;
+struct TuneRec {
+    int tile, bpc, stages, graph;
+};
+std::map<uint64_t, TuneRec> g_tune;
 bool g_tune_loaded = false;
 
 void tune_load() {
@@ -1808,17 +1815,24 @@ void tune_load() {
     const char *path = getenv("OZ2H_TUNE_CACHE");
     if (!path) return;
     std::ifstream in(path);
-    uint64_t sig;
-    int tile, bpc;
-    while (in >> std::hex >> sig >> std::dec >> tile >> bpc) g_tune[sig] = {tile, bpc};
+    std::string line;
+    while (std::getline(in, line)) {   // signature tile bpc [stages graph]
+        std::istringstream ls(line);
+        uint64_t sig;
+        TuneRec r{OZ2H_TILE_AUTO, 0, 3, 1};
+        if (!(ls >> std::hex >> sig >> std::dec >> r.tile >> r.bpc)) continue;
+        if (!(ls >> r.stages >> r.graph)) r.stages = 3, r.graph = 1;
+        g_tune[sig] = r;
+    }
 }
 
-void tune_store(uint64_t sig, int tile, int bpc) {
-    g_tune[sig] = {tile, bpc};
+void tune_store(uint64_t sig, const TuneRec &r) {
+    g_tune[sig] = r;
     const char *path = getenv("OZ2H_TUNE_CACHE");
     if (!path) return;
     std::ofstream out(path, std::ios::app);
-    out << std::hex << sig << std::dec << " " << tile << " " << bpc << "\n";
+    out << std::hex << sig << std::dec << " " << r.tile << " " << r.bpc << " " << r.stages << " " << r.graph
+        << "\n";
 }
 
 // work items of the grouped GEMM for a tile shape, heaviest first (two-limb moduli and
@@ -1928,9 +1942,15 @@ int launch_batched_gemm(oz2h_batched_plan *bp, const BatchChunk &ch, char *ws, h
         // bpc > 0: a persistent grid of bpc blocks per compute unit; bpc = 0: one block per item
         const int grid = bp->bpc > 0 ? (int)std::min<int64_t>(n, (int64_t)bp->ncu * bp->bpc) : n;
         const GemmItem *it = ch.d_items[c];
-        if (c == OZ2H_TILE_256x128 - 1) k_resgemm_grouped<128, 64><<<grid, 256, 0, s>>>(bp->d_probs, it, n, ws);
-        else if (c == OZ2H_TILE_128x256 - 1) k_resgemm_grouped<64, 128><<<grid, 256, 0, s>>>(bp->d_probs, it, n, ws);
-        else k_resgemm_grouped<64, 64><<<grid, 256, 0, s>>>(bp->d_probs, it, n, ws);
+#define OZ2H_GG(NS)                                                                                   \
+    do {                                                                                              \
+        if (c == OZ2H_TILE_256x128 - 1) k_resgemm_grouped<128, 64, NS><<<grid, 256, 0, s>>>(bp->d_probs, it, n, ws); \
+        else if (c == OZ2H_TILE_128x256 - 1) k_resgemm_grouped<64, 128, NS><<<grid, 256, 0, s>>>(bp->d_probs, it, n, ws); \
+        else k_resgemm_grouped<64, 64, NS><<<grid, 256, 0, s>>>(bp->d_probs, it, n, ws);          \
+    } while (0)
+        if (bp->stages == 2) OZ2H_GG(2);
+        else OZ2H_GG(3);
+#undef OZ2H_GG
         int st = check_launch("grouped residue GEMM");
         if (st) return st;
     }
@@ -2399,8 +2419,10 @@ int oz2h_batched_plan_create(int32_t count, const oz2h_problem *probs, const oz2
         tune_load();
         auto it = g_tune.find(bp->signature);
         if (it != g_tune.end() && o->tile == OZ2H_TILE_AUTO) {
-            bp->tile = it->second.first;
-            bp->bpc = it->second.second;
+            bp->tile = it->second.tile;
+            bp->bpc = it->second.bpc;
+            bp->stages = it->second.stages;
+            bp->use_graph = it->second.graph != 0;
         }
     }
     if ((st = upload_items(bp.get()))) return st;
@@ -2448,6 +2470,10 @@ int oz2h_batched_run_eager(oz2h_batched_plan *plan, void *ws, size_t ws_bytes, h
 int oz2h_batched_run(oz2h_batched_plan *plan, void *ws, size_t ws_bytes, hipStream_t stream) {
     int st = check_batched_run(plan, ws, ws_bytes);
     if (st) return st;
+    if (!plan->use_graph) {   // the tuner measured direct launches faster
+        st = launch_batched_all(plan, (char *)ws, stream);
+        return st ? st : ok();
+    }
     if (!plan->exec || plan->cap_ws != ws) {
         drop_graph(plan);
         OZ2H_HIP(hipStreamBeginCapture(plan->cap, hipStreamCaptureModeThreadLocal));
@@ -2472,48 +2498,83 @@ int oz2h_batched_tune(oz2h_batched_plan *plan, void *ws, size_t ws_bytes, hipStr
     if (st) return st;
     // each candidate is timed over whole runs (with two chunks the GEMMs share the compute
     // units with the other chunk's residues and CRT, so a GEMM timed alone would mislead)
-    auto gemm_all = [&]() { return launch_batched_all(plan, (char *)ws, stream); };
     hipEvent_t e0, e1;
     OZ2H_HIP(hipEventCreate(&e0));
     OZ2H_HIP(hipEventCreate(&e1));
+    auto time_runs = [&](auto run, float &acc) {
+        if ((st = run())) return;   // warm-up (and graph capture)
+        acc = 0;
+        for (int rep = 0; rep < 5 && !st; ++rep) {
+            (void)hipEventRecord(e0, stream);
+            st = run();
+            (void)hipEventRecord(e1, stream);
+            if (hipEventSynchronize(e1) != hipSuccess) st = fail(OZ2H_EDEVICE, "tuning run failed");
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            acc += ms;
+        }
+    };
+    auto direct = [&]() { return launch_batched_all(plan, (char *)ws, stream); };
     float best = 1e30f;
-    int bt = plan->tile, bb = plan->bpc;
+    TuneRec b{plan->tile, plan->bpc, plan->stages, 1};
     const int tiles[4] = {OZ2H_TILE_AUTO, OZ2H_TILE_128x128, OZ2H_TILE_256x128, OZ2H_TILE_128x256};
     const int bpcs[4] = {1, 2, 4, 0};
-    for (int ti : tiles)
-        for (int bc : bpcs) {
-            plan->tile = ti;
-            plan->bpc = bc;
-            if ((st = upload_items(plan))) break;
-            if ((st = gemm_all())) break;   // warm-up
-            float acc = 0;
-            for (int rep = 0; rep < 3 && !st; ++rep) {
-                (void)hipEventRecord(e0, stream);
-                st = gemm_all();
-                (void)hipEventRecord(e1, stream);
-                if (hipEventSynchronize(e1) != hipSuccess) st = fail(OZ2H_EDEVICE, "tuning run failed");
-                float ms = 0;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                acc += ms;
+    const int stage_counts[2] = {3, 2};
+    for (int ns : stage_counts)
+        for (int ti : tiles)
+            for (int bc : bpcs) {
+                if (st) break;
+                plan->tile = ti;
+                plan->bpc = bc;
+                plan->stages = ns;
+                if ((st = upload_items(plan))) break;
+                float acc = 0;
+                time_runs(direct, acc);
+                if (!st && acc < best) {
+                    best = acc;
+                    b = TuneRec{ti, bc, ns, 1};
+                }
             }
-            if (st) break;
-            if (acc < best) {
-                best = acc;
-                bt = ti;
-                bb = bc;
-            }
-        }
+    if (!st) {
+        plan->tile = b.tile;
+        plan->bpc = b.bpc;
+        plan->stages = b.stages;
+        drop_graph(plan);
+        st = upload_items(plan);
+    }
+    if (!st) {   // the winner replayed as a graph against the same launches issued directly
+        plan->use_graph = true;
+        float g = 0;
+        time_runs([&]() { return oz2h_batched_run(plan, ws, ws_bytes, stream); }, g);
+        float d = 0;
+        if (!st) time_runs(direct, d);
+        b.graph = st || g <= d ? 1 : 0;
+        plan->use_graph = b.graph != 0;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st) return st;
-    plan->tile = bt;
-    plan->bpc = bb;
-    drop_graph(plan);
-    if ((st = upload_items(plan))) return st;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        tune_store(plan->signature, bt, bb);
+        tune_store(plan->signature, b);
     }
+    return ok();
+}
+
+int oz2h_batched_get_schedule(const oz2h_batched_plan *plan, int32_t *gemm_stages, int32_t *graph) {
+    if (!plan) return fail(OZ2H_EINVAL, "plan is NULL");
+    if (gemm_stages) *gemm_stages = plan->stages;
+    if (graph) *graph = plan->use_graph ? 1 : 0;
+    return ok();
+}
+
+int oz2h_batched_set_schedule(oz2h_batched_plan *plan, int32_t gemm_stages, int32_t graph) {
+    if (!plan) return fail(OZ2H_EINVAL, "plan is NULL");
+    if ((gemm_stages != 2 && gemm_stages != 3) || (graph != 0 && graph != 1))
+        return fail(OZ2H_EINVAL, "gemm_stages must be 2 or 3 and graph 0 or 1");
+    if (gemm_stages != plan->stages) drop_graph(plan);
+    plan->stages = gemm_stages;
+    plan->use_graph = graph != 0;
     return ok();
 }
 

@@ -145,7 +145,7 @@ constexpr uint16_t kSkipItem = 0xFFFF;
 
 // stage 3, persistent grouped launch: a grid of a few blocks per compute unit
 // walks the cost-sorted item list with a grid stride
-template <int WM, int WN>
+template <int WM, int WN, int NS = 3>
 __global__ __launch_bounds__(256) void k_resgemm_grouped(const ProbDev *__restrict__ probs,
                                                          const GemmItem *__restrict__ items,
                                                          int nitems, char *ws) {
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(256) void k_resgemm_grouped(const ProbDev *__restri
                          P.kpad, P.rpad[0] * P.kpad, P.rpad[1] * P.kpad, P.mi,
                          (int16_t *)(ws + P.v_off), P.rpad[0] * P.rpad[1], P.rpad[1], nullptr};
         __syncthreads();   // the previous item's LDS tiles are no longer read
-        gemm_tile<WM, WN, false>(g, it.mt, it.nt, it.l);
+        gemm_tile<WM, WN, false, NS>(g, it.mt, it.nt, it.l);
     }
 }
 

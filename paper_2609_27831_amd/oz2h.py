@@ -115,6 +115,8 @@ SIGNATURES = {
     "oz2h_batched_run_eager": (ctypes.c_int, [_P, _P, _SZ, _P]),
     "oz2h_batched_get_config": (ctypes.c_int, [_P, _P, _P, _P]),
     "oz2h_batched_set_config": (ctypes.c_int, [_P, _I32, _I32]),
+    "oz2h_batched_get_schedule": (ctypes.c_int, [_P, _P, _P]),
+    "oz2h_batched_set_schedule": (ctypes.c_int, [_P, _I32, _I32]),
     "oz2h_batched_plan_destroy": (None, [_P]),
 }
 
@@ -680,10 +682,16 @@ class BatchedPlan:
         t, bc, n = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
         _check(lib().oz2h_batched_get_config(self.handle, ctypes.addressof(t), ctypes.addressof(bc),
                                              ctypes.addressof(n)))
-        return {"tile": t.value, "blocks_per_cu": bc.value, "gemm_items": n.value}
+        ns, g = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().oz2h_batched_get_schedule(self.handle, ctypes.addressof(ns), ctypes.addressof(g)))
+        return {"tile": t.value, "blocks_per_cu": bc.value, "gemm_items": n.value,
+                "gemm_stages": ns.value, "graph": bool(g.value)}
 
     def set_config(self, tile: int, blocks_per_cu: int):
         _check(lib().oz2h_batched_set_config(self.handle, tile, blocks_per_cu))
+
+    def set_schedule(self, gemm_stages: int, graph: bool):
+        _check(lib().oz2h_batched_set_schedule(self.handle, gemm_stages, int(graph)))
 
     def destroy(self):
         if self.handle:

@@ -102,6 +102,39 @@ def test_batched_tiles_and_schedules(oz, tile, bpc):
             assert np.array_equal(a, b), f"product {i}"
 
 
+@pytest.mark.parametrize("stages,graph", [(2, True), (2, False), (3, False)])
+def test_batched_gemm_stages_and_run_mode(oz, stages, graph):
+    """The two-stage grouped GEMM and the direct-launch mode of oz2h_batched_run give the
+    plain calls' results bit for bit (two runs in a row, the second after a schedule change
+    back and forth)."""
+    import torch
+    batch = make_batch(17, 10, 100, 700, ps=(53, 113, 512))
+    probs = [(dev_mp(A), dev_mp(B), oz.empty_mp(A.shape[0], B.shape[1], A.p), 0, 0) for A, B in batch]
+    bp = oz.BatchedPlan(probs)
+    bp.set_schedule(stages, graph)
+    cfg = bp.config()
+    assert cfg["gemm_stages"] == stages and cfg["graph"] == graph
+    ws = bp.workspace()
+    print(f"batched stages={stages} graph={graph}", cfg, flush=True)
+    ref = []
+    for Ad, Bd, _, _, _ in probs:
+        Cp = oz.gemm(oz.Plan.create(Ad.p, Ad.shape[1]), Ad, Bd)
+        torch.cuda.synchronize()
+        ref.append(_host(Cp))
+    for rep in range(2):
+        if rep:
+            bp.set_schedule(5 - stages, not graph)
+            bp.set_schedule(stages, graph)
+        bp.run(ws)
+        torch.cuda.synchronize()
+        for i, (_, _, C, _, _) in enumerate(probs):
+            for a, b in zip(_host(C), ref[i]):
+                assert np.array_equal(a, b), f"run {rep} product {i}"
+    with pytest.raises(oz.Oz2hError):
+        bp.set_schedule(4, True)
+    bp.destroy()
+
+
 def test_batched_autotune(oz):
     import torch
     batch = make_batch(13, 8, 64, 512)
@@ -111,6 +144,7 @@ def test_batched_autotune(oz):
     cfg = bp.tune(ws)
     print("tuned", cfg, flush=True)
     assert cfg["tile"] in (0, 1, 2, 3) and cfg["blocks_per_cu"] in (0, 1, 2, 4)
+    assert cfg["gemm_stages"] in (2, 3)
     bp.run(ws)
     torch.cuda.synchronize()
     for i, (Ad, Bd, C, _, _) in enumerate(probs):
@@ -120,7 +154,9 @@ def test_batched_autotune(oz):
             assert np.array_equal(a, b)
     # a second plan with the same shapes picks the tuned configuration up
     bp2 = oz.BatchedPlan(probs)
-    assert bp2.config()["tile"] == cfg["tile"] and bp2.config()["blocks_per_cu"] == cfg["blocks_per_cu"]
+    c2 = bp2.config()
+    assert c2["tile"] == cfg["tile"] and c2["blocks_per_cu"] == cfg["blocks_per_cu"]
+    assert c2["gemm_stages"] == cfg["gemm_stages"] and c2["graph"] == cfg["graph"]
 
 
 def test_batched_full_workload(oz, c_oracle):
