@@ -92,25 +92,13 @@ __global__ __launch_bounds__(256) void k_exp_scan_grouped(const ProbDev *__restr
         const int lane = threadIdx.x & 63;
         const int64_t r = rb * 4 + (threadIdx.x >> 6);
         if (r >= rows) return;   // whole wave
-        const int64_t k0 = kb * kExpChunk, k1 = min(K, k0 + kExpChunk);
-        for (int64_t k = k0 + lane; k < k1; k += 64) {
-            const int64_t idx = r * rs + k;
-            if (sign[idx]) m = max(m, exps[idx]);
-        }
-        for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off));
+        const int64_t k0 = kb * kExpChunk;
+        m = exp_max_wave(sign, exps, nullptr, r * rs, k0, min(K, k0 + kExpChunk), lane);
         if (lane == 0 && m != INT_MIN) atomicMax(out + r, m);
     } else {
         const int64_t r = rb * 256 + threadIdx.x;
         if (r >= rows) return;
-        const int64_t k0 = kb * kExpRowsK;
-#pragma unroll
-        for (int u = 0; u < kExpRowsK; ++u) {
-            const int64_t k = k0 + u;
-            if (k < K) {
-                const int64_t idx = r * rs + k * cs;
-                if (sign[idx]) m = max(m, exps[idx]);
-            }
-        }
+        m = exp_max_thread(sign, exps, nullptr, r * rs, cs, kb * kExpRowsK, K);
         if (m != INT_MIN) atomicMax(out + r, m);
     }
 }

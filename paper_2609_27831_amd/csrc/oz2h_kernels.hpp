@@ -35,6 +35,47 @@ __global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
+// Largest exponent of the nonzero entries of one contiguous stretch [k0, k1) of a row (base
+// offset rb), over a wave: lane reads k0 + lane + 64 u.  Every load is issued before any is
+// used: entries past k1 read entry k0 (always in range) and are ignored, and the exponent is
+// read whatever the sign.  INT_MIN when the stretch has no nonzero entry.
+__device__ __forceinline__ int exp_max_wave(const int8_t *__restrict__ sign, const int32_t *__restrict__ exps,
+                                            const int32_t *__restrict__ koff, int64_t rb, int64_t k0,
+                                            int64_t k1, int lane) {
+    constexpr int U = kExpChunk / 64;
+    int sg[U], ex[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t k = k0 + lane + 64 * u;
+        const int64_t kk = k < k1 ? k : k0;
+        sg[u] = k < k1 ? sign[rb + kk] : 0;
+        ex[u] = exps[rb + kk] + (koff ? koff[kk] : 0);
+    }
+    int m = INT_MIN;
+#pragma unroll
+    for (int u = 0; u < U; ++u) m = sg[u] ? max(m, ex[u]) : m;
+    for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off));
+    return m;
+}
+
+// The same for one thread over kExpRowsK entries k0 .. of a row with entry stride cs.
+__device__ __forceinline__ int exp_max_thread(const int8_t *__restrict__ sign, const int32_t *__restrict__ exps,
+                                              const int32_t *__restrict__ koff, int64_t rb, int64_t cs,
+                                              int64_t k0, int64_t count) {
+    int sg[kExpRowsK], ex[kExpRowsK];
+#pragma unroll
+    for (int u = 0; u < kExpRowsK; ++u) {
+        const int64_t k = k0 + u;
+        const int64_t kk = k < count ? k : k0;
+        sg[u] = k < count ? sign[rb + kk * cs] : 0;
+        ex[u] = exps[rb + kk * cs] + (koff ? koff[kk] : 0);
+    }
+    int m = INT_MIN;
+#pragma unroll
+    for (int u = 0; u < kExpRowsK; ++u) m = sg[u] ? max(m, ex[u]) : m;
+    return m;
+}
+
 // rows whose entries are contiguous along the contraction (cs == 1): one wave
 // per (row, kExpChunk-entry chunk), lanes stride 1, partial maxima combined by atomicMax
 // koff (nullable): a per-contraction-index exponent offset added before the max
@@ -48,13 +89,7 @@ __global__ __launch_bounds__(256) void k_exp_kcontig(const int8_t *__restrict__ 
     const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (r >= rows) return;
     const int64_t k0 = (int64_t)blockIdx.y * kExpChunk;
-    const int64_t k1 = min(count, k0 + kExpChunk);
-    int m = INT_MIN;
-    for (int64_t k = k0 + lane; k < k1; k += 64) {
-        const int64_t idx = r * rs + k;
-        if (sign[idx]) m = max(m, exps[idx] + (koff ? koff[k] : 0));
-    }
-    for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off));
+    int m = exp_max_wave(sign, exps, koff, r * rs, k0, min(count, k0 + kExpChunk), lane);
     if (lane == 0 && m != INT_MIN) atomicMax(out + r, m);
 }
 
@@ -67,16 +102,7 @@ __global__ __launch_bounds__(256) void k_exp_generic(const int8_t *__restrict__ 
                                                      int32_t *__restrict__ out) {
     const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (r >= rows) return;
-    const int64_t k0 = (int64_t)blockIdx.y * kExpRowsK;
-    int m = INT_MIN;
-#pragma unroll
-    for (int u = 0; u < kExpRowsK; ++u) {
-        const int64_t k = k0 + u;
-        if (k < count) {
-            const int64_t idx = r * rs + k * cs;
-            if (sign[idx]) m = max(m, exps[idx] + (koff ? koff[k] : 0));
-        }
-    }
+    const int m = exp_max_thread(sign, exps, koff, r * rs, cs, (int64_t)blockIdx.y * kExpRowsK, count);
     if (m != INT_MIN) atomicMax(out + r, m);
 }
 
