@@ -87,6 +87,26 @@ def test_residue_planes(oz, c_oracle, p, lo, hi, side, flags):
                          f"p={p} side={side} flags={flags}")
 
 
+# the lowest and highest p of every word count 1 .. 13 at K = 150 (t = p + 16 + 8): integers of
+# up to 12 words keep their words in registers, one kernel per word count; 13 words take the
+# kernel with LDS words
+_WORD_P = [p for w in range(1, 14) for p in (max(2, 32 * w - 56), 32 * w - 25)]
+
+
+@pytest.mark.parametrize("p", _WORD_P)
+def test_residue_planes_every_word_count(oz, c_oracle, p):
+    """Stage 2 against the oracle's integers for every word count of the narrow kernel, on
+    both operand sides, with exponents spread over +-40 (shifts across word boundaries)."""
+    side = "A" if (p // 32) % 2 else "B"
+    R, C = (70, 150) if side == "A" else (150, 70)
+    K = C if side == "A" else R
+    plan = oz.Plan.create(p, K)
+    assert plan.nw32 == -(-(p + 16 + 8 + 1) // 32)
+    X = synth.mp_random(97 + p, R, C, p, -40, 40)
+    X.sign[rng_idx(R, C, 0.07, p)] = 0
+    check_residue_planes(oz, c_oracle, plan, X, side, K, f"p={p} side={side} words={plan.nw32}")
+
+
 def test_residue_planes_wide_set_narrow_integers(oz, c_oracle):
     """The fp64 residue kernel with groups of 16 moduli: integers below 8 words (p = 113)
     against a 100-modulus prefix of the global list (54 one-limb, 46 two-limb), so that
