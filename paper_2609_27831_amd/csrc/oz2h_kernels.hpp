@@ -498,7 +498,7 @@ __device__ __forceinline__ void cvt4_words(uint32_t a, uint32_t b, uint32_t c, u
         : "v"(a), "v"(b), "v"(c), "v"(d));
 }
 
-// an NC-word chunk (NC = 16 or 4) into NE accumulators: lane j's weights c[i] are word
+// an NC-word chunk (NC = 16, 4 or 2) into NE accumulators: lane j's weights c[i] are word
 // w0 + i's; word w0 + i of entry u comes from lane i of the row.  For each broadcast lane the
 // NE entries follow each other, so that consecutive multiply-adds are independent.
 template <int NC, int NE, int I = 0>
@@ -564,7 +564,11 @@ __device__ __forceinline__ void residues_row_block(const ResRowArgs &a, uint32_t
     const int j = lane & 15, q = lane >> 4;
     const int h0 = NH == 2 ? 0 : (wv & 1);        // first entry half of this wave
     const int g0w = NH == 2 ? wv : (wv >> 1), gstep = NH == 2 ? 4 : 2;
-    const int nfull = a.nw32 >> 4, ntail = ((a.nw32 & 15) + 3) >> 2;
+    // words past the full 16-word chunks: chunks of 4, and a last chunk of 2 when at most two
+    // words remain (the words past nw32 are zero in LDS)
+    const int nfull = a.nw32 >> 4, nrem = a.nw32 & 15;
+    const int ntail = (nrem & 3) == 3 ? (nrem >> 2) + 1 : nrem >> 2;
+    const bool tail2 = (nrem & 3) == 1 || (nrem & 3) == 2;
     int8_t *prow = a.planes + r * a.kpad + k0;   // the block's segment of plane 0
     for (int g = g0w; g < a.rg16; g += gstep) {
         const int l = 16 * g + j;
@@ -574,10 +578,10 @@ __device__ __forceinline__ void residues_row_block(const ResRowArgs &a, uint32_t
         double acc[EPR];
 #pragma unroll
         for (int i = 0; i < EPR; ++i) acc[i] = 0.0;
-        // one NC-word chunk (NC = 16 or 4) from word w0 with the weights c
+        // one NC-word chunk (NC = 16, 4 or 2) from word w0 with the weights c
         auto chunk = [&](auto nc_, int w0, const double *c) {
             constexpr int NC = decltype(nc_)::value;
-            const uint32_t *wr = words + (size_t)(w0 + (NC == 16 ? j : (j & 3))) * kResRowS + 16 * q;
+            const uint32_t *wr = words + (size_t)(w0 + (j & (NC - 1))) * kResRowS + 16 * q;
 #pragma unroll
             for (int eb = 0; eb < EPR / 8; ++eb) {
                 const int e = 64 * (h0 + eb / 2) + 8 * (eb % 2);   // + 16 q, entries e .. e + 7
@@ -602,6 +606,12 @@ __device__ __forceinline__ void residues_row_block(const ResRowArgs &a, uint32_t
 #pragma unroll
             for (int i = 0; i < 4; ++i) c4[i] = crow[16 * nfull + 4 * c + i];
             chunk(std::integral_constant<int, 4>{}, 16 * nfull + 4 * c, c4);
+        }
+        if (tail2) {
+            double c2[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) c2[i] = crow[16 * nfull + 4 * ntail + i];
+            chunk(std::integral_constant<int, 2>{}, 16 * nfull + 4 * ntail, c2);
         }
 
         // per entry half: lane (q, j) holds the residues of its modulus for the 16 consecutive

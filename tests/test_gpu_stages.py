@@ -76,6 +76,8 @@ def rng_idx(r, c, frac, seed=0):
     # the row-broadcast VALU kernel (integers of 32 words or more) on both sides, and the
     # matrix-core variant
     (2048, -16, 16, "B", 0), (1536, -40, 40, "A", 0), (960, -8, 8, "A", 0), (3000, -8, 8, "B", 0),
+    # 34, 37 and 38 words: a last chunk of two words, after none or one chunk of four
+    (1050, -24, 24, "A", 0), (1150, -24, 24, "B", 0), (1180, -24, 24, "A", 0),
     (2048, -16, 16, "A", 1), (512, -32, 32, "B", 1)])
 def test_residue_planes(oz, c_oracle, p, lo, hi, side, flags):
     """Stage 2 vs Python-int centred residues of the oracle's integers a^."""
