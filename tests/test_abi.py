@@ -187,3 +187,14 @@ def test_backend_flags_rejected_where_unsupported(oz):
         with pytest.raises(oz.Oz2hError) as ei:
             oz.Plan.create_grad(64, 8, 8, 8, oz.default_opts(flags=flags))
         assert ei.value.code == oz.EUNSUPPORTED
+
+
+def test_batched_schedule_calls_reject_null_plans(oz):
+    """The batched schedule calls check their arguments on the host before any device work."""
+    import ctypes
+    L = oz.lib()
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    assert L.oz2h_batched_get_schedule(None, ctypes.addressof(a), ctypes.addressof(b)) == oz.EINVAL
+    assert L.oz2h_batched_set_schedule(None, 2, 1) == oz.EINVAL
+    assert L.oz2h_batched_get_config(None, None, None, None) == oz.EINVAL
+    assert L.oz2h_batched_set_config(None, 0, 0) == oz.EINVAL
