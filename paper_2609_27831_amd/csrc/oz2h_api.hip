@@ -1800,8 +1800,10 @@ uint64_t fnv1a(const void *data, size_t n, uint64_t h = 1469598103934665603ull) 
     return h;
 }
 
-// autotuner cache: shape signature -> (tile, blocks per CU); optionally mirrored in the
-// text file named by OZ2H_TUNE_CACHE (one "signature tile bpc" line per entry)
+// autotuner cache: shape signature -> (tile, blocks per CU, GEMM LDS stages, graph replay);
+// optionally mirrored in the text file named by OZ2H_TUNE_CACHE (one "signature tile bpc
+// stages graph" line per entry; lines of the older "signature tile bpc" form take three
+// stages and graph replay).  Lines that do not parse or hold values out of range are skipped.
 std::mutex g_tune_mu;
 struct TuneRec {
     int tile, bpc, stages, graph;
@@ -1822,6 +1824,9 @@ void tune_load() {
         TuneRec r{OZ2H_TILE_AUTO, 0, 3, 1};
         if (!(ls >> std::hex >> sig >> std::dec >> r.tile >> r.bpc)) continue;
         if (!(ls >> r.stages >> r.graph)) r.stages = 3, r.graph = 1;
+        if (r.tile < OZ2H_TILE_AUTO || r.tile > OZ2H_TILE_128x256 || r.bpc < 0 || r.bpc > 16 ||
+            (r.stages != 2 && r.stages != 3) || (r.graph != 0 && r.graph != 1))
+            continue;
         g_tune[sig] = r;
     }
 }

@@ -159,6 +159,62 @@ def test_batched_autotune(oz):
     assert c2["gemm_stages"] == cfg["gemm_stages"] and c2["graph"] == cfg["graph"]
 
 
+_TUNE_CHILD = r"""
+import json, sys
+import torch
+sys.path.insert(0, sys.argv[1])
+from paper_2609_27831_amd import oz2h
+from tests.gpu_util import dev_mp
+from tests.test_gpu_batched import make_batch
+batch = make_batch(17, 4, 64, 256)
+probs = [(dev_mp(A), dev_mp(B), oz2h.empty_mp(A.shape[0], B.shape[1], A.p), 0, 0) for A, B in batch]
+bp = oz2h.BatchedPlan(probs)
+cfg = bp.tune(bp.workspace()) if sys.argv[2] == "tune" else bp.config()
+torch.cuda.synchronize()
+print(json.dumps(cfg))
+"""
+
+
+def test_batched_tune_cache_file(oz, tmp_path):
+    """OZ2H_TUNE_CACHE: a tuned configuration is appended as "signature tile bpc stages graph"
+    and picked up by a new process; an older three-field line takes three stages and graph
+    replay; lines that do not parse or hold out-of-range values are skipped.  Each step runs in
+    a fresh process, since the library reads the file once per process."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = tmp_path / "tune.txt"
+    env = dict(os.environ, OZ2H_TUNE_CACHE=str(cache))
+
+    def child(mode):
+        print(f"tune-cache child: {mode}", flush=True)
+        r = subprocess.run([sys.executable, "-c", _TUNE_CHILD, root, mode], cwd=root, env=env,
+                           capture_output=True, text=True, timeout=240)
+        assert r.returncode == 0, r.stderr[-2000:]
+        return json.loads(r.stdout.strip().splitlines()[-1])
+
+    tuned = child("tune")
+    lines = cache.read_text().split()
+    assert len(lines) == 5
+    sig = lines[0]
+    assert [int(x) for x in lines[1:]] == [tuned["tile"], tuned["blocks_per_cu"],
+                                           tuned["gemm_stages"], int(tuned["graph"])]
+    got = child("config")
+    assert {k: got[k] for k in ("tile", "blocks_per_cu", "gemm_stages", "graph")} == \
+        {k: tuned[k] for k in ("tile", "blocks_per_cu", "gemm_stages", "graph")}
+    # later lines win; the three-field line is taken, the bad ones are skipped
+    with open(cache, "a") as f:
+        f.write(f"{sig} 1 0\n")
+        f.write(f"{sig} 9 0 3 1\n")        # tile out of range
+        f.write(f"{sig} 2 0 4 1\n")        # four LDS stages
+        f.write(f"{sig} 2 99 3 0\n")       # blocks per CU out of range
+        f.write("not a record\n")
+    got = child("config")
+    assert (got["tile"], got["blocks_per_cu"], got["gemm_stages"], got["graph"]) == (1, 0, 3, True)
+
+
 def test_batched_full_workload(oz, c_oracle):
     """The full batched workload (64 products, M, N, K log-uniform in [128, 4096],
     p in {53, 113, 256, 512}, exponents U[-4, 4], the generator and seed the bench uses):
