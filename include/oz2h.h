@@ -531,7 +531,10 @@ size_t oz2h_batched_workspace_size(const oz2h_batched_plan *plan);
  * result goes to an in-process cache keyed by the batch's shapes (and, if the
  * environment variable OZ2H_TUNE_CACHE names a file, is appended there, one line
  * "signature tile blocks_per_cu stages graph"; plans created later with
- * OZ2H_TILE_AUTO pick it up).  Synchronizes `stream`; the runs write the outputs
+ * OZ2H_TILE_AUTO pick it up, the file being read once per process; a later line for
+ * the same signature wins, and lines that do not parse or hold values outside the
+ * ranges of oz2h_batched_set_config and oz2h_batched_set_schedule are skipped).
+ * Synchronizes `stream`; the runs write the outputs
  * C (with the product's results).
  */
 int oz2h_batched_tune(oz2h_batched_plan *plan, void *workspace, size_t ws_bytes,
