@@ -716,7 +716,7 @@ def main():
                          "kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one MI355X only; --gpus N > 1 is not supported "
+        print("bench.py: measures one MI355X only; --gpus N > 1 is not supported "
               "(the multi-GPU sharding is a design only)", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
