@@ -1460,7 +1460,9 @@ BwdLayout bwd_layout(const PlanHost &h) {
 // saved planes [G][R rows][ldi] (rows r < R, columns c < C valid) -> [G][Co][Ro]
 int launch_plane_transpose(const int8_t *in, int64_t R, int64_t C, int64_t ldi, int64_t ips,
                            int8_t *out, int64_t Ro, int64_t Co, int G, hipStream_t s) {
-    dim3 grid((unsigned)(Co / 64), (unsigned)(Ro / 64), (unsigned)G);
+    if (Co % 128 || Ro % 128 || ldi % 16 || C > ldi || Co / 128 > INT32_MAX || Ro / 128 > 65535 || G > 65535)
+        return fail(OZ2H_EINVAL, "plane transpose: shapes the 128 x 128 tile kernel does not take");
+    dim3 grid((unsigned)(Co / 128), (unsigned)(Ro / 128), (unsigned)G);
     k_plane_transpose<<<grid, 256, 0, s>>>(in, R, C, ldi, ips, out, Ro, Co, (int64_t)Co * Ro);
     return check_launch("plane transpose");
 }

@@ -2097,38 +2097,54 @@ __global__ __launch_bounds__(64) void k_crt_row_finish(CrtArgs a, CrtRowArgs r) 
 }
 
 // planes [G][R][C] (int8, row stride ldi) -> [G][Co][Ro] (row stride Ro), zero where
-// the source is out of range.  A block moves a 64 x 64 byte tile: 16-byte global
-// loads of source rows into LDS, then each thread gathers 16 bytes of a source column
-// (one output row) and writes them with one 16-byte store.  Requires ldi, C, Ro and
-// Co to be multiples of 16 (the residue planes are padded to 128).
+// the source row is out of range.  A block moves a 128 x 128 byte tile.  Thread t loads the
+// 16-byte column chunk t % 8 of source rows 4 (t / 8) .. + 3 (four loads in flight), turns
+// each 4 x 4 byte block into four dwords (one source column, four source rows each) and
+// writes them to an LDS tile of output rows; the 16-byte chunks of an output row are stored
+// XOR-swizzled by its column chunk, so that a dword write instruction touches 32 banks
+// rather than 8.  Then 8 consecutive threads read one output row's eight chunks and store
+// them as one 128-byte segment.  Requires ldi to be a multiple of 16 with C <= ldi (a chunk
+// that starts below C stays in its row; its bytes past C, the planes' zero padding, land in
+// output rows >= C) and Ro, Co multiples of 128 (the residue planes are padded to 128 and
+// the GEMM tiles to 128 or 256).
 __global__ __launch_bounds__(256) void k_plane_transpose(const int8_t *__restrict__ in, int64_t R,
                                                          int64_t C, int64_t ldi, int64_t ips,
                                                          int8_t *__restrict__ out, int64_t Ro,
                                                          int64_t Co, int64_t ops) {
-    __shared__ uint8_t tile[64][64 + 4];
+    __shared__ __attribute__((aligned(16))) uint32_t tile[128 * 32];   // [output row][32 dwords]
     const int64_t g = blockIdx.z;
-    const int64_t c0 = (int64_t)blockIdx.x * 64, r0 = (int64_t)blockIdx.y * 64;   // source tile
-    const int t = threadIdx.x, tr = t >> 2, tq = (t & 3) * 16;
-    {   // source row r0 + tr, columns c0 + tq .. + 15
-        const int64_t r = r0 + tr, c = c0 + tq;
-        v4i x = v4i{0, 0, 0, 0};
-        if (r < R && c < C) x = *(const v4i *)(in + g * ips + r * ldi + c);
-        uint32_t *dst = (uint32_t *)&tile[tr][tq];
-        dst[0] = (uint32_t)x[0];
-        dst[1] = (uint32_t)x[1];
-        dst[2] = (uint32_t)x[2];
-        dst[3] = (uint32_t)x[3];
+    const int64_t c0 = (int64_t)blockIdx.x * 128, r0 = (int64_t)blockIdx.y * 128;   // source tile
+    const int t = threadIdx.x;
+    {
+        const int cc = t & 7, rg = t >> 3;   // column chunk, group of four source rows
+        const int64_t c = c0 + 16 * cc;
+        v4i x[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t r = r0 + 4 * rg + i;
+            x[i] = v4i{0, 0, 0, 0};
+            if (r < R && c < C) x[i] = *(const v4i *)(in + g * ips + r * ldi + c);
+        }
+        // dword of output row o = 16 cc + 4 q + j: byte j of each of the four rows' word q
+        const int pc = 4 * ((rg >> 2) ^ cc) + (rg & 3);   // swizzled dword position in the row
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t d = (((uint32_t)x[0][q] >> (8 * j)) & 0xFFu) |
+                                   ((((uint32_t)x[1][q] >> (8 * j)) & 0xFFu) << 8) |
+                                   ((((uint32_t)x[2][q] >> (8 * j)) & 0xFFu) << 16) |
+                                   ((((uint32_t)x[3][q] >> (8 * j)) & 0xFFu) << 24);
+                tile[(16 * cc + 4 * q + j) * 32 + pc] = d;
+            }
     }
     __syncthreads();
-    {   // output row c0 + tr (= source column), output columns r0 + tq .. + 15 (= source rows)
-        const int64_t orow = c0 + tr, ocol = r0 + tq;
-        uint32_t w[4];
+    const int qc = t & 7;   // logical chunk: output columns r0 + 16 qc .. + 15
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            w[j] = (uint32_t)tile[tq + 4 * j][tr] | ((uint32_t)tile[tq + 4 * j + 1][tr] << 8) |
-                   ((uint32_t)tile[tq + 4 * j + 2][tr] << 16) | ((uint32_t)tile[tq + 4 * j + 3][tr] << 24);
-        if (orow < Co && ocol < Ro)
-            *(v4i *)(out + g * ops + orow * Ro + ocol) = v4i{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
+    for (int i = 0; i < 4; ++i) {
+        const int o = (t >> 3) + 32 * i;   // output row c0 + o
+        const v4i v = *(const v4i *)&tile[o * 32 + 4 * (qc ^ ((o >> 4) & 7))];
+        *(v4i *)(out + g * ops + (c0 + o) * Ro + r0 + 16 * qc) = v;
     }
 }
 
