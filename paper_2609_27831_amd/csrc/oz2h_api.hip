@@ -1594,6 +1594,20 @@ int oz2h_gemm_backward(const oz2h_plan *plan, int64_t M, int64_t N, int64_t K, c
     return ok();
 }
 
+// carrier kernels: blocks of 256 elements staged through LDS while their carrier run is at
+// most 32 KiB (CW <= 16), blocks of 64 up to 64 KiB (CW <= 128), direct slot access beyond
+struct CarrierLaunch {
+    int64_t blocks;
+    int threads;
+    size_t lds;   // 0: direct
+};
+static CarrierLaunch carrier_launch(int64_t n, int nl) {
+    const int cw = 2 + 2 * nl;
+    if (cw <= 16) return {(n + 255) / 256, 256, (size_t)256 * cw * sizeof(double)};
+    if (cw <= 128) return {(n + 63) / 64, 64, (size_t)64 * cw * sizeof(double)};
+    return {(n + 255) / 256, 256, 0};
+}
+
 int oz2h_carrier_pack(int64_t rows, int64_t cols, int32_t p, oz2h_cmat X, double *carrier,
                       hipStream_t stream) {
     int dev = -1;
@@ -1603,8 +1617,14 @@ int oz2h_carrier_pack(int64_t rows, int64_t cols, int32_t p, oz2h_cmat X, double
     if (rows * cols == 0) return ok();
     if (!carrier || (st = check_cmat(X, "X", rows, cols))) return st ? st : fail(OZ2H_EINVAL, "carrier is NULL");
     const int nl = (p + 63) / 64;
-    k_carrier_pack<<<(unsigned)((rows * cols + 255) / 256), 256, 0, stream>>>(
-        rows, cols, p, nl, X.sign, X.exp, X.limbs, X.ld, carrier);
+    const CarrierLaunch cl = carrier_launch(rows * cols, nl);
+    if (cl.blocks > INT32_MAX) return fail(OZ2H_ERANGE, "carrier pack: too many elements for one launch");
+    if (cl.lds)
+        k_carrier_pack<true><<<(unsigned)cl.blocks, cl.threads, cl.lds, stream>>>(
+            rows, cols, p, nl, X.sign, X.exp, X.limbs, X.ld, carrier);
+    else
+        k_carrier_pack<false><<<(unsigned)cl.blocks, cl.threads, 0, stream>>>(
+            rows, cols, p, nl, X.sign, X.exp, X.limbs, X.ld, carrier);
     st = check_launch("carrier pack");
     return st ? st : ok();
 }
@@ -1619,8 +1639,14 @@ int oz2h_carrier_unpack(int64_t rows, int64_t cols, int32_t p, const double *car
     if (!carrier) return fail(OZ2H_EINVAL, "carrier is NULL");
     if ((st = check_mat_out(&X, "X", cols))) return st;
     const int nl = (p + 63) / 64;
-    k_carrier_unpack<<<(unsigned)((rows * cols + 255) / 256), 256, 0, stream>>>(
-        rows, cols, p, nl, carrier, X.sign, X.exp, X.limbs, X.ld, bad);
+    const CarrierLaunch cl = carrier_launch(rows * cols, nl);
+    if (cl.blocks > INT32_MAX) return fail(OZ2H_ERANGE, "carrier unpack: too many elements for one launch");
+    if (cl.lds)
+        k_carrier_unpack<true><<<(unsigned)cl.blocks, cl.threads, cl.lds, stream>>>(
+            rows, cols, p, nl, carrier, X.sign, X.exp, X.limbs, X.ld, bad);
+    else
+        k_carrier_unpack<false><<<(unsigned)cl.blocks, cl.threads, 0, stream>>>(
+            rows, cols, p, nl, carrier, X.sign, X.exp, X.limbs, X.ld, bad);
     st = check_launch("carrier unpack");
     return st ? st : ok();
 }

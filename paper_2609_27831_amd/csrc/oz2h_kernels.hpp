@@ -2166,16 +2166,11 @@ __global__ void k_zero_out(int8_t *__restrict__ s, int32_t *__restrict__ e,
 // Every slot but [0] is an exactly representable integer, so the encoding
 // survives any copy, view or device move of a floating tensor.
 
-__global__ __launch_bounds__(256) void k_carrier_pack(int64_t rows, int64_t cols, int p, int nl,
-                                                      const int8_t *__restrict__ sign,
-                                                      const int32_t *__restrict__ exps,
-                                                      const uint64_t *__restrict__ limbs,
-                                                      int64_t ld, double *__restrict__ car) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= rows * cols) return;
-    const int64_t r = idx / cols, c = idx - r * cols, src = r * ld + c;
-    const int cw = 2 + 2 * nl;
-    double *o = car + idx * cw;
+// the CW slots of element src of X into o
+__device__ __forceinline__ void carrier_encode(int p, int nl, const int8_t *__restrict__ sign,
+                                               const int32_t *__restrict__ exps,
+                                               const uint64_t *__restrict__ limbs, int64_t src,
+                                               double *o) {
     const int s = sign[src];
     const int e = s ? exps[src] : 0;
     const int top = p - 64 * (nl - 1);   // bits of the top limb, 1..64
@@ -2202,19 +2197,58 @@ __global__ __launch_bounds__(256) void k_carrier_pack(int64_t rows, int64_t cols
     o[1] = 4.0 * (double)e + (double)(s + 1);
 }
 
+// STAGED: a block's elements are consecutive, so its part of the carrier is one contiguous
+// run of blockDim.x * CW doubles; each thread writes its CW slots into LDS and the block then
+// copies the run out with consecutive lanes on consecutive doubles (one thread per element
+// writing its own slots directly puts lanes CW * 8 bytes apart).  Dynamic LDS:
+// blockDim.x * CW doubles.
+template <bool STAGED>
+__global__ __launch_bounds__(256) void k_carrier_pack(int64_t rows, int64_t cols, int p, int nl,
+                                                      const int8_t *__restrict__ sign,
+                                                      const int32_t *__restrict__ exps,
+                                                      const uint64_t *__restrict__ limbs,
+                                                      int64_t ld, double *__restrict__ car) {
+    extern __shared__ __attribute__((aligned(16))) double cstage[];
+    const int64_t n = rows * cols, e0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t idx = e0 + threadIdx.x;
+    const int cw = 2 + 2 * nl;
+    if (idx < n) {
+        const int64_t r = idx / cols, c = idx - r * cols;
+        carrier_encode(p, nl, sign, exps, limbs, r * ld + c,
+                       STAGED ? cstage + (size_t)threadIdx.x * cw : car + idx * cw);
+    }
+    if constexpr (STAGED) {
+        __syncthreads();
+        const int64_t total = (n - e0 < (int64_t)blockDim.x ? n - e0 : (int64_t)blockDim.x) * cw;
+        double *dst = car + e0 * cw;
+        for (int64_t i = threadIdx.x; i < total; i += blockDim.x) dst[i] = cstage[i];
+    }
+}
+
 // bad (nullable) gets a 1 if any element is not a valid encoding; such an
 // element is written as zero
+// STAGED: the block first copies its contiguous run of the carrier into LDS (consecutive
+// lanes on consecutive doubles), then each thread decodes its element from there.
+template <bool STAGED>
 __global__ __launch_bounds__(256) void k_carrier_unpack(int64_t rows, int64_t cols, int p, int nl,
                                                         const double *__restrict__ car,
                                                         int8_t *__restrict__ sign,
                                                         int32_t *__restrict__ exps,
                                                         uint64_t *__restrict__ limbs, int64_t ld,
                                                         int32_t *bad) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= rows * cols) return;
-    const int64_t r = idx / cols, c = idx - r * cols, dst = r * ld + c;
+    extern __shared__ __attribute__((aligned(16))) double cstage[];
+    const int64_t n = rows * cols, e0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t idx = e0 + threadIdx.x;
     const int cw = 2 + 2 * nl;
-    const double *in = car + idx * cw;
+    if constexpr (STAGED) {
+        const int64_t total = (n - e0 < (int64_t)blockDim.x ? n - e0 : (int64_t)blockDim.x) * cw;
+        const double *src = car + e0 * cw;
+        for (int64_t i = threadIdx.x; i < total; i += blockDim.x) cstage[i] = src[i];
+        __syncthreads();
+    }
+    if (idx >= n) return;
+    const int64_t r = idx / cols, c = idx - r * cols, dst = r * ld + c;
+    const double *in = STAGED ? cstage + (size_t)threadIdx.x * cw : car + idx * cw;
     const double code = in[1];
     bool ok = code == rint(code) && fabs(code) < 0x1p33;
     const double q = floor(code * 0.25);
