@@ -56,7 +56,7 @@ def _assert_equals_oracle(got, ref, sel=None):
 
 # ---------------------------------------------------------------- carriers
 
-@pytest.mark.parametrize("p", [2, 53, 64, 65, 256, 448, 2048, 4100])
+@pytest.mark.parametrize("p", [2, 53, 64, 65, 256, 448, 2048, 3000, 4032, 4100])
 def test_carrier_round_trip(oz, p):
     import torch
     X = synth.mp_random(300 + p, 37, 29, p, -1100, 1100)
