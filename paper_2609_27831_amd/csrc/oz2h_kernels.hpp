@@ -1158,24 +1158,36 @@ __device__ __forceinline__ void gemm_tile(const Args &args, int64_t mt, int64_t 
     } else {
         int16_t *base2 = nullptr;
         if constexpr (MODE == ZGAUSS) base2 = args.V2 + (int64_t)l * args.v_ps + lane_off;
+        // per row group x: every old value is loaded before the first store, so the group
+        // waits once (stores count against the same counter as loads: interleaved, each
+        // load would wait for the stores before it)
 #pragma unroll
-        for (int x = 0; x < FM; ++x)
+        for (int x = 0; x < FM; ++x) {
+            int32_t t1[FN][16], t2[FN][16];
 #pragma unroll
             for (int y = 0; y < FN; ++y)
 #pragma unroll
                 for (int e = 0; e < 16; ++e) {
                     const int64_t o = (int64_t)(x * 32 + 8 * (e >> 2) + (e & 3)) * ldv + y * 32;
-                    const int32_t v = acc[x][y][e], t1 = base[o];
+                    t1[y][e] = base[o];
+                    if constexpr (MODE == ZGAUSS) t2[y][e] = base2[o];
+                }
+#pragma unroll
+            for (int y = 0; y < FN; ++y)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int64_t o = (int64_t)(x * 32 + 8 * (e >> 2) + (e & 3)) * ldv + y * 32;
+                    const int32_t v = acc[x][y][e];
                     if constexpr (MODE == ZADD) {
-                        base[o] = (int16_t)centred_mod((double)(t1 + v), md, inv_m);
+                        base[o] = (int16_t)centred_mod((double)(t1[y][e] + v), md, inv_m);
                     } else if constexpr (MODE == ZSUB) {
-                        base[o] = (int16_t)centred_mod((double)(t1 - v), md, inv_m);
+                        base[o] = (int16_t)centred_mod((double)(t1[y][e] - v), md, inv_m);
                     } else {
-                        const int32_t t2 = base2[o];
-                        base[o] = (int16_t)centred_mod((double)(t1 - t2), md, inv_m);
-                        base2[o] = (int16_t)centred_mod((double)(v - t1 - t2), md, inv_m);
+                        base[o] = (int16_t)centred_mod((double)(t1[y][e] - t2[y][e]), md, inv_m);
+                        base2[o] = (int16_t)centred_mod((double)(v - t1[y][e] - t2[y][e]), md, inv_m);
                     }
                 }
+        }
     }
 }
 
