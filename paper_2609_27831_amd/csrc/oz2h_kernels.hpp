@@ -2042,11 +2042,7 @@ __global__ __launch_bounds__(64) void k_crt_row_finish(CrtArgs a, CrtRowArgs r) 
         const int gc = min(g, ng - 1);
 #pragma unroll
         for (int u = 0; u < 16; ++u) dv[u] = r.dig[(int64_t)(16 * gc + u) * r.estride + ep];
-        // carry-out of the group below; always loaded (group 0 reads group 0's and drops it),
-        // since a load under a branch is waited for, with the digit loads before it, at the
-        // branch's end, and the next group's digits would no longer arrive during a group
-        const int32_t cv = r.cout[(int64_t)(gc > 0 ? gc - 1 : 0) * r.estride + ep];
-        co = gc > 0 ? cv : 0;
+        co = gc > 0 ? r.cout[(int64_t)(gc - 1) * r.estride + ep] : 0;
     };
     uint32_t da[16], db[16];
     int32_t ca, cb;
