@@ -2258,38 +2258,65 @@ __global__ __launch_bounds__(256) void k_carrier_unpack(int64_t rows, int64_t co
         for (int64_t i = threadIdx.x; i < total; i += blockDim.x) cstage[i] = src[i];
         __syncthreads();
     }
-    if (idx >= n) return;
-    const int64_t r = idx / cols, c = idx - r * cols, dst = r * ld + c;
-    const double *in = STAGED ? cstage + (size_t)threadIdx.x * cw : car + idx * cw;
-    const double code = in[1];
-    bool ok = code == rint(code) && fabs(code) < 0x1p33;
-    const double q = floor(code * 0.25);
-    const int s = ok ? (int)(code - 4.0 * q) - 1 : 0;
-    const int64_t e = (int64_t)q;
-    ok = ok && s <= 1 && e >= INT_MIN && e <= INT_MAX;
-    const int top = p - 64 * (nl - 1);
-    for (int l = 0; l < nl; ++l) {
-        const double lo = in[2 + 2 * l], hi = in[3 + 2 * l];
-        ok = ok && lo == rint(lo) && hi == rint(hi) && lo >= 0.0 && hi >= 0.0 &&
-             lo < 0x1p32 && hi < 0x1p32;
+    // STAGED with ld == cols: the block's limbs are one contiguous run too; each thread puts
+    // its limbs over its own (already read) LDS slots and the block stores the run together
+    const bool dense = STAGED && ld == cols;
+    if (!dense && idx >= n) return;
+    if (idx < n) {
+        const int64_t r = idx / cols, c = idx - r * cols, dst = r * ld + c;
+        double *in = STAGED ? cstage + (size_t)threadIdx.x * cw : const_cast<double *>(car) + idx * cw;
+        const double code = in[1];
+        bool ok = code == rint(code) && fabs(code) < 0x1p33;
+        const double q = floor(code * 0.25);
+        const int s = ok ? (int)(code - 4.0 * q) - 1 : 0;
+        const int64_t e = (int64_t)q;
+        ok = ok && s <= 1 && e >= INT_MIN && e <= INT_MAX;
+        const int top = p - 64 * (nl - 1);
+        for (int l = 0; l < nl; ++l) {
+            const double lo = in[2 + 2 * l], hi = in[3 + 2 * l];
+            ok = ok && lo == rint(lo) && hi == rint(hi) && lo >= 0.0 && hi >= 0.0 &&
+                 lo < 0x1p32 && hi < 0x1p32;
+        }
+        uint64_t topl = 0, any = 0;
+        // dense: limb l goes over LDS slot l, kept as a double bit pattern (slot l was read
+        // before: limb l reads slots 2 + 2l and 3 + 2l)
+        auto put = [&](int l, uint64_t v) {
+            if (dense) in[l] = __builtin_bit_cast(double, v);
+            else limbs[dst * nl + l] = v;
+        };
+        for (int l = 0; l < nl; ++l) {
+            const uint64_t x = ok ? ((uint64_t)(uint32_t)in[2 + 2 * l] |
+                                     ((uint64_t)(uint32_t)in[3 + 2 * l] << 32)) : 0;
+            if (l == nl - 1) topl = x;
+            any |= x;
+            put(l, s && ok ? x : 0);
+        }
+        // a nonzero value must be normalised (bit p - 1 set, nothing above it), a
+        // zero must have zero limbs
+        if (ok) ok = s ? (topl >> (top - 1)) == 1 : any == 0;
+        if (!ok) {
+            for (int l = 0; l < nl; ++l) put(l, 0);
+            if (bad) *bad = 1;
+        }
+        sign[dst] = ok ? (int8_t)s : 0;
+        exps[dst] = ok && s ? (int32_t)e : 0;
     }
-    uint64_t topl = 0, any = 0;
-    for (int l = 0; l < nl; ++l) {
-        const uint64_t x = ok ? ((uint64_t)(uint32_t)in[2 + 2 * l] |
-                                 ((uint64_t)(uint32_t)in[3 + 2 * l] << 32)) : 0;
-        if (l == nl - 1) topl = x;
-        any |= x;
-        limbs[dst * nl + l] = s && ok ? x : 0;
+    if (dense) {
+        __syncthreads();
+        const int64_t cnt = n - e0 < (int64_t)blockDim.x ? n - e0 : (int64_t)blockDim.x;
+        uint64_t *out = limbs + e0 * nl;
+        const int bd = blockDim.x, dt = bd / nl, dw = bd % nl;   // flat f = t nl + l advances by bd
+        int t = (int)threadIdx.x / nl, l = (int)threadIdx.x - t * nl;
+        for (int64_t f = threadIdx.x; f < cnt * nl; f += bd) {
+            out[f] = __builtin_bit_cast(uint64_t, cstage[(size_t)t * cw + l]);
+            t += dt;
+            l += dw;
+            if (l >= nl) {
+                l -= nl;
+                ++t;
+            }
+        }
     }
-    // a nonzero value must be normalised (bit p - 1 set, nothing above it), a
-    // zero must have zero limbs
-    if (ok) ok = s ? (topl >> (top - 1)) == 1 : any == 0;
-    if (!ok) {
-        for (int l = 0; l < nl; ++l) limbs[dst * nl + l] = 0;
-        if (bad) *bad = 1;
-    }
-    sign[dst] = ok ? (int8_t)s : 0;
-    exps[dst] = ok && s ? (int32_t)e : 0;
 }
 
 }  // namespace oz2h

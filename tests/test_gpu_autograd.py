@@ -90,6 +90,33 @@ def test_carrier_round_trip(oz, p):
             assert c0[i, j] == want
 
 
+@pytest.mark.parametrize("p", [64, 448, 2048])
+def test_carrier_unpack_into_strided_output(oz, p):
+    """oz2h_carrier_unpack into a matrix of row stride ld > cols (the C call; the binding
+    allocates dense outputs): the columns it covers equal the dense unpack, the others are
+    left untouched."""
+    import torch
+    X = synth.mp_random(500 + p, 37, 29, p, -50, 50)
+    X.sign[2, :] = 0
+    car = oz.carrier_pack(dev_mp(X))
+    dense = oz.carrier_unpack(car, p)
+    wide = oz.empty_mp(37, 29 + 5, p)
+    wide.sign.fill_(7)
+    wide.exp.fill_(-3)
+    wide.limbs.fill_(-1)
+    bad = torch.zeros(1, dtype=torch.int32, device="cuda")
+    print(f"carrier strided unpack p={p}", flush=True)
+    st = oz.lib().oz2h_carrier_unpack(37, 29, p, car.data_ptr(), wide.mat(), bad.data_ptr(), None)
+    assert st == 0
+    torch.cuda.synchronize()
+    assert int(bad.item()) == 0
+    ds, de, dl = dense.to_host()
+    ws, we, wl = wide.to_host()
+    assert np.array_equal(ws[:, :29], ds) and np.array_equal(we[:, :29], de)
+    assert np.array_equal(wl[:, :29], dl)
+    assert (ws[:, 29:] == 7).all() and (we[:, 29:] == -3).all()
+    assert (wl[:, 29:] == np.uint64(0xFFFFFFFFFFFFFFFF)).all()
+
 def test_carrier_rejects_arithmetic(oz):
     import torch
     X = synth.mp_random(7, 4, 5, 128, -8, 8)
