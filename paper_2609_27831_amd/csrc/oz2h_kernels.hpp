@@ -180,29 +180,20 @@ __device__ __forceinline__ int build_words(OZ2H_G(uint64_t) *__restrict__ sl, in
         prev = cur;
     };
     auto ld = [&](int l) { return sl[min(l, nlimb - 1)]; };
-    // limbs in batches of B, all B loads issued before the first is used (addresses clamped to
-    // the last limb, so no load sits under a branch); limbs past the top are zero, then one
-    // more word of zeros for the carry-out of the shift
-    auto run = [&](auto b_) {
-        constexpr int B = decltype(b_)::value;
-        int l0 = 0;
-        for (; l0 < nlimb; l0 += B) {
-            uint64_t rb[B];
-#pragma unroll
-            for (int u = 0; u < B; ++u) rb[u] = ld(l0 + u);
-#pragma unroll
-            for (int u = 0; u < B; ++u) {
-                const int l = l0 + u;
-                uint64_t x = l < nlimb ? rb[u] : 0ull;
-                if (l == nlimb - 1) x &= topm;
-                word(2 * l, (uint32_t)x);
-                word(2 * l + 1, (uint32_t)(x >> 32));
-            }
-        }
-        word(2 * l0, 0u);
+    uint64_t r0 = ld(0), r1 = ld(1);
+    auto limb = [&](int l, uint64_t &r) {
+        uint64_t x = l < nlimb ? r : 0ull;
+        if (l == nlimb - 1) x &= topm;
+        r = ld(l + 2);
+        word(2 * l, (uint32_t)x);
+        word(2 * l + 1, (uint32_t)(x >> 32));
     };
-    if (nlimb > 4) run(std::integral_constant<int, 8>{});
-    else run(std::integral_constant<int, 2>{});
+    // limbs 0 .. nlimb - 1, then one more word of zeros for the carry-out of the shift
+    for (int l = 0; l < nlimb; l += 2) {
+        limb(l, r0);
+        limb(l + 1, r1);
+    }
+    word(2 * ((nlimb + 1) & ~1), 0u);
     if (rbit && (sticky || (col[0] & 1u))) {   // round half to even: add one
         for (int w = 0; w < nw; ++w) {
             const uint32_t v = col[w * st] + 1u;
